@@ -1,0 +1,594 @@
+"""Pins for the FP64 CPU oracle: each test checks the oracle against something
+other than itself -- hand-derived fixtures (tests/golden), closed forms,
+invariants, library routines, brute force on tiny inputs, and finite
+differences -- chosen so that a dropped term, a wrong sign or index, or a
+transposed operand in the oracle fails one of them.  CPU only.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_0709_3331_amd import inputs
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _gold(name):
+    with open(os.path.join(GOLD, name)) as fh:
+        return json.load(fh)
+
+
+def _rand_cloud(n, seed, sigma=1.0):
+    return inputs.gaussian_cloud(n, sigma, 1e-3, 1e-5, seed)
+
+
+def _relrms(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+# --------------------------------------------------------------------------
+# Direct sum (C-1): Eq. (1)-(2) in reduced units with softening.
+# --------------------------------------------------------------------------
+def test_direct_two_body_golden():
+    g = _gold("two_body.json")
+    f, phi = oracle.direct(g["x"], g["q"], g["eps"])
+    np.testing.assert_allclose(f, g["f"], rtol=0, atol=1e-17)
+    np.testing.assert_allclose(phi, g["phi"], rtol=1e-15)
+    U = oracle.energy(np.zeros((2, 3)), g["q"], np.ones(2), phi)[1]
+    assert abs(U - g["U"]) < 1e-16
+
+
+def test_direct_softened_pair_closed_form():
+    # |F| = r / (r^2 + eps^2)^{3/2}: pair at distance r = 0.3, eps = 0.4 -> h = 0.5
+    x = np.array([[0.0, 0.0, 0.0], [0.0, 0.3, 0.0]])
+    f, phi = oracle.direct(x, [1.0, 1.0], 0.4)
+    assert f[0, 1] == pytest.approx(-0.3 / 0.125, rel=1e-15)   # repulsion, h^3 = 0.125
+    assert f[1, 1] == pytest.approx(+0.3 / 0.125, rel=1e-15)
+    assert phi[0] == pytest.approx(2.0, rel=1e-15)               # 1/h
+    assert f[0, 0] == 0.0 and f[0, 2] == 0.0
+
+
+def test_direct_cube_corners_symmetry():
+    # Eight equal charges at the corners of a cube: zero field at the centre,
+    # potential 8/sqrt(3) at eps = 0 (symmetry; textbook).
+    c = np.array([[sx, sy, sz] for sx in (-1, 1) for sy in (-1, 1) for sz in (-1, 1)], float)
+    x = np.vstack([c, np.zeros((1, 3))])
+    q = np.ones(9)
+    f, phi = oracle.direct(x, q, 0.0)
+    assert np.abs(f[8]).max() < 1e-15
+    assert phi[8] == pytest.approx(8 / np.sqrt(3), rel=1e-15)
+
+
+def test_direct_newton_third_law_and_invariances():
+    cl = _rand_cloud(512, 3)
+    f, phi = oracle.direct(cl.x, cl.q, 0.01)
+    assert np.abs(f.sum(0)).max() / np.abs(f).sum() < 1e-14
+    # permutation invariance
+    p = np.random.default_rng(1).permutation(cl.n)
+    f2, phi2 = oracle.direct(cl.x[p], cl.q[p], 0.01)
+    np.testing.assert_allclose(f2, f[p], rtol=1e-12, atol=1e-12 * np.abs(f).max())
+    np.testing.assert_allclose(phi2, phi[p], rtol=1e-12, atol=1e-12)
+    # translation invariance
+    f3, phi3 = oracle.direct(cl.x + np.array([10.0, -3.0, 0.25]), cl.q, 0.01)
+    assert _relrms(f3, f) < 1e-11
+    # homogeneity at eps = 0: x -> 2x gives F/4, phi/2
+    f4, phi4 = oracle.direct(cl.x, cl.q, 0.0)
+    f5, phi5 = oracle.direct(2.0 * cl.x, cl.q, 0.0)
+    np.testing.assert_allclose(f5, f4 / 4, rtol=1e-13, atol=1e-13 * np.abs(f4).max())
+    np.testing.assert_allclose(phi5, phi4 / 2, rtol=1e-13, atol=1e-13)
+
+
+def test_direct_targets_match_full():
+    cl = _rand_cloud(300, 5)
+    f, phi = oracle.direct(cl.x, cl.q, 0.02)
+    t = np.array([0, 7, 150, 299])
+    ft, pt = oracle.direct_targets(cl.x, cl.q, 0.02, t)
+    np.testing.assert_array_equal(ft, f[t])
+    np.testing.assert_array_equal(pt, phi[t])
+
+
+# --------------------------------------------------------------------------
+# Cube and keys (C-2.1, C-2.2).
+# --------------------------------------------------------------------------
+def test_cube_hand_examples():
+    lo, e = oracle.cube([[0, 0, 0], [1, 0, 0]])
+    assert e == 1 and list(lo) == [0, 0, 0]          # 2^1 > 1, 2^0 = 1 is not
+    _, e = oracle.cube([[0, 0, 0], [0.75, 0.5, 0]])
+    assert e == 0
+    _, e = oracle.cube([[0, 0, 0], [0, 0, 0.5]])
+    assert e == 0                                      # 2^0 > 0.5 >= 2^-1
+    _, e = oracle.cube([[0, 0, 0], [0, 0, 0.49]])
+    assert e == -1
+    lo, e = oracle.cube([[1, 2, 3], [1, 2, 3]])
+    assert e == 0 and list(lo) == [1, 2, 3]            # zero extent
+    lo, e = oracle.cube([[-5, 1, 0], [3, -2, 1]])
+    assert list(lo) == [-5, -2, 0] and e == 4          # extent 8 -> 16
+    with pytest.raises(ValueError):
+        oracle.cube([[0, np.nan, 0]])
+
+
+def test_keys_golden_b10():
+    g = _gold("keys_b10.json")
+    x = np.array(g["x"])
+    lo, e = oracle.cube(x)
+    assert list(lo) == g["lo"] and e == g["e"]
+    k = oracle.keys(x, lo, e, g["b"])
+    assert [int(v) for v in k] == g["keys"]
+    assert [int(v) >> 27 for v in k] == g["top_octant"]
+
+
+def test_keys_cell_centres_quantise_exactly():
+    # a point at lo + (k + 1/2) 2^(e-b) lies in cell k of the finest level
+    rng = np.random.default_rng(2)
+    b, e = 21, 3
+    lo = np.array([-4.0, -4.0, -4.0])
+    kk = rng.integers(0, 2 ** b, size=(200, 3))
+    x = lo + (kk + 0.5) * 2.0 ** (e - b)
+    x = np.vstack([x, lo, lo + 7.99])       # keep the cube at lo, side 2^3
+    lo2, e2 = oracle.cube(x)
+    assert e2 == e and np.all(lo2 == lo)
+    k = oracle.keys(x, lo, e, b)
+    # recover X, Y, Z from the key by reading digit columns (geometric octant labels)
+    for r in range(200):
+        X = Y = Z = 0
+        for t in range(b):
+            X |= ((int(k[r]) >> (3 * t + 2)) & 1) << t
+            Y |= ((int(k[r]) >> (3 * t + 1)) & 1) << t
+            Z |= ((int(k[r]) >> (3 * t)) & 1) << t
+        assert (X, Y, Z) == tuple(int(v) for v in kk[r])
+
+
+def test_keys_clamp_and_range():
+    x = np.array([[0.0, 0.0, 0.0], [0.999999999, 0.4, 0.5]])
+    lo, e = oracle.cube(x)
+    assert e == 0
+    k = oracle.keys(x, lo, e, 21)
+    assert int(k.max()) < 2 ** 63
+    # x in the upper half, y in the lower half, z exactly at the midpoint -> upper half
+    assert (int(k[1]) >> 60) == 5
+    # the largest coordinate maps to the last cell, 2^21 - 1, on every level
+    assert all(((int(k[1]) >> (3 * t + 2)) & 1) == 1 for t in range(21))
+
+
+def test_keys_octants_match_geometry():
+    # every level: the key digit is the octant of the particle relative to the
+    # centre of the box named by the preceding digits (computed geometrically)
+    cl = _rand_cloud(256, 4)
+    lo, e = oracle.cube(cl.x)
+    b = 21
+    k = oracle.keys(cl.x, lo, e, b)
+    for i in range(cl.n):
+        c = lo + 2.0 ** (e - 1)
+        half = 2.0 ** (e - 1)
+        for lvl in range(1, 12):
+            oct_geo = 4 * (cl.x[i, 0] >= c[0]) + 2 * (cl.x[i, 1] >= c[1]) + (cl.x[i, 2] >= c[2])
+            digit = (int(k[i]) >> (3 * (b - lvl))) & 7
+            assert digit == oct_geo
+            half /= 2
+            c = c + np.array([half if (digit >> 2) & 1 else -half,
+                              half if (digit >> 1) & 1 else -half,
+                              half if digit & 1 else -half])
+
+
+def test_sort_is_stable_library_order():
+    rng = np.random.default_rng(7)
+    key = rng.integers(0, 50, size=5000).astype(np.uint64)
+    p = oracle.stable_order(key)
+    np.testing.assert_array_equal(p, np.argsort(key, kind="stable"))
+
+
+# --------------------------------------------------------------------------
+# Tree (C-2.3 .. C-2.5) against the hand-derived example and invariants.
+# --------------------------------------------------------------------------
+def test_tiny_tree_golden():
+    g = _gold("tiny_tree.json")
+    t = oracle.Tree(g["x"], g["q"], 0.5, 0.01, b=g["b"], leaf_cap=g["leaf_cap"], G=1)
+    lo, e = t.cube()
+    assert list(lo) == g["lo"] and e == g["e"]
+    assert [int(v) for v in oracle.keys(g["x"], lo, e, g["b"])] == g["keys"]
+    assert list(t.perm()) == g["perm"]
+    lv, fi, co, sk = t.nodes()
+    assert list(lv) == g["level"] and list(fi) == g["first"]
+    assert list(co) == g["count"] and list(sk) == g["skip"]
+    np.testing.assert_array_equal(t.centres(), np.array(g["centre"]))
+    assert list(t.arch_series()) == g["arch_series"]
+    gf, gc, gn = t.groups()
+    assert [list(v) for v in zip(gf, gc, gn)] == g["groups_G1"]
+    t2 = oracle.Tree(g["x"], g["q"], 0.5, 0.01, b=g["b"], leaf_cap=g["leaf_cap"], G=2)
+    gf, gc, gn = t2.groups()
+    assert [list(v) for v in zip(gf, gc, gn)] == g["groups_G2"]
+    m = t.moments()[3]
+    ref = g["moments_node3"]
+    assert m[0] == ref["Q"]
+    np.testing.assert_allclose(m[1:4], ref["p"], rtol=1e-15)
+    np.testing.assert_allclose(m[4:10], ref["S"], rtol=1e-13)
+
+
+def _check_tree_invariants(t, x, leaf_cap, G):
+    lv, fi, co, sk = t.nodes()
+    M = t.nnodes
+    n = t.n
+    xs = x[t.perm()]
+    cen = t.centres()
+    lo, e = t.cube()
+    assert fi[0] == 0 and co[0] == n and sk[0] == M
+    leaves = []
+    for k in range(M):
+        kids = []
+        ch = k + 1
+        while ch < sk[k]:
+            kids.append(ch)
+            ch = sk[ch]
+        assert ch == sk[k]
+        s = 2.0 ** (e - lv[k])
+        # geometric containment in the box [c - s/2, c + s/2)
+        pts = xs[fi[k]:fi[k] + co[k]]
+        assert np.all(pts >= cen[k] - s / 2 - 1e-12) and np.all(pts <= cen[k] + s / 2 + 1e-12)
+        if not kids:
+            leaves.append(k)
+            assert co[k] <= leaf_cap or lv[k] == t.b
+        else:
+            assert co[k] > leaf_cap and lv[k] < t.b
+            assert sum(co[c] for c in kids) == co[k]
+            assert fi[kids[0]] == fi[k]
+            octs = []
+            for c in kids:
+                assert lv[c] == lv[k] + 1
+                assert fi[c] + co[c] == (fi[sk[c]] if sk[c] < M and sk[c] < sk[k] else fi[k] + co[k])
+                d = cen[c] - cen[k]
+                o = 4 * (d[0] > 0) + 2 * (d[1] > 0) + (d[2] > 0)
+                octs.append(o)
+                np.testing.assert_allclose(np.abs(d), s / 4, rtol=1e-12)
+            assert octs == sorted(octs) and len(set(octs)) == len(octs)
+    # leaves partition [0, n) in order
+    pos = 0
+    for k in leaves:
+        assert fi[k] == pos
+        pos += co[k]
+    assert pos == n
+    # groups partition [0, n) in order and follow the canonical rule
+    gf, gc, gn = t.groups()
+    assert gf[0] == 0 and gf[-1] + gc[-1] == n and np.all(gf[1:] == gf[:-1] + gc[:-1])
+    assert np.all(gc <= G)
+
+
+@pytest.mark.parametrize("leaf_cap,G,b", [(1, 1, 21), (8, 64, 21), (4, 16, 10), (16, 8, 21)])
+def test_tree_invariants_random(leaf_cap, G, b):
+    cl = _rand_cloud(2000, 11)
+    t = oracle.Tree(cl.x, cl.q, 0.5, 0.01, b=b, leaf_cap=leaf_cap, G=G)
+    _check_tree_invariants(t, cl.x, leaf_cap, G)
+
+
+def test_tree_coincident_particles():
+    x = np.zeros((40, 3)); x[20:] = 1.0
+    q = np.ones(40)
+    t = oracle.Tree(x, q, 0.5, 0.01, b=21, leaf_cap=8, G=16)
+    _check_tree_invariants(t, x, 8, 16)
+    lv, fi, co, sk = t.nodes()
+    assert lv.max() == 21 and co[lv == 21].tolist() == [20, 20]
+    gf, gc, gn = t.groups()
+    assert gc.tolist() == [16, 4, 16, 4]
+
+
+def test_arch_series_rebuild_roundtrip():
+    cl = _rand_cloud(3000, 12)
+    t = oracle.Tree(cl.x, cl.q, 0.5, 0.01, leaf_cap=4)
+    s = t.arch_series()
+    assert s.size == 2 * t.nnodes and (s == -1).sum() == t.nnodes
+    par, nch = oracle.rebuild(s, t.nnodes)
+    lv, fi, co, sk = t.nodes()
+    for k in range(t.nnodes):
+        kids = []
+        ch = k + 1
+        while ch < sk[k]:
+            kids.append(ch)
+            ch = sk[ch]
+        assert nch[k] == len(kids)
+        for c in kids:
+            assert par[c] == k + 1
+    assert par[0] == 0
+    with pytest.raises(ValueError):
+        oracle.rebuild(s[:-1], t.nnodes)
+
+
+# --------------------------------------------------------------------------
+# Moments (pseudo-particle of Sec. 3) and the expansion C-2.7.
+# --------------------------------------------------------------------------
+def test_moments_parallel_axis_and_root_charge():
+    cl = _rand_cloud(1500, 13)
+    t = oracle.Tree(cl.x, cl.q, 0.5, 0.01, leaf_cap=4)
+    m = t.moments()
+    cen = t.centres()
+    lv, fi, co, sk = t.nodes()
+    assert m[0, 0] == 0.0                     # neutral cloud of +-1 charges
+    for k in range(t.nnodes):
+        ch = k + 1
+        acc = np.zeros(10)
+        if ch >= sk[k]:
+            continue
+        while ch < sk[k]:
+            d = cen[ch] - cen[k]
+            Q, p = m[ch, 0], m[ch, 1:4]
+            S = np.array([[m[ch, 4], m[ch, 7], m[ch, 8]], [m[ch, 7], m[ch, 5], m[ch, 9]],
+                          [m[ch, 8], m[ch, 9], m[ch, 6]]])
+            # shift of origin by d: p' = p + Q d ; S' = S + p d^T + d p^T + Q d d^T
+            p2 = p + Q * d
+            S2 = S + np.outer(p, d) + np.outer(d, p) + Q * np.outer(d, d)
+            acc += np.array([Q, *p2, S2[0, 0], S2[1, 1], S2[2, 2], S2[0, 1], S2[0, 2], S2[1, 2]])
+            ch = sk[ch]
+        scale = np.abs(cl.q).sum() * 2.0 ** (2 * (t.cube()[1] - lv[k]))
+        assert np.abs(acc - m[k]).max() < 1e-13 * max(scale, 1.0)
+
+
+def test_expansion_single_charge_at_centre_is_exact():
+    mom = np.array([1.0, 0, 0, 0, 0, 0, 0, 0, 0, 0])
+    r = np.array([0.3, -0.7, 1.1])
+    E, phi = oracle.cell_eval(mom, r, 0.05)
+    f, ph = oracle.direct(np.vstack([r, np.zeros(3)]), [1.0, 1.0], 0.05)
+    np.testing.assert_allclose(E, f[0], rtol=1e-15)
+    assert phi == pytest.approx(ph[0], rel=1e-15)
+
+
+def test_expansion_dipole_pair_closed_form():
+    # +q at a, -q at -a: Q = 0, p = 2 q a, S = 0; at eps = 0 the far field is the
+    # textbook dipole field (3 (p.rhat) rhat - p) / r^3, exact up to O((a/r)^2).
+    a = np.array([0.01, 0.02, -0.015])
+    p = 2 * a
+    mom = np.array([0.0, *p, 0, 0, 0, 0, 0, 0])
+    for r in (np.array([1.0, 0.5, -0.3]), np.array([-2.0, 0.1, 0.4])):
+        E, phi = oracle.cell_eval(mom, r, 0.0)
+        rn = np.linalg.norm(r)
+        rh = r / rn
+        Ed = (3 * p.dot(rh) * rh - p) / rn ** 3
+        np.testing.assert_allclose(E, Ed, rtol=1e-14, atol=1e-18)
+        assert phi == pytest.approx(p.dot(r) / rn ** 3, rel=1e-14)
+        f, ph = oracle.direct(np.vstack([r, a, -a]), [1.0, 1.0, -1.0], 0.0)
+        assert np.linalg.norm(E - f[0]) / np.linalg.norm(f[0]) < 5 * (np.linalg.norm(a) / rn) ** 2
+
+
+def test_expansion_eps0_equals_traceless_quadrupole():
+    rng = np.random.default_rng(14)
+    pts = rng.uniform(-0.1, 0.1, size=(12, 3))
+    qs = rng.choice([-1.0, 1.0], size=12)
+    Q = qs.sum()
+    p = (qs[:, None] * pts).sum(0)
+    S = np.einsum("i,ia,ib->ab", qs, pts, pts)
+    mom = np.array([Q, *p, S[0, 0], S[1, 1], S[2, 2], S[0, 1], S[0, 2], S[1, 2]])
+    # Jackson-form quadrupole tensor Qt_ab = sum q (3 r'_a r'_b - r'^2 delta_ab)
+    Qt = 3 * S - np.trace(S) * np.eye(3)
+    r = np.array([0.9, -0.4, 0.6])
+    rn = np.linalg.norm(r)
+    phi_tb = Q / rn + p.dot(r) / rn ** 3 + 0.5 * r.dot(Qt).dot(r) / rn ** 5
+    E, phi = oracle.cell_eval(mom, r, 0.0)
+    assert phi == pytest.approx(phi_tb, rel=1e-14)
+    # E = -grad phi, checked by central differences of the textbook potential
+    h = 1e-6
+    g = np.zeros(3)
+    for d in range(3):
+        rp, rm = r.copy(), r.copy()
+        rp[d] += h; rm[d] -= h
+        fp = Q / np.linalg.norm(rp) + p.dot(rp) / np.linalg.norm(rp) ** 3 + 0.5 * rp.dot(Qt).dot(rp) / np.linalg.norm(rp) ** 5
+        fm = Q / np.linalg.norm(rm) + p.dot(rm) / np.linalg.norm(rm) ** 3 + 0.5 * rm.dot(Qt).dot(rm) / np.linalg.norm(rm) ** 5
+        g[d] = (fp - fm) / (2 * h)
+    np.testing.assert_allclose(E, -g, rtol=1e-8)
+
+
+def test_expansion_truncation_is_third_order():
+    rng = np.random.default_rng(15)
+    pts = rng.uniform(-0.05, 0.05, size=(20, 3))
+    qs = rng.choice([-1.0, 1.0], size=20)
+    Q = qs.sum(); p = (qs[:, None] * pts).sum(0)
+    S = np.einsum("i,ia,ib->ab", qs, pts, pts)
+    mom = np.array([Q, *p, S[0, 0], S[1, 1], S[2, 2], S[0, 1], S[0, 2], S[1, 2]])
+    errs = []
+    dirn = np.array([0.6, 0.48, 0.64])
+    for dist in (0.4, 0.8, 1.6, 3.2):
+        r = dist * dirn
+        E, _ = oracle.cell_eval(mom, r, 0.002)
+        f, _ = oracle.direct(np.vstack([r, pts]), np.concatenate([[1.0], qs]), 0.002)
+        errs.append(np.linalg.norm(E - f[0]) / np.linalg.norm(f[0]))
+    ratios = [errs[i] / errs[i + 1] for i in range(3)]
+    # the neglected octupole term makes the relative error fall ~ (a/d)^3 -> x8 per doubling
+    for rt in ratios:
+        assert 5.0 < rt < 12.0, ratios
+
+
+def test_expansion_jacobian_is_minus_grad_of_field():
+    rng = np.random.default_rng(16)
+    mom = rng.normal(size=10) * np.array([1, .1, .1, .1, .01, .01, .01, .01, .01, .01])
+    r = np.array([0.5, -0.3, 0.8])
+    J = oracle.cell_jacobian(mom, r, 0.05)
+    h = 1e-6
+    for d in range(3):
+        rp, rm = r.copy(), r.copy()
+        rp[d] += h; rm[d] -= h
+        Ep, _ = oracle.cell_eval(mom, rp, 0.05)
+        Em, _ = oracle.cell_eval(mom, rm, 0.05)
+        np.testing.assert_allclose(J[:, d], (Ep - Em) / (2 * h), rtol=1e-7, atol=1e-9)
+    np.testing.assert_allclose(J, J.T, rtol=1e-13, atol=1e-15)
+
+
+# --------------------------------------------------------------------------
+# Walk and tree forces (C-2.6 .. C-2.8).
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("G,leaf_cap", [(1, 1), (16, 8), (64, 8)])
+def test_tree_theta0_equals_direct(G, leaf_cap):
+    cl = _rand_cloud(1024, 17)
+    fd, phid = oracle.direct(cl.x, cl.q, 0.01)
+    t = oracle.Tree(cl.x, cl.q, 0.0, 0.01, leaf_cap=leaf_cap, G=G)
+    r = t.eval()
+    assert r["m2p"] == 0 and r["p2p"] == cl.n ** 2
+    assert _relrms(r["f"], fd) < 1e-14
+    assert _relrms(r["phi"], phid) < 1e-14
+
+
+def test_tree_error_falls_with_theta():
+    cl = _rand_cloud(4096, 0)
+    fd, _ = oracle.direct(cl.x, cl.q, 0.01)
+    errs = []
+    for th in (0.7, 0.5, 0.3, 0.15):
+        errs.append(_relrms(oracle.tree_forces(cl.x, cl.q, th, 0.01)["f"], fd))
+    assert all(errs[i] > errs[i + 1] for i in range(3)), errs
+    assert errs[2] < 1e-3 and errs[3] < 1e-4
+
+
+def test_walk_lists_cover_every_source_once_and_respect_mac():
+    cl = _rand_cloud(700, 18)
+    theta, G = 0.6, 16
+    t = oracle.Tree(cl.x, cl.q, theta, 0.01, leaf_cap=4, G=G, keep_lists=True)
+    lv, fi, co, sk = t.nodes()
+    cen = t.centres()
+    lo, e = t.cube()
+    xs = cl.x[t.perm()]
+    gf, gc, gn = t.groups()
+    for g in range(t.ngroups):
+        mc, pl = t.lists(g)
+        covered = np.zeros(cl.n, dtype=int)
+        for k in mc:
+            covered[fi[k]:fi[k] + co[k]] += 1
+            s = 2.0 ** (e - lv[k])
+            d = xs[gf[g]:gf[g] + gc[g]] - cen[k]
+            assert np.all(s < theta * np.sqrt((d ** 2).sum(1)) * (1 + 1e-12))
+        for k in pl:
+            assert sk[k] == k + 1          # only leaves are opened into P2P
+            covered[fi[k]:fi[k] + co[k]] += 1
+        assert np.all(covered == 1)
+
+
+def test_walk_brute_force_tiny():
+    # brute force from the definition: a node is in the accepted list of a group
+    # iff every member accepts it and every strict ancestor is rejected by some member
+    cl = _rand_cloud(16, 19)
+    theta = 0.9
+    t = oracle.Tree(cl.x, cl.q, theta, 0.01, b=21, leaf_cap=1, G=4, keep_lists=True)
+    lv, fi, co, sk = t.nodes()
+    cen = t.centres()
+    lo, e = t.cube()
+    xs = cl.x[t.perm()]
+    parent = np.full(t.nnodes, -1)
+    for k in range(t.nnodes):
+        ch = k + 1
+        while ch < sk[k]:
+            parent[ch] = k
+            ch = sk[ch]
+    gf, gc, gn = t.groups()
+    for g in range(t.ngroups):
+        tg = xs[gf[g]:gf[g] + gc[g]]
+
+        def acc(k):
+            s = 2.0 ** (e - lv[k])
+            return all(s * s < theta * theta * float(np.dot(v - cen[k], v - cen[k])) for v in tg)
+
+        want_m, want_p = [], []
+        for k in range(t.nnodes):
+            anc = parent[k]
+            ok = True
+            while anc >= 0:
+                if acc(anc):
+                    ok = False
+                anc = parent[anc]
+            if not ok:
+                continue
+            if acc(k):
+                want_m.append(k)
+            elif sk[k] == k + 1:
+                want_p.append(k)
+        mc, pl = t.lists(g)
+        assert sorted(mc.tolist()) == want_m and sorted(pl.tolist()) == want_p
+
+
+# --------------------------------------------------------------------------
+# Verlet (C-3) and energies.
+# --------------------------------------------------------------------------
+def test_verlet_circular_orbit_closed_form():
+    # ion (+1) and electron-like partner (-1), equal masses 1, softened attraction.
+    # Separation D = 2R, force F = D/(D^2+eps^2)^{3/2}; circular speed v = sqrt(F R).
+    eps, R = 0.05, 0.5
+    D = 2 * R
+    F = D / (D * D + eps * eps) ** 1.5
+    v = np.sqrt(F * R)
+    T = 2 * np.pi * R / v
+    x = np.array([[R, 0, 0], [-R, 0, 0]], float)
+    vel = np.array([[0, v, 0], [0, -v, 0]], float)
+    nsteps = 4000
+    dt = T / nsteps
+    x1, v1, _ = oracle.verlet(x, vel, [1.0, -1.0], [1.0, 1.0], dt, nsteps, eps)
+    assert np.abs(x1 - x).max() < 1e-5       # back to the start after one period
+    assert np.abs(np.linalg.norm(x1[0]) - R) < 1e-8
+
+
+def test_verlet_momentum_reversibility_and_order():
+    cl = _rand_cloud(64, 20)
+    m = cl.m
+    x1, v1, f1 = oracle.verlet(cl.x, cl.v, cl.q, m, 1e-6, 50, 0.01)
+    p0 = (m[:, None] * cl.v).sum(0)
+    p1 = (m[:, None] * v1).sum(0)
+    assert np.abs(p1 - p0).max() < 1e-12 * np.abs(m[:, None] * cl.v).sum()
+    # time reversal: negate v, integrate back
+    x2, v2, _ = oracle.verlet(x1, -v1, cl.q, m, 1e-6, 50, 0.01, f=f1)
+    assert np.abs(x2 - cl.x).max() < 1e-10
+    assert np.abs(-v2 - cl.v).max() < 1e-7 * np.abs(cl.v).max()
+    # energy error is second order in dt
+    def drift(dt, n):
+        _, phi0 = oracle.direct(cl.x, cl.q, 0.05)
+        E0 = oracle.energy(cl.v, cl.q, m, phi0)[2]
+        xa, va, _ = oracle.verlet(cl.x, cl.v, cl.q, m, dt, n, 0.05)
+        _, phia = oracle.direct(xa, cl.q, 0.05)
+        return abs(oracle.energy(va, cl.q, m, phia)[2] - E0)
+    e1, e2 = drift(4e-5, 25), drift(2e-5, 50)
+    assert 3.0 < e1 / e2 < 5.0
+
+
+def test_energy_closed_form():
+    v = np.array([[1.0, 2.0, 2.0], [0.0, 0.0, 3.0]])      # |v|^2 = 9 and 9
+    q = np.array([1.0, -1.0]); m = np.array([2.0, 0.5])
+    out = oracle.energy(v, q, m, np.array([0.4, -0.2]))
+    assert out[0] == pytest.approx(0.5 * 2 * 9 + 0.5 * 0.5 * 9)
+    assert out[3] == pytest.approx(9.0) and out[4] == pytest.approx(2.25)
+    assert out[1] == pytest.approx(0.5 * (0.4 + 0.2))
+    assert out[2] == pytest.approx(out[0] + out[1])
+
+
+# --------------------------------------------------------------------------
+# Adjoint (C-4).
+# --------------------------------------------------------------------------
+def test_direct_vjp_matches_finite_differences_and_is_symmetric():
+    cl = _rand_cloud(60, 21)
+    eps = 0.05
+    rng = np.random.default_rng(22)
+    u = rng.normal(size=(cl.n, 3)); w = rng.normal(size=(cl.n, 3))
+    xb = oracle.direct_vjp(cl.x, cl.q, eps, u)
+    h = 1e-5
+    fp, _ = oracle.direct(cl.x + h * w, cl.q, eps)
+    fm, _ = oracle.direct(cl.x - h * w, cl.q, eps)
+    jw = (fp - fm) / (2 * h)
+    assert abs((u * jw).sum() - (xb * w).sum()) < 1e-6 * abs((xb * w).sum()) + 1e-9
+    # dF/dx is minus the Hessian of U: symmetric
+    xw = oracle.direct_vjp(cl.x, cl.q, eps, w)
+    assert abs((xb * w).sum() - (xw * u).sum()) < 1e-10 * abs((xb * w).sum())
+
+
+def test_tree_vjp_theta0_equals_direct_vjp():
+    cl = _rand_cloud(300, 23)
+    u = np.random.default_rng(24).normal(size=(cl.n, 3))
+    t = oracle.Tree(cl.x, cl.q, 0.0, 0.02, leaf_cap=4, G=16, keep_lists=True)
+    np.testing.assert_allclose(t.vjp(u), oracle.direct_vjp(cl.x, cl.q, 0.02, u), rtol=1e-10,
+                               atol=1e-10 * np.abs(oracle.direct_vjp(cl.x, cl.q, 0.02, u)).max())
+
+
+def test_tree_vjp_matches_frozen_list_finite_differences():
+    cl = _rand_cloud(800, 25)
+    eps = 0.02
+    t = oracle.Tree(cl.x, cl.q, 0.6, eps, leaf_cap=4, G=16, keep_lists=True)
+    rng = np.random.default_rng(26)
+    for _ in range(3):
+        u = rng.normal(size=(cl.n, 3)); w = rng.normal(size=(cl.n, 3))
+        xb = t.vjp(u)
+        h = 1e-6    # central differences converge as h^2 here; 1e-6 leaves ~1e-8
+        fp = t.eval(cl.x + h * w, want_phi=False)["f"]
+        fm = t.eval(cl.x - h * w, want_phi=False)["f"]
+        fd = (u * (fp - fm) / (2 * h)).sum()
+        assert abs(fd - (xb * w).sum()) < 1e-6 * abs(fd)
