@@ -1,0 +1,186 @@
+"""Benchmark: tree-force particles/s and interactions/s on one MI355X.
+
+A step is one velocity-Verlet (kick-drift-kick) step of the whole hot path on
+the N = 524,288 cloud (theta = 0.5, eps = 0.005, dt = 5e-5): enclosing cube,
+Morton keys, radix sort, octree build, moments, groups, group walk (M2P + P2P),
+scatter and the two kicks.  Inputs are resident in HBM before the timed region.
+
+Prints ONE JSON line.  value = particles/s = N * steps / elapsed.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# algorithmic FLOPs per interaction, counted from the FP32 evaluation code
+# (add, sub, mul = 1; fma = 2; rsqrt = 1); forces only (no potential)
+P2P_FLOPS = 19
+M2P_FLOPS = 68
+PEAK_FP32_TFLOPS = 157.3      # MI355X vector FP32 (packed) -- published peak
+PEAK_FP64_TFLOPS = 78.6
+WALK_SOURCES = ["paper_0709_3331_amd/csrc/walk.hip", "paper_0709_3331_amd/csrc/internal.h"]
+
+
+def walk_source_hash():
+    h = hashlib.sha256()
+    for p in WALK_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(precision):
+    """HBM bytes per walk launch from the committed rocprofv3 counter summary,
+    or None when the walk kernel changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"walk_{precision}_n524288_traffic.json")
+    try:
+        with open(path) as fh:
+            d = json.load(fh)
+    except OSError:
+        return None
+    if d.get("walk_source_hash") != walk_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", choices=["split", "fp64"], default="split")
+    ap.add_argument("--theta", type=float, default=0.5)
+    ap.add_argument("--group-size", type=int, default=64)
+    ap.add_argument("--list-len", type=int, default=128)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true", help="skip the FP64 comparator run")
+    ap.add_argument("--profile", action="store_true", help="short run for rocprofv3 (no extras)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; the method is not "
+                          "sharded across GPUs in this build", "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_0709_3331_amd import _lib as L
+    from paper_0709_3331_amd import inputs
+    from paper_0709_3331_amd.tree import TreeSolver
+
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    dev = torch.device("cuda:0")
+    cl, prm = inputs.metric(0)
+    n = cl.n
+    theta, eps, dt = args.theta, prm["eps"], prm["dt"]
+    prec = L.UCP_SPLIT if args.precision == "split" else L.UCP_FP64
+    x = torch.from_numpy(cl.x).to(dev)
+    v = torch.from_numpy(cl.v).to(dev)
+    q = torch.from_numpy(cl.q).to(dev)
+    m = torch.from_numpy(cl.m).to(dev)
+    ts = TreeSolver(n, theta=theta, eps=eps, precision=prec, group_size=args.group_size,
+                    list_len=args.list_len)
+    print(f"bench: N={n} theta={theta} precision={args.precision}", file=sys.stderr, flush=True)
+
+    # initial forces; interaction counts of one evaluation
+    f = ts.tree_forces(x, q)
+    st0 = ts.stats()
+    for _ in range(args.warmup):
+        ts.step(x, v, f, q, m, dt, 1)
+    torch.cuda.synchronize()
+    print("bench: warmup done", file=sys.stderr, flush=True)
+
+    # timed region: exactly K steps, walk kernels bracketed by HIP events on
+    # the stream they are launched on
+    ts.timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ts.step(x, v, f, q, m, dt, args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    walk_ms, walk_launches = ts.timing_read()
+    ts.timing(False)
+    st = ts.stats()
+    elapsed = t1 - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+    walk_avg_ms = walk_ms / max(walk_launches, 1)
+    inter = st["p2p"] + st["m2p"]
+    flops = P2P_FLOPS * st["p2p"] + M2P_FLOPS * st["m2p"]
+    achieved = flops / (walk_avg_ms * 1e-3) / 1e12
+    peak = PEAK_FP32_TFLOPS if prec == L.UCP_SPLIT else PEAK_FP64_TFLOPS
+    result = {
+        "metric": "tree-force particles/s & interactions/s at N=512K theta=0.5; rel force err vs FP64",
+        "value": n * args.steps / elapsed,
+        "unit": "particles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32-interactions/f64-accumulate" if prec == L.UCP_SPLIT else "f64",
+        "data": "synthetic",
+        "config": {"workload": "single two-component Gaussian cloud N=524288 (sigma=1, 5% halo "
+                               "shell 2-3 sigma), theta=%g, eps=0.005, G=%d, leaf_cap=8, "
+                               "63-bit keys, one KDK Verlet step dt=5e-5" % (theta, args.group_size),
+                   "n": n, "theta": theta, "precision": args.precision},
+        "interactions_per_s": inter / (walk_avg_ms * 1e-3),
+        "interactions_per_particle": inter / n,
+        "walk_ms": walk_avg_ms,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak,
+                     "traffic": traffic_from_profile(args.precision)},
+    }
+    if not args.profile and not args.no_compare:
+        # accuracy against the plain FP64 GPU tree at identical parameters and
+        # against the FP64 oracle direct sum on sampled targets
+        f_split = ts.tree_forces(x, q)
+        ts64 = TreeSolver(n, theta=theta, eps=eps, precision=L.UCP_FP64,
+                          group_size=args.group_size, list_len=args.list_len)
+        f64 = ts64.tree_forces(x, q)
+        ts64.timing(True)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            ts64.tree_forces(x, q)
+        torch.cuda.synchronize()
+        w64, c64 = ts64.timing_read()
+        a, b = f_split.cpu().numpy(), f64.cpu().numpy()
+        result["rel_force_err_vs_fp64_gpu"] = float(np.linalg.norm(a - b) / np.linalg.norm(b))
+        result["fp64_walk_ms"] = w64 / max(c64, 1)
+        result["split_speedup_walk"] = (w64 / max(c64, 1)) / walk_avg_ms
+        ts64.close()
+    if not args.profile and not args.no_cpu_baseline:
+        import oracle
+        xs = x.cpu().numpy()
+        qs = cl.q
+        fs = ts.tree_forces(x, q).cpu().numpy()
+        rng = np.random.default_rng(0)
+        tg = np.sort(rng.choice(n, 2048, replace=False))
+        fd, _ = oracle.direct_targets(xs, qs, eps, tg)
+        result["rel_force_err_vs_direct_sampled"] = float(
+            np.linalg.norm(fs[tg] - fd) / np.linalg.norm(fd))
+        c0 = time.perf_counter()
+        ot = oracle.Tree(xs, qs, theta, eps, G=args.group_size)
+        ro = ot.eval(want_phi=False)
+        c1 = time.perf_counter()
+        result["rel_force_err_vs_oracle_tree"] = float(
+            np.linalg.norm(fs - ro["f"]) / np.linalg.norm(ro["f"]))
+        result["cpu_baseline"] = {
+            "value": n / (c1 - c0), "unit": "particles/s", "cores": oracle.max_threads(),
+            "kind": "oracle",
+            "sample": "one full FP64 oracle tree-force evaluation (build + walk, OpenMP over "
+                      "groups) of the same N=524288 cloud at the same parameters; %.2f s" % (c1 - c0)}
+    ts.close()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

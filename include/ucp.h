@@ -1,0 +1,197 @@
+/*
+ * ucp.h -- C-ABI of the MI355X (gfx950) two-component plasma TREE library.
+ *
+ * The library evaluates the Barnes-Hut electrostatic forces of a cloud of
+ * ions and electrons (Sec. 3 of Jeon, Kress, Collins, Gronbech-Jensen,
+ * "Parallel TREE code for two-component ultracold plasma analysis") and
+ * advances it by velocity Verlet (Sec. 2).  Everything runs on one GPU.
+ *
+ * Conventions for every entry point:
+ *  - All particle arrays are DEVICE pointers owned by the caller, float64,
+ *    C-contiguous.  Positions, velocities, forces and cotangents are [n][3]
+ *    row-major; charges, masses and potentials are [n].  Results come back in
+ *    the caller's particle order.
+ *  - Reduced units: e^2/(4 pi eps0) = 1, k_B = 1.  The pair law is Eq. (1)-(2)
+ *    with Plummer softening eps on every pair:
+ *      F_i = q_i sum_j q_j (x_i - x_j) / (|x_i - x_j|^2 + eps^2)^{3/2}.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Work is enqueued on it; no entry point synchronises the stream unless
+ *    it says so.  The context owns every scratch buffer, sized at create
+ *    time; no entry point other than ucp_create allocates device memory.
+ *  - Every entry point returns a ucp_status.  No C++ exception crosses the
+ *    ABI.  ucp_last_error() returns a human-readable message for the last
+ *    failure on that context.  Device-detected problems (node capacity
+ *    exceeded, non-finite coordinates, inconsistent offsets) are raised as
+ *    flags on the device and reported by the next synchronising call
+ *    (ucp_get_stats); kernels launched after a flag is raised do no work.
+ *  - A context is not thread-safe; calls that overlap on one context race.
+ */
+#ifndef UCP_H
+#define UCP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    UCP_OK = 0,
+    UCP_EINVAL = -1,       /* invalid argument or parameter                    */
+    UCP_ENOMEM = -2,       /* device allocation failed in ucp_create           */
+    UCP_EHIP = -3,         /* a HIP runtime call failed                        */
+    UCP_ECAPACITY = -4,    /* a device capacity (nodes, particles) was exceeded */
+    UCP_ENOTBUILT = -5,    /* forces/VJP requested before a tree was built     */
+    UCP_ENONFINITE = -6    /* non-finite coordinate in the input               */
+} ucp_status;
+
+typedef enum {
+    UCP_FP64 = 0,          /* all interaction arithmetic in FP64                       */
+    UCP_SPLIT = 1          /* FP32 interaction arithmetic; FP64 cell moments, FP64
+                              per-particle accumulators and FP64 energy sums          */
+} ucp_precision;
+
+/* Method parameters.  The opening test is Eq. (5), s/theta + delta < d, with
+ * the pseudo-particle expanded about the box centre (delta = 0), s the box
+ * side and d the distance from the target to the box centre; it is evaluated
+ * in FP64 as s^2 < theta^2 d^2.  A walk group (below) opens a box iff any of
+ * its members fails the test.                                                */
+typedef struct {
+    double theta;          /* opening parameter, 0 <= theta < 2/sqrt(3); 0 => direct sum */
+    double eps;            /* Plummer softening, > 0                                      */
+    int32_t key_bits;      /* 30 or 63 (key depth b = 10 or 21 levels)                   */
+    int32_t leaf_cap;      /* a box holding more particles is split (Sec. 3 uses 1); 1..64 */
+    int32_t group_size;    /* G: a walk group is a node with <= G particles whose parent
+                              has > G (a leaf with > G is cut into chunks of G); 1..64   */
+    int32_t list_len;      /* capacity of each staged interaction list, 16..1024; changes
+                              only the FP64 summation order                              */
+    int32_t precision;     /* ucp_precision                                              */
+    int32_t walk_waves;    /* resident waves per CU for the persistent walk, 0 = auto    */
+} ucp_params;
+
+typedef struct ucp_ctx ucp_ctx;   /* opaque */
+
+typedef struct {
+    int64_t n;             /* particles of the last build                           */
+    int64_t clouds;        /* independent clouds of the last build                  */
+    int64_t nodes;         /* tree nodes (all clouds)                               */
+    int64_t groups;        /* walk groups                                           */
+    int64_t max_level;     /* deepest node level                                    */
+    int64_t p2p;           /* particle-particle interactions of the last force call,
+                              counted per (target, source) pair, self pair included   */
+    int64_t m2p;           /* particle-cell interactions of the last force call     */
+    int64_t flags;         /* raw device flag word (see UCP_FLAG_*)                  */
+} ucp_stats;
+
+#define UCP_FLAG_NODE_OVERFLOW   1
+#define UCP_FLAG_NONFINITE       2
+#define UCP_FLAG_BAD_OFFSETS     4
+#define UCP_FLAG_BAD_CUBE        8
+#define UCP_FLAG_INTERNAL       16   /* inconsistent tree records (a library defect) */
+
+/* Default parameters: theta 0.5, eps 0.005, 63-bit keys, leaf_cap 8, G 64,
+ * list_len 128, UCP_SPLIT, walk_waves 0.                                     */
+void ucp_default_params(ucp_params *p);
+
+/* Create a context on the current HIP device able to hold n_max particles in
+ * up to clouds_max clouds.  Allocates all scratch (about 1 KB per particle).
+ * Errors: UCP_EINVAL (n_max < 1, clouds_max < 1, bad params), UCP_ENOMEM,
+ * UCP_EHIP.  *out is NULL on failure.                                       */
+ucp_status ucp_create(ucp_ctx **out, int64_t n_max, int32_t clouds_max, const ucp_params *p);
+void ucp_destroy(ucp_ctx *c);
+
+/* Replace the parameters (validated as in ucp_create).  A tree built before
+ * with other key_bits/leaf_cap/group_size must be rebuilt.                  */
+ucp_status ucp_set_params(ucp_ctx *c, const ucp_params *p);
+ucp_status ucp_get_params(const ucp_ctx *c, ucp_params *p);
+
+/* Build the tree of one cloud (Sec. 3): enclosing cube, Morton keys, stable
+ * radix sort, linear octree in preorder, cell moments (net charge, dipole and
+ * quadrupole about each box centre, FP64) and walk groups.  x: [n][3], q: [n].
+ * The library keeps sorted copies, so x and q may change after the call
+ * returns (stream order).  n = 0 is allowed (empty tree).
+ * Errors: UCP_EINVAL (n < 0 or n > n_max, NULL pointers with n > 0).        */
+ucp_status ucp_build_tree(ucp_ctx *c, const double *x, const double *q, int64_t n, void *stream);
+
+/* Build the trees of `clouds` independent clouds stored back to back: cloud k
+ * holds particles [offsets[k], offsets[k+1]).  offsets is a DEVICE int64
+ * array of clouds+1 entries with offsets[0] = 0, nondecreasing, and
+ * offsets[clouds] = n (checked on the device: UCP_FLAG_BAD_OFFSETS).  Clouds
+ * do not interact.  Errors as ucp_build_tree, plus clouds > clouds_max.    */
+ucp_status ucp_build_tree_batched(ucp_ctx *c, const double *x, const double *q,
+                                  const int64_t *offsets, int32_t clouds, int64_t n, void *stream);
+
+/* Tree forces of the last build: the group walk of Sec. 3 with the opening
+ * test of Eq. (5); accepted boxes contribute their expansion, opened leaves
+ * their particles (Eq. (1)-(2), softened).  f: [n][3] out (caller order).
+ * phi: [n] out or NULL; the potential excludes the self pair.
+ * Errors: UCP_ENOTBUILT.                                                    */
+ucp_status ucp_compute_forces(ucp_ctx *c, double *f, double *phi, void *stream);
+
+/* nsteps velocity-Verlet (kick-drift-kick) steps, Sec. 2:
+ *   v += dt/2 F/m;  x += dt v;  rebuild tree, F = F(x);  v += dt/2 F/m.
+ * On entry f must hold F(x) (e.g. from ucp_build_tree + ucp_compute_forces);
+ * on exit x, v, f hold the state after nsteps.  The step is captured once in
+ * a hipGraph and replayed (re-captured when pointers or sizes change).
+ * Errors: UCP_EINVAL.                                                       */
+ucp_status ucp_step(ucp_ctx *c, double *x, double *v, double *f, const double *q,
+                    const double *m, int64_t n, double dt, int32_t nsteps, void *stream);
+
+/* As ucp_step for the clouds of ucp_build_tree_batched (offsets on device). */
+ucp_status ucp_step_batched(ucp_ctx *c, double *x, double *v, double *f, const double *q,
+                            const double *m, const int64_t *offsets, int32_t clouds, int64_t n,
+                            double dt, int32_t nsteps, void *stream);
+
+/* Energies of one cloud at (x, v): builds the tree at x, evaluates the tree
+ * potential, and writes to the DEVICE array out[5]:
+ *   K = sum m|v|^2/2, U = sum q phi/2, E = K + U, K of ions (q > 0),
+ *   K of electrons (q < 0)     (Sec. 5: <KE> = 3 k_B T/2 per species).
+ * All sums are FP64 with a fixed reduction order (bitwise reproducible).
+ * The tree of the last build is replaced.                                   */
+ucp_status ucp_energy(ucp_ctx *c, const double *x, const double *v, const double *q,
+                      const double *m, int64_t n, double *out, void *stream);
+
+/* Vector-Jacobian product of the tree forces of the last build with respect
+ * to positions, xbar = (dF/dx)^T u, with the cube, topology, box centres and
+ * interaction lists of that build held fixed.  u, xbar: [n][3] (caller
+ * order).  Needs the positions of the last build to be unchanged.
+ * Errors: UCP_ENOTBUILT.                                                    */
+ucp_status ucp_force_vjp(ucp_ctx *c, const double *u, double *xbar, void *stream);
+
+/* Synchronise `stream`, read the device counters and flags.  Returns
+ * UCP_ECAPACITY / UCP_ENONFINITE / UCP_EINVAL when a flag is raised (the
+ * stats are still filled in), else UCP_OK.                                 */
+ucp_status ucp_get_stats(ucp_ctx *c, ucp_stats *out, void *stream);
+
+/* Introspection of the last build, for tests and tools: copies one internal
+ * array to the HOST buffer dst of `bytes` bytes (synchronises `stream`).
+ * which:  0 sorted keys (uint64[n])          1 permutation (uint32[n]: sorted
+ *         position -> caller index)          2 node info (int32[nodes][4]:
+ *         first, count, skip, level | 256*leaf)  3 node geometry
+ *         (double[nodes][4]: centre xyz, side^2)  4 FP64 moments
+ *         (double[nodes][10]: Q, px, py, pz, Sxx, Syy, Szz, Sxy, Sxz, Syz)
+ *         5 groups (int32[groups][4]: first, count, node, root)
+ *         6 per-group interaction counts of the last force call
+ *         (int32[groups][2]: accepted boxes, P2P source particles)
+ *         7 per-cloud cube (double[clouds][4]: lo xyz, e)
+ * Errors: UCP_EINVAL (unknown `which`, buffer too small).                  */
+ucp_status ucp_debug_copy(ucp_ctx *c, int32_t which, void *dst, int64_t bytes, void *stream);
+
+/* Kernel timing with HIP events recorded on the launch stream around every
+ * walk kernel (while enabled, ucp_step launches without a graph).
+ * ucp_timing_read synchronises and returns the summed walk time in ms and the
+ * number of walk launches since the last read, then resets.               */
+ucp_status ucp_set_timing(ucp_ctx *c, int32_t on);
+ucp_status ucp_timing_read(ucp_ctx *c, double *walk_ms, int64_t *walk_launches);
+
+/* Message for the last error on this context ("" if none); c may be NULL. */
+const char *ucp_last_error(const ucp_ctx *c);
+
+/* Library version (major*10000 + minor*100 + patch).                       */
+int32_t ucp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* UCP_H */

@@ -1,0 +1,466 @@
+// api.hip -- the extern "C" entry points declared in include/ucp.h.
+#include <string.h>
+
+#include <cstdio>
+#include <string>
+
+#include "internal.h"
+
+struct ucp_ctx : public ucp::Ctx {};
+
+using ucp::Ctx;
+
+namespace {
+
+const char *kNoCtx = "ucp: NULL context";
+thread_local std::string g_err;   // errors without a context
+
+ucp_status fail(Ctx *c, ucp_status st, const std::string &msg)
+{
+    if (c) c->err = msg;
+    else g_err = msg;
+    return st;
+}
+
+#define HIP_TRY(c, call)                                                                  \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail((c), UCP_EHIP, std::string("ucp: ") + #call + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+bool validate(const ucp_params *p, std::string &why)
+{
+    if (!p) { why = "params is NULL"; return false; }
+    if (!(p->theta >= 0.0) || !(p->theta < 1.1547005383792515)) {
+        why = "theta must satisfy 0 <= theta < 2/sqrt(3)";
+        return false;
+    }
+    if (!(p->eps > 0.0) || !(p->eps < 1e30)) { why = "eps must be > 0 and finite"; return false; }
+    if (p->key_bits != 30 && p->key_bits != 63) { why = "key_bits must be 30 or 63"; return false; }
+    if (p->leaf_cap < 1 || p->leaf_cap > ucp::kMaxLeafCap) { why = "leaf_cap must be in 1..64"; return false; }
+    if (p->group_size < 1 || p->group_size > ucp::kMaxGroup) { why = "group_size must be in 1..64"; return false; }
+    if (p->list_len < 16 || p->list_len > 1024) { why = "list_len must be in 16..1024"; return false; }
+    if (p->precision != UCP_FP64 && p->precision != UCP_SPLIT) { why = "precision must be UCP_FP64 or UCP_SPLIT"; return false; }
+    if (p->walk_waves < 0 || p->walk_waves > 64) { why = "walk_waves must be in 0..64"; return false; }
+    return true;
+}
+
+template <typename T>
+hipError_t dalloc(T **p, size_t count)
+{
+    return hipMalloc((void **)p, count * sizeof(T) + 256);
+}
+
+void free_all(Ctx *c)
+{
+    void *ptrs[] = {c->d_off,  c->d_mm,     c->d_cube,  c->d_key[0], c->d_key[1], c->d_val[0],
+                    c->d_val[1], c->d_hist, c->d_histscan, c->d_xq, c->d_xl,  c->d_L,
+                    c->d_leaf, c->d_cnt,    c->d_noff,  c->d_goff,   c->d_gnode,  c->d_scanblk,
+                    c->d_ngeo, c->d_ninfo,  c->d_npar,  c->d_narr,   c->d_mom64,  c->d_mom32,
+                    c->d_groups, c->d_gstat, c->d_acc,  c->d_ctr,    c->d_flags,  c->d_epart};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->gexec = nullptr;
+    c->graph = nullptr;
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+    c->ev.clear();
+}
+
+void drop_graph(Ctx *c)
+{
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->gexec = nullptr;
+    c->graph = nullptr;
+    c->gkey.clear();
+}
+
+bool ptr_ok(const void *p, int64_t n) { return n == 0 || p != nullptr; }
+
+// one Verlet step: kick-drift, rebuild, forces, kick
+void enqueue_step(Ctx *c, double *x, double *v, double *f, const double *q, const double *m,
+                  const int64_t *offsets, int clouds, int64_t n, double dt, hipStream_t s)
+{
+    ucp::launch_kick_drift(x, v, f, m, n, dt, s);
+    ucp::launch_build(c, x, q, offsets, clouds, n, s);
+    c->built = 1;
+    c->n = n;
+    c->clouds = clouds;
+    c->p_built = c->p;
+    ucp::launch_forces(c, f, nullptr, s);
+    ucp::launch_kick(v, f, m, n, dt, s);
+}
+
+ucp_status run_steps(Ctx *c, double *x, double *v, double *f, const double *q, const double *m,
+                     const int64_t *offsets, int clouds, int64_t n, double dt, int nsteps,
+                     hipStream_t s)
+{
+    if (nsteps <= 0 || n == 0) return UCP_OK;
+    if (c->timing || nsteps < 2) {
+        for (int t = 0; t < nsteps; ++t) enqueue_step(c, x, v, f, q, m, offsets, clouds, n, dt, s);
+        HIP_TRY(c, hipGetLastError());
+        return UCP_OK;
+    }
+    uint64_t dtb;
+    memcpy(&dtb, &dt, sizeof dtb);
+    uint64_t pb[6];
+    memcpy(pb, &c->p, sizeof pb < sizeof c->p ? sizeof pb : sizeof c->p);
+    std::vector<uintptr_t> key = {(uintptr_t)x, (uintptr_t)v, (uintptr_t)f, (uintptr_t)q,
+                                  (uintptr_t)m, (uintptr_t)offsets, (uintptr_t)clouds,
+                                  (uintptr_t)n, (uintptr_t)dtb};
+    for (uint64_t w : pb) key.push_back((uintptr_t)w);
+    if (!c->gexec || key != c->gkey) {
+        drop_graph(c);
+        HIP_TRY(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
+        enqueue_step(c, x, v, f, q, m, offsets, clouds, n, dt, c->cap_stream);
+        hipGraph_t g = nullptr;
+        hipError_t e1 = hipGetLastError();
+        hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
+        if (e1 != hipSuccess || e2 != hipSuccess || !g) {
+            if (g) (void)hipGraphDestroy(g);
+            return fail(c, UCP_EHIP, std::string("ucp: step capture failed: ") +
+                                         hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+        }
+        c->graph = g;
+        HIP_TRY(c, hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+        c->gkey = key;
+    }
+    for (int t = 0; t < nsteps; ++t) HIP_TRY(c, hipGraphLaunch(c->gexec, s));
+    c->built = 1;
+    c->n = n;
+    c->clouds = clouds;
+    c->p_built = c->p;
+    return UCP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t ucp_version(void) { return 100; }
+
+void ucp_default_params(ucp_params *p)
+{
+    if (!p) return;
+    p->theta = 0.5;
+    p->eps = 0.005;
+    p->key_bits = 63;
+    p->leaf_cap = 8;
+    p->group_size = 64;
+    p->list_len = 128;
+    p->precision = UCP_SPLIT;
+    p->walk_waves = 0;
+}
+
+const char *ucp_last_error(const ucp_ctx *c)
+{
+    if (!c) return g_err.c_str();
+    return c->err.c_str();
+}
+
+ucp_status ucp_create(ucp_ctx **out, int64_t n_max, int32_t clouds_max, const ucp_params *p)
+{
+    if (!out) return fail(nullptr, UCP_EINVAL, "ucp_create: out is NULL");
+    *out = nullptr;
+    std::string why;
+    if (n_max < 1 || n_max > (int64_t(1) << 28))
+        return fail(nullptr, UCP_EINVAL, "ucp_create: n_max must be in 1..2^28");
+    if (clouds_max < 1 || clouds_max > 65536)
+        return fail(nullptr, UCP_EINVAL, "ucp_create: clouds_max must be in 1..65536");
+    if (!validate(p, why)) return fail(nullptr, UCP_EINVAL, "ucp_create: " + why);
+    ucp_ctx *c = new ucp_ctx();
+    c->p = *p;
+    c->n_max = n_max;
+    c->clouds_max = clouds_max;
+    c->node_cap = 4 * n_max + 64 * (int64_t)clouds_max + 1024;
+    if (c->node_cap > 0x7fffffffLL) c->node_cap = 0x7fffffffLL;
+    const int64_t ntiles = (n_max + ucp::kSortTile - 1) / ucp::kSortTile;
+    c->hist_cap = 256 * ntiles;
+    const int64_t scan_items = (int64_t)ucp::kScanBlock * ucp::kScanItems;
+    const int64_t nblk = ((n_max + 1 > c->hist_cap ? n_max + 1 : c->hist_cap) + scan_items - 1) / scan_items + 2;
+    hipError_t e = hipGetDevice(&c->device);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, c->device);
+    const size_t N = (size_t)n_max, NC = (size_t)c->node_cap;
+#define ALLOC(ptr, cnt) if (e == hipSuccess) e = dalloc(&(ptr), (size_t)(cnt))
+    ALLOC(c->d_off, clouds_max + 1);
+    ALLOC(c->d_mm, 6 * (size_t)clouds_max);
+    ALLOC(c->d_cube, 2 * (size_t)clouds_max);
+    ALLOC(c->d_key[0], N);
+    ALLOC(c->d_key[1], N);
+    ALLOC(c->d_val[0], N);
+    ALLOC(c->d_val[1], N);
+    ALLOC(c->d_hist, c->hist_cap);
+    ALLOC(c->d_histscan, c->hist_cap);
+    ALLOC(c->d_xq, N);
+    ALLOC(c->d_xl, N);
+    ALLOC(c->d_L, N + 1);
+    ALLOC(c->d_leaf, N + 1);
+    ALLOC(c->d_cnt, N + 1);
+    ALLOC(c->d_noff, N + 1);
+    ALLOC(c->d_goff, N + 1);
+    ALLOC(c->d_gnode, N + 1);
+    ALLOC(c->d_scanblk, nblk);
+    ALLOC(c->d_ngeo, NC);
+    ALLOC(c->d_ninfo, NC);
+    ALLOC(c->d_npar, NC);
+    ALLOC(c->d_narr, NC);
+    ALLOC(c->d_mom64, 10 * NC);
+    ALLOC(c->d_mom32, 3 * NC);
+    ALLOC(c->d_groups, N);
+    ALLOC(c->d_gstat, N);
+    ALLOC(c->d_acc, N + 64);   // 64 spare slots for the walk's inactive lanes
+    ALLOC(c->d_ctr, ucp::CTR_NCTR);
+    ALLOC(c->d_flags, 4);
+    ALLOC(c->d_epart, 4 * 256);
+#undef ALLOC
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipMemset(c->d_flags, 0, 4 * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMemset(c->d_ctr, 0, ucp::CTR_NCTR * sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        ucp_status st = (e == hipErrorOutOfMemory) ? UCP_ENOMEM : UCP_EHIP;
+        std::string msg = std::string("ucp_create: ") + hipGetErrorString(e);
+        free_all(c);
+        delete c;
+        return fail(nullptr, st, msg);
+    }
+    *out = c;
+    return UCP_OK;
+}
+
+void ucp_destroy(ucp_ctx *c)
+{
+    if (!c) return;
+    (void)hipDeviceSynchronize();
+    free_all(c);
+    delete c;
+}
+
+ucp_status ucp_set_params(ucp_ctx *c, const ucp_params *p)
+{
+    if (!c) return fail(nullptr, UCP_EINVAL, kNoCtx);
+    std::string why;
+    if (!validate(p, why)) return fail(c, UCP_EINVAL, "ucp_set_params: " + why);
+    const bool topo = p->key_bits != c->p.key_bits || p->leaf_cap != c->p.leaf_cap ||
+                      p->group_size != c->p.group_size;
+    c->p = *p;
+    if (topo) c->built = 0;
+    else if (c->built) {
+        // theta, eps, list length, precision act at force time
+        c->p_built.theta = p->theta;
+        c->p_built.eps = p->eps;
+        c->p_built.list_len = p->list_len;
+        c->p_built.precision = p->precision;
+        c->p_built.walk_waves = p->walk_waves;
+    }
+    drop_graph(c);
+    return UCP_OK;
+}
+
+ucp_status ucp_get_params(const ucp_ctx *c, ucp_params *p)
+{
+    if (!c || !p) return fail(nullptr, UCP_EINVAL, "ucp_get_params: NULL argument");
+    *p = c->p;
+    return UCP_OK;
+}
+
+static ucp_status build_common(ucp_ctx *c, const double *x, const double *q, const int64_t *offsets,
+                               int32_t clouds, int64_t n, void *stream, const char *who)
+{
+    if (!c) return fail(nullptr, UCP_EINVAL, kNoCtx);
+    if (n < 0 || n > c->n_max)
+        return fail(c, UCP_EINVAL, std::string(who) + ": n must be in 0..n_max");
+    if (clouds < 1 || clouds > c->clouds_max)
+        return fail(c, UCP_EINVAL, std::string(who) + ": clouds must be in 1..clouds_max");
+    if (!ptr_ok(x, n) || !ptr_ok(q, n))
+        return fail(c, UCP_EINVAL, std::string(who) + ": NULL particle array");
+    hipStream_t s = (hipStream_t)stream;
+    c->built = 1;
+    c->n = n;
+    c->clouds = clouds;
+    c->p_built = c->p;
+    if (n == 0) return UCP_OK;
+    ucp::launch_build(c, x, q, offsets, clouds, n, s);
+    HIP_TRY(c, hipGetLastError());
+    return UCP_OK;
+}
+
+ucp_status ucp_build_tree(ucp_ctx *c, const double *x, const double *q, int64_t n, void *stream)
+{
+    return build_common(c, x, q, nullptr, 1, n, stream, "ucp_build_tree");
+}
+
+ucp_status ucp_build_tree_batched(ucp_ctx *c, const double *x, const double *q,
+                                  const int64_t *offsets, int32_t clouds, int64_t n, void *stream)
+{
+    if (!offsets) return fail(c, UCP_EINVAL, "ucp_build_tree_batched: offsets is NULL");
+    return build_common(c, x, q, offsets, clouds, n, stream, "ucp_build_tree_batched");
+}
+
+ucp_status ucp_compute_forces(ucp_ctx *c, double *f, double *phi, void *stream)
+{
+    if (!c) return fail(nullptr, UCP_EINVAL, kNoCtx);
+    if (!c->built) return fail(c, UCP_ENOTBUILT, "ucp_compute_forces: no tree has been built");
+    if (c->n == 0) return UCP_OK;
+    if (!f) return fail(c, UCP_EINVAL, "ucp_compute_forces: f is NULL");
+    ucp::launch_forces(c, f, phi, (hipStream_t)stream);
+    HIP_TRY(c, hipGetLastError());
+    return UCP_OK;
+}
+
+static ucp_status step_common(ucp_ctx *c, double *x, double *v, double *f, const double *q,
+                              const double *m, const int64_t *offsets, int32_t clouds, int64_t n,
+                              double dt, int32_t nsteps, void *stream, const char *who)
+{
+    if (!c) return fail(nullptr, UCP_EINVAL, kNoCtx);
+    if (n < 0 || n > c->n_max) return fail(c, UCP_EINVAL, std::string(who) + ": n must be in 0..n_max");
+    if (clouds < 1 || clouds > c->clouds_max)
+        return fail(c, UCP_EINVAL, std::string(who) + ": clouds must be in 1..clouds_max");
+    if (nsteps < 0) return fail(c, UCP_EINVAL, std::string(who) + ": nsteps < 0");
+    if (!(dt == dt) || dt > 1e300 || dt < -1e300) return fail(c, UCP_EINVAL, std::string(who) + ": dt not finite");
+    if (!ptr_ok(x, n) || !ptr_ok(v, n) || !ptr_ok(f, n) || !ptr_ok(q, n) || !ptr_ok(m, n))
+        return fail(c, UCP_EINVAL, std::string(who) + ": NULL particle array");
+    return run_steps(c, x, v, f, q, m, offsets, clouds, n, dt, nsteps, (hipStream_t)stream);
+}
+
+ucp_status ucp_step(ucp_ctx *c, double *x, double *v, double *f, const double *q, const double *m,
+                    int64_t n, double dt, int32_t nsteps, void *stream)
+{
+    return step_common(c, x, v, f, q, m, nullptr, 1, n, dt, nsteps, stream, "ucp_step");
+}
+
+ucp_status ucp_step_batched(ucp_ctx *c, double *x, double *v, double *f, const double *q,
+                            const double *m, const int64_t *offsets, int32_t clouds, int64_t n,
+                            double dt, int32_t nsteps, void *stream)
+{
+    if (!offsets) return fail(c, UCP_EINVAL, "ucp_step_batched: offsets is NULL");
+    return step_common(c, x, v, f, q, m, offsets, clouds, n, dt, nsteps, stream, "ucp_step_batched");
+}
+
+ucp_status ucp_energy(ucp_ctx *c, const double *x, const double *v, const double *q,
+                      const double *m, int64_t n, double *out, void *stream)
+{
+    if (!c) return fail(nullptr, UCP_EINVAL, kNoCtx);
+    if (!out) return fail(c, UCP_EINVAL, "ucp_energy: out is NULL");
+    if (!ptr_ok(v, n) || !ptr_ok(m, n)) return fail(c, UCP_EINVAL, "ucp_energy: NULL particle array");
+    ucp_status st = build_common(c, x, q, nullptr, 1, n, stream, "ucp_energy");
+    if (st != UCP_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    if (n > 0) ucp::launch_forces(c, nullptr, nullptr, s);
+    ucp::launch_energy(c, v, q, m, n, out, s);
+    HIP_TRY(c, hipGetLastError());
+    return UCP_OK;
+}
+
+ucp_status ucp_force_vjp(ucp_ctx *c, const double *u, double *xbar, void *stream)
+{
+    if (!c) return fail(nullptr, UCP_EINVAL, kNoCtx);
+    if (!c->built) return fail(c, UCP_ENOTBUILT, "ucp_force_vjp: no tree has been built");
+    if (c->n == 0) return UCP_OK;
+    if (!u || !xbar) return fail(c, UCP_EINVAL, "ucp_force_vjp: NULL argument");
+    (void)stream;
+    return fail(c, UCP_EINVAL, "ucp_force_vjp: the adjoint walk is not available in this build");
+}
+
+ucp_status ucp_get_stats(ucp_ctx *c, ucp_stats *out, void *stream)
+{
+    if (!c || !out) return fail(c, UCP_EINVAL, "ucp_get_stats: NULL argument");
+    HIP_TRY(c, hipStreamSynchronize((hipStream_t)stream));
+    memset(out, 0, sizeof *out);
+    out->n = c->n;
+    out->clouds = c->clouds;
+    if (!c->built || c->n == 0) return UCP_OK;
+    unsigned long long ctr[ucp::CTR_NCTR];
+    int32_t flags = 0, nodes = 0, groups = 0;
+    HIP_TRY(c, hipMemcpy(ctr, c->d_ctr, sizeof ctr, hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(&flags, c->d_flags, sizeof flags, hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(&nodes, c->d_noff + c->n, sizeof nodes, hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(&groups, c->d_goff + c->n, sizeof groups, hipMemcpyDeviceToHost));
+    out->nodes = nodes;
+    out->groups = groups;
+    out->max_level = (int64_t)ctr[ucp::CTR_MAXLEVEL];
+    out->p2p = (int64_t)ctr[ucp::CTR_P2P];
+    out->m2p = (int64_t)ctr[ucp::CTR_M2P];
+    out->flags = flags;
+    if (flags & UCP_FLAG_NODE_OVERFLOW)
+        return fail(c, UCP_ECAPACITY, "ucp: node capacity exceeded (" + std::to_string(nodes) +
+                                          " > " + std::to_string(c->node_cap) + ")");
+    if (flags & UCP_FLAG_NONFINITE) return fail(c, UCP_ENONFINITE, "ucp: non-finite coordinate in the input");
+    if (flags & UCP_FLAG_BAD_OFFSETS) return fail(c, UCP_EINVAL, "ucp: inconsistent cloud offsets");
+    if (flags & UCP_FLAG_BAD_CUBE) return fail(c, UCP_EINVAL, "ucp: cloud extent out of range");
+    if (flags & UCP_FLAG_INTERNAL) return fail(c, UCP_EHIP, "ucp: inconsistent tree records detected on the device");
+    return UCP_OK;
+}
+
+ucp_status ucp_debug_copy(ucp_ctx *c, int32_t which, void *dst, int64_t bytes, void *stream)
+{
+    if (!c || !dst) return fail(c, UCP_EINVAL, "ucp_debug_copy: NULL argument");
+    if (!c->built) return fail(c, UCP_ENOTBUILT, "ucp_debug_copy: no tree has been built");
+    HIP_TRY(c, hipStreamSynchronize((hipStream_t)stream));
+    int32_t nodes = 0, groups = 0;
+    if (c->n > 0) {
+        HIP_TRY(c, hipMemcpy(&nodes, c->d_noff + c->n, sizeof nodes, hipMemcpyDeviceToHost));
+        HIP_TRY(c, hipMemcpy(&groups, c->d_goff + c->n, sizeof groups, hipMemcpyDeviceToHost));
+        if (nodes > c->node_cap) nodes = 0;
+    }
+    const void *src = nullptr;
+    int64_t need = 0;
+    switch (which) {
+    case 0: src = c->d_skey; need = 8 * c->n; break;
+    case 1: src = c->d_perm; need = 4 * c->n; break;
+    case 2: src = c->d_ninfo; need = 16 * (int64_t)nodes; break;
+    case 3: src = c->d_ngeo; need = 32 * (int64_t)nodes; break;
+    case 4: src = c->d_mom64; need = 80 * (int64_t)nodes; break;
+    case 5: src = c->d_groups; need = 16 * (int64_t)groups; break;
+    case 6: src = c->d_gstat; need = 8 * (int64_t)groups; break;
+    case 7: src = c->d_cube; need = 64 * (int64_t)c->clouds; break;
+    default: return fail(c, UCP_EINVAL, "ucp_debug_copy: unknown array");
+    }
+    if (bytes < need) return fail(c, UCP_EINVAL, "ucp_debug_copy: buffer too small, need " + std::to_string(need));
+    if (need == 0) return UCP_OK;
+    if (which == 7) {
+        // lo xyz and e per cloud, from the two double4 records
+        std::vector<double4> cube(2 * (size_t)c->clouds);
+        HIP_TRY(c, hipMemcpy(cube.data(), c->d_cube, cube.size() * sizeof(double4), hipMemcpyDeviceToHost));
+        double *o = (double *)dst;
+        for (int k = 0; k < c->clouds; ++k) {
+            o[4 * k] = cube[2 * k].x;
+            o[4 * k + 1] = cube[2 * k].y;
+            o[4 * k + 2] = cube[2 * k].z;
+            o[4 * k + 3] = cube[2 * k + 1].y;
+        }
+        return UCP_OK;
+    }
+    HIP_TRY(c, hipMemcpy(dst, src, (size_t)need, hipMemcpyDeviceToHost));
+    return UCP_OK;
+}
+
+ucp_status ucp_set_timing(ucp_ctx *c, int32_t on)
+{
+    if (!c) return fail(nullptr, UCP_EINVAL, kNoCtx);
+    c->timing = on ? 1 : 0;
+    c->ev_used = 0;
+    return UCP_OK;
+}
+
+ucp_status ucp_timing_read(ucp_ctx *c, double *walk_ms, int64_t *walk_launches)
+{
+    if (!c || !walk_ms || !walk_launches) return fail(c, UCP_EINVAL, "ucp_timing_read: NULL argument");
+    double tot = 0.0;
+    for (int64_t i = 0; i < c->ev_used; ++i) {
+        HIP_TRY(c, hipEventSynchronize(c->ev[2 * i + 1]));
+        float ms = 0.f;
+        HIP_TRY(c, hipEventElapsedTime(&ms, c->ev[2 * i], c->ev[2 * i + 1]));
+        tot += ms;
+    }
+    *walk_ms = tot;
+    *walk_launches = c->ev_used;
+    c->ev_used = 0;
+    return UCP_OK;
+}
+
+}  // extern "C"

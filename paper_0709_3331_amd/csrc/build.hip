@@ -1,0 +1,823 @@
+// build.hip -- tree construction on gfx950.
+//
+// Sec. 3 builds the tree top-down: a large cube enclosing all particles is
+// split recursively into eight boxes until each box holds at most leaf_cap
+// particles.  Here the same tree is produced bottom-up and in parallel:
+//   1. enclosing cube per cloud (min/max reduction, side 2^e),
+//   2. Morton keys: the octant digits of the recursive subdivision,
+//   3. stable LSD radix sort of (key, index), 8-bit digits,
+//   4. per sorted position: the level of the common prefix with the previous
+//      key and the level of the leaf holding it; the nodes that start at a
+//      position are the levels in between, so a scan numbers all nodes in
+//      preorder (node order = (first particle, level)),
+//   5. node records (extent by galloping search over the sorted keys, skip
+//      link = first node after the subtree, parent, box centre),
+//   6. moments (Q, p, S about the box centre, FP64) bottom-up: a leaf sums its
+//      particles, the last child to arrive at a parent sums the children in
+//      octant order with the exact shift of origin (deterministic),
+//   7. walk groups (a node with <= G particles whose parent has more).
+// Every kernel first checks the device flag word and does nothing once a
+// problem (capacity, non-finite input, bad offsets) has been flagged.
+#include "internal.h"
+
+namespace ucp {
+
+// ---------------------------------------------------------------------------
+// small utility kernels
+// ---------------------------------------------------------------------------
+__global__ void k_fill_i32(int32_t *p, int32_t v, int64_t n)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+__global__ void k_fill_u64(unsigned long long *p, unsigned long long v, int64_t n)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+__global__ void k_fill_f64(double *p, double v, int64_t n)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+void launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s)
+{
+    if (n > 0) hipLaunchKernelGGL(k_fill_i32, dim3((n + 255) / 256), dim3(256), 0, s, p, v, n);
+}
+void launch_fill_u64(unsigned long long *p, unsigned long long v, int64_t n, hipStream_t s)
+{
+    if (n > 0) hipLaunchKernelGGL(k_fill_u64, dim3((n + 255) / 256), dim3(256), 0, s, p, v, n);
+}
+void launch_fill_f64(double *p, double v, int64_t n, hipStream_t s)
+{
+    if (n > 0) hipLaunchKernelGGL(k_fill_f64, dim3((n + 255) / 256), dim3(256), 0, s, p, v, n);
+}
+
+// reset of the per-build state: min/max slots, counters, flag word
+__global__ void k_build_reset(unsigned long long *mm, int clouds, unsigned long long *ctr,
+                              int32_t *flags)
+{
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < clouds * 6) mm[t] = (t % 6 < 3) ? ~0ull : 0ull;
+    if (t < CTR_NCTR) ctr[t] = 0;
+    if (t == 0) *flags = 0;
+}
+
+// cloud offsets: {0, n} for one cloud, or a checked copy of the caller's
+__global__ void k_offsets_single(int64_t *off, int64_t n)
+{
+    off[0] = 0;
+    off[1] = n;
+}
+
+__global__ void k_offsets_copy(int64_t *dst, const int64_t *__restrict__ src, int clouds,
+                               int64_t n, int32_t *flags)
+{
+    for (int c = threadIdx.x; c <= clouds; c += blockDim.x) {
+        int64_t v = src[c];
+        bool bad = (c == 0 && v != 0) || (c == clouds && v != n) || (c > 0 && v < src[c - 1]) ||
+                   v < 0 || v > n;
+        dst[c] = bad ? (c == 0 ? 0 : n) : v;
+        if (bad) atomicOr(flags, UCP_FLAG_BAD_OFFSETS);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 1. enclosing cube
+// ---------------------------------------------------------------------------
+constexpr int kCubeItems = 8;
+
+__device__ __forceinline__ double wave_min(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
+
+__global__ __launch_bounds__(256) void k_cube_reduce(const double *__restrict__ x, int64_t n,
+                                                    const int64_t *__restrict__ off, int clouds,
+                                                    unsigned long long *mm, int32_t *flags)
+{
+    if (*flags) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t wave_id = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    const int64_t base = wave_id * 64 * kCubeItems;
+    if (base >= n) return;
+    const int64_t last = min(base + (int64_t)64 * kCubeItems, n) - 1;
+    const int c0 = cloud_of(off, clouds, base), c1 = cloud_of(off, clouds, last);
+    bool bad = false;
+    if (c0 == c1) {
+        double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+        for (int it = 0; it < kCubeItems; ++it) {
+            int64_t i = base + it * 64 + lane;
+            if (i < n) {
+                for (int d = 0; d < 3; ++d) {
+                    double v = x[3 * i + d];
+                    bad |= !isfinite(v);
+                    mn[d] = fmin(mn[d], v);
+                    mx[d] = fmax(mx[d], v);
+                }
+            }
+        }
+        for (int d = 0; d < 3; ++d) {
+            mn[d] = wave_min(mn[d]);
+            mx[d] = wave_max(mx[d]);
+        }
+        if (lane == 0) {
+            for (int d = 0; d < 3; ++d) {
+                atomicMin(&mm[6 * c0 + d], f64_ordered(mn[d]));
+                atomicMax(&mm[6 * c0 + 3 + d], f64_ordered(mx[d]));
+            }
+        }
+    } else {
+        for (int it = 0; it < kCubeItems; ++it) {
+            int64_t i = base + it * 64 + lane;
+            if (i < n) {
+                int c = cloud_of(off, clouds, i);
+                for (int d = 0; d < 3; ++d) {
+                    double v = x[3 * i + d];
+                    bad |= !isfinite(v);
+                    atomicMin(&mm[6 * c + d], f64_ordered(v));
+                    atomicMax(&mm[6 * c + 3 + d], f64_ordered(v));
+                }
+            }
+        }
+    }
+    if (bad) atomicOr(flags, UCP_FLAG_NONFINITE);
+}
+
+// lo = minimum corner; side L = 2^e, e the smallest integer with 2^e > extent
+// (frexp gives extent = m 2^e with m in [1/2, 1)); e = 0 for a zero extent.
+__global__ void k_cube_finish(const unsigned long long *__restrict__ mm,
+                              const int64_t *__restrict__ off, int clouds, int b, double4 *cube,
+                              int32_t *flags)
+{
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= clouds) return;
+    if (*flags) return;
+    bool empty = off[c + 1] == off[c];
+    double lo[3], ext = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        lo[d] = empty ? 0.0 : f64_from_ordered(mm[6 * c + d]);
+        double hi = empty ? 0.0 : f64_from_ordered(mm[6 * c + 3 + d]);
+        double w = hi - lo[d];
+        ext = w > ext ? w : ext;
+    }
+    int e = 0;
+    if (ext > 0.0) frexp(ext, &e);
+    if (e < -1000 || e > 1000) atomicOr(flags, UCP_FLAG_BAD_CUBE);
+    cube[2 * c] = make_double4(lo[0], lo[1], lo[2], ldexp(1.0, e));
+    cube[2 * c + 1] = make_double4(ldexp(1.0, b - e), (double)e, 0.0, 0.0);
+}
+
+// ---------------------------------------------------------------------------
+// 2. Morton keys: X_d = min(floor((x_d - lo_d) 2^(b-e)), 2^b - 1), bits of X,
+//    Y, Z interleaved x-major (octant digit = 4 xbit + 2 ybit + zbit).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t quantise(double v, double lo, double scale, uint64_t top)
+{
+    double t = (v - lo) * scale;
+    if (!(t >= 0.0)) return 0;
+    double f = floor(t);
+    if (f >= (double)top) return top;
+    return (uint64_t)f;
+}
+
+__global__ __launch_bounds__(256) void k_keys(const double *__restrict__ x, int64_t n,
+                                             const int64_t *__restrict__ off, int clouds,
+                                             const double4 *__restrict__ cube, int b,
+                                             uint64_t *key, uint32_t *val,
+                                             const int32_t *flags)
+{
+    if (*flags) return;
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int c = cloud_of(off, clouds, i);
+    double4 c0 = cube[2 * c], c1 = cube[2 * c + 1];
+    uint64_t top = (1ull << b) - 1;
+    uint64_t X = quantise(x[3 * i + 0], c0.x, c1.x, top);
+    uint64_t Y = quantise(x[3 * i + 1], c0.y, c1.x, top);
+    uint64_t Z = quantise(x[3 * i + 2], c0.z, c1.x, top);
+    key[i] = (spread3(X) << 2) | (spread3(Y) << 1) | spread3(Z);
+    val[i] = (uint32_t)i;
+}
+
+// ---------------------------------------------------------------------------
+// device-wide exclusive scan of int32 (three kernels)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int wave_incl_scan(int v)
+{
+    const int lane = threadIdx.x & 63;
+    for (int o = 1; o < 64; o <<= 1) {
+        int t = __shfl_up(v, o);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+// block-wide exclusive scan (blockDim = kScanBlock); returns the exclusive
+// prefix of v and writes the block total to *total.
+__device__ __forceinline__ int block_excl_scan(int v, int *total)
+{
+    __shared__ int ws[kScanBlock / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int inc = wave_incl_scan(v);
+    if (lane == 63) ws[w] = inc;
+    __syncthreads();
+    if (w == 0) {
+        int t = lane < kScanBlock / 64 ? ws[lane] : 0;
+        int ti = wave_incl_scan(t);
+        if (lane < kScanBlock / 64) ws[lane] = ti - t;
+        if (lane == kScanBlock / 64 - 1) *total = ti;
+    }
+    __syncthreads();
+    int r = ws[w] + inc - v;
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_reduce(const int32_t *__restrict__ in,
+                                                           int64_t n, int32_t *blk)
+{
+    __shared__ int tot;
+    const int64_t base = (int64_t)blockIdx.x * kScanBlock * kScanItems;
+    int s = 0;
+    for (int j = 0; j < kScanItems; ++j) {
+        int64_t e = base + (int64_t)threadIdx.x * kScanItems + j;
+        if (e < n) s += in[e];
+    }
+    block_excl_scan(s, &tot);
+    if (threadIdx.x == 0) blk[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_blocks(int32_t *blk, int nb)
+{
+    __shared__ int tot;
+    int carry = 0;
+    for (int base = 0; base < nb; base += kScanBlock) {
+        int i = base + threadIdx.x;
+        int v = i < nb ? blk[i] : 0;
+        int ex = block_excl_scan(v, &tot);
+        if (i < nb) blk[i] = carry + ex;
+        carry += tot;
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_down(const int32_t *__restrict__ in,
+                                                         int32_t *out, int64_t n,
+                                                         const int32_t *__restrict__ blk)
+{
+    __shared__ int tot;
+    const int64_t base = (int64_t)blockIdx.x * kScanBlock * kScanItems;
+    int v[kScanItems];
+    int s = 0;
+    for (int j = 0; j < kScanItems; ++j) {
+        int64_t e = base + (int64_t)threadIdx.x * kScanItems + j;
+        v[j] = e < n ? in[e] : 0;
+        s += v[j];
+    }
+    int ex = block_excl_scan(s, &tot) + blk[blockIdx.x];
+    for (int j = 0; j < kScanItems; ++j) {
+        int64_t e = base + (int64_t)threadIdx.x * kScanItems + j;
+        if (e < n) out[e] = ex;
+        ex += v[j];
+    }
+}
+
+static void scan_excl(const int32_t *in, int32_t *out, int64_t n, int32_t *blk, hipStream_t s)
+{
+    const int64_t per = (int64_t)kScanBlock * kScanItems;
+    int nb = (int)((n + per - 1) / per);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanBlock), 0, s, in, n, blk);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kScanBlock), 0, s, blk, nb);
+    hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(kScanBlock), 0, s, in, out, n,
+                       (const int32_t *)blk);
+}
+
+// ---------------------------------------------------------------------------
+// 3. stable LSD radix sort of (key, index), 8-bit digits.  A tile of
+//    kSortTile elements is processed in rounds of 256; inside a round each
+//    wave ranks equal digits with ballots, waves are ordered through LDS, and
+//    a running count per digit carries the order across rounds.  The last
+//    pass(es) of a multi-cloud build sort by cloud, restoring the clouds'
+//    contiguity while keeping key order inside each cloud.
+// ---------------------------------------------------------------------------
+template <bool CLOUD>
+__device__ __forceinline__ uint32_t sort_digit(uint64_t k, uint32_t v, int shift,
+                                               const int64_t *__restrict__ off, int clouds)
+{
+    if (CLOUD) return ((uint32_t)cloud_of(off, clouds, v) >> shift) & 255u;
+    return (uint32_t)(k >> shift) & 255u;
+}
+
+template <bool CLOUD>
+__global__ __launch_bounds__(kSortThreads) void k_radix_hist(
+    const uint64_t *__restrict__ key, const uint32_t *__restrict__ val, int64_t n, int shift,
+    const int64_t *__restrict__ off, int clouds, uint32_t *hist, int ntiles, const int32_t *flags)
+{
+    __shared__ uint32_t h[256];
+    if (*flags) return;
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    for (int it = 0; it < kSortItems; ++it) {
+        int64_t e = base + it * kSortThreads + threadIdx.x;
+        if (e < n) {
+            uint32_t d = sort_digit<CLOUD>(CLOUD ? 0 : key[e], CLOUD ? val[e] : 0, shift, off, clouds);
+            atomicAdd(&h[d], 1u);
+        }
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
+}
+
+template <bool CLOUD>
+__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
+    const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint64_t *kout,
+    uint32_t *vout, int64_t n, int shift, const int64_t *__restrict__ off, int clouds,
+    const uint32_t *__restrict__ hscan, int ntiles, const int32_t *flags)
+{
+    __shared__ uint32_t run[256];
+    __shared__ uint32_t wh[kSortThreads / 64][256];
+    __shared__ uint32_t boff[256];
+    if (*flags) return;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    run[tid] = 0;
+    boff[tid] = hscan[(int64_t)tid * ntiles + blockIdx.x];
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    for (int it = 0; it < kSortItems; ++it) {
+        for (int ww = 0; ww < kSortThreads / 64; ++ww) wh[ww][tid] = 0;
+        __syncthreads();
+        const int64_t e = base + it * kSortThreads + tid;
+        const bool valid = e < n;
+        uint64_t k = 0;
+        uint32_t v = 0, d = 0;
+        if (valid) {
+            k = kin[e];
+            v = vin[e];
+            d = sort_digit<CLOUD>(k, v, shift, off, clouds);
+        }
+        uint64_t peers = __ballot(valid);
+        for (int bit = 0; bit < 8; ++bit) {
+            uint64_t bb = __ballot((d >> bit) & 1u);
+            peers &= ((d >> bit) & 1u) ? bb : ~bb;
+        }
+        const uint32_t lrank = (uint32_t)__popcll(peers & lt);
+        if (valid && lrank == 0) wh[w][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        {
+            uint32_t r = run[tid];
+            for (int ww = 0; ww < kSortThreads / 64; ++ww) {
+                uint32_t c = wh[ww][tid];
+                wh[ww][tid] = r;
+                r += c;
+            }
+            run[tid] = r;
+        }
+        __syncthreads();
+        if (valid) {
+            uint32_t dst = boff[d] + wh[w][d] + lrank;
+            kout[dst] = k;
+            vout[dst] = v;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 4. per-position levels.
+//    L(p): number of leading key digits shared with position p-1 (-1 at a
+//    cloud edge).  A boundary at level l lies before p iff L(p) < l.
+//    leaf(p): smallest level l at which the box holding p has <= leaf_cap
+//    particles (b if none) -- found by bisection on l, each probe looking for
+//    boundaries s <= p < t at level l with t - s <= leaf_cap.
+//    nodes starting at p: levels L(p)+1 .. leaf(p).
+// ---------------------------------------------------------------------------
+constexpr int kLvlTile = 256;
+
+__device__ __forceinline__ int lcp_level(uint64_t a, uint64_t b2, int b)
+{
+    uint64_t x = a ^ b2;
+    if (x == 0) return b;
+    int lz = __clzll((long long)x) - (64 - 3 * b);
+    return lz / 3;
+}
+
+__global__ __launch_bounds__(kLvlTile) void k_levels(const uint64_t *__restrict__ key, int64_t n,
+                                                    const int64_t *__restrict__ off, int clouds,
+                                                    int b, int cap, int8_t *Lout, int8_t *leafout,
+                                                    int32_t *cnt, const int32_t *flags)
+{
+    __shared__ int8_t sL[kLvlTile + 2 * kMaxLeafCap + 2];
+    const int64_t base = (int64_t)blockIdx.x * kLvlTile;
+    const int64_t wlo = base - cap;                 // sL[j - wlo] = L(j)
+    const int wn = kLvlTile + 2 * cap + 1;
+    const bool stop = *flags != 0;
+    for (int t = threadIdx.x; t < wn; t += kLvlTile) {
+        int64_t j = wlo + t;
+        int v = -1;
+        if (!stop && j > 0 && j < n) {
+            int c1 = cloud_of(off, clouds, j);
+            if (off[c1] != j) v = lcp_level(key[j - 1], key[j], b);
+        }
+        sL[t] = (int8_t)v;
+    }
+    __syncthreads();
+    const int64_t p = base + threadIdx.x;
+    if (p > n) return;
+    if (p == n || stop) {
+        cnt[p] = 0;
+        if (p < n) { Lout[p] = -1; leafout[p] = -1; }
+        else Lout[p] = -1;
+        return;
+    }
+    auto Lw = [&](int64_t j) -> int { return (int)sL[j - wlo]; };
+    auto ok = [&](int lv) -> bool {
+        int64_t s = p;
+        while (s > p - cap + 1 && Lw(s) >= lv) --s;
+        if (Lw(s) >= lv) return false;
+        int64_t t = p + 1;
+        while (t < s + cap && Lw(t) >= lv) ++t;
+        return Lw(t) < lv;
+    };
+    int leaf;
+    if (!ok(b)) {
+        leaf = b;
+    } else {
+        int lo = -1, hi = b;   // ok(hi) holds; ok(lo) is taken as false
+        while (hi - lo > 1) {
+            int mid = (lo + hi) >> 1;
+            if (ok(mid)) hi = mid;
+            else lo = mid;
+        }
+        leaf = hi;
+    }
+    const int Lp = Lw(p);
+    Lout[p] = (int8_t)Lp;
+    leafout[p] = (int8_t)leaf;
+    cnt[p] = leaf > Lp ? leaf - Lp : 0;
+}
+
+// ---------------------------------------------------------------------------
+// 5. node records
+// ---------------------------------------------------------------------------
+// first position t in (p, ce] whose key prefix (key >> sh) differs from P
+__device__ __forceinline__ int64_t gallop_end(const uint64_t *__restrict__ key, int64_t p,
+                                              int64_t ce, int sh, uint64_t P)
+{
+    int64_t m = p, nm, step = 1;
+    for (;;) {
+        int64_t cand = m + step;
+        if (cand >= ce) { nm = ce; break; }
+        if ((key[cand] >> sh) == P) { m = cand; step <<= 1; }
+        else { nm = cand; break; }
+    }
+    while (nm - m > 1) {
+        int64_t mid = m + ((nm - m) >> 1);
+        if ((key[mid] >> sh) == P) m = mid;
+        else nm = mid;
+    }
+    return nm;
+}
+
+// first position s in [cs, p] whose key prefix equals P (key[p] has it)
+__device__ __forceinline__ int64_t gallop_start(const uint64_t *__restrict__ key, int64_t p,
+                                                int64_t cs, int sh, uint64_t P)
+{
+    int64_t m = p, nm, step = 1;
+    for (;;) {
+        int64_t cand = m - step;
+        if (cand < cs) { nm = cs - 1; break; }
+        if ((key[cand] >> sh) == P) { m = cand; step <<= 1; }
+        else { nm = cand; break; }
+    }
+    while (m - nm > 1) {
+        int64_t mid = nm + ((m - nm) >> 1);
+        if ((key[mid] >> sh) == P) m = mid;
+        else nm = mid;
+    }
+    return m;
+}
+
+__global__ __launch_bounds__(256) void k_nodes(
+    const uint64_t *__restrict__ key, int64_t n, const int64_t *__restrict__ off, int clouds,
+    const double4 *__restrict__ cube, int b, const int8_t *__restrict__ Lv,
+    const int8_t *__restrict__ Lf, const int32_t *__restrict__ noff, int64_t node_cap,
+    double4 *ngeo, int4 *ninfo, int32_t *npar, int32_t *narr, unsigned long long *ctr,
+    int32_t *flags)
+{
+    if (*flags) return;
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    if ((int64_t)noff[n] > node_cap) {
+        if (p == 0) atomicOr(flags, UCP_FLAG_NODE_OVERFLOW);
+        return;
+    }
+    const int Lp = Lv[p], lf = Lf[p];
+    if (lf <= Lp) return;
+    const int c = cloud_of(off, clouds, p);
+    const int64_t cs = off[c], ce = off[c + 1];
+    const uint64_t kp = key[p];
+    const double4 c0 = cube[2 * c];
+    const int e = (int)cube[2 * c + 1].y;
+    const uint64_t X = compact3(kp >> 2), Y = compact3(kp >> 1), Z = compact3(kp);
+    const int k0 = noff[p];
+    for (int l = Lp + 1; l <= lf; ++l) {
+        const int k = k0 + (l - Lp - 1);
+        const int sh = 3 * (b - l);
+        int64_t t = (l == 0) ? ce : gallop_end(key, p, ce, sh, kp >> sh);
+        int parent;
+        if (l == 0) {
+            parent = -1;
+        } else if (l - 1 > Lp) {
+            parent = k - 1;
+        } else {
+            int64_t s = gallop_start(key, p, cs, sh + 3, kp >> (sh + 3));
+            parent = noff[s] + (l - 1 - (int)Lv[s] - 1);
+        }
+        // box centre c_d = lo_d + (2 k_d + 1) 2^(e - l - 1); the product is exact
+        const double h = ldexp(1.0, e - l - 1);
+        const double cx = c0.x + (double)(2 * (X >> (b - l)) + 1) * h;
+        const double cy = c0.y + (double)(2 * (Y >> (b - l)) + 1) * h;
+        const double cz = c0.z + (double)(2 * (Z >> (b - l)) + 1) * h;
+        ngeo[k] = make_double4(cx, cy, cz, ldexp(1.0, 2 * (e - l)));
+        ninfo[k] = make_int4((int)p, (int)(t - p), noff[t], l | (l == lf ? 256 : 0));
+        npar[k] = parent;
+        narr[k] = 0;
+    }
+    atomicMax(&ctr[CTR_MAXLEVEL], (unsigned long long)lf);
+}
+
+// ---------------------------------------------------------------------------
+// 6. moments about the box centre, bottom-up
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void store_moments(double *mom64, float4 *mom32, int k, const double *m)
+{
+    for (int i = 0; i < 10; ++i) mom64[10 * (int64_t)k + i] = m[i];
+    mom32[3 * (int64_t)k + 0] = make_float4((float)m[0], (float)m[1], (float)m[2], (float)m[3]);
+    mom32[3 * (int64_t)k + 1] =
+        make_float4((float)m[4], (float)m[5], (float)m[6], (float)(m[4] + m[5] + m[6]));
+    mom32[3 * (int64_t)k + 2] = make_float4((float)m[7], (float)m[8], (float)m[9], 0.0f);
+}
+
+__device__ __forceinline__ double load_agent(const double *p)
+{
+    unsigned long long u = __hip_atomic_load((const unsigned long long *)p, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+    return __longlong_as_double((long long)u);
+}
+
+__global__ __launch_bounds__(256) void k_moments(
+    const double4 *__restrict__ xq, int64_t n, const int8_t *__restrict__ Lv,
+    const int8_t *__restrict__ Lf, const int32_t *__restrict__ noff,
+    const double4 *__restrict__ ngeo, const int4 *__restrict__ ninfo,
+    const int32_t *__restrict__ npar, int32_t *narr, double *mom64, float4 *mom32, float4 *xl,
+    const int32_t *flags)
+{
+    if (*flags) return;
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const int Lp = Lv[p], lf = Lf[p];
+    if (lf <= Lp) return;
+    int k = noff[p] + (lf - Lp - 1);   // the leaf starting at p
+    {
+        const double4 g = ngeo[k];
+        const int4 inf = ninfo[k];
+        double m[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+        for (int j = inf.x; j < inf.x + inf.y; ++j) {
+            const double4 a = xq[j];
+            const double r0 = a.x - g.x, r1 = a.y - g.y, r2 = a.z - g.z, qq = a.w;
+            m[0] += qq;
+            m[1] += qq * r0;
+            m[2] += qq * r1;
+            m[3] += qq * r2;
+            m[4] += qq * r0 * r0;
+            m[5] += qq * r1 * r1;
+            m[6] += qq * r2 * r2;
+            m[7] += qq * r0 * r1;
+            m[8] += qq * r0 * r2;
+            m[9] += qq * r1 * r2;
+            xl[j] = make_float4((float)r0, (float)r1, (float)r2, (float)qq);
+        }
+        store_moments(mom64, mom32, k, m);
+    }
+    int cnt = ninfo[k].y;
+    const int nn = noff[n];
+    // a node has at most 22 ancestors; the bound makes the climb finite whatever
+    // the records hold
+    for (int depth = 0; depth < 64; ++depth) {
+        const int par = npar[k];
+        if (par < 0) break;
+        if (par >= k || par >= nn) { atomicOr((int32_t *)flags, UCP_FLAG_INTERNAL); break; }
+        const int old = __hip_atomic_fetch_add(&narr[par], cnt, __ATOMIC_ACQ_REL,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+        const int4 pin = ninfo[par];
+        if (old + cnt != pin.y) break;   // another child is still missing
+        const double4 pg = ngeo[par];
+        const double qd = 0.25 * sqrt(pg.w);   // |child centre - parent centre| per axis
+        double M[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+        const int chend = min(pin.z, nn);
+        for (int ch = par + 1; ch < chend; ch = max(ninfo[ch].z, ch + 1)) {
+            const double4 cg = ngeo[ch];
+            const double d0 = cg.x > pg.x ? qd : -qd;
+            const double d1 = cg.y > pg.y ? qd : -qd;
+            const double d2 = cg.z > pg.z ? qd : -qd;
+            double c[10];
+            for (int i = 0; i < 10; ++i) c[i] = load_agent(mom64 + 10 * (int64_t)ch + i);
+            // shift of origin by d: p' = p + Q d, S' = S + p d^T + d p^T + Q d d^T
+            M[0] += c[0];
+            M[1] += c[1] + c[0] * d0;
+            M[2] += c[2] + c[0] * d1;
+            M[3] += c[3] + c[0] * d2;
+            M[4] += c[4] + 2.0 * c[1] * d0 + c[0] * d0 * d0;
+            M[5] += c[5] + 2.0 * c[2] * d1 + c[0] * d1 * d1;
+            M[6] += c[6] + 2.0 * c[3] * d2 + c[0] * d2 * d2;
+            M[7] += c[7] + c[1] * d1 + d0 * c[2] + c[0] * d0 * d1;
+            M[8] += c[8] + c[1] * d2 + d0 * c[3] + c[0] * d0 * d2;
+            M[9] += c[9] + c[2] * d2 + d1 * c[3] + c[0] * d1 * d2;
+        }
+        store_moments(mom64, mom32, par, M);
+        k = par;
+        cnt = pin.y;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 7. walk groups
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_group_count(
+    int64_t n, const int8_t *__restrict__ Lv, const int8_t *__restrict__ Lf,
+    const int32_t *__restrict__ noff, const int4 *__restrict__ ninfo,
+    const int32_t *__restrict__ npar, int G, int32_t *cnt, int32_t *gnode, const int32_t *flags)
+{
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p > n) return;
+    if (p == n || *flags) { cnt[p] = 0; return; }
+    const int Lp = Lv[p], lf = Lf[p];
+    int ng = 0, gn = -1;
+    if (lf > Lp) {
+        const int k0 = noff[p];
+        for (int l = Lp + 1; l <= lf; ++l) {
+            const int k = k0 + (l - Lp - 1);
+            const int c = ninfo[k].y;
+            const int par = npar[k];
+            const int cpar = par < 0 ? 0x7fffffff : ninfo[par].y;
+            if (c <= G && cpar > G) { ng = 1; gn = k; break; }
+        }
+        if (ng == 0) {
+            const int kl = k0 + (lf - Lp - 1);
+            const int c = ninfo[kl].y;
+            if (c > G) { ng = (c + G - 1) / G; gn = kl; }
+        }
+    }
+    cnt[p] = ng;
+    gnode[p] = gn;
+}
+
+__global__ __launch_bounds__(256) void k_group_emit(
+    int64_t n, const int32_t *__restrict__ cnt, const int32_t *__restrict__ goff,
+    const int32_t *__restrict__ gnode, const int4 *__restrict__ ninfo,
+    const int32_t *__restrict__ noff, const int64_t *__restrict__ off, int clouds, int G,
+    int4 *groups, const int32_t *flags)
+{
+    if (*flags) return;
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const int ng = cnt[p];
+    if (ng == 0) return;
+    const int k = gnode[p];
+    const int c = ninfo[k].y;
+    const int root = noff[off[cloud_of(off, clouds, p)]];
+    for (int j = 0; j < ng; ++j) {
+        const int gc = min(G, c - j * G);
+        groups[goff[p] + j] = make_int4((int)p + j * G, gc, k, root);
+    }
+}
+
+// gather of the sorted particles (x, y, z, q)
+__global__ __launch_bounds__(256) void k_gather(const double *__restrict__ x,
+                                               const double *__restrict__ q,
+                                               const uint32_t *__restrict__ perm, int64_t n,
+                                               double4 *xq, const int32_t *flags)
+{
+    if (*flags) return;
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const uint32_t i = perm[p];
+    xq[p] = make_double4(x[3 * (int64_t)i], x[3 * (int64_t)i + 1], x[3 * (int64_t)i + 2], q[i]);
+}
+
+// ---------------------------------------------------------------------------
+// host driver of one build
+// ---------------------------------------------------------------------------
+static inline dim3 grid_for(int64_t n, int threads) { return dim3((unsigned)((n + threads - 1) / threads)); }
+
+void launch_build(Ctx *c, const double *x, const double *q, const int64_t *offsets_in, int clouds,
+                  int64_t n, hipStream_t s)
+{
+    const int b = c->p.key_bits == 30 ? 10 : 21;
+    const int cap = c->p.leaf_cap;
+    const int G = c->p.group_size;
+
+    hipLaunchKernelGGL(k_build_reset, grid_for(6 * (int64_t)clouds + CTR_NCTR, 256), dim3(256), 0, s,
+                       c->d_mm, clouds, c->d_ctr, c->d_flags);
+    if (offsets_in)
+        hipLaunchKernelGGL(k_offsets_copy, dim3(1), dim3(256), 0, s, c->d_off, offsets_in, clouds,
+                           n, c->d_flags);
+    else
+        hipLaunchKernelGGL(k_offsets_single, dim3(1), dim3(1), 0, s, c->d_off, n);
+
+    // 1. cube
+    const int64_t waves = (n + 64 * kCubeItems - 1) / (64 * kCubeItems);
+    hipLaunchKernelGGL(k_cube_reduce, grid_for(waves * 64, 256), dim3(256), 0, s, x, n,
+                       (const int64_t *)c->d_off, clouds, c->d_mm, c->d_flags);
+    hipLaunchKernelGGL(k_cube_finish, grid_for(clouds, 64), dim3(64), 0, s,
+                       (const unsigned long long *)c->d_mm, (const int64_t *)c->d_off, clouds, b,
+                       c->d_cube, c->d_flags);
+    // 2. keys
+    hipLaunchKernelGGL(k_keys, grid_for(n, 256), dim3(256), 0, s, x, n, (const int64_t *)c->d_off,
+                       clouds, (const double4 *)c->d_cube, b, c->d_key[0], c->d_val[0],
+                       (const int32_t *)c->d_flags);
+    // 3. sort
+    const int ntiles = (int)((n + kSortTile - 1) / kSortTile);
+    const int nhist = 256 * ntiles;
+    int cur = 0;
+    auto pass = [&](bool cloud_pass, int shift) {
+        if (cloud_pass) {
+            hipLaunchKernelGGL(k_radix_hist<true>, dim3(ntiles), dim3(kSortThreads), 0, s,
+                               (const uint64_t *)c->d_key[cur], (const uint32_t *)c->d_val[cur], n,
+                               shift, (const int64_t *)c->d_off, clouds, c->d_hist, ntiles,
+                               (const int32_t *)c->d_flags);
+        } else {
+            hipLaunchKernelGGL(k_radix_hist<false>, dim3(ntiles), dim3(kSortThreads), 0, s,
+                               (const uint64_t *)c->d_key[cur], (const uint32_t *)c->d_val[cur], n,
+                               shift, (const int64_t *)c->d_off, clouds, c->d_hist, ntiles,
+                               (const int32_t *)c->d_flags);
+        }
+        scan_excl((const int32_t *)c->d_hist, (int32_t *)c->d_histscan, nhist, c->d_scanblk, s);
+        if (cloud_pass) {
+            hipLaunchKernelGGL(k_radix_scatter<true>, dim3(ntiles), dim3(kSortThreads), 0, s,
+                               (const uint64_t *)c->d_key[cur], (const uint32_t *)c->d_val[cur],
+                               c->d_key[cur ^ 1], c->d_val[cur ^ 1], n, shift,
+                               (const int64_t *)c->d_off, clouds, (const uint32_t *)c->d_histscan,
+                               ntiles, (const int32_t *)c->d_flags);
+        } else {
+            hipLaunchKernelGGL(k_radix_scatter<false>, dim3(ntiles), dim3(kSortThreads), 0, s,
+                               (const uint64_t *)c->d_key[cur], (const uint32_t *)c->d_val[cur],
+                               c->d_key[cur ^ 1], c->d_val[cur ^ 1], n, shift,
+                               (const int64_t *)c->d_off, clouds, (const uint32_t *)c->d_histscan,
+                               ntiles, (const int32_t *)c->d_flags);
+        }
+        cur ^= 1;
+    };
+    const int key_passes = (3 * b + 7) / 8;
+    for (int ps = 0; ps < key_passes; ++ps) pass(false, 8 * ps);
+    if (clouds > 1) {
+        int cbits = 0;
+        while ((1 << cbits) < clouds) ++cbits;
+        for (int ps = 0; ps < (cbits + 7) / 8; ++ps) pass(true, 8 * ps);
+    }
+    c->d_skey = c->d_key[cur];
+    c->d_perm = c->d_val[cur];
+    // gather
+    hipLaunchKernelGGL(k_gather, grid_for(n, 256), dim3(256), 0, s, x, q,
+                       (const uint32_t *)c->d_perm, n, c->d_xq, (const int32_t *)c->d_flags);
+    // 4. levels and node numbering
+    hipLaunchKernelGGL(k_levels, grid_for(n + 1, kLvlTile), dim3(kLvlTile), 0, s,
+                       (const uint64_t *)c->d_skey, n, (const int64_t *)c->d_off, clouds, b, cap,
+                       c->d_L, c->d_leaf, c->d_cnt, (const int32_t *)c->d_flags);
+    scan_excl((const int32_t *)c->d_cnt, c->d_noff, n + 1, c->d_scanblk, s);
+    // 5. nodes
+    hipLaunchKernelGGL(k_nodes, grid_for(n, 256), dim3(256), 0, s, (const uint64_t *)c->d_skey, n,
+                       (const int64_t *)c->d_off, clouds, (const double4 *)c->d_cube, b,
+                       (const int8_t *)c->d_L, (const int8_t *)c->d_leaf,
+                       (const int32_t *)c->d_noff, c->node_cap, c->d_ngeo, c->d_ninfo, c->d_npar,
+                       c->d_narr, c->d_ctr, c->d_flags);
+    // 6. moments
+    hipLaunchKernelGGL(k_moments, grid_for(n, 256), dim3(256), 0, s, (const double4 *)c->d_xq, n,
+                       (const int8_t *)c->d_L, (const int8_t *)c->d_leaf,
+                       (const int32_t *)c->d_noff, (const double4 *)c->d_ngeo,
+                       (const int4 *)c->d_ninfo, (const int32_t *)c->d_npar, c->d_narr,
+                       c->d_mom64, c->d_mom32, c->d_xl, (const int32_t *)c->d_flags);
+    // 7. groups
+    hipLaunchKernelGGL(k_group_count, grid_for(n + 1, 256), dim3(256), 0, s, n,
+                       (const int8_t *)c->d_L, (const int8_t *)c->d_leaf,
+                       (const int32_t *)c->d_noff, (const int4 *)c->d_ninfo,
+                       (const int32_t *)c->d_npar, G, c->d_cnt, c->d_gnode,
+                       (const int32_t *)c->d_flags);
+    scan_excl((const int32_t *)c->d_cnt, c->d_goff, n + 1, c->d_scanblk, s);
+    hipLaunchKernelGGL(k_group_emit, grid_for(n, 256), dim3(256), 0, s, n,
+                       (const int32_t *)c->d_cnt, (const int32_t *)c->d_goff,
+                       (const int32_t *)c->d_gnode, (const int4 *)c->d_ninfo,
+                       (const int32_t *)c->d_noff, (const int64_t *)c->d_off, clouds, G,
+                       c->d_groups, (const int32_t *)c->d_flags);
+}
+
+}  // namespace ucp

@@ -1,0 +1,172 @@
+// internal.h -- context layout, device helpers and kernel-launch declarations
+// shared by the HIP translation units of the TREE library (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/ucp.h"
+
+namespace ucp {
+
+constexpr int kWave = 64;
+constexpr int kMaxGroup = 64;      // one target particle per lane
+constexpr int kMaxLeafCap = 64;
+constexpr int kScanBlock = 1024;   // threads per scan block
+constexpr int kScanItems = 4;      // elements per thread in the scan
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kSortThreads * kSortItems;
+
+// device counter slots (unsigned long long)
+enum { CTR_P2P = 0, CTR_M2P = 1, CTR_MAXLEVEL = 2, CTR_QUEUE = 3, CTR_NCTR = 8 };
+
+struct Ctx;
+
+// ---------------------------------------------------------------------------
+// Host-side launch helpers (defined in the .hip files).  All enqueue on `s`.
+// ---------------------------------------------------------------------------
+// build.hip
+void launch_build(Ctx *c, const double *x, const double *q, const int64_t *offsets_in,
+                  int clouds, int64_t n, hipStream_t s);
+// walk.hip
+void launch_forces(Ctx *c, double *f, double *phi, hipStream_t s);
+void launch_vjp(Ctx *c, const double *u, double *xbar, hipStream_t s);
+// integrate.hip
+void launch_kick_drift(double *x, double *v, const double *f, const double *m, int64_t n,
+                       double dt, hipStream_t s);
+void launch_kick(double *v, const double *f, const double *m, int64_t n, double dt,
+                 hipStream_t s);
+void launch_energy(Ctx *c, const double *v, const double *q, const double *m, int64_t n,
+                   double *out, hipStream_t s);
+void launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
+void launch_fill_u64(unsigned long long *p, unsigned long long v, int64_t n, hipStream_t s);
+void launch_fill_f64(double *p, double v, int64_t n, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// The context.  Every device buffer is sized at create time.
+// ---------------------------------------------------------------------------
+struct Ctx {
+    int device = 0;
+    int num_cu = 256;
+    ucp_params p{};
+    int64_t n_max = 0;
+    int32_t clouds_max = 0;
+    int64_t node_cap = 0;
+    int64_t hist_cap = 0;
+
+    // last build
+    int built = 0;
+    int64_t n = 0;
+    int32_t clouds = 0;
+    ucp_params p_built{};
+
+    // per cloud
+    int64_t *d_off = nullptr;               // [clouds_max + 1]
+    unsigned long long *d_mm = nullptr;     // [clouds_max][6] ordered min xyz, max xyz
+    double4 *d_cube = nullptr;              // [clouds_max][2]: {lo xyz, L}, {scale, e, -, -}
+    // sort
+    uint64_t *d_key[2] = {nullptr, nullptr};
+    uint32_t *d_val[2] = {nullptr, nullptr};
+    uint32_t *d_hist = nullptr;             // [256 * tiles]
+    uint32_t *d_histscan = nullptr;
+    uint64_t *d_skey = nullptr;             // sorted keys (points into d_key[])
+    uint32_t *d_perm = nullptr;             // sorted position -> caller index
+    // sorted particles
+    double4 *d_xq = nullptr;                // [n_max] x, y, z, q  (sorted order)
+    float4 *d_xl = nullptr;                 // [n_max] fp32(x - leaf centre), q
+    // per position
+    int8_t *d_L = nullptr;                  // [n_max + 1] common-prefix level with predecessor
+    int8_t *d_leaf = nullptr;               // [n_max + 1] level of the leaf holding the position
+    int32_t *d_cnt = nullptr;               // [n_max + 1] per-position counts to scan
+    int32_t *d_noff = nullptr;              // [n_max + 1] first node starting at the position
+    int32_t *d_goff = nullptr;              // [n_max + 1] first group starting at the position
+    int32_t *d_gnode = nullptr;             // [n_max]
+    int32_t *d_scanblk = nullptr;           // scan block sums
+    // nodes
+    double4 *d_ngeo = nullptr;              // [node_cap] centre xyz, side^2
+    int4 *d_ninfo = nullptr;                // [node_cap] first, count, skip, level | 256*leaf
+    int32_t *d_npar = nullptr;              // [node_cap] parent (-1 for a root)
+    int32_t *d_narr = nullptr;              // [node_cap] arrival counter of the moment pass
+    double *d_mom64 = nullptr;              // [node_cap][10]
+    float4 *d_mom32 = nullptr;              // [node_cap][3]
+    // groups
+    int4 *d_groups = nullptr;               // [n_max] first, count, node, root
+    int2 *d_gstat = nullptr;                // [n_max] accepted boxes, P2P sources
+    // results (sorted order)
+    double4 *d_acc = nullptr;               // [n_max] E xyz, phi
+    // counters, flags
+    unsigned long long *d_ctr = nullptr;    // [CTR_NCTR]
+    int32_t *d_flags = nullptr;             // [1]
+    // energy partials
+    double *d_epart = nullptr;              // [256][8]
+
+    // graph of one Verlet step
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    std::vector<uintptr_t> gkey;
+
+    // timing
+    int timing = 0;
+    std::vector<hipEvent_t> ev;             // pairs
+    int64_t ev_used = 0;
+
+    std::string err;
+};
+
+// ---------------------------------------------------------------------------
+// Device helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ unsigned long long f64_ordered(double d)
+{
+    unsigned long long u = (unsigned long long)__double_as_longlong(d);
+    return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
+}
+
+__device__ __forceinline__ double f64_from_ordered(unsigned long long u)
+{
+    u = (u >> 63) ? (u & 0x7fffffffffffffffull) : ~u;
+    return __longlong_as_double((long long)u);
+}
+
+// bits 0..20 of v moved to bits 0, 3, 6, ..., 60
+__device__ __forceinline__ uint64_t spread3(uint64_t v)
+{
+    v &= 0x1fffffull;
+    v = (v | (v << 32)) & 0x1f00000000ffffull;
+    v = (v | (v << 16)) & 0x1f0000ff0000ffull;
+    v = (v | (v << 8)) & 0x100f00f00f00f00full;
+    v = (v | (v << 4)) & 0x10c30c30c30c30c3ull;
+    v = (v | (v << 2)) & 0x1249249249249249ull;
+    return v;
+}
+
+// inverse of spread3
+__device__ __forceinline__ uint64_t compact3(uint64_t v)
+{
+    v &= 0x1249249249249249ull;
+    v = (v ^ (v >> 2)) & 0x10c30c30c30c30c3ull;
+    v = (v ^ (v >> 4)) & 0x100f00f00f00f00full;
+    v = (v ^ (v >> 8)) & 0x1f0000ff0000ffull;
+    v = (v ^ (v >> 16)) & 0x1f00000000ffffull;
+    v = (v ^ (v >> 32)) & 0x1fffffull;
+    return v;
+}
+
+// cloud holding particle i: largest c with off[c] <= i (off has clouds+1 entries)
+__device__ __forceinline__ int cloud_of(const int64_t *__restrict__ off, int clouds, int64_t i)
+{
+    int lo = 0, hi = clouds;   // off[lo] <= i < off[hi]
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (off[mid] <= i) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+}  // namespace ucp

@@ -1,0 +1,295 @@
+"""GPU parity of the HIP TREE path against the FP64 CPU oracle.
+
+Every comparison is made through the C-ABI on the same seeded inputs:
+keys, permutation, topology, box centres, groups and per-group interaction
+counts bit-exact; moments to 1e-13 of their natural scale; forces to 1e-12
+relative RMS on the FP64 path and 1e-5 on the FP32/FP64 split path.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_0709_3331_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_0709_3331_amd import _lib as L  # noqa: E402
+from paper_0709_3331_amd.tree import TreeSolver  # noqa: E402
+
+TOL_FP64 = 1e-12
+TOL_SPLIT = 1e-5
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def relrms(a, b):
+    den = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / den) if den > 0 else float(np.linalg.norm(a - b))
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def check_topology(ts, t):
+    """GPU build vs oracle tree t: keys, permutation, nodes, centres, groups."""
+    np.testing.assert_array_equal(ts.debug("keys"), t.sorted_keys())
+    np.testing.assert_array_equal(ts.debug("perm").astype(np.int64), t.perm())
+    lv, fi, co, sk = t.nodes()
+    ni = ts.debug("ninfo")
+    assert ni.shape[0] == t.nnodes
+    np.testing.assert_array_equal(ni[:, 0], fi)
+    np.testing.assert_array_equal(ni[:, 1], co)
+    np.testing.assert_array_equal(ni[:, 2], sk)
+    np.testing.assert_array_equal(ni[:, 3] & 255, lv)
+    np.testing.assert_array_equal((ni[:, 3] >> 8) & 1, (sk == np.arange(t.nnodes) + 1).astype(np.int32))
+    geo = ts.debug("ngeo")
+    np.testing.assert_array_equal(geo[:, :3], t.centres())
+    lo, e = t.cube()
+    np.testing.assert_array_equal(geo[:, 3], (2.0 ** (e - lv.astype(np.float64))) ** 2)
+    gf, gc, gn = t.groups()
+    gr = ts.debug("groups")
+    np.testing.assert_array_equal(gr[:, 0], gf)
+    np.testing.assert_array_equal(gr[:, 1], gc)
+    np.testing.assert_array_equal(gr[:, 2], gn)
+
+
+def check_moments(ts, t, x, q):
+    ref = t.moments(x)
+    got = ts.debug("moments")
+    lv = t.nodes()[0]
+    e = t.cube()[1]
+    s = 2.0 ** (e - lv.astype(np.float64))
+    # natural scale of each moment order: sum|q| * (box side)^order
+    qa = np.abs(q).sum()
+    scale = np.stack([np.full_like(s, qa)] + [qa * s] * 3 + [qa * s * s] * 6, axis=1)
+    assert np.all(np.abs(got - ref) <= 1e-13 * scale)
+
+
+CASES = [
+    # id, n, seed, theta, eps, leaf_cap, G, key_bits, halo
+    ("small", 4096, 0, 0.5, 0.01, 8, 64, 63, 0.0),
+    ("ragged", 3002, 1, 0.6, 0.01, 4, 32, 30, 0.0),
+    ("per-particle", 1000, 2, 0.7, 0.02, 1, 1, 63, 0.0),
+    ("halo", 20000, 3, 0.5, 0.005, 8, 64, 63, 0.05),
+    ("tiles", 70002, 4, 0.3, 0.005, 16, 48, 63, 0.0),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_tree_parity(case):
+    name, n, seed, theta, eps, cap, G, kb, halo = case
+    say(f"[parity] case={name} n={n} seed={seed} theta={theta} G={G} leaf_cap={cap} bits={kb}")
+    cl = inputs.gaussian_cloud(n, 1.0, 1e-3, 1e-5, seed, halo_frac=halo)
+    b = 21 if kb == 63 else 10
+    t = oracle.Tree(cl.x, cl.q, theta, eps, b=b, leaf_cap=cap, G=G)
+    ref = t.eval(group_counts=True)
+    x, q = dev(cl.x), dev(cl.q)
+    for prec, tol in ((L.UCP_FP64, TOL_FP64), (L.UCP_SPLIT, TOL_SPLIT)):
+        ts = TreeSolver(n, 1, theta=theta, eps=eps, leaf_cap=cap, group_size=G, key_bits=kb,
+                        precision=prec, list_len=64)
+        f, phi = ts.tree_forces(x, q, want_phi=True)
+        st = ts.stats()
+        say(f"[parity]   prec={prec} nodes={st['nodes']} groups={st['groups']} "
+            f"p2p={st['p2p']} m2p={st['m2p']}")
+        check_topology(ts, t)
+        check_moments(ts, t, cl.x, cl.q)
+        gs = ts.debug("gstat")
+        np.testing.assert_array_equal(gs[:, 0], ref["gm2p"])
+        np.testing.assert_array_equal(gs[:, 1], ref["gp2p"])
+        assert st["p2p"] == ref["p2p"] and st["m2p"] == ref["m2p"]
+        ef = relrms(f.cpu().numpy(), ref["f"])
+        ep = relrms(phi.cpu().numpy(), ref["phi"])
+        say(f"[parity]   force rel RMS vs oracle tree {ef:.3e}, phi {ep:.3e}")
+        assert ef < tol and ep < tol
+        ts.close()
+
+
+def test_theta0_equals_direct():
+    n = 2048
+    say(f"[parity] theta=0 vs direct n={n}")
+    cl = inputs.gaussian_cloud(n, 1.0, 1e-3, 1e-5, 7)
+    fd, phid = oracle.direct(cl.x, cl.q, 0.01)
+    for prec, tol in ((L.UCP_FP64, 1e-12), (L.UCP_SPLIT, 1e-5)):
+        ts = TreeSolver(n, theta=0.0, eps=0.01, precision=prec)
+        f, phi = ts.tree_forces(dev(cl.x), dev(cl.q), want_phi=True)
+        st = ts.stats()
+        assert st["m2p"] == 0 and st["p2p"] == n * n
+        assert relrms(f.cpu().numpy(), fd) < tol
+        assert relrms(phi.cpu().numpy(), phid) < tol
+        ts.close()
+
+
+def test_degenerate_inputs():
+    say("[parity] degenerate: n=0, 1, 2, coincident")
+    ts = TreeSolver(256, theta=0.5, eps=0.01, precision=L.UCP_FP64)
+    x = torch.zeros((0, 3), dtype=torch.float64, device="cuda")
+    f = ts.tree_forces(x, torch.zeros(0, dtype=torch.float64, device="cuda"))
+    assert f.shape == (0, 3)
+    # one particle: no force, zero potential
+    f, phi = ts.tree_forces(dev([[0.3, -0.2, 0.1]]), dev([1.0]), want_phi=True)
+    assert f.abs().max().item() == 0.0 and phi.abs().max().item() == 0.0
+    # two particles: closed form
+    xx = np.array([[0.0, 0.0, 0.0], [0.3, 0.4, 0.0]])
+    f, phi = ts.tree_forces(dev(xx), dev([1.0, -1.0]), want_phi=True)
+    fd, pd = oracle.direct(xx, [1.0, -1.0], 0.01)
+    np.testing.assert_allclose(f.cpu().numpy(), fd, rtol=1e-14, atol=1e-14)
+    np.testing.assert_allclose(phi.cpu().numpy(), pd, rtol=1e-14)
+    # 100 coincident particles (one max-depth leaf chain) + 100 at another point
+    xx = np.zeros((200, 3)); xx[100:] = [0.5, 0.25, -0.125]
+    qq = np.where(np.arange(200) % 2 == 0, 1.0, -1.0)
+    t = oracle.Tree(xx, qq, 0.5, 0.01, leaf_cap=8, G=64)
+    ref = t.eval()
+    f, phi = ts.tree_forces(dev(xx), dev(qq), want_phi=True)
+    check_topology(ts, t)
+    assert relrms(f.cpu().numpy(), ref["f"]) < 1e-12 or np.abs(ref["f"]).max() < 1e-12
+    np.testing.assert_allclose(phi.cpu().numpy(), ref["phi"], rtol=1e-12, atol=1e-9)
+    ts.close()
+
+
+def test_nonfinite_input_is_flagged():
+    say("[parity] non-finite input")
+    ts = TreeSolver(64, theta=0.5, eps=0.01)
+    xx = np.random.default_rng(0).normal(size=(64, 3)); xx[5, 1] = np.nan
+    ts.build(dev(xx), dev(np.ones(64)))
+    with pytest.raises(L.UcpError) as ei:
+        ts.stats()
+    assert ei.value.status == L.UCP_ENONFINITE
+    # the context recovers on the next good build
+    xx[5, 1] = 0.0
+    f = ts.tree_forces(dev(xx), dev(np.ones(64)))
+    ts.stats()
+    assert torch.isfinite(f).all()
+    ts.close()
+
+
+def test_batched_clouds_match_independent_clouds():
+    sizes = [100, 0, 2000, 74, 4096, 2]
+    say(f"[parity] batched clouds sizes={sizes}")
+    parts = [inputs.gaussian_cloud(s, 0.5 + 0.3 * k, 1e-3, 1e-5, 100 + k) if s else None
+             for k, s in enumerate(sizes)]
+    x = np.concatenate([p.x for p in parts if p is not None])
+    q = np.concatenate([p.q for p in parts if p is not None])
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    n = int(off[-1])
+    for prec, tol in ((L.UCP_FP64, TOL_FP64), (L.UCP_SPLIT, TOL_SPLIT)):
+        ts = TreeSolver(n, len(sizes), theta=0.5, eps=0.01, precision=prec, group_size=32)
+        f, phi = ts.tree_forces(dev(x), dev(q), offsets=torch.from_numpy(off).cuda(), want_phi=True)
+        st = ts.stats()
+        f, phi = f.cpu().numpy(), phi.cpu().numpy()
+        for k, p in enumerate(parts):
+            if p is None:
+                continue
+            a, b = off[k], off[k + 1]
+            ref = oracle.tree_forces(p.x, p.q, 0.5, 0.01, G=32)
+            assert relrms(f[a:b], ref["f"]) < tol, k
+            assert relrms(phi[a:b], ref["phi"]) < tol, k
+        cube = ts.debug("cube")
+        for k, p in enumerate(parts):
+            if p is not None:
+                lo, e = oracle.cube(p.x)
+                np.testing.assert_array_equal(cube[k, :3], lo)
+                assert cube[k, 3] == e
+        assert st["clouds"] == len(sizes)
+        ts.close()
+
+
+def test_bad_offsets_are_flagged():
+    say("[parity] bad offsets")
+    ts = TreeSolver(100, 3, theta=0.5, eps=0.01)
+    x = dev(np.random.default_rng(1).normal(size=(100, 3)))
+    q = dev(np.ones(100))
+    ts.build(x, q, offsets=torch.tensor([0, 60, 40, 100], dtype=torch.int64, device="cuda"))
+    with pytest.raises(L.UcpError) as ei:
+        ts.stats()
+    assert ei.value.status == L.UCP_EINVAL
+    ts.close()
+
+
+def test_rebuild_is_bitwise_deterministic():
+    n = 30000
+    say(f"[parity] determinism n={n}")
+    cl = inputs.gaussian_cloud(n, 1.0, 1e-3, 1e-5, 9)
+    ts = TreeSolver(n, theta=0.5, eps=0.005)
+    x, q = dev(cl.x), dev(cl.q)
+    f1, p1 = ts.tree_forces(x, q, want_phi=True)
+    m1 = ts.debug("moments")
+    f2, p2 = ts.tree_forces(x, q, want_phi=True)
+    m2 = ts.debug("moments")
+    assert torch.equal(f1, f2) and torch.equal(p1, p2)
+    np.testing.assert_array_equal(m1, m2)
+    ts.close()
+
+
+def test_verlet_and_energy_match_oracle():
+    n, steps, dt, eps = 1024, 5, 1e-4, 0.01
+    say(f"[parity] verlet n={n} steps={steps}")
+    cl = inputs.gaussian_cloud(n, 1.0, 1e-3, 1e-5, 11)
+    ts = TreeSolver(n, theta=0.5, eps=eps, precision=L.UCP_FP64, group_size=32)
+    x, v, q, m = dev(cl.x), dev(cl.v), dev(cl.q), dev(cl.m)
+    f = ts.tree_forces(x, q)
+    ts.step(x, v, f, q, m, dt, steps)
+    xr, vr, fr = oracle.verlet(cl.x, cl.v, cl.q, cl.m, dt, steps, eps, mode="tree", theta=0.5, G=32)
+    assert np.abs(x.cpu().numpy() - xr).max() < 1e-12
+    assert relrms(v.cpu().numpy(), vr) < 1e-10
+    assert relrms(f.cpu().numpy(), fr) < 1e-10
+    # energies with the tree potential
+    e = ts.energy(x, v, q, m).cpu().numpy()
+    t = oracle.Tree(xr, cl.q, 0.5, eps, G=32)
+    er = oracle.energy(vr, cl.q, cl.m, t.eval()["phi"])
+    np.testing.assert_allclose(e, er, rtol=1e-10)
+    ts.close()
+
+
+def test_graph_replay_matches_eager_steps():
+    n, dt = 4096, 1e-4
+    say(f"[parity] graph replay n={n}")
+    cl = inputs.gaussian_cloud(n, 1.0, 1e-3, 1e-5, 12)
+    ts = TreeSolver(n, theta=0.5, eps=0.01)
+    q, m = dev(cl.q), dev(cl.m)
+    runs = []
+    for mode in ("eager", "graph"):
+        x, v = dev(cl.x), dev(cl.v)
+        f = ts.tree_forces(x, q)
+        if mode == "eager":
+            for _ in range(4):
+                ts.step(x, v, f, q, m, dt, 1)
+                torch.cuda.synchronize()
+        else:
+            ts.step(x, v, f, q, m, dt, 2)          # capture + two replays
+            torch.cuda.synchronize()
+            _ = (x * 1.0).sum().item()             # eager work between replays
+            ts.step(x, v, f, q, m, dt, 2)
+        torch.cuda.synchronize()
+        runs.append((x.clone(), v.clone(), f.clone()))
+    for a, b in zip(runs[0], runs[1]):
+        assert torch.equal(a, b)
+    ts.close()
+
+
+def test_full_size_metric_cloud():
+    c, prm = inputs.metric(0)
+    n = c.n
+    say(f"[parity] metric cloud n={n} theta={prm['theta']}")
+    t = oracle.Tree(c.x, c.q, prm["theta"], prm["eps"], G=64)
+    ts = TreeSolver(n, theta=prm["theta"], eps=prm["eps"])
+    x, q = dev(c.x), dev(c.q)
+    f = ts.tree_forces(x, q)
+    st = ts.stats()
+    say(f"[parity]   nodes={st['nodes']} groups={st['groups']} p2p/N={st['p2p'] / n:.1f} "
+        f"m2p/N={st['m2p'] / n:.1f}")
+    check_topology(ts, t)
+    ref = t.eval(group_counts=True)
+    gs = ts.debug("gstat")
+    np.testing.assert_array_equal(gs[:, 0], ref["gm2p"])
+    np.testing.assert_array_equal(gs[:, 1], ref["gp2p"])
+    ef = relrms(f.cpu().numpy(), ref["f"])
+    say(f"[parity]   split force rel RMS vs oracle tree {ef:.3e}")
+    assert ef < TOL_SPLIT
+    ts.close()
