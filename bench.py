@@ -128,9 +128,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f32-interactions/f64-accumulate" if prec == L.UCP_SPLIT else "f64",
         "data": "synthetic",
-        "config": {"workload": "single two-component Gaussian cloud N=524288 (sigma=1, 5% halo "
-                               "shell 2-3 sigma), theta=%g, eps=0.005, G=%d, leaf_cap=8, "
-                               "63-bit keys, one KDK Verlet step dt=5e-5" % (theta, args.group_size),
+        "config": {"workload": f"single two-component Gaussian cloud N=524288 (sigma=1, 5% halo "
+                               f"shell 2-3 sigma), theta={theta:g}, eps=0.005, G={args.group_size}, "
+                               f"leaf_cap=8, 63-bit keys, one KDK Verlet step dt=5e-5",
                    "n": n, "theta": theta, "precision": args.precision},
         "interactions_per_s": inter / (walk_avg_ms * 1e-3),
         "interactions_per_particle": inter / n,

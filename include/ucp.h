@@ -63,8 +63,8 @@ typedef struct {
     int32_t leaf_cap;      /* a box holding more particles is split (Sec. 3 uses 1); 1..64 */
     int32_t group_size;    /* G: a walk group is a node with <= G particles whose parent
                               has > G (a leaf with > G is cut into chunks of G); 1..64   */
-    int32_t list_len;      /* capacity of each staged interaction list, 16..1024; changes
-                              only the FP64 summation order                              */
+    int32_t list_len;      /* capacity of each LDS interaction list of a walk group,
+                              64..512; changes only the summation order                  */
     int32_t precision;     /* ucp_precision                                              */
     int32_t walk_waves;    /* resident waves per CU for the persistent walk, 0 = auto    */
 } ucp_params;
@@ -88,6 +88,7 @@ typedef struct {
 #define UCP_FLAG_BAD_OFFSETS     4
 #define UCP_FLAG_BAD_CUBE        8
 #define UCP_FLAG_INTERNAL       16   /* inconsistent tree records (a library defect) */
+#define UCP_FLAG_WALK_STACK     32   /* a walk group overflowed its traversal stack     */
 
 /* Default parameters: theta 0.5, eps 0.005, 63-bit keys, leaf_cap 8, G 64,
  * list_len 128, UCP_SPLIT, walk_waves 0.                                     */

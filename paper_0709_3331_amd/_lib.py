@@ -16,7 +16,7 @@ UCP_OK, UCP_EINVAL, UCP_ENOMEM, UCP_EHIP, UCP_ECAPACITY, UCP_ENOTBUILT, UCP_ENON
     0, -1, -2, -3, -4, -5, -6
 UCP_FP64, UCP_SPLIT = 0, 1
 UCP_FLAG_NODE_OVERFLOW, UCP_FLAG_NONFINITE, UCP_FLAG_BAD_OFFSETS, UCP_FLAG_BAD_CUBE = 1, 2, 4, 8
-UCP_FLAG_INTERNAL = 16
+UCP_FLAG_INTERNAL, UCP_FLAG_WALK_STACK = 16, 32
 STATUS_NAMES = {0: "UCP_OK", -1: "UCP_EINVAL", -2: "UCP_ENOMEM", -3: "UCP_EHIP",
                 -4: "UCP_ECAPACITY", -5: "UCP_ENOTBUILT", -6: "UCP_ENONFINITE"}
 

@@ -40,7 +40,7 @@ bool validate(const ucp_params *p, std::string &why)
     if (p->key_bits != 30 && p->key_bits != 63) { why = "key_bits must be 30 or 63"; return false; }
     if (p->leaf_cap < 1 || p->leaf_cap > ucp::kMaxLeafCap) { why = "leaf_cap must be in 1..64"; return false; }
     if (p->group_size < 1 || p->group_size > ucp::kMaxGroup) { why = "group_size must be in 1..64"; return false; }
-    if (p->list_len < 16 || p->list_len > 1024) { why = "list_len must be in 16..1024"; return false; }
+    if (p->list_len < 64 || p->list_len > 512) { why = "list_len must be in 64..512"; return false; }
     if (p->precision != UCP_FP64 && p->precision != UCP_SPLIT) { why = "precision must be UCP_FP64 or UCP_SPLIT"; return false; }
     if (p->walk_waves < 0 || p->walk_waves > 64) { why = "walk_waves must be in 0..64"; return false; }
     return true;
@@ -55,9 +55,9 @@ hipError_t dalloc(T **p, size_t count)
 void free_all(Ctx *c)
 {
     void *ptrs[] = {c->d_off,  c->d_mm,     c->d_cube,  c->d_key[0], c->d_key[1], c->d_val[0],
-                    c->d_val[1], c->d_hist, c->d_histscan, c->d_xq, c->d_xl,  c->d_L,
+                    c->d_val[1], c->d_hist, c->d_histscan, c->d_xq, c->d_L,
                     c->d_leaf, c->d_cnt,    c->d_noff,  c->d_goff,   c->d_gnode,  c->d_scanblk,
-                    c->d_ngeo, c->d_ninfo,  c->d_npar,  c->d_narr,   c->d_mom64,  c->d_mom32,
+                    c->d_ngeo, c->d_ninfo,  c->d_npar,  c->d_mom64,  c->d_mom32,
                     c->d_groups, c->d_gstat, c->d_acc,  c->d_ctr,    c->d_flags,  c->d_epart};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -196,7 +196,6 @@ ucp_status ucp_create(ucp_ctx **out, int64_t n_max, int32_t clouds_max, const uc
     ALLOC(c->d_hist, c->hist_cap);
     ALLOC(c->d_histscan, c->hist_cap);
     ALLOC(c->d_xq, N);
-    ALLOC(c->d_xl, N);
     ALLOC(c->d_L, N + 1);
     ALLOC(c->d_leaf, N + 1);
     ALLOC(c->d_cnt, N + 1);
@@ -207,9 +206,8 @@ ucp_status ucp_create(ucp_ctx **out, int64_t n_max, int32_t clouds_max, const uc
     ALLOC(c->d_ngeo, NC);
     ALLOC(c->d_ninfo, NC);
     ALLOC(c->d_npar, NC);
-    ALLOC(c->d_narr, NC);
-    ALLOC(c->d_mom64, 10 * NC);
-    ALLOC(c->d_mom32, 3 * NC);
+    ALLOC(c->d_mom64, 16 * NC);
+    ALLOC(c->d_mom32, 16 * NC);
     ALLOC(c->d_groups, N);
     ALLOC(c->d_gstat, N);
     ALLOC(c->d_acc, N + 64);   // 64 spare slots for the walk's inactive lanes
@@ -393,6 +391,8 @@ ucp_status ucp_get_stats(ucp_ctx *c, ucp_stats *out, void *stream)
     if (flags & UCP_FLAG_BAD_OFFSETS) return fail(c, UCP_EINVAL, "ucp: inconsistent cloud offsets");
     if (flags & UCP_FLAG_BAD_CUBE) return fail(c, UCP_EINVAL, "ucp: cloud extent out of range");
     if (flags & UCP_FLAG_INTERNAL) return fail(c, UCP_EHIP, "ucp: inconsistent tree records detected on the device");
+    if (flags & UCP_FLAG_WALK_STACK)
+        return fail(c, UCP_ECAPACITY, "ucp: walk traversal stack exceeded (use a smaller group_size)");
     return UCP_OK;
 }
 
@@ -414,14 +414,24 @@ ucp_status ucp_debug_copy(ucp_ctx *c, int32_t which, void *dst, int64_t bytes, v
     case 1: src = c->d_perm; need = 4 * c->n; break;
     case 2: src = c->d_ninfo; need = 16 * (int64_t)nodes; break;
     case 3: src = c->d_ngeo; need = 32 * (int64_t)nodes; break;
-    case 4: src = c->d_mom64; need = 80 * (int64_t)nodes; break;
+    case 4: src = c->d_mom64; need = 80 * (int64_t)nodes; break;   // repacked below
     case 5: src = c->d_groups; need = 16 * (int64_t)groups; break;
     case 6: src = c->d_gstat; need = 8 * (int64_t)groups; break;
-    case 7: src = c->d_cube; need = 64 * (int64_t)c->clouds; break;
+    case 7: src = c->d_cube; need = 32 * (int64_t)c->clouds; break;
     default: return fail(c, UCP_EINVAL, "ucp_debug_copy: unknown array");
     }
     if (bytes < need) return fail(c, UCP_EINVAL, "ucp_debug_copy: buffer too small, need " + std::to_string(need));
     if (need == 0) return UCP_OK;
+    if (which == 4) {
+        // Q, px, py, pz, Sxx, Syy, Szz, Sxy, Sxz, Syz from the 16-double records
+        std::vector<double> rec(16 * (size_t)nodes);
+        HIP_TRY(c, hipMemcpy(rec.data(), c->d_mom64, rec.size() * sizeof(double), hipMemcpyDeviceToHost));
+        double *o = (double *)dst;
+        static const int pick[10] = {3, 4, 5, 6, 8, 9, 10, 11, 12, 13};
+        for (int32_t k = 0; k < nodes; ++k)
+            for (int i = 0; i < 10; ++i) o[10 * (size_t)k + i] = rec[16 * (size_t)k + pick[i]];
+        return UCP_OK;
+    }
     if (which == 7) {
         // lo xyz and e per cloud, from the two double4 records
         std::vector<double4> cube(2 * (size_t)c->clouds);

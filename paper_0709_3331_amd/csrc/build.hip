@@ -86,7 +86,7 @@ __global__ void k_offsets_copy(int64_t *dst, const int64_t *__restrict__ src, in
 // ---------------------------------------------------------------------------
 // 1. enclosing cube
 // ---------------------------------------------------------------------------
-constexpr int kCubeItems = 8;
+constexpr int kCubeItems = 16;    // particles per thread; a block covers 256 * 16
 
 __device__ __forceinline__ double wave_min(double v)
 {
@@ -99,25 +99,26 @@ __device__ __forceinline__ double wave_max(double v)
     return v;
 }
 
+// per block: min/max of its chunk, reduced through LDS, one atomic per
+// component; a chunk that straddles clouds falls back to per-particle atomics
 __global__ __launch_bounds__(256) void k_cube_reduce(const double *__restrict__ x, int64_t n,
                                                     const int64_t *__restrict__ off, int clouds,
                                                     unsigned long long *mm, int32_t *flags)
 {
+    __shared__ double red[6][4];
     if (*flags) return;
-    const int lane = threadIdx.x & 63;
-    const int64_t wave_id = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
-    const int64_t base = wave_id * 64 * kCubeItems;
-    if (base >= n) return;
-    const int64_t last = min(base + (int64_t)64 * kCubeItems, n) - 1;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t base = (int64_t)blockIdx.x * 256 * kCubeItems;
+    const int64_t last = min(base + (int64_t)256 * kCubeItems, n) - 1;
     const int c0 = cloud_of(off, clouds, base), c1 = cloud_of(off, clouds, last);
     bool bad = false;
     if (c0 == c1) {
         double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
         for (int it = 0; it < kCubeItems; ++it) {
-            int64_t i = base + it * 64 + lane;
+            const int64_t i = base + it * 256 + threadIdx.x;
             if (i < n) {
                 for (int d = 0; d < 3; ++d) {
-                    double v = x[3 * i + d];
+                    const double v = x[3 * i + d];
                     bad |= !isfinite(v);
                     mn[d] = fmin(mn[d], v);
                     mx[d] = fmax(mx[d], v);
@@ -128,19 +129,26 @@ __global__ __launch_bounds__(256) void k_cube_reduce(const double *__restrict__ 
             mn[d] = wave_min(mn[d]);
             mx[d] = wave_max(mx[d]);
         }
-        if (lane == 0) {
+        if (lane == 0)
             for (int d = 0; d < 3; ++d) {
-                atomicMin(&mm[6 * c0 + d], f64_ordered(mn[d]));
-                atomicMax(&mm[6 * c0 + 3 + d], f64_ordered(mx[d]));
+                red[d][w] = mn[d];
+                red[3 + d][w] = mx[d];
             }
+        __syncthreads();
+        if (threadIdx.x < 6) {
+            const int d = threadIdx.x;
+            double v = red[d][0];
+            for (int j = 1; j < 4; ++j) v = d < 3 ? fmin(v, red[d][j]) : fmax(v, red[d][j]);
+            if (d < 3) atomicMin(&mm[6 * c0 + d], f64_ordered(v));
+            else atomicMax(&mm[6 * c0 + d], f64_ordered(v));
         }
     } else {
         for (int it = 0; it < kCubeItems; ++it) {
-            int64_t i = base + it * 64 + lane;
+            const int64_t i = base + it * 256 + threadIdx.x;
             if (i < n) {
-                int c = cloud_of(off, clouds, i);
+                const int c = cloud_of(off, clouds, i);
                 for (int d = 0; d < 3; ++d) {
-                    double v = x[3 * i + d];
+                    const double v = x[3 * i + d];
                     bad |= !isfinite(v);
                     atomicMin(&mm[6 * c + d], f64_ordered(v));
                     atomicMax(&mm[6 * c + 3 + d], f64_ordered(v));
@@ -510,8 +518,7 @@ __global__ __launch_bounds__(256) void k_nodes(
     const uint64_t *__restrict__ key, int64_t n, const int64_t *__restrict__ off, int clouds,
     const double4 *__restrict__ cube, int b, const int8_t *__restrict__ Lv,
     const int8_t *__restrict__ Lf, const int32_t *__restrict__ noff, int64_t node_cap,
-    double4 *ngeo, int4 *ninfo, int32_t *npar, int32_t *narr, unsigned long long *ctr,
-    int32_t *flags)
+    double4 *ngeo, int4 *ninfo, int32_t *npar, unsigned long long *ctr, int32_t *flags)
 {
     if (*flags) return;
     const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -550,47 +557,50 @@ __global__ __launch_bounds__(256) void k_nodes(
         ngeo[k] = make_double4(cx, cy, cz, ldexp(1.0, 2 * (e - l)));
         ninfo[k] = make_int4((int)p, (int)(t - p), noff[t], l | (l == lf ? 256 : 0));
         npar[k] = parent;
-        narr[k] = 0;
     }
     atomicMax(&ctr[CTR_MAXLEVEL], (unsigned long long)lf);
 }
 
 // ---------------------------------------------------------------------------
-// 6. moments about the box centre, bottom-up
+// 6. moments about the box centre, one level at a time from the deepest up:
+//    the node (p, l) exists iff L(p) < l <= leaf(p); a leaf sums its
+//    particles, an internal node sums its children (one level deeper, written
+//    by the previous launch) in octant order with the exact shift of origin.
+//    Record per node, FP64 (16 doubles): cx cy cz Q px py pz trS Sxx Syy Szz
+//    Sxy Sxz Syz 0 0; FP32 copy (16 floats): 0 0 0 Q px py pz trS Sxx ... 0 0.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void store_moments(double *mom64, float4 *mom32, int k, const double *m)
+__device__ __forceinline__ void store_moments(double *mom64, float *mom32, int k, const double4 &g,
+                                              const double *m)
 {
-    for (int i = 0; i < 10; ++i) mom64[10 * (int64_t)k + i] = m[i];
-    mom32[3 * (int64_t)k + 0] = make_float4((float)m[0], (float)m[1], (float)m[2], (float)m[3]);
-    mom32[3 * (int64_t)k + 1] =
-        make_float4((float)m[4], (float)m[5], (float)m[6], (float)(m[4] + m[5] + m[6]));
-    mom32[3 * (int64_t)k + 2] = make_float4((float)m[7], (float)m[8], (float)m[9], 0.0f);
+    // m: Q, px, py, pz, Sxx, Syy, Szz, Sxy, Sxz, Syz
+    const double trS = m[4] + m[5] + m[6];
+    const double rec[16] = {g.x, g.y, g.z, m[0], m[1], m[2], m[3], trS,
+                            m[4], m[5], m[6], m[7], m[8], m[9], 0.0, 0.0};
+    double2 *d2 = (double2 *)(mom64 + 16 * (int64_t)k);
+    for (int i = 0; i < 8; ++i) d2[i] = make_double2(rec[2 * i], rec[2 * i + 1]);
+    float4 *f4 = (float4 *)(mom32 + 16 * (int64_t)k);
+    f4[0] = make_float4(0.f, 0.f, 0.f, (float)m[0]);
+    f4[1] = make_float4((float)m[1], (float)m[2], (float)m[3], (float)trS);
+    f4[2] = make_float4((float)m[4], (float)m[5], (float)m[6], (float)m[7]);
+    f4[3] = make_float4((float)m[8], (float)m[9], 0.f, 0.f);
 }
 
-__device__ __forceinline__ double load_agent(const double *p)
-{
-    unsigned long long u = __hip_atomic_load((const unsigned long long *)p, __ATOMIC_RELAXED,
-                                             __HIP_MEMORY_SCOPE_AGENT);
-    return __longlong_as_double((long long)u);
-}
-
-__global__ __launch_bounds__(256) void k_moments(
-    const double4 *__restrict__ xq, int64_t n, const int8_t *__restrict__ Lv,
+__global__ __launch_bounds__(256) void k_moments_level(
+    int level, const double4 *__restrict__ xq, int64_t n, const int8_t *__restrict__ Lv,
     const int8_t *__restrict__ Lf, const int32_t *__restrict__ noff,
-    const double4 *__restrict__ ngeo, const int4 *__restrict__ ninfo,
-    const int32_t *__restrict__ npar, int32_t *narr, double *mom64, float4 *mom32, float4 *xl,
+    const double4 *__restrict__ ngeo, const int4 *__restrict__ ninfo, double *mom64, float *mom32,
     const int32_t *flags)
 {
     if (*flags) return;
     const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (p >= n) return;
     const int Lp = Lv[p], lf = Lf[p];
-    if (lf <= Lp) return;
-    int k = noff[p] + (lf - Lp - 1);   // the leaf starting at p
-    {
-        const double4 g = ngeo[k];
-        const int4 inf = ninfo[k];
-        double m[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (!(Lp < level && level <= lf)) return;
+    const int k = noff[p] + (level - Lp - 1);
+    const double4 g = ngeo[k];
+    const int4 inf = ninfo[k];
+    double m[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (level == lf) {
         for (int j = inf.x; j < inf.x + inf.y; ++j) {
             const double4 a = xq[j];
             const double r0 = a.x - g.x, r1 = a.y - g.y, r2 = a.z - g.z, qq = a.w;
@@ -604,49 +614,32 @@ __global__ __launch_bounds__(256) void k_moments(
             m[7] += qq * r0 * r1;
             m[8] += qq * r0 * r2;
             m[9] += qq * r1 * r2;
-            xl[j] = make_float4((float)r0, (float)r1, (float)r2, (float)qq);
         }
-        store_moments(mom64, mom32, k, m);
-    }
-    int cnt = ninfo[k].y;
-    const int nn = noff[n];
-    // a node has at most 22 ancestors; the bound makes the climb finite whatever
-    // the records hold
-    for (int depth = 0; depth < 64; ++depth) {
-        const int par = npar[k];
-        if (par < 0) break;
-        if (par >= k || par >= nn) { atomicOr((int32_t *)flags, UCP_FLAG_INTERNAL); break; }
-        const int old = __hip_atomic_fetch_add(&narr[par], cnt, __ATOMIC_ACQ_REL,
-                                               __HIP_MEMORY_SCOPE_AGENT);
-        const int4 pin = ninfo[par];
-        if (old + cnt != pin.y) break;   // another child is still missing
-        const double4 pg = ngeo[par];
-        const double qd = 0.25 * sqrt(pg.w);   // |child centre - parent centre| per axis
-        double M[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-        const int chend = min(pin.z, nn);
-        for (int ch = par + 1; ch < chend; ch = max(ninfo[ch].z, ch + 1)) {
+    } else {
+        const double qd = 0.25 * sqrt(g.w);   // |child centre - parent centre| per axis
+        const int nn = noff[n];
+        const int chend = min(inf.z, nn);
+        for (int ch = k + 1; ch < chend; ch = max(ninfo[ch].z, ch + 1)) {
             const double4 cg = ngeo[ch];
-            const double d0 = cg.x > pg.x ? qd : -qd;
-            const double d1 = cg.y > pg.y ? qd : -qd;
-            const double d2 = cg.z > pg.z ? qd : -qd;
-            double c[10];
-            for (int i = 0; i < 10; ++i) c[i] = load_agent(mom64 + 10 * (int64_t)ch + i);
+            const double d0 = cg.x > g.x ? qd : -qd;
+            const double d1 = cg.y > g.y ? qd : -qd;
+            const double d2 = cg.z > g.z ? qd : -qd;
+            const double *c = mom64 + 16 * (int64_t)ch;
+            const double Q = c[3], p0 = c[4], p1 = c[5], p2 = c[6];
             // shift of origin by d: p' = p + Q d, S' = S + p d^T + d p^T + Q d d^T
-            M[0] += c[0];
-            M[1] += c[1] + c[0] * d0;
-            M[2] += c[2] + c[0] * d1;
-            M[3] += c[3] + c[0] * d2;
-            M[4] += c[4] + 2.0 * c[1] * d0 + c[0] * d0 * d0;
-            M[5] += c[5] + 2.0 * c[2] * d1 + c[0] * d1 * d1;
-            M[6] += c[6] + 2.0 * c[3] * d2 + c[0] * d2 * d2;
-            M[7] += c[7] + c[1] * d1 + d0 * c[2] + c[0] * d0 * d1;
-            M[8] += c[8] + c[1] * d2 + d0 * c[3] + c[0] * d0 * d2;
-            M[9] += c[9] + c[2] * d2 + d1 * c[3] + c[0] * d1 * d2;
+            m[0] += Q;
+            m[1] += p0 + Q * d0;
+            m[2] += p1 + Q * d1;
+            m[3] += p2 + Q * d2;
+            m[4] += c[8] + 2.0 * p0 * d0 + Q * d0 * d0;
+            m[5] += c[9] + 2.0 * p1 * d1 + Q * d1 * d1;
+            m[6] += c[10] + 2.0 * p2 * d2 + Q * d2 * d2;
+            m[7] += c[11] + p0 * d1 + d0 * p1 + Q * d0 * d1;
+            m[8] += c[12] + p0 * d2 + d0 * p2 + Q * d0 * d2;
+            m[9] += c[13] + p1 * d2 + d1 * p2 + Q * d1 * d2;
         }
-        store_moments(mom64, mom32, par, M);
-        k = par;
-        cnt = pin.y;
     }
+    store_moments(mom64, mom32, k, g, m);
 }
 
 // ---------------------------------------------------------------------------
@@ -735,8 +728,7 @@ void launch_build(Ctx *c, const double *x, const double *q, const int64_t *offse
         hipLaunchKernelGGL(k_offsets_single, dim3(1), dim3(1), 0, s, c->d_off, n);
 
     // 1. cube
-    const int64_t waves = (n + 64 * kCubeItems - 1) / (64 * kCubeItems);
-    hipLaunchKernelGGL(k_cube_reduce, grid_for(waves * 64, 256), dim3(256), 0, s, x, n,
+    hipLaunchKernelGGL(k_cube_reduce, grid_for(n, 256 * kCubeItems), dim3(256), 0, s, x, n,
                        (const int64_t *)c->d_off, clouds, c->d_mm, c->d_flags);
     hipLaunchKernelGGL(k_cube_finish, grid_for(clouds, 64), dim3(64), 0, s,
                        (const unsigned long long *)c->d_mm, (const int64_t *)c->d_off, clouds, b,
@@ -799,13 +791,14 @@ void launch_build(Ctx *c, const double *x, const double *q, const int64_t *offse
                        (const int64_t *)c->d_off, clouds, (const double4 *)c->d_cube, b,
                        (const int8_t *)c->d_L, (const int8_t *)c->d_leaf,
                        (const int32_t *)c->d_noff, c->node_cap, c->d_ngeo, c->d_ninfo, c->d_npar,
-                       c->d_narr, c->d_ctr, c->d_flags);
-    // 6. moments
-    hipLaunchKernelGGL(k_moments, grid_for(n, 256), dim3(256), 0, s, (const double4 *)c->d_xq, n,
-                       (const int8_t *)c->d_L, (const int8_t *)c->d_leaf,
-                       (const int32_t *)c->d_noff, (const double4 *)c->d_ngeo,
-                       (const int4 *)c->d_ninfo, (const int32_t *)c->d_npar, c->d_narr,
-                       c->d_mom64, c->d_mom32, c->d_xl, (const int32_t *)c->d_flags);
+                       c->d_ctr, c->d_flags);
+    // 6. moments, deepest level first
+    for (int l = b; l >= 0; --l)
+        hipLaunchKernelGGL(k_moments_level, grid_for(n, 256), dim3(256), 0, s, l,
+                           (const double4 *)c->d_xq, n, (const int8_t *)c->d_L,
+                           (const int8_t *)c->d_leaf, (const int32_t *)c->d_noff,
+                           (const double4 *)c->d_ngeo, (const int4 *)c->d_ninfo, c->d_mom64,
+                           c->d_mom32, (const int32_t *)c->d_flags);
     // 7. groups
     hipLaunchKernelGGL(k_group_count, grid_for(n + 1, 256), dim3(256), 0, s, n,
                        (const int8_t *)c->d_L, (const int8_t *)c->d_leaf,

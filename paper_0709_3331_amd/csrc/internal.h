@@ -77,7 +77,6 @@ struct Ctx {
     uint32_t *d_perm = nullptr;             // sorted position -> caller index
     // sorted particles
     double4 *d_xq = nullptr;                // [n_max] x, y, z, q  (sorted order)
-    float4 *d_xl = nullptr;                 // [n_max] fp32(x - leaf centre), q
     // per position
     int8_t *d_L = nullptr;                  // [n_max + 1] common-prefix level with predecessor
     int8_t *d_leaf = nullptr;               // [n_max + 1] level of the leaf holding the position
@@ -90,9 +89,8 @@ struct Ctx {
     double4 *d_ngeo = nullptr;              // [node_cap] centre xyz, side^2
     int4 *d_ninfo = nullptr;                // [node_cap] first, count, skip, level | 256*leaf
     int32_t *d_npar = nullptr;              // [node_cap] parent (-1 for a root)
-    int32_t *d_narr = nullptr;              // [node_cap] arrival counter of the moment pass
-    double *d_mom64 = nullptr;              // [node_cap][10]
-    float4 *d_mom32 = nullptr;              // [node_cap][3]
+    double *d_mom64 = nullptr;              // [node_cap][16] cx cy cz Q p[3] trS S[6] 0 0
+    float *d_mom32 = nullptr;               // [node_cap][16] 0 0 0 Q p[3] trS S[6] 0 0
     // groups
     int4 *d_groups = nullptr;               // [n_max] first, count, node, root
     int2 *d_gstat = nullptr;                // [n_max] accepted boxes, P2P sources

@@ -1,44 +1,55 @@
 // walk.hip -- the group tree walk of Sec. 3 on gfx950.
 //
-// One wavefront per walk group, one target particle per lane.  The wave walks
-// the preorder node array of its cloud without a stack (first child = k + 1,
-// next sibling / end of subtree = skip link).  At each node every lane
-// evaluates the opening test of Eq. (5) with delta = 0 in FP64,
+// One wavefront per walk group.  The wave walks the preorder node array of
+// its cloud without a stack (first child = k + 1, next sibling / end of
+// subtree = skip link).  At each node every target evaluates the opening test
+// of Eq. (5) with delta = 0 in FP64,
 //     accept  iff  s^2 < theta^2 d^2,   d^2 = fma(dz,dz, fma(dy,dy, dx*dx)),
-// and the wave opens the node iff any active lane fails (wave ballot).
-// Accepted boxes go to an LDS-staged M2P list, opened leaves to an LDS-staged
-// P2P list; a full list is evaluated (flushed) for all lanes at once.
+// and the wave opens the node iff any target fails (wave ballot).  Accepted
+// boxes are staged into an LDS M2P list, the particles of opened leaves into
+// an LDS P2P list; a full list is evaluated (flushed) at once.
+//
+// Lane layout: a group of c <= 64 targets gives each target lpt = floor(64/c)
+// lanes.  The lanes of one target take the staged entries round-robin and
+// their partial sums are added in fixed lane order at the end of the group
+// (deterministic), so small groups still keep most lanes busy.
 //
 // Precision (template PREC):
-//   UCP_FP64  -- everything in FP64 (r = x_i - c and x_i - x_j in FP64).
-//   UCP_SPLIT -- the offset of the target from a box centre is formed in FP64
-//                and rounded once to FP32; source particles are stored as
-//                FP32 offsets from their leaf centre, and the target offset
-//                from the same leaf centre is formed in FP64 per leaf; the
-//                interaction arithmetic is FP32 (FP32 moments rounded from the
-//                FP64 ones), partial sums per flushed chunk are FP32 and are
-//                accumulated into FP64 per-lane accumulators.
+//   UCP_FP64  -- staged entries are FP64 (absolute box centres and positions),
+//                the interaction arithmetic is FP64 (r = x_i - c, x_i - x_j).
+//   UCP_SPLIT -- staged entries are FP32 offsets from the group box centre
+//                c_g, formed in FP64 and rounded once (box centre - c_g,
+//                source - c_g), with FP32 moments rounded from the FP64 ones;
+//                the target offset x_i - c_g is also formed in FP64 and
+//                rounded once.  The interaction arithmetic is FP32; partial
+//                sums of each flushed list are FP32 and are accumulated into
+//                FP64 per-lane accumulators.
+//
+// No divergent branch encloses a wave-level operation or the loop heads of
+// the persistent loop: list staging writes one value per lane, idle lanes
+// write to private spare slots.
+#include <type_traits>
+
 #include "internal.h"
 
 namespace ucp {
 
 struct WalkArgs {
     const double4 *xq;
-    const float4 *xl;
     const double4 *ngeo;
     const int4 *ninfo;
     const double *mom64;
-    const float4 *mom32;
+    const float *mom32;
     const int4 *groups;
     const int32_t *ngroups;
     const int32_t *nnodes;
-    int32_t *flags_rw;
-    int64_t n;
-    int64_t n_spare;    // first of 64 spare accumulator slots (capacity n_max)
     int2 *gstat;
     double4 *acc;
     unsigned long long *ctr;
     const int32_t *flags;
+    int32_t *flags_rw;
+    int64_t n;
+    int64_t n_spare;    // first of 64 spare accumulator slots (capacity n_max)
     double th2;
     double eps2;
     float eps2f;
@@ -47,8 +58,62 @@ struct WalkArgs {
 
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+constexpr int kStackCap = 256;   // traversal stack entries per wave
+
+// LDS layout of one wave (bytes): traversal stack (node, end of its sibling
+// range), member positions (FP64), M2P and P2P index lists, a staging area
+// (64 M2P records of 16 values, or 64 P2P particles, or the final per-lane
+// partial sums) and two 64-int tables for expanding leaves into particles.
+template <int PREC>
+__host__ __device__ constexpr int walk_stage_bytes()
+{
+    return PREC == UCP_SPLIT ? 64 * 16 * 4 : 64 * 16 * 8;
+}
+template <int PREC>
+__host__ __device__ constexpr int walk_wave_bytes(int L)
+{
+    return kStackCap * 8 + 64 * 3 * 8 + 2 * 4 * L + walk_stage_bytes<PREC>() + 2 * 64 * 4;
+}
+
+__device__ __forceinline__ int lanes_before(unsigned long long mask, int lane)
+{
+    return __popcll(mask & (lane == 0 ? 0ull : (~0ull >> (64 - lane))));
+}
+
+__device__ __forceinline__ double wave_fmin(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ double wave_fmax(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ int wave_isum(int v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+__device__ __forceinline__ int wave_incl_scan_i(int v, int lane)
+{
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(v, o);
+        v += lane >= o ? t : 0;
+    }
+    return v;
+}
+
 // ---------------------------------------------------------------------------
-// evaluation of one accepted box (C-2.7 expansion of the softened kernel)
+// evaluation of one accepted box: second-order expansion of the softened
+// kernel about the box centre (r = target - centre, h^2 = |r|^2 + eps^2)
 //   phi = Q/h + (p.r)/h^3 + (3 r.S.r/h^5 - trS/h^3)/2
 //   E   = [Q/h^3 + 3(p.r)/h^5 + 7.5 r.S.r/h^7 - 1.5 trS/h^5] r - p/h^3 - 3 S r/h^5
 // ---------------------------------------------------------------------------
@@ -70,163 +135,270 @@ __device__ __forceinline__ void m2p_eval(T rx, T ry, T rz, T Q, T px, T py, T pz
     const T Srz = Sxz * rx + Syz * ry + Szz * rz;
     const T rSr = rx * Srx + ry * Sry + rz * Srz;
     const T pr = px * rx + py * ry + pz * rz;
-    const T alpha = Q * ih3 + (T)3 * pr * ih5 + (T)7.5 * rSr * ih7 - (T)1.5 * trS * ih5;
+    const T alpha = Q * ih3 + ((T)3 * pr - (T)1.5 * trS) * ih5 + (T)7.5 * rSr * ih7;
     const T b3 = (T)3 * ih5;
-    ex += alpha * rx - px * ih3 - b3 * Srx;
-    ey += alpha * ry - py * ih3 - b3 * Sry;
-    ez += alpha * rz - pz * ih3 - b3 * Srz;
+    ex += alpha * rx - (px * ih3 + b3 * Srx);
+    ey += alpha * ry - (py * ih3 + b3 * Sry);
+    ez += alpha * rz - (pz * ih3 + b3 * Srz);
     if (PHI) ph += Q * ih + pr * ih3 + (T)0.5 * ((T)3 * rSr * ih5 - trS * ih3);
 }
 
-template <int PREC, bool PHI>
+// Evaluate the M2P and P2P index lists of a group.  Entries are staged into
+// LDS 64 at a time (one per lane), then the lpt lanes of each target take the
+// staged entries round-robin.
+template <int PREC, bool PHI, typename T>
 __device__ __forceinline__ void flush_lists(const WalkArgs &a, const int *ml, int nm, const int *pl,
-                                            int np, const double4 &xi, int i, double &E0,
-                                            double &E1, double &E2, double &PH)
+                                            int np, T *stage, int *pfx, int *lfirst, int lane,
+                                            int sub, int lpt, const double4 &cg, T tx, T ty, T tz,
+                                            int i, double &E0, double &E1, double &E2, double &PH)
 {
-    // the list entries were written by lane 0; make them visible to the wave
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    if constexpr (PREC == UCP_SPLIT) {
-        float ex = 0.f, ey = 0.f, ez = 0.f, ph = 0.f;
-        for (int e = 0; e < nm; ++e) {
-            const int k = uni(ml[e]);
-            const double4 g = a.ngeo[k];
-            const float4 m0 = a.mom32[3 * k], m1 = a.mom32[3 * k + 1], m2 = a.mom32[3 * k + 2];
-            const float rx = (float)(xi.x - g.x), ry = (float)(xi.y - g.y), rz = (float)(xi.z - g.z);
-            m2p_eval<float, PHI>(rx, ry, rz, m0.x, m0.y, m0.z, m0.w, m1.x, m1.y, m1.z, m2.x, m2.y,
-                                 m2.z, m1.w, a.eps2f, ex, ey, ez, ph);
-            if ((e & 7) == 7) {
-                E0 += ex; E1 += ey; E2 += ez; PH += ph;
-                ex = ey = ez = ph = 0.f;
+    const T eps2 = PREC == UCP_SPLIT ? (T)a.eps2f : (T)a.eps2;
+    wave_sync();   // the lists were written by other lanes
+    for (int base = 0; base < nm; base += 64) {
+        const int cnt = min(64, nm - base);
+        {
+            const int k = ml[base + (lane < cnt ? lane : cnt - 1)];
+            T *rec = stage + 16 * lane;
+            if constexpr (PREC == UCP_SPLIT) {
+                const float4 *m4 = (const float4 *)(a.mom32 + 16 * (int64_t)k);
+                const double4 g = a.ngeo[k];
+                float4 r0 = m4[0];
+                r0.x = (float)(g.x - cg.x);
+                r0.y = (float)(g.y - cg.y);
+                r0.z = (float)(g.z - cg.z);
+                float4 *d4 = (float4 *)rec;
+                d4[0] = r0;
+                d4[1] = m4[1];
+                d4[2] = m4[2];
+                d4[3] = m4[3];
+            } else {
+                const double2 *m2 = (const double2 *)(a.mom64 + 16 * (int64_t)k);
+                double2 *d2 = (double2 *)rec;
+                for (int q = 0; q < 7; ++q) d2[q] = m2[q];
             }
         }
-        E0 += ex; E1 += ey; E2 += ez; PH += ph;
-        for (int e = 0; e < np; ++e) {
-            const int k = uni(pl[e]);
-            const double4 g = a.ngeo[k];
-            const int4 inf = a.ninfo[k];
-            const float tx = (float)(xi.x - g.x), ty = (float)(xi.y - g.y), tz = (float)(xi.z - g.z);
-            float sx = 0.f, sy = 0.f, sz = 0.f, sp = 0.f;
-            const int j0 = uni(inf.x), j1 = uni(inf.x + inf.y);
-            for (int j = j0; j < j1; ++j) {
-                const float4 s = a.xl[j];
-                const float rx = tx - s.x, ry = ty - s.y, rz = tz - s.z;
-                const float h2 = rx * rx + ry * ry + rz * rz + a.eps2f;
-                const float ih = __builtin_amdgcn_rsqf(h2);
-                const float w = s.w * ih * ih * ih;
-                sx += w * rx;
-                sy += w * ry;
-                sz += w * rz;
-                if (PHI) sp += (j != i) ? s.w * ih : 0.f;
-            }
-            E0 += sx; E1 += sy; E2 += sz; PH += sp;
+        wave_sync();
+        T ex = 0, ey = 0, ez = 0, ph = 0;
+        for (int e = sub; e < cnt; e += lpt) {
+            const T *r = stage + 16 * e;
+            m2p_eval<T, PHI>(tx - r[0], ty - r[1], tz - r[2], r[3], r[4], r[5], r[6], r[8], r[9],
+                             r[10], r[11], r[12], r[13], r[7], eps2, ex, ey, ez, ph);
         }
-    } else {
-        for (int e = 0; e < nm; ++e) {
-            const int k = uni(ml[e]);
-            const double4 g = a.ngeo[k];
-            const double *m = a.mom64 + 10 * (int64_t)k;
-            const double rx = xi.x - g.x, ry = xi.y - g.y, rz = xi.z - g.z;
-            m2p_eval<double, PHI>(rx, ry, rz, m[0], m[1], m[2], m[3], m[4], m[5], m[6], m[7], m[8],
-                                  m[9], m[4] + m[5] + m[6], a.eps2, E0, E1, E2, PH);
-        }
-        for (int e = 0; e < np; ++e) {
-            const int k = uni(pl[e]);
-            const int4 inf = a.ninfo[k];
-            const int j0 = uni(inf.x), j1 = uni(inf.x + inf.y);
-            for (int j = j0; j < j1; ++j) {
-                const double4 s = a.xq[j];
-                const double rx = xi.x - s.x, ry = xi.y - s.y, rz = xi.z - s.z;
-                const double h2 = rx * rx + ry * ry + rz * rz + a.eps2;
-                const double ih = 1.0 / sqrt(h2);
-                const double w = s.w * ih * ih * ih;
-                E0 += w * rx;
-                E1 += w * ry;
-                E2 += w * rz;
-                if (PHI) PH += (j != i) ? s.w * ih : 0.0;
+        E0 += (double)ex;
+        E1 += (double)ey;
+        E2 += (double)ez;
+        PH += (double)ph;
+        wave_sync();
+    }
+    int *sidx = (int *)(stage + 4 * 64);
+    for (int base = 0; base < np; base += 64) {
+        const int cntL = min(64, np - base);
+        const int k = pl[base + (lane < cntL ? lane : cntL - 1)];
+        const int4 inf = a.ninfo[k];
+        const int cl = lane < cntL ? inf.y : 0;
+        const int incl = wave_incl_scan_i(cl, lane);
+        const int total = uni(__shfl(incl, 63));
+        pfx[lane] = incl;
+        lfirst[lane] = inf.x - (incl - cl);   // particle j = lfirst[l] + (global offset)
+        wave_sync();
+        for (int pb = 0; pb < total; pb += 64) {
+            const int ncur = min(64, total - pb);
+            const int P = pb + (lane < ncur ? lane : ncur - 1);
+            // leaf holding concatenated particle P: first l with pfx[l] > P
+            int lo = -1, hi = cntL - 1;
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (pfx[mid] > P) hi = mid;
+                else lo = mid;
             }
+            const int j = lfirst[hi] + P;
+            const double4 s = a.xq[j];
+            T *st = stage + 4 * lane;
+            if constexpr (PREC == UCP_SPLIT) {
+                *(float4 *)st = make_float4((float)(s.x - cg.x), (float)(s.y - cg.y),
+                                            (float)(s.z - cg.z), (float)s.w);
+            } else {
+                *(double4 *)st = s;
+            }
+            sidx[lane] = j;
+            wave_sync();
+            T ex = 0, ey = 0, ez = 0, ph = 0;
+            for (int e = sub; e < ncur; e += lpt) {
+                const T *q4 = stage + 4 * e;
+                const T rx = tx - q4[0], ry = ty - q4[1], rz = tz - q4[2];
+                const T h2 = rx * rx + ry * ry + rz * rz + eps2;
+                T ih;
+                if constexpr (sizeof(T) == 4) ih = __builtin_amdgcn_rsqf(h2);
+                else ih = 1.0 / sqrt(h2);
+                const T w = q4[3] * ih * ih * ih;
+                ex += w * rx;
+                ey += w * ry;
+                ez += w * rz;
+                if (PHI) ph += (sidx[e] != i) ? q4[3] * ih : (T)0;
+            }
+            E0 += (double)ex;
+            E1 += (double)ey;
+            E2 += (double)ez;
+            PH += (double)ph;
+            wave_sync();
         }
     }
-    // the lists are rewritten by lane 0 after this point
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 template <int PREC, bool PHI>
 __global__ __launch_bounds__(256) void k_walk(WalkArgs a)
 {
-    HIP_DYNAMIC_SHARED(int, lds)
+    using T = typename std::conditional<PREC == UCP_SPLIT, float, double>::type;
+    HIP_DYNAMIC_SHARED(char, lds_raw)
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    int *ml = lds + wave * 2 * a.L;
-    int *pl = ml + a.L;
+    const int L = a.L;
+    char *wbase = lds_raw + (size_t)wave * walk_wave_bytes<PREC>(L);
+    int2 *stk = (int2 *)wbase;                                   // [kStackCap]
+    double *tpos = (double *)(wbase + kStackCap * 8);             // [64][3]
+    int *ml = (int *)(tpos + 64 * 3);                             // [L]
+    int *pl = ml + L;                                             // [L]
+    T *stage = (T *)(pl + L);                                     // [64][16]
+    int *pfx = (int *)((char *)stage + walk_stage_bytes<PREC>()); // [64]
+    int *lfirst = pfx + 64;                                       // [64]
     if (*a.flags) return;
     // every loop below is bounded by these totals, whatever the records hold
     const int ng = min(*a.ngroups, (int)a.n);
     const int nn = *a.nnodes;
-    // No divergent branch anywhere in this loop: a divergent "if (lane == 0)"
-    // around the queue atomic lets the compiler send only lane 0 back through
-    // the atomic while the other lanes re-enter the body with a stale index.
-    // Every lane executes the atomic; only lane 0 adds 1, so lane 0 receives
-    // the queue value before its own increment.
+    // No divergent branch anywhere around the queue: every lane executes the
+    // atomic, only lane 0 adds 1, so lane 0 receives the value before its own
+    // increment.
     for (;;) {
-        const unsigned long long old =
-            atomicAdd(&a.ctr[CTR_QUEUE], lane == 0 ? 1ull : 0ull);
+        const unsigned long long old = atomicAdd(&a.ctr[CTR_QUEUE], lane == 0 ? 1ull : 0ull);
         const int g = uni((int)old);
         if (g >= ng) break;
         const int4 gr = a.groups[g];
-        if (uni(gr.x) < 0 || uni(gr.y) < 1 || uni(gr.y) > kMaxGroup || (int64_t)uni(gr.x) + uni(gr.y) > a.n ||
-            uni(gr.w) < 0 || uni(gr.w) >= nn) {
-            atomicOr(a.flags_rw, UCP_FLAG_INTERNAL);
+        const int gfirst = uni(gr.x), c = uni(gr.y), gnode = uni(gr.z), root = uni(gr.w);
+        if (gfirst < 0 || c < 1 || c > kMaxGroup || (int64_t)gfirst + c > a.n || gnode < 0 ||
+            gnode >= nn || root < 0 || root >= nn) {
+            atomicOr(a.flags_rw, lane == 0 ? UCP_FLAG_INTERNAL : 0);
             continue;
         }
-        const int gcount = uni(gr.y);
-        const bool act = lane < gcount;
-        const int i = gr.x + (act ? lane : 0);
+        const int lpt = 64 / c;
+        const int t = lane / lpt, sub = lane - t * lpt;
+        const bool act = t < c;
+        const int i = gfirst + (act ? t : 0);
         const double4 xi = a.xq[i];
+        const double4 cg = a.ngeo[gnode];
+        T tx, ty, tz;
+        if constexpr (PREC == UCP_SPLIT) {
+            tx = (float)(xi.x - cg.x);
+            ty = (float)(xi.y - cg.y);
+            tz = (float)(xi.z - cg.z);
+        } else {
+            tx = xi.x;
+            ty = xi.y;
+            tz = xi.z;
+        }
+        // member positions for the exact opening test, and their bounding box
+        tpos[3 * t + 0] = xi.x;   // lanes of one target store the same values
+        tpos[3 * t + 1] = xi.y;
+        tpos[3 * t + 2] = xi.z;
+        const double bminx = wave_fmin(act ? xi.x : INFINITY), bmaxx = wave_fmax(act ? xi.x : -INFINITY);
+        const double bminy = wave_fmin(act ? xi.y : INFINITY), bmaxy = wave_fmax(act ? xi.y : -INFINITY);
+        const double bminz = wave_fmin(act ? xi.z : INFINITY), bmaxz = wave_fmax(act ? xi.z : -INFINITY);
+        stk[0] = make_int2(root, min(a.ninfo[root].z, nn));
+        int sp = 1;
+        wave_sync();
         double E0 = 0.0, E1 = 0.0, E2 = 0.0, PH = 0.0;
-        int nm = 0, np = 0, tot_m = 0, tot_src = 0;
-        int k = uni(gr.w);
-        const int kend = min(uni(a.ninfo[k].z), nn);
-        while (k < kend) {
-            const double4 geo = a.ngeo[k];
-            const int4 inf = a.ninfo[k];
-            const double dx = xi.x - geo.x, dy = xi.y - geo.y, dz = xi.z - geo.z;
-            const double d2 = fma(dz, dz, fma(dy, dy, dx * dx));
-            const bool fail = act && !(geo.w < a.th2 * d2);
-            // the skip link always moves forward (k + 1 at least)
-            const int skip = max(uni(inf.z), k + 1);
-            if (__ballot(fail) == 0ull) {
-                ml[nm] = k;   // every lane stores the same value
-                ++nm;
-                k = skip;
-            } else if (inf.w & 256) {
-                if (uni(inf.x) < 0 || (int64_t)uni(inf.x) + uni(inf.y) > a.n || uni(inf.y) < 0) {
-                    atomicOr(a.flags_rw, UCP_FLAG_INTERNAL);
-                } else {
-                    pl[np] = k;
-                    ++np;
-                    tot_src += uni(inf.y);
-                }
-                k = skip;
-            } else {
-                ++k;
-            }
-            if (nm == a.L || np == a.L) {
-                flush_lists<PREC, PHI>(a, ml, nm, pl, np, xi, i, E0, E1, E2, PH);
-                tot_m += nm;
+        int nm = 0, np = 0, my_m = 0, my_src = 0;
+        bool overflow = false;
+        const double th2 = a.th2;
+        while (sp > 0) {
+            if (nm > L - 64 || np > L - 64) {
+                flush_lists<PREC, PHI>(a, ml, nm, pl, np, stage, pfx, lfirst, lane, sub, lpt, cg,
+                                       tx, ty, tz, i, E0, E1, E2, PH);
                 nm = np = 0;
             }
+            const int B = min(64, sp);
+            const bool have = lane < B;
+            const int2 ent = stk[sp - B + (have ? lane : B - 1)];
+            wave_sync();
+            sp -= B;
+            const int k = (ent.x >= 0 && ent.x < nn) ? ent.x : 0;
+            const int end = min(ent.y, nn);
+            const double4 geo = a.ngeo[k];
+            const int4 inf = a.ninfo[k];
+            // opening test, Eq. (5): accept iff s^2 < theta^2 d^2 for every member.
+            // The group box bounds decide when a margin far above rounding
+            // proves every member agrees; otherwise every member is tested.
+            const double nx = fmax(0.0, fmax(bminx - geo.x, geo.x - bmaxx));
+            const double ny = fmax(0.0, fmax(bminy - geo.y, geo.y - bmaxy));
+            const double nz = fmax(0.0, fmax(bminz - geo.z, geo.z - bmaxz));
+            const double fx = fmax(fabs(bminx - geo.x), fabs(bmaxx - geo.x));
+            const double fy = fmax(fabs(bminy - geo.y), fabs(bmaxy - geo.y));
+            const double fz = fmax(fabs(bminz - geo.z), fabs(bmaxz - geo.z));
+            const double dmin2 = nx * nx + ny * ny + nz * nz;
+            const double dmax2 = fx * fx + fy * fy + fz * fz;
+            bool acc;
+            if (geo.w < th2 * dmin2 * (1.0 - 1e-12)) {
+                acc = true;
+            } else if (geo.w >= th2 * dmax2 * (1.0 + 1e-12)) {
+                acc = false;
+            } else {
+                acc = true;
+                for (int m = 0; m < c; ++m) {
+                    const double dx = tpos[3 * m] - geo.x, dy = tpos[3 * m + 1] - geo.y,
+                                 dz = tpos[3 * m + 2] - geo.z;
+                    const double d2 = fma(dz, dz, fma(dy, dy, dx * dx));
+                    if (!(geo.w < th2 * d2)) { acc = false; break; }
+                }
+            }
+            const bool isleaf = (inf.w & 256) != 0;
+            const bool leaf_ok = inf.x >= 0 && inf.y >= 0 && (int64_t)inf.x + inf.y <= a.n;
+            const bool take_m = have && acc;
+            const bool take_p = have && !acc && isleaf && leaf_ok;
+            const bool push_c = have && !acc && !isleaf;
+            const int skipk = max(inf.z, k + 1);
+            const bool push_s = have && skipk < end;
+            const unsigned long long bm = __ballot(take_m), bp = __ballot(take_p);
+            const unsigned long long bc = __ballot(push_c), bs = __ballot(push_s);
+            const int nc = __popcll(bc), ns = __popcll(bs);
+            if (sp + nc + ns > kStackCap) { overflow = true; break; }
+            if (take_m) ml[nm + lanes_before(bm, lane)] = k;
+            if (take_p) pl[np + lanes_before(bp, lane)] = k;
+            if (push_c) stk[sp + lanes_before(bc, lane)] = make_int2(k + 1, skipk);
+            if (push_s) stk[sp + nc + lanes_before(bs, lane)] = make_int2(skipk, end);
+            nm += __popcll(bm);
+            np += __popcll(bp);
+            sp += nc + ns;
+            my_m += take_m ? 1 : 0;
+            my_src += take_p ? inf.y : 0;
+            wave_sync();
         }
-        flush_lists<PREC, PHI>(a, ml, nm, pl, np, xi, i, E0, E1, E2, PH);
-        tot_m += nm;
-        // inactive lanes store to a per-lane spare slot past the particles
-        a.acc[act ? (int64_t)i : a.n_spare + lane] = make_double4(E0, E1, E2, PH);
+        if (overflow) atomicOr(a.flags_rw, lane == 0 ? UCP_FLAG_WALK_STACK : 0);
+        flush_lists<PREC, PHI>(a, ml, nm, pl, np, stage, pfx, lfirst, lane, sub, lpt, cg, tx, ty,
+                               tz, i, E0, E1, E2, PH);
+        // sum the lpt partial results of each target in fixed lane order
+        double *red = (double *)stage;   // 64 x 4 doubles
+        red[4 * lane + 0] = E0;
+        red[4 * lane + 1] = E1;
+        red[4 * lane + 2] = E2;
+        red[4 * lane + 3] = PH;
+        wave_sync();
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        for (int s = 0; s < lpt; ++s) {
+            const int src = lane + s < 64 ? lane + s : 63;
+            s0 += red[4 * src + 0];
+            s1 += red[4 * src + 1];
+            s2 += red[4 * src + 2];
+            s3 += red[4 * src + 3];
+        }
+        wave_sync();
+        // only lane sub == 0 of an active target owns the result; the others
+        // store to their private spare slot past the particles
+        a.acc[(act && sub == 0) ? (int64_t)i : a.n_spare + lane] = make_double4(s0, s1, s2, s3);
+        const int tot_m = wave_isum(my_m), tot_src = wave_isum(my_src);
         a.gstat[g] = make_int2(tot_m, tot_src);   // same value from every lane
         const unsigned long long zero = 0ull;
-        atomicAdd(&a.ctr[CTR_P2P], lane == 0 ? (unsigned long long)gcount * (unsigned long long)tot_src : zero);
-        atomicAdd(&a.ctr[CTR_M2P], lane == 0 ? (unsigned long long)gcount * (unsigned long long)tot_m : zero);
+        atomicAdd(&a.ctr[CTR_P2P],
+                  lane == 0 ? (unsigned long long)c * (unsigned long long)tot_src : zero);
+        atomicAdd(&a.ctr[CTR_M2P],
+                  lane == 0 ? (unsigned long long)c * (unsigned long long)tot_m : zero);
     }
 }
 
@@ -262,9 +434,9 @@ __global__ __launch_bounds__(256) void k_scatter(const double4 *__restrict__ acc
 template <int PREC, bool PHI>
 static void launch_walk_t(Ctx *c, const WalkArgs &wa, hipStream_t s)
 {
-    const int waves_per_cu = c->p.walk_waves > 0 ? c->p.walk_waves : 16;
+    const int waves_per_cu = c->p_built.walk_waves > 0 ? c->p_built.walk_waves : 32;
     const int blocks = (c->num_cu * waves_per_cu + 3) / 4;
-    const size_t lds = (size_t)4 * 2 * wa.L * sizeof(int);
+    const size_t lds = (size_t)4 * walk_wave_bytes<PREC>(wa.L);
     hipLaunchKernelGGL((k_walk<PREC, PHI>), dim3(blocks), dim3(256), lds, s, wa);
 }
 
@@ -273,7 +445,6 @@ void launch_forces(Ctx *c, double *f, double *phi, hipStream_t s)
     const int64_t n = c->n;
     WalkArgs wa;
     wa.xq = c->d_xq;
-    wa.xl = c->d_xl;
     wa.ngeo = c->d_ngeo;
     wa.ninfo = c->d_ninfo;
     wa.mom64 = c->d_mom64;
@@ -281,13 +452,13 @@ void launch_forces(Ctx *c, double *f, double *phi, hipStream_t s)
     wa.groups = c->d_groups;
     wa.ngroups = c->d_goff + n;
     wa.nnodes = c->d_noff + n;
-    wa.flags_rw = c->d_flags;
-    wa.n = n;
-    wa.n_spare = c->n_max;
     wa.gstat = c->d_gstat;
     wa.acc = c->d_acc;
     wa.ctr = c->d_ctr;
     wa.flags = c->d_flags;
+    wa.flags_rw = c->d_flags;
+    wa.n = n;
+    wa.n_spare = c->n_max;
     wa.th2 = c->p_built.theta * c->p_built.theta;
     wa.eps2 = c->p_built.eps * c->p_built.eps;
     wa.eps2f = (float)wa.eps2;
@@ -296,11 +467,11 @@ void launch_forces(Ctx *c, double *f, double *phi, hipStream_t s)
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (c->timing) {
         if ((int64_t)c->ev.size() < 2 * (c->ev_used + 1)) {
-            hipEvent_t a, b;
-            (void)hipEventCreate(&a);
-            (void)hipEventCreate(&b);
-            c->ev.push_back(a);
-            c->ev.push_back(b);
+            hipEvent_t ea, eb;
+            (void)hipEventCreate(&ea);
+            (void)hipEventCreate(&eb);
+            c->ev.push_back(ea);
+            c->ev.push_back(eb);
         }
         e0 = c->ev[2 * c->ev_used];
         e1 = c->ev[2 * c->ev_used + 1];

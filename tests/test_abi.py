@@ -43,7 +43,7 @@ def test_default_params_and_version():
 
 @pytest.mark.parametrize("over", [dict(theta=-0.1), dict(theta=1.2), dict(eps=0.0),
                                   dict(key_bits=32), dict(leaf_cap=0), dict(leaf_cap=65),
-                                  dict(group_size=0), dict(group_size=65), dict(list_len=8),
+                                  dict(group_size=0), dict(group_size=65), dict(list_len=8), dict(list_len=600),
                                   dict(precision=3)])
 def test_create_rejects_bad_params_without_gpu(over):
     p = L.default_params(**over)
