@@ -62,6 +62,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 comparator run")
     ap.add_argument("--profile", action="store_true", help="short run for rocprofv3 (no extras)")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a 256 MiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the method is not "
@@ -178,6 +180,13 @@ def main():
             "kind": "oracle",
             "sample": "one full FP64 oracle tree-force evaluation (build + walk, OpenMP over "
                       "groups) of the same N=524288 cloud at the same parameters; %.2f s" % (c1 - c0)}
+    if args.calib_copy:
+        a = torch.ones(64 << 20, dtype=torch.float32, device=dev)   # 256 MiB
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        result["calib_copy_bytes"] = {"read": a.numel() * 4, "write": b.numel() * 4}
     ts.close()
     print(json.dumps(result), flush=True)
 

@@ -71,10 +71,13 @@ constexpr int kStackCap = 256;   // traversal stack entries per wave
 // range), member positions (FP64), M2P and P2P index lists, a staging area
 // (64 M2P records of 16 values, or 64 P2P particles, or the final per-lane
 // partial sums) and two 64-int tables for expanding leaves into particles.
+// staged M2P records are kRec values apart: 80-byte (FP32) records put eight
+// consecutive records on distinct LDS banks
+constexpr int kRec = 20;
 template <int PREC>
 __host__ __device__ constexpr int walk_stage_bytes()
 {
-    return PREC == UCP_SPLIT ? 64 * 16 * 4 : 64 * 16 * 8;
+    return PREC == UCP_SPLIT ? 64 * kRec * 4 : 64 * kRec * 8;
 }
 template <int PREC>
 __host__ __device__ constexpr int walk_wave_bytes(int L)
@@ -116,31 +119,53 @@ __device__ __forceinline__ int wave_incl_scan_i(int v, int lane)
 // kernel about the box centre (r = target - centre, h^2 = |r|^2 + eps^2)
 //   phi = Q/h + (p.r)/h^3 + (3 r.S.r/h^5 - trS/h^3)/2
 //   E   = [Q/h^3 + 3(p.r)/h^5 + 7.5 r.S.r/h^7 - 1.5 trS/h^5] r - p/h^3 - 3 S r/h^5
+// evaluated as E = h^-3 [ b r - u ] with u = p + 3 h^-2 S r and
+// b = Q + h^-2 (3 p.r - 1.5 trS + 7.5 h^-2 r.S.r); the staged record holds
+// c[3], Q, p[3], 1.5 trS, Sxx, Syy, Szz, Sxy, Sxz, Syz.
 // ---------------------------------------------------------------------------
 template <typename T, bool PHI>
 __device__ __forceinline__ void m2p_eval(T rx, T ry, T rz, T Q, T px, T py, T pz, T Sxx, T Syy,
-                                         T Szz, T Sxy, T Sxz, T Syz, T trS, T eps2, T &ex, T &ey,
-                                         T &ez, T &ph)
+                                         T Szz, T Sxy, T Sxz, T Syz, T trS15, T eps2, T &ex,
+                                         T &ey, T &ez, T &ph)
 {
-    const T h2 = rx * rx + ry * ry + rz * rz + eps2;
+    const T h2 = fma(rx, rx, fma(ry, ry, fma(rz, rz, eps2)));
     T ih;
     if constexpr (sizeof(T) == 4) ih = __builtin_amdgcn_rsqf(h2);
     else ih = 1.0 / sqrt(h2);
     const T ih2 = ih * ih;
     const T ih3 = ih2 * ih;
-    const T ih5 = ih3 * ih2;
-    const T ih7 = ih5 * ih2;
-    const T Srx = Sxx * rx + Sxy * ry + Sxz * rz;
-    const T Sry = Sxy * rx + Syy * ry + Syz * rz;
-    const T Srz = Sxz * rx + Syz * ry + Szz * rz;
-    const T rSr = rx * Srx + ry * Sry + rz * Srz;
-    const T pr = px * rx + py * ry + pz * rz;
-    const T alpha = Q * ih3 + ((T)3 * pr - (T)1.5 * trS) * ih5 + (T)7.5 * rSr * ih7;
-    const T b3 = (T)3 * ih5;
-    ex += alpha * rx - (px * ih3 + b3 * Srx);
-    ey += alpha * ry - (py * ih3 + b3 * Sry);
-    ez += alpha * rz - (pz * ih3 + b3 * Srz);
-    if (PHI) ph += Q * ih + pr * ih3 + (T)0.5 * ((T)3 * rSr * ih5 - trS * ih3);
+    const T Srx = fma(Sxx, rx, fma(Sxy, ry, Sxz * rz));
+    const T Sry = fma(Sxy, rx, fma(Syy, ry, Syz * rz));
+    const T Srz = fma(Sxz, rx, fma(Syz, ry, Szz * rz));
+    const T rSr = fma(rx, Srx, fma(ry, Sry, rz * Srz));
+    const T pr = fma(px, rx, fma(py, ry, pz * rz));
+    const T w = (T)3 * ih2;
+    const T ux = fma(w, Srx, px), uy = fma(w, Sry, py), uz = fma(w, Srz, pz);
+    const T a = fma((T)7.5 * ih2, rSr, fma((T)3, pr, -trS15));
+    const T b = fma(ih2, a, Q);
+    ex = fma(ih3, fma(b, rx, -ux), ex);
+    ey = fma(ih3, fma(b, ry, -uy), ey);
+    ez = fma(ih3, fma(b, rz, -uz), ez);
+    // phi = h^-1 [ Q + h^-2 (p.r - trS/2 + 1.5 h^-2 r.S.r) ]
+    if (PHI) ph = fma(ih, fma(ih2, fma((T)1.5 * ih2, rSr, pr - trS15 * (T)(1.0 / 3.0)), Q), ph);
+}
+
+// one staged M2P record, read with 16-byte LDS loads
+template <typename T, bool PHI>
+__device__ __forceinline__ void m2p_rec(const T *r, T tx, T ty, T tz, T eps2, T &ex, T &ey, T &ez,
+                                        T &ph)
+{
+    if constexpr (sizeof(T) == 4) {
+        const float4 a = ((const float4 *)r)[0], b = ((const float4 *)r)[1];
+        const float4 c = ((const float4 *)r)[2], d = ((const float4 *)r)[3];
+        m2p_eval<T, PHI>(tx - a.x, ty - a.y, tz - a.z, a.w, b.x, b.y, b.z, c.x, c.y, c.z, c.w, d.x,
+                         d.y, b.w, eps2, ex, ey, ez, ph);
+    } else {
+        const double2 *v = (const double2 *)r;
+        const double2 a = v[0], b = v[1], c = v[2], d = v[3], e = v[4], f = v[5], g = v[6];
+        m2p_eval<T, PHI>(tx - a.x, ty - a.y, tz - b.x, b.y, c.x, c.y, d.x, e.x, e.y, f.x, f.y, g.x,
+                         g.y, d.y, eps2, ex, ey, ez, ph);
+    }
 }
 
 // Evaluate the M2P and P2P index lists of a group.  Entries are staged into
@@ -158,36 +183,40 @@ __device__ __forceinline__ void flush_lists(const WalkArgs &a, const int *ml, in
         const int cnt = min(64, nm - base);
         {
             const int k = ml[base + (lane < cnt ? lane : cnt - 1)];
-            T *rec = stage + 16 * lane;
+            T *rec = stage + kRec * lane;
             if constexpr (PREC == UCP_SPLIT) {
                 const float4 *m4 = (const float4 *)(a.mom32 + 16 * (int64_t)k);
                 const double4 g = a.ngeo[k];
-                float4 r0 = m4[0];
+                float4 r0 = m4[0], r1 = m4[1];
                 r0.x = (float)(g.x - cg.x);
                 r0.y = (float)(g.y - cg.y);
                 r0.z = (float)(g.z - cg.z);
+                r1.w *= 1.5f;
                 float4 *d4 = (float4 *)rec;
                 d4[0] = r0;
-                d4[1] = m4[1];
+                d4[1] = r1;
                 d4[2] = m4[2];
                 d4[3] = m4[3];
             } else {
                 const double2 *m2 = (const double2 *)(a.mom64 + 16 * (int64_t)k);
                 double2 *d2 = (double2 *)rec;
                 for (int q = 0; q < 7; ++q) d2[q] = m2[q];
+                d2[3].y *= 1.5;
             }
         }
         wave_sync();
-        T ex = 0, ey = 0, ez = 0, ph = 0;
-        for (int e = sub; e < cnt; e += lpt) {
-            const T *r = stage + 16 * e;
-            m2p_eval<T, PHI>(tx - r[0], ty - r[1], tz - r[2], r[3], r[4], r[5], r[6], r[8], r[9],
-                             r[10], r[11], r[12], r[13], r[7], eps2, ex, ey, ez, ph);
+        // two independent partial sums (records e and e + lpt) for ILP
+        T ex = 0, ey = 0, ez = 0, ph = 0, fx = 0, fy = 0, fz = 0, fp = 0;
+        int e = sub;
+        for (; e + lpt < cnt; e += 2 * lpt) {
+            m2p_rec<T, PHI>(stage + kRec * e, tx, ty, tz, eps2, ex, ey, ez, ph);
+            m2p_rec<T, PHI>(stage + kRec * (e + lpt), tx, ty, tz, eps2, fx, fy, fz, fp);
         }
-        E0 += (double)ex;
-        E1 += (double)ey;
-        E2 += (double)ez;
-        PH += (double)ph;
+        if (e < cnt) m2p_rec<T, PHI>(stage + kRec * e, tx, ty, tz, eps2, ex, ey, ez, ph);
+        E0 += (double)(ex + fx);
+        E1 += (double)(ey + fy);
+        E2 += (double)(ez + fz);
+        PH += (double)(ph + fp);
         wave_sync();
     }
     int *sidx = (int *)(stage + 4 * 64);
@@ -224,17 +253,24 @@ __device__ __forceinline__ void flush_lists(const WalkArgs &a, const int *ml, in
             wave_sync();
             T ex = 0, ey = 0, ez = 0, ph = 0;
             for (int e = sub; e < ncur; e += lpt) {
-                const T *q4 = stage + 4 * e;
-                const T rx = tx - q4[0], ry = ty - q4[1], rz = tz - q4[2];
-                const T h2 = rx * rx + ry * ry + rz * rz + eps2;
+                T sx, sy, sz, sq;
+                if constexpr (sizeof(T) == 4) {
+                    const float4 v = ((const float4 *)stage)[e];
+                    sx = v.x; sy = v.y; sz = v.z; sq = v.w;
+                } else {
+                    const double4 v = ((const double4 *)stage)[e];
+                    sx = v.x; sy = v.y; sz = v.z; sq = v.w;
+                }
+                const T rx = tx - sx, ry = ty - sy, rz = tz - sz;
+                const T h2 = fma(rx, rx, fma(ry, ry, fma(rz, rz, eps2)));
                 T ih;
                 if constexpr (sizeof(T) == 4) ih = __builtin_amdgcn_rsqf(h2);
                 else ih = 1.0 / sqrt(h2);
-                const T w = q4[3] * ih * ih * ih;
-                ex += w * rx;
-                ey += w * ry;
-                ez += w * rz;
-                if (PHI) ph += (sidx[e] != i) ? q4[3] * ih : (T)0;
+                const T w = sq * (ih * ih * ih);
+                ex = fma(w, rx, ex);
+                ey = fma(w, ry, ey);
+                ez = fma(w, rz, ez);
+                if (PHI) ph += (sidx[e] != i) ? sq * ih : (T)0;
             }
             E0 += (double)ex;
             E1 += (double)ey;
@@ -257,7 +293,7 @@ __global__ __launch_bounds__(256) void k_walk(WalkArgs a)
     double *tpos = (double *)(wbase + kStackCap * 8);             // [64][3]
     int *ml = (int *)(tpos + 64 * 3);                             // [L]
     int *pl = ml + L;                                             // [L]
-    T *stage = (T *)(pl + L);                                     // [64][16]
+    T *stage = (T *)(pl + L);                                     // [64][kRec]
     int *pfx = (int *)((char *)stage + walk_stage_bytes<PREC>()); // [64]
     int *lfirst = pfx + 64;                                       // [64]
     if (*a.flags) return;
