@@ -57,7 +57,7 @@ void free_all(Ctx *c)
     void *ptrs[] = {c->d_off,  c->d_mm,     c->d_cube,  c->d_key[0], c->d_key[1], c->d_val[0],
                     c->d_val[1], c->d_hist, c->d_histscan, c->d_xq, c->d_L,
                     c->d_leaf, c->d_cnt,    c->d_noff,  c->d_goff,   c->d_gnode,  c->d_scanblk,
-                    c->d_ngeo, c->d_ninfo,  c->d_npar,  c->d_mom64,  c->d_mom32,
+                    c->d_ngeo, c->d_ninfo,  c->d_npar,  c->d_mom64,  c->d_nrec,
                     c->d_groups, c->d_gstat, c->d_acc,  c->d_ctr,    c->d_flags,  c->d_epart};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -207,7 +207,7 @@ ucp_status ucp_create(ucp_ctx **out, int64_t n_max, int32_t clouds_max, const uc
     ALLOC(c->d_ninfo, NC);
     ALLOC(c->d_npar, NC);
     ALLOC(c->d_mom64, 16 * NC);
-    ALLOC(c->d_mom32, 16 * NC);
+    ALLOC(c->d_nrec, 8 * NC);
     ALLOC(c->d_groups, N);
     ALLOC(c->d_gstat, N);
     ALLOC(c->d_acc, N + 64);   // 64 spare slots for the walk's inactive lanes

@@ -518,7 +518,8 @@ __global__ __launch_bounds__(256) void k_nodes(
     const uint64_t *__restrict__ key, int64_t n, const int64_t *__restrict__ off, int clouds,
     const double4 *__restrict__ cube, int b, const int8_t *__restrict__ Lv,
     const int8_t *__restrict__ Lf, const int32_t *__restrict__ noff, int64_t node_cap,
-    double4 *ngeo, int4 *ninfo, int32_t *npar, unsigned long long *ctr, int32_t *flags)
+    double4 *ngeo, int4 *ninfo, int32_t *npar, float4 *nrec, unsigned long long *ctr,
+    int32_t *flags)
 {
     if (*flags) return;
     const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -554,9 +555,13 @@ __global__ __launch_bounds__(256) void k_nodes(
         const double cx = c0.x + (double)(2 * (X >> (b - l)) + 1) * h;
         const double cy = c0.y + (double)(2 * (Y >> (b - l)) + 1) * h;
         const double cz = c0.z + (double)(2 * (Z >> (b - l)) + 1) * h;
-        ngeo[k] = make_double4(cx, cy, cz, ldexp(1.0, 2 * (e - l)));
-        ninfo[k] = make_int4((int)p, (int)(t - p), noff[t], l | (l == lf ? 256 : 0));
+        const double4 geo = make_double4(cx, cy, cz, ldexp(1.0, 2 * (e - l)));
+        const int4 inf = make_int4((int)p, (int)(t - p), noff[t], l | (l == lf ? 256 : 0));
+        ngeo[k] = geo;
+        ninfo[k] = inf;
         npar[k] = parent;
+        *(double4 *)(nrec + 8 * (int64_t)k) = geo;
+        *(int4 *)(nrec + 8 * (int64_t)k + 2) = make_int4(inf.z, inf.x, inf.y, inf.w);
     }
     atomicMax(&ctr[CTR_MAXLEVEL], (unsigned long long)lf);
 }
@@ -567,9 +572,10 @@ __global__ __launch_bounds__(256) void k_nodes(
 //    particles, an internal node sums its children (one level deeper, written
 //    by the previous launch) in octant order with the exact shift of origin.
 //    Record per node, FP64 (16 doubles): cx cy cz Q px py pz trS Sxx Syy Szz
-//    Sxy Sxz Syz 0 0; FP32 copy (16 floats): 0 0 0 Q px py pz trS Sxx ... 0 0.
+//    Sxy Sxz Syz 0 0; FP32 copy in the second line of the walk record:
+//    Q px py pz, 1.5 trS Sxx Syy Szz, Sxy Sxz Syz 0.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void store_moments(double *mom64, float *mom32, int k, const double4 &g,
+__device__ __forceinline__ void store_moments(double *mom64, float4 *nrec, int k, const double4 &g,
                                               const double *m)
 {
     // m: Q, px, py, pz, Sxx, Syy, Szz, Sxy, Sxz, Syz
@@ -578,17 +584,16 @@ __device__ __forceinline__ void store_moments(double *mom64, float *mom32, int k
                             m[4], m[5], m[6], m[7], m[8], m[9], 0.0, 0.0};
     double2 *d2 = (double2 *)(mom64 + 16 * (int64_t)k);
     for (int i = 0; i < 8; ++i) d2[i] = make_double2(rec[2 * i], rec[2 * i + 1]);
-    float4 *f4 = (float4 *)(mom32 + 16 * (int64_t)k);
-    f4[0] = make_float4(0.f, 0.f, 0.f, (float)m[0]);
-    f4[1] = make_float4((float)m[1], (float)m[2], (float)m[3], (float)trS);
-    f4[2] = make_float4((float)m[4], (float)m[5], (float)m[6], (float)m[7]);
-    f4[3] = make_float4((float)m[8], (float)m[9], 0.f, 0.f);
+    float4 *f4 = nrec + 8 * (int64_t)k + 4;
+    f4[0] = make_float4((float)m[0], (float)m[1], (float)m[2], (float)m[3]);
+    f4[1] = make_float4((float)(1.5 * trS), (float)m[4], (float)m[5], (float)m[6]);
+    f4[2] = make_float4((float)m[7], (float)m[8], (float)m[9], 0.f);
 }
 
 __global__ __launch_bounds__(256) void k_moments_level(
     int level, const double4 *__restrict__ xq, int64_t n, const int8_t *__restrict__ Lv,
     const int8_t *__restrict__ Lf, const int32_t *__restrict__ noff,
-    const double4 *__restrict__ ngeo, const int4 *__restrict__ ninfo, double *mom64, float *mom32,
+    const double4 *__restrict__ ngeo, const int4 *__restrict__ ninfo, double *mom64, float4 *nrec,
     const int32_t *flags)
 {
     if (*flags) return;
@@ -639,7 +644,7 @@ __global__ __launch_bounds__(256) void k_moments_level(
             m[9] += c[13] + p1 * d2 + d1 * p2 + Q * d1 * d2;
         }
     }
-    store_moments(mom64, mom32, k, g, m);
+    store_moments(mom64, nrec, k, g, m);
 }
 
 // ---------------------------------------------------------------------------
@@ -791,14 +796,14 @@ void launch_build(Ctx *c, const double *x, const double *q, const int64_t *offse
                        (const int64_t *)c->d_off, clouds, (const double4 *)c->d_cube, b,
                        (const int8_t *)c->d_L, (const int8_t *)c->d_leaf,
                        (const int32_t *)c->d_noff, c->node_cap, c->d_ngeo, c->d_ninfo, c->d_npar,
-                       c->d_ctr, c->d_flags);
+                       c->d_nrec, c->d_ctr, c->d_flags);
     // 6. moments, deepest level first
     for (int l = b; l >= 0; --l)
         hipLaunchKernelGGL(k_moments_level, grid_for(n, 256), dim3(256), 0, s, l,
                            (const double4 *)c->d_xq, n, (const int8_t *)c->d_L,
                            (const int8_t *)c->d_leaf, (const int32_t *)c->d_noff,
                            (const double4 *)c->d_ngeo, (const int4 *)c->d_ninfo, c->d_mom64,
-                           c->d_mom32, (const int32_t *)c->d_flags);
+                           c->d_nrec, (const int32_t *)c->d_flags);
     // 7. groups
     hipLaunchKernelGGL(k_group_count, grid_for(n + 1, 256), dim3(256), 0, s, n,
                        (const int8_t *)c->d_L, (const int8_t *)c->d_leaf,

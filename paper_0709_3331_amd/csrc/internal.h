@@ -90,7 +90,10 @@ struct Ctx {
     int4 *d_ninfo = nullptr;                // [node_cap] first, count, skip, level | 256*leaf
     int32_t *d_npar = nullptr;              // [node_cap] parent (-1 for a root)
     double *d_mom64 = nullptr;              // [node_cap][16] cx cy cz Q p[3] trS S[6] 0 0
-    float *d_mom32 = nullptr;               // [node_cap][16] 0 0 0 Q p[3] trS S[6] 0 0
+    // node record for the walk, two 64-byte lines per node:
+    //   line 1: cx cy cz side^2 (double), skip first count level|256*leaf (int)
+    //   line 2: Q px py pz | 1.5 trS Sxx Syy Szz | Sxy Sxz Syz 0   (float)
+    float4 *d_nrec = nullptr;               // [node_cap][8]
     // groups
     int4 *d_groups = nullptr;               // [n_max] first, count, node, root
     int2 *d_gstat = nullptr;                // [n_max] accepted boxes, P2P sources

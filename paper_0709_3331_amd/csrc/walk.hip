@@ -1,13 +1,19 @@
 // walk.hip -- the group tree walk of Sec. 3 on gfx950.
 //
-// One wavefront per walk group.  The wave walks the preorder node array of
-// its cloud without a stack (first child = k + 1, next sibling / end of
-// subtree = skip link).  At each node every target evaluates the opening test
-// of Eq. (5) with delta = 0 in FP64,
+// One wavefront per walk group.  The wave keeps an LDS stack of sibling
+// ranges [k, end) of the preorder node array (first child = k + 1, next
+// sibling = skip link) and tests up to 64 nodes at once, one per lane.  For
+// each node the opening test of Eq. (5) with delta = 0 is evaluated in FP64
+// for every target of the group,
 //     accept  iff  s^2 < theta^2 d^2,   d^2 = fma(dz,dz, fma(dy,dy, dx*dx)),
-// and the wave opens the node iff any target fails (wave ballot).  Accepted
-// boxes are staged into an LDS M2P list, the particles of opened leaves into
-// an LDS P2P list; a full list is evaluated (flushed) at once.
+// and the node is opened iff any target fails.  Accepted boxes go to an LDS
+// M2P list, opened leaves to an LDS P2P list; a full list is evaluated
+// (flushed) at once.
+//
+// Node record (two 64-byte lines per node, written by the build): line 1
+// holds the FP64 centre, side^2, skip, first, count and level|leaf flag and
+// is all the traversal reads; line 2 holds the FP32 moments, read when an
+// accepted box is staged.
 //
 // Lane layout: a group of c <= 64 targets gives each target lpt = floor(64/c)
 // lanes.  The lanes of one target take the staged entries round-robin and
@@ -36,10 +42,8 @@ namespace ucp {
 
 struct WalkArgs {
     const double4 *xq;
-    const double4 *ngeo;
-    const int4 *ninfo;
+    const float4 *nrec;
     const double *mom64;
-    const float *mom32;
     const int4 *groups;
     const int32_t *ngroups;
     const int32_t *nnodes;
@@ -65,12 +69,18 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-constexpr int kStackCap = 256;   // traversal stack entries per wave
+// Traversal stack entries per wave.  A batch pops at most kStackSoft - sp
+// entries (at least one) and pushes at most two per popped entry, children on
+// top, so the stack never passes kStackSoft by more than the depth of the
+// tree (22 levels for 63-bit keys).
+constexpr int kStackCap = 192;
+constexpr int kStackSoft = kStackCap - 40;
 
 // LDS layout of one wave (bytes): traversal stack (node, end of its sibling
-// range), member positions (FP64), M2P and P2P index lists, a staging area
-// (64 M2P records of 16 values, or 64 P2P particles, or the final per-lane
-// partial sums) and two 64-int tables for expanding leaves into particles.
+// range), the M2P list (node, FP32 offset of its centre from the group centre),
+// the P2P list (first particle, count of an opened leaf), a staging area (64
+// M2P records of 16 values, or 64 P2P particles, or the final per-lane partial
+// sums) and two 64-int tables for expanding leaves into particles.
 // staged M2P records are kRec values apart: 80-byte (FP32) records put eight
 // consecutive records on distinct LDS banks
 constexpr int kRec = 20;
@@ -82,7 +92,7 @@ __host__ __device__ constexpr int walk_stage_bytes()
 template <int PREC>
 __host__ __device__ constexpr int walk_wave_bytes(int L)
 {
-    return kStackCap * 8 + 64 * 3 * 8 + 2 * 4 * L + walk_stage_bytes<PREC>() + 2 * 64 * 4;
+    return kStackCap * 8 + 16 * L + 8 * L + walk_stage_bytes<PREC>() + 2 * 64 * 4;
 }
 
 __device__ __forceinline__ int lanes_before(unsigned long long mask, int lane)
@@ -100,6 +110,15 @@ __device__ __forceinline__ double wave_fmax(double v)
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
     return v;
 }
+// value of v held by lane src (src uniform over the wave)
+__device__ __forceinline__ double readlane_d(double v, int src)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), src);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 __device__ __forceinline__ int wave_isum(int v)
 {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
@@ -150,7 +169,9 @@ __device__ __forceinline__ void m2p_eval(T rx, T ry, T rz, T Q, T px, T py, T pz
     if (PHI) ph = fma(ih, fma(ih2, fma((T)1.5 * ih2, rSr, pr - trS15 * (T)(1.0 / 3.0)), Q), ph);
 }
 
-// one staged M2P record, read with 16-byte LDS loads
+// one staged M2P record, read with 16-byte LDS loads.  FP32 record: dx dy dz 0,
+// Q px py pz, 1.5 trS Sxx Syy Szz, Sxy Sxz Syz 0; FP64 record: cx cy cz Q px py
+// pz 1.5 trS Sxx Syy Szz Sxy Sxz Syz.
 template <typename T, bool PHI>
 __device__ __forceinline__ void m2p_rec(const T *r, T tx, T ty, T tz, T eps2, T &ex, T &ey, T &ez,
                                         T &ph)
@@ -158,8 +179,8 @@ __device__ __forceinline__ void m2p_rec(const T *r, T tx, T ty, T tz, T eps2, T 
     if constexpr (sizeof(T) == 4) {
         const float4 a = ((const float4 *)r)[0], b = ((const float4 *)r)[1];
         const float4 c = ((const float4 *)r)[2], d = ((const float4 *)r)[3];
-        m2p_eval<T, PHI>(tx - a.x, ty - a.y, tz - a.z, a.w, b.x, b.y, b.z, c.x, c.y, c.z, c.w, d.x,
-                         d.y, b.w, eps2, ex, ey, ez, ph);
+        m2p_eval<T, PHI>(tx - a.x, ty - a.y, tz - a.z, b.x, b.y, b.z, b.w, c.y, c.z, c.w, d.x, d.y,
+                         d.z, c.x, eps2, ex, ey, ez, ph);
     } else {
         const double2 *v = (const double2 *)r;
         const double2 a = v[0], b = v[1], c = v[2], d = v[3], e = v[4], f = v[5], g = v[6];
@@ -172,8 +193,8 @@ __device__ __forceinline__ void m2p_rec(const T *r, T tx, T ty, T tz, T eps2, T 
 // LDS 64 at a time (one per lane), then the lpt lanes of each target take the
 // staged entries round-robin.
 template <int PREC, bool PHI, typename T>
-__device__ __forceinline__ void flush_lists(const WalkArgs &a, const int *ml, int nm, const int *pl,
-                                            int np, T *stage, int *pfx, int *lfirst, int lane,
+__device__ __forceinline__ void flush_lists(const WalkArgs &a, const int4 *ml, int nm,
+                                            const int2 *pl, int np, T *stage, int *pfx, int *lfirst, int lane,
                                             int sub, int lpt, const double4 &cg, T tx, T ty, T tz,
                                             int i, double &E0, double &E1, double &E2, double &PH)
 {
@@ -182,21 +203,18 @@ __device__ __forceinline__ void flush_lists(const WalkArgs &a, const int *ml, in
     for (int base = 0; base < nm; base += 64) {
         const int cnt = min(64, nm - base);
         {
-            const int k = ml[base + (lane < cnt ? lane : cnt - 1)];
+            const int4 ent = ml[base + (lane < cnt ? lane : cnt - 1)];
+            const int k = ent.x;
             T *rec = stage + kRec * lane;
             if constexpr (PREC == UCP_SPLIT) {
-                const float4 *m4 = (const float4 *)(a.mom32 + 16 * (int64_t)k);
-                const double4 g = a.ngeo[k];
-                float4 r0 = m4[0], r1 = m4[1];
-                r0.x = (float)(g.x - cg.x);
-                r0.y = (float)(g.y - cg.y);
-                r0.z = (float)(g.z - cg.z);
-                r1.w *= 1.5f;
+                const float4 *m4 = a.nrec + 8 * (int64_t)k + 4;
+                const float4 r1 = m4[0], r2 = m4[1], r3 = m4[2];
                 float4 *d4 = (float4 *)rec;
-                d4[0] = r0;
+                d4[0] = make_float4(__int_as_float(ent.y), __int_as_float(ent.z),
+                                    __int_as_float(ent.w), 0.f);
                 d4[1] = r1;
-                d4[2] = m4[2];
-                d4[3] = m4[3];
+                d4[2] = r2;
+                d4[3] = r3;
             } else {
                 const double2 *m2 = (const double2 *)(a.mom64 + 16 * (int64_t)k);
                 double2 *d2 = (double2 *)rec;
@@ -222,13 +240,12 @@ __device__ __forceinline__ void flush_lists(const WalkArgs &a, const int *ml, in
     int *sidx = (int *)(stage + 4 * 64);
     for (int base = 0; base < np; base += 64) {
         const int cntL = min(64, np - base);
-        const int k = pl[base + (lane < cntL ? lane : cntL - 1)];
-        const int4 inf = a.ninfo[k];
-        const int cl = lane < cntL ? inf.y : 0;
+        const int2 lf = pl[base + (lane < cntL ? lane : cntL - 1)];
+        const int cl = lane < cntL ? lf.y : 0;
         const int incl = wave_incl_scan_i(cl, lane);
         const int total = uni(__shfl(incl, 63));
         pfx[lane] = incl;
-        lfirst[lane] = inf.x - (incl - cl);   // particle j = lfirst[l] + (global offset)
+        lfirst[lane] = lf.x - (incl - cl);   // particle j = lfirst[l] + (global offset)
         wave_sync();
         for (int pb = 0; pb < total; pb += 64) {
             const int ncur = min(64, total - pb);
@@ -290,9 +307,8 @@ __global__ __launch_bounds__(256) void k_walk(WalkArgs a)
     const int L = a.L;
     char *wbase = lds_raw + (size_t)wave * walk_wave_bytes<PREC>(L);
     int2 *stk = (int2 *)wbase;                                   // [kStackCap]
-    double *tpos = (double *)(wbase + kStackCap * 8);             // [64][3]
-    int *ml = (int *)(tpos + 64 * 3);                             // [L]
-    int *pl = ml + L;                                             // [L]
+    int4 *ml = (int4 *)(wbase + kStackCap * 8);                   // [L]
+    int2 *pl = (int2 *)(ml + L);                                  // [L]
     T *stage = (T *)(pl + L);                                     // [64][kRec]
     int *pfx = (int *)((char *)stage + walk_stage_bytes<PREC>()); // [64]
     int *lfirst = pfx + 64;                                       // [64]
@@ -319,7 +335,7 @@ __global__ __launch_bounds__(256) void k_walk(WalkArgs a)
         const bool act = t < c;
         const int i = gfirst + (act ? t : 0);
         const double4 xi = a.xq[i];
-        const double4 cg = a.ngeo[gnode];
+        const double4 cg = *(const double4 *)(a.nrec + 8 * (int64_t)gnode);
         T tx, ty, tz;
         if constexpr (PREC == UCP_SPLIT) {
             tx = (float)(xi.x - cg.x);
@@ -330,14 +346,11 @@ __global__ __launch_bounds__(256) void k_walk(WalkArgs a)
             ty = xi.y;
             tz = xi.z;
         }
-        // member positions for the exact opening test, and their bounding box
-        tpos[3 * t + 0] = xi.x;   // lanes of one target store the same values
-        tpos[3 * t + 1] = xi.y;
-        tpos[3 * t + 2] = xi.z;
+        // bounding box of the members (lane m * lpt holds member m)
         const double bminx = wave_fmin(act ? xi.x : INFINITY), bmaxx = wave_fmax(act ? xi.x : -INFINITY);
         const double bminy = wave_fmin(act ? xi.y : INFINITY), bmaxy = wave_fmax(act ? xi.y : -INFINITY);
         const double bminz = wave_fmin(act ? xi.z : INFINITY), bmaxz = wave_fmax(act ? xi.z : -INFINITY);
-        stk[0] = make_int2(root, min(a.ninfo[root].z, nn));
+        stk[0] = make_int2(root, min(((const int *)(a.nrec + 8 * (int64_t)root + 2))[0], nn));
         int sp = 1;
         wave_sync();
         double E0 = 0.0, E1 = 0.0, E2 = 0.0, PH = 0.0;
@@ -350,15 +363,16 @@ __global__ __launch_bounds__(256) void k_walk(WalkArgs a)
                                        tx, ty, tz, i, E0, E1, E2, PH);
                 nm = np = 0;
             }
-            const int B = min(64, sp);
+            const int B = min(min(64, sp), max(1, kStackSoft - sp));
             const bool have = lane < B;
             const int2 ent = stk[sp - B + (have ? lane : B - 1)];
             wave_sync();
             sp -= B;
             const int k = (ent.x >= 0 && ent.x < nn) ? ent.x : 0;
             const int end = min(ent.y, nn);
-            const double4 geo = a.ngeo[k];
-            const int4 inf = a.ninfo[k];
+            const float4 *rp = a.nrec + 8 * (int64_t)k;
+            const double4 geo = *(const double4 *)rp;
+            const int4 inf = *(const int4 *)(rp + 2);   // skip, first, count, level|256*leaf
             // opening test, Eq. (5): accept iff s^2 < theta^2 d^2 for every member.
             // The group box bounds decide when a margin far above rounding
             // proves every member agrees; otherwise every member is tested.
@@ -370,40 +384,51 @@ __global__ __launch_bounds__(256) void k_walk(WalkArgs a)
             const double fz = fmax(fabs(bminz - geo.z), fabs(bmaxz - geo.z));
             const double dmin2 = nx * nx + ny * ny + nz * nz;
             const double dmax2 = fx * fx + fy * fy + fz * fz;
-            bool acc;
-            if (geo.w < th2 * dmin2 * (1.0 - 1e-12)) {
-                acc = true;
-            } else if (geo.w >= th2 * dmax2 * (1.0 + 1e-12)) {
-                acc = false;
-            } else {
-                acc = true;
-                for (int m = 0; m < c; ++m) {
-                    const double dx = tpos[3 * m] - geo.x, dy = tpos[3 * m + 1] - geo.y,
-                                 dz = tpos[3 * m + 2] - geo.z;
-                    const double d2 = fma(dz, dz, fma(dy, dy, dx * dx));
-                    if (!(geo.w < th2 * d2)) { acc = false; break; }
-                }
+            const bool sure_acc = geo.w < th2 * dmin2 * (1.0 - 1e-12);
+            const bool sure_open = geo.w >= th2 * dmax2 * (1.0 + 1e-12);
+            const bool band = have && !sure_acc && !sure_open;
+            bool acc = sure_acc || band;
+            // members in turn, broadcast from their lanes, while a lane in the
+            // band still accepts
+            unsigned long long live = __ballot(band);
+            for (int m = 0; live != 0ull && m < c; ++m) {
+                const int src = m * lpt;
+                const double dx = readlane_d(xi.x, src) - geo.x;
+                const double dy = readlane_d(xi.y, src) - geo.y;
+                const double dz = readlane_d(xi.z, src) - geo.z;
+                const double d2 = fma(dz, dz, fma(dy, dy, dx * dx));
+                acc = acc && (!band || geo.w < th2 * d2);
+                live = __ballot(band && acc);
             }
             const bool isleaf = (inf.w & 256) != 0;
-            const bool leaf_ok = inf.x >= 0 && inf.y >= 0 && (int64_t)inf.x + inf.y <= a.n;
+            const bool leaf_ok = inf.y >= 0 && inf.z >= 0 && (int64_t)inf.y + inf.z <= a.n;
             const bool take_m = have && acc;
             const bool take_p = have && !acc && isleaf && leaf_ok;
             const bool push_c = have && !acc && !isleaf;
-            const int skipk = max(inf.z, k + 1);
+            const int skipk = max(inf.x, k + 1);
             const bool push_s = have && skipk < end;
             const unsigned long long bm = __ballot(take_m), bp = __ballot(take_p);
             const unsigned long long bc = __ballot(push_c), bs = __ballot(push_s);
             const int nc = __popcll(bc), ns = __popcll(bs);
             if (sp + nc + ns > kStackCap) { overflow = true; break; }
-            if (take_m) ml[nm + lanes_before(bm, lane)] = k;
-            if (take_p) pl[np + lanes_before(bp, lane)] = k;
-            if (push_c) stk[sp + lanes_before(bc, lane)] = make_int2(k + 1, skipk);
-            if (push_s) stk[sp + nc + lanes_before(bs, lane)] = make_int2(skipk, end);
+            if (take_m) {
+                int4 e = make_int4(k, 0, 0, 0);
+                if constexpr (PREC == UCP_SPLIT) {
+                    e.y = __float_as_int((float)(geo.x - cg.x));
+                    e.z = __float_as_int((float)(geo.y - cg.y));
+                    e.w = __float_as_int((float)(geo.z - cg.z));
+                }
+                ml[nm + lanes_before(bm, lane)] = e;
+            }
+            if (take_p) pl[np + lanes_before(bp, lane)] = make_int2(inf.y, inf.z);
+            // sibling ranges below, child ranges on top
+            if (push_s) stk[sp + lanes_before(bs, lane)] = make_int2(skipk, end);
+            if (push_c) stk[sp + ns + lanes_before(bc, lane)] = make_int2(k + 1, skipk);
             nm += __popcll(bm);
             np += __popcll(bp);
             sp += nc + ns;
             my_m += take_m ? 1 : 0;
-            my_src += take_p ? inf.y : 0;
+            my_src += take_p ? inf.z : 0;
             wave_sync();
         }
         if (overflow) atomicOr(a.flags_rw, lane == 0 ? UCP_FLAG_WALK_STACK : 0);
@@ -481,10 +506,8 @@ void launch_forces(Ctx *c, double *f, double *phi, hipStream_t s)
     const int64_t n = c->n;
     WalkArgs wa;
     wa.xq = c->d_xq;
-    wa.ngeo = c->d_ngeo;
-    wa.ninfo = c->d_ninfo;
+    wa.nrec = c->d_nrec;
     wa.mom64 = c->d_mom64;
-    wa.mom32 = c->d_mom32;
     wa.groups = c->d_groups;
     wa.ngroups = c->d_goff + n;
     wa.nnodes = c->d_noff + n;
