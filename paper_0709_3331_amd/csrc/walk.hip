@@ -387,18 +387,20 @@ __global__ __launch_bounds__(256) void k_walk(WalkArgs a)
             const bool sure_acc = geo.w < th2 * dmin2 * (1.0 - 1e-12);
             const bool sure_open = geo.w >= th2 * dmax2 * (1.0 + 1e-12);
             const bool band = have && !sure_acc && !sure_open;
-            bool acc = sure_acc || band;
-            // members in turn, broadcast from their lanes, while a lane in the
-            // band still accepts
-            unsigned long long live = __ballot(band);
-            for (int m = 0; live != 0ull && m < c; ++m) {
-                const int src = m * lpt;
-                const double dx = readlane_d(xi.x, src) - geo.x;
-                const double dy = readlane_d(xi.y, src) - geo.y;
-                const double dz = readlane_d(xi.z, src) - geo.z;
+            bool acc = sure_acc;
+            // nodes in the band one at a time: the node is broadcast from its
+            // lane and every lane tests its own member
+            unsigned long long bandm = __ballot(band);
+            while (bandm != 0ull) {
+                const int bl = __builtin_ctzll(bandm);
+                bandm &= bandm - 1ull;
+                const double dx = xi.x - readlane_d(geo.x, bl);
+                const double dy = xi.y - readlane_d(geo.y, bl);
+                const double dz = xi.z - readlane_d(geo.z, bl);
                 const double d2 = fma(dz, dz, fma(dy, dy, dx * dx));
-                acc = acc && (!band || geo.w < th2 * d2);
-                live = __ballot(band && acc);
+                const bool fail = act && !(readlane_d(geo.w, bl) < th2 * d2);
+                const bool ok = __ballot(fail) == 0ull;
+                acc = lane == bl ? ok : acc;
             }
             const bool isleaf = (inf.w & 256) != 0;
             const bool leaf_ok = inf.y >= 0 && inf.z >= 0 && (int64_t)inf.y + inf.z <= a.n;
