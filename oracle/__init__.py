@@ -44,7 +44,7 @@ def _load():
         "orc_cube": (i32, [i64, _dp, _dp, C.POINTER(C.c_int)]),
         "orc_keys": (None, [i64, _dp, _dp, i32, i32, _u64p]),
         "orc_sort": (None, [i64, _u64p, _i64p]),
-        "orc_tree_new": (vp, [i64, _dp, _dp, dbl, dbl, i32, i32, i32, i32]),
+        "orc_tree_new": (vp, [i64, _dp, _dp, dbl, dbl, i32, i32, i32, i32, i32]),
         "orc_tree_free": (None, [vp]),
         "orc_tree_nnodes": (i64, [vp]),
         "orc_tree_ngroups": (i64, [vp]),
@@ -59,8 +59,8 @@ def _load():
         "orc_tree_vjp": (i32, [vp, _dp, _dp, _dp, _dp]),
         "orc_tree_arch_series": (i64, [vp, _i64p]),
         "orc_rebuild": (i64, [i64, _i64p, i64, _i64p, _i64p]),
-        "orc_verlet": (i32, [i64, _dp, _dp, _dp, _dp, i32, dbl, dbl, i32, i32, i32, dbl, i32,
-                             _dp, i32]),
+        "orc_verlet": (i32, [i64, _dp, _dp, _dp, _dp, i32, dbl, dbl, i32, i32, i32, i32, dbl,
+                             i32, _dp, i32]),
         "orc_energy": (None, [i64, _dp, _dp, _dp, _dp, _dp]),
         "orc_cell_eval": (None, [_dp, _dp, dbl, _dp, _dp]),
         "orc_cell_jacobian": (None, [_dp, _dp, dbl, _dp]),
@@ -153,15 +153,19 @@ def stable_order(key):
 
 class Tree:
     """Oracle Barnes-Hut tree (C-2): cube, keys, recursive preorder build,
-    centres, canonical groups and (optionally) frozen interaction lists."""
+    centres, walk groups and (optionally) frozen interaction lists.
 
-    def __init__(self, x, q, theta, eps, b=21, leaf_cap=8, G=64, keep_lists=False):
+    group_mode 0: node groups (a node of at most G particles whose parent holds
+    more); group_mode 1: consecutive runs of G key-sorted particles."""
+
+    def __init__(self, x, q, theta, eps, b=21, leaf_cap=8, G=64, keep_lists=False, group_mode=0):
         lib = _load()
         self.x = _f64(x, (-1, 3)); self.q = _f64(q)
         self.n = self.x.shape[0]
         self.theta, self.eps, self.b, self.leaf_cap, self.G = theta, eps, b, leaf_cap, G
+        self.group_mode = group_mode
         h = lib.orc_tree_new(self.n, self.x, self.q, float(theta), float(eps), int(b),
-                             int(leaf_cap), int(G), int(bool(keep_lists)))
+                             int(leaf_cap), int(G), int(group_mode), int(bool(keep_lists)))
         if not h:
             raise ValueError("oracle tree: invalid parameters or non-finite input")
         self._h = h
@@ -289,9 +293,9 @@ def rebuild(series, cap):
     return par[:m], nch[:m]
 
 
-def tree_forces(x, q, theta, eps, b=21, leaf_cap=8, G=64, want_phi=True):
+def tree_forces(x, q, theta, eps, b=21, leaf_cap=8, G=64, want_phi=True, group_mode=0):
     """Convenience: build the oracle tree and evaluate it."""
-    t = Tree(x, q, theta, eps, b, leaf_cap, G)
+    t = Tree(x, q, theta, eps, b, leaf_cap, G, group_mode=group_mode)
     r = t.eval(want_phi=want_phi)
     r["nodes"] = t.nnodes
     r["groups"] = t.ngroups
@@ -302,15 +306,15 @@ def tree_forces(x, q, theta, eps, b=21, leaf_cap=8, G=64, want_phi=True):
 # C-3 Verlet and energies.
 # --------------------------------------------------------------------------
 def verlet(x, v, q, m, dt, nsteps, eps, mode="direct", theta=0.5, b=21, leaf_cap=8, G=64,
-           f=None):
+           f=None, group_mode=0):
     """KDK velocity Verlet; returns (x, v, f) after nsteps (copies)."""
     x = _f64(x, (-1, 3)).copy(); v = _f64(v, (-1, 3)).copy()
     q = _f64(q); m = _f64(m)
     fv = 1 if f is not None else 0
     f = np.zeros_like(x) if f is None else _f64(f, (-1, 3)).copy()
     rc = _load().orc_verlet(x.shape[0], x, v, q, m, 0 if mode == "direct" else 1, float(theta),
-                            float(eps), int(b), int(leaf_cap), int(G), float(dt), int(nsteps),
-                            f, fv)
+                            float(eps), int(b), int(leaf_cap), int(G), int(group_mode), float(dt),
+                            int(nsteps), f, fv)
     if rc != 0:
         raise ValueError("verlet failed")
     return x, v, f

@@ -255,6 +255,7 @@ struct orc_tree {
     double *centre;    /* [M][3] */
     /* groups, in preorder (= sorted position) order */
     int64_t ng, ngcap;
+    int group_mode;    /* 0: node groups, 1: consecutive chunks */
     int64_t *gfirst, *gcount, *gnode;
     /* optional frozen interaction lists per group */
     int keep_lists;
@@ -315,10 +316,14 @@ static void node_centre(const orc_tree *t, int64_t k, double *c)
 
 static double node_side(const orc_tree *t, int64_t k) { return ldexp(1.0, t->e - t->level[k]); }
 
-/* C-2.5  Walk groups: a group is a node holding at most G particles whose    */
-/* parent holds more than G (the root if it holds at most G); a leaf holding  */
-/* more than G particles is cut into consecutive chunks of G.  G = 1 is the   */
-/* per-particle walk of Sec. 3.                                              */
+/* C-2.5  Walk groups.  Node groups (mode 0): a group is a node holding at    */
+/* most G particles whose parent holds more than G (the root if it holds at  */
+/* most G); a leaf holding more than G particles is cut into consecutive      */
+/* chunks of G.  Chunk groups (mode 1): the key-sorted particles are cut into */
+/* consecutive runs of G, the last run holding the remainder; the group node  */
+/* recorded is the root.  In both modes G = 1 is the per-particle walk of     */
+/* Sec. 3.  The group only decides which targets share one opening decision; */
+/* the decision itself is made per member (see C-2.6).                       */
 static void group_add(orc_tree *t, int64_t f, int64_t c, int64_t node)
 {
     if (t->ng == t->ngcap) {
@@ -345,6 +350,12 @@ static void groups_rec(orc_tree *t, int64_t k)
         return;
     }
     for (int64_t ch = k + 1; ch < t->skip[k]; ch = t->skip[ch]) groups_rec(t, ch);
+}
+
+static void groups_chunk(orc_tree *t)
+{
+    for (int64_t f = 0; f < t->n; f += t->G)
+        group_add(t, f, t->n - f < t->G ? t->n - f : t->G, 0);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -467,10 +478,11 @@ static void sorted_copy(const orc_tree *t, const double *x, const double *q, dou
 void orc_tree_free(orc_tree *t);
 
 orc_tree *orc_tree_new(int64_t n, const double *x, const double *q, double theta, double eps,
-                       int b, int leaf_cap, int G, int keep_lists)
+                       int b, int leaf_cap, int G, int group_mode, int keep_lists)
 {
     (void)q;
     if (n < 0 || (b != 10 && b != 21) || leaf_cap < 1 || G < 1) return NULL;
+    if (group_mode != 0 && group_mode != 1) return NULL;
     orc_tree *t = (orc_tree *)calloc(1, sizeof(orc_tree));
     t->n = n;
     t->theta = theta;
@@ -478,6 +490,7 @@ orc_tree *orc_tree_new(int64_t n, const double *x, const double *q, double theta
     t->b = b;
     t->leaf_cap = leaf_cap;
     t->G = G;
+    t->group_mode = group_mode;
     t->keep_lists = keep_lists;
     t->skey = (uint64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(uint64_t));
     t->perm = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
@@ -491,7 +504,8 @@ orc_tree *orc_tree_new(int64_t n, const double *x, const double *q, double theta
     build_rec(t, 0, 0, n);
     t->centre = (double *)malloc((size_t)t->M * 3 * sizeof(double));
     for (int64_t k = 0; k < t->M; ++k) node_centre(t, k, t->centre + 3 * k);
-    groups_rec(t, 0);
+    if (group_mode == 0) groups_rec(t, 0);
+    else groups_chunk(t);
     if (keep_lists) {
         double *xs = (double *)malloc((size_t)n * 3 * sizeof(double));
         sorted_copy(t, x, NULL, xs, NULL);
@@ -837,15 +851,15 @@ int64_t orc_rebuild(int64_t len, const int64_t *series, int64_t cap, int64_t *pa
 /* ------------------------------------------------------------------------- */
 /* C-3  Velocity Verlet, kick-drift-kick (Sec. 2):                            */
 /*   v += dt/2 F(x)/m;  x += dt v;  v += dt/2 F(x')/m.                        */
-/* mode 0: direct forces; mode 1: tree forces at (theta, eps, b, leaf_cap, G), */
-/* the tree rebuilt at every step.  f holds F(x_0) on entry when f_valid,     */
-/* and F(x_n) on exit.                                                       */
+/* mode 0: direct forces; mode 1: tree forces at (theta, eps, b, leaf_cap, G, */
+/* group_mode), the tree rebuilt at every step.  f holds F(x_0) on entry     */
+/* when f_valid, and F(x_n) on exit.                                         */
 /* ------------------------------------------------------------------------- */
 static int forces_any(int mode, int64_t n, const double *x, const double *q, double theta,
-                      double eps, int b, int leaf_cap, int G, double *f)
+                      double eps, int b, int leaf_cap, int G, int group_mode, double *f)
 {
     if (mode == 0) { orc_direct(n, x, q, eps, f, NULL); return 0; }
-    orc_tree *t = orc_tree_new(n, x, q, theta, eps, b, leaf_cap, G, 0);
+    orc_tree *t = orc_tree_new(n, x, q, theta, eps, b, leaf_cap, G, group_mode, 0);
     if (!t) return -1;
     orc_tree_eval(t, x, q, f, NULL, NULL, NULL, NULL);
     orc_tree_free(t);
@@ -853,17 +867,18 @@ static int forces_any(int mode, int64_t n, const double *x, const double *q, dou
 }
 
 int orc_verlet(int64_t n, double *x, double *v, const double *q, const double *m, int mode,
-               double theta, double eps, int b, int leaf_cap, int G, double dt, int nsteps,
-               double *f, int f_valid)
+               double theta, double eps, int b, int leaf_cap, int G, int group_mode, double dt,
+               int nsteps, double *f, int f_valid)
 {
-    if (!f_valid && forces_any(mode, n, x, q, theta, eps, b, leaf_cap, G, f)) return -1;
+    if (!f_valid && forces_any(mode, n, x, q, theta, eps, b, leaf_cap, G, group_mode, f))
+        return -1;
     for (int s = 0; s < nsteps; ++s) {
         for (int64_t i = 0; i < n; ++i)
             for (int d = 0; d < 3; ++d) {
                 v[3 * i + d] += 0.5 * dt * f[3 * i + d] / m[i];
                 x[3 * i + d] += dt * v[3 * i + d];
             }
-        if (forces_any(mode, n, x, q, theta, eps, b, leaf_cap, G, f)) return -1;
+        if (forces_any(mode, n, x, q, theta, eps, b, leaf_cap, G, group_mode, f)) return -1;
         for (int64_t i = 0; i < n; ++i)
             for (int d = 0; d < 3; ++d) v[3 * i + d] += 0.5 * dt * f[3 * i + d] / m[i];
     }

@@ -273,6 +273,42 @@ def test_tree_coincident_particles():
     assert gc.tolist() == [16, 4, 16, 4]
 
 
+@pytest.mark.parametrize("n,G", [(2000, 64), (2000, 7), (64, 64), (6, 64), (2, 1)])
+def test_chunk_groups_are_consecutive_runs(n, G):
+    cl = _rand_cloud(n, 13)
+    t = oracle.Tree(cl.x, cl.q, 0.5, 0.01, leaf_cap=8, G=G, group_mode=1)
+    gf, gc, gn = t.groups()
+    ng = -(-n // G)
+    assert t.ngroups == ng
+    assert gf.tolist() == list(range(0, n, G))
+    assert gc.tolist() == [min(G, n - f) for f in range(0, n, G)]
+    assert np.all(gn == 0)
+    with pytest.raises(ValueError):
+        oracle.Tree(cl.x, cl.q, 0.5, 0.01, G=G, group_mode=2)
+
+
+def test_group_modes_agree_for_single_particle_groups():
+    # G = 1: both rules give the per-particle walk, so lists, counts and forces agree
+    cl = _rand_cloud(1500, 14)
+    r0 = oracle.tree_forces(cl.x, cl.q, 0.6, 0.01, leaf_cap=4, G=1, group_mode=0)
+    r1 = oracle.tree_forces(cl.x, cl.q, 0.6, 0.01, leaf_cap=4, G=1, group_mode=1)
+    assert r0["m2p"] == r1["m2p"] and r0["p2p"] == r1["p2p"]
+    np.testing.assert_array_equal(r0["f"], r1["f"])
+    np.testing.assert_array_equal(r0["phi"], r1["phi"])
+
+
+def test_chunk_group_of_everything_is_one_walk():
+    # one group holding every particle: a box is accepted only if all targets accept it,
+    # so the lists are those of the whole cloud seen as one target set, and the result
+    # converges to the direct sum as theta -> 0
+    cl = _rand_cloud(300, 15)
+    t = oracle.Tree(cl.x, cl.q, 0.3, 0.01, leaf_cap=4, G=300, group_mode=1, keep_lists=True)
+    assert t.ngroups == 1
+    r = t.eval()
+    fd, pd = oracle.direct(cl.x, cl.q, 0.01)
+    assert np.linalg.norm(r["f"] - fd) / np.linalg.norm(fd) < 1e-3
+
+
 def test_arch_series_rebuild_roundtrip():
     cl = _rand_cloud(3000, 12)
     t = oracle.Tree(cl.x, cl.q, 0.5, 0.01, leaf_cap=4)
@@ -435,10 +471,12 @@ def test_tree_error_falls_with_theta():
     assert errs[2] < 1e-3 and errs[3] < 1e-4
 
 
-def test_walk_lists_cover_every_source_once_and_respect_mac():
+@pytest.mark.parametrize("group_mode", [0, 1])
+def test_walk_lists_cover_every_source_once_and_respect_mac(group_mode):
     cl = _rand_cloud(700, 18)
     theta, G = 0.6, 16
-    t = oracle.Tree(cl.x, cl.q, theta, 0.01, leaf_cap=4, G=G, keep_lists=True)
+    t = oracle.Tree(cl.x, cl.q, theta, 0.01, leaf_cap=4, G=G, keep_lists=True,
+                    group_mode=group_mode)
     lv, fi, co, sk = t.nodes()
     cen = t.centres()
     lo, e = t.cube()
@@ -458,12 +496,14 @@ def test_walk_lists_cover_every_source_once_and_respect_mac():
         assert np.all(covered == 1)
 
 
-def test_walk_brute_force_tiny():
+@pytest.mark.parametrize("group_mode,G", [(0, 4), (1, 4), (1, 5)])
+def test_walk_brute_force_tiny(group_mode, G):
     # brute force from the definition: a node is in the accepted list of a group
     # iff every member accepts it and every strict ancestor is rejected by some member
     cl = _rand_cloud(16, 19)
     theta = 0.9
-    t = oracle.Tree(cl.x, cl.q, theta, 0.01, b=21, leaf_cap=1, G=4, keep_lists=True)
+    t = oracle.Tree(cl.x, cl.q, theta, 0.01, b=21, leaf_cap=1, G=G, keep_lists=True,
+                    group_mode=group_mode)
     lv, fi, co, sk = t.nodes()
     cen = t.centres()
     lo, e = t.cube()
