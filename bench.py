@@ -59,6 +59,7 @@ def main():
     ap.add_argument("--theta", type=float, default=0.5)
     ap.add_argument("--group-size", type=int, default=64)
     ap.add_argument("--list-len", type=int, default=128)
+    ap.add_argument("--group-mode", choices=["node", "chunk"], default="chunk")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 comparator run")
     ap.add_argument("--profile", action="store_true", help="short run for rocprofv3 (no extras)")
@@ -87,8 +88,9 @@ def main():
     v = torch.from_numpy(cl.v).to(dev)
     q = torch.from_numpy(cl.q).to(dev)
     m = torch.from_numpy(cl.m).to(dev)
+    gm = L.UCP_GROUP_CHUNK if args.group_mode == "chunk" else L.UCP_GROUP_NODE
     ts = TreeSolver(n, theta=theta, eps=eps, precision=prec, group_size=args.group_size,
-                    list_len=args.list_len)
+                    list_len=args.list_len, group_mode=gm)
     print(f"bench: N={n} theta={theta} precision={args.precision}", file=sys.stderr, flush=True)
 
     # initial forces; interaction counts of one evaluation
@@ -131,9 +133,11 @@ def main():
         "dtype": "f32-interactions/f64-accumulate" if prec == L.UCP_SPLIT else "f64",
         "data": "synthetic",
         "config": {"workload": f"single two-component Gaussian cloud N=524288 (sigma=1, 5% halo "
-                               f"shell 2-3 sigma), theta={theta:g}, eps=0.005, G={args.group_size}, "
+                               f"shell 2-3 sigma), theta={theta:g}, eps=0.005, G={args.group_size} "
+                               f"({args.group_mode} groups), "
                                f"leaf_cap=8, 63-bit keys, one KDK Verlet step dt=5e-5",
-                   "n": n, "theta": theta, "precision": args.precision},
+                   "n": n, "theta": theta, "precision": args.precision,
+                   "group_size": args.group_size, "group_mode": args.group_mode},
         "interactions_per_s": inter / (walk_avg_ms * 1e-3),
         "interactions_per_particle": inter / n,
         "walk_ms": walk_avg_ms,
@@ -146,7 +150,7 @@ def main():
         # against the FP64 oracle direct sum on sampled targets
         f_split = ts.tree_forces(x, q)
         ts64 = TreeSolver(n, theta=theta, eps=eps, precision=L.UCP_FP64,
-                          group_size=args.group_size, list_len=args.list_len)
+                          group_size=args.group_size, list_len=args.list_len, group_mode=gm)
         f64 = ts64.tree_forces(x, q)
         ts64.timing(True)
         torch.cuda.synchronize()
@@ -170,7 +174,7 @@ def main():
         result["rel_force_err_vs_direct_sampled"] = float(
             np.linalg.norm(fs[tg] - fd) / np.linalg.norm(fd))
         c0 = time.perf_counter()
-        ot = oracle.Tree(xs, qs, theta, eps, G=args.group_size)
+        ot = oracle.Tree(xs, qs, theta, eps, G=args.group_size, group_mode=gm)
         ro = ot.eval(want_phi=False)
         c1 = time.perf_counter()
         result["rel_force_err_vs_oracle_tree"] = float(

@@ -51,6 +51,17 @@ typedef enum {
                               per-particle accumulators and FP64 energy sums          */
 } ucp_precision;
 
+/* Walk groups.  The targets of one group share one traversal of the tree;
+ * each member still takes its own decision of Eq. (5), and a box is opened
+ * for the group iff any member rejects it.  Both rules give the per-particle
+ * walk of Sec. 3 at G = 1.                                                   */
+typedef enum {
+    UCP_GROUP_NODE = 0,    /* a node holding <= G particles whose parent holds > G
+                              (a leaf holding > G is cut into runs of G)             */
+    UCP_GROUP_CHUNK = 1    /* consecutive runs of G particles in key order, per
+                              cloud; the last run of a cloud holds the remainder     */
+} ucp_group_mode;
+
 /* Method parameters.  The opening test is Eq. (5), s/theta + delta < d, with
  * the pseudo-particle expanded about the box centre (delta = 0), s the box
  * side and d the distance from the target to the box centre; it is evaluated
@@ -61,12 +72,13 @@ typedef struct {
     double eps;            /* Plummer softening, > 0                                      */
     int32_t key_bits;      /* 30 or 63 (key depth b = 10 or 21 levels)                   */
     int32_t leaf_cap;      /* a box holding more particles is split (Sec. 3 uses 1); 1..64 */
-    int32_t group_size;    /* G: a walk group is a node with <= G particles whose parent
-                              has > G (a leaf with > G is cut into chunks of G); 1..64   */
+    int32_t group_size;    /* G: largest walk group, 1..64; see group_mode            */
     int32_t list_len;      /* capacity of each LDS interaction list of a walk group,
                               64..512; changes only the summation order                  */
     int32_t precision;     /* ucp_precision                                              */
     int32_t walk_waves;    /* resident waves per CU for the persistent walk, 0 = auto    */
+    int32_t group_mode;    /* ucp_group_mode: how the sorted particles are cut into
+                              walk groups                                                */
 } ucp_params;
 
 typedef struct ucp_ctx ucp_ctx;   /* opaque */
@@ -91,7 +103,7 @@ typedef struct {
 #define UCP_FLAG_WALK_STACK     32   /* a walk group overflowed its traversal stack     */
 
 /* Default parameters: theta 0.5, eps 0.005, 63-bit keys, leaf_cap 8, G 64,
- * list_len 128, UCP_SPLIT, walk_waves 0.                                     */
+ * list_len 128, UCP_SPLIT, walk_waves 0, UCP_GROUP_CHUNK.                    */
 void ucp_default_params(ucp_params *p);
 
 /* Create a context on the current HIP device able to hold n_max particles in
@@ -102,7 +114,7 @@ ucp_status ucp_create(ucp_ctx **out, int64_t n_max, int32_t clouds_max, const uc
 void ucp_destroy(ucp_ctx *c);
 
 /* Replace the parameters (validated as in ucp_create).  A tree built before
- * with other key_bits/leaf_cap/group_size must be rebuilt.                  */
+ * with other key_bits/leaf_cap/group_size/group_mode must be rebuilt.        */
 ucp_status ucp_set_params(ucp_ctx *c, const ucp_params *p);
 ucp_status ucp_get_params(const ucp_ctx *c, ucp_params *p);
 

@@ -43,6 +43,10 @@ bool validate(const ucp_params *p, std::string &why)
     if (p->list_len < 64 || p->list_len > 512) { why = "list_len must be in 64..512"; return false; }
     if (p->precision != UCP_FP64 && p->precision != UCP_SPLIT) { why = "precision must be UCP_FP64 or UCP_SPLIT"; return false; }
     if (p->walk_waves < 0 || p->walk_waves > 64) { why = "walk_waves must be in 0..64"; return false; }
+    if (p->group_mode != UCP_GROUP_NODE && p->group_mode != UCP_GROUP_CHUNK) {
+        why = "group_mode must be UCP_GROUP_NODE or UCP_GROUP_CHUNK";
+        return false;
+    }
     return true;
 }
 
@@ -154,6 +158,7 @@ void ucp_default_params(ucp_params *p)
     p->list_len = 128;
     p->precision = UCP_SPLIT;
     p->walk_waves = 0;
+    p->group_mode = UCP_GROUP_CHUNK;
 }
 
 const char *ucp_last_error(const ucp_ctx *c)
@@ -244,7 +249,7 @@ ucp_status ucp_set_params(ucp_ctx *c, const ucp_params *p)
     std::string why;
     if (!validate(p, why)) return fail(c, UCP_EINVAL, "ucp_set_params: " + why);
     const bool topo = p->key_bits != c->p.key_bits || p->leaf_cap != c->p.leaf_cap ||
-                      p->group_size != c->p.group_size;
+                      p->group_size != c->p.group_size || p->group_mode != c->p.group_mode;
     c->p = *p;
     if (topo) c->built = 0;
     else if (c->built) {

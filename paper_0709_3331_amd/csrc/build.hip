@@ -653,13 +653,22 @@ __global__ __launch_bounds__(256) void k_moments_level(
 __global__ __launch_bounds__(256) void k_group_count(
     int64_t n, const int8_t *__restrict__ Lv, const int8_t *__restrict__ Lf,
     const int32_t *__restrict__ noff, const int4 *__restrict__ ninfo,
-    const int32_t *__restrict__ npar, int G, int32_t *cnt, int32_t *gnode, const int32_t *flags)
+    const int32_t *__restrict__ npar, const int64_t *__restrict__ off, int clouds, int G,
+    int mode, int32_t *cnt, int32_t *gnode, const int32_t *flags)
 {
     const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (p > n) return;
     if (p == n || *flags) { cnt[p] = 0; return; }
-    const int Lp = Lv[p], lf = Lf[p];
     int ng = 0, gn = -1;
+    if (mode == UCP_GROUP_CHUNK) {
+        // a run of G starts at every G-th particle of the cloud
+        const int64_t o = off[cloud_of(off, clouds, p)];
+        if ((p - o) % G == 0) { ng = 1; gn = noff[o]; }
+        cnt[p] = ng;
+        gnode[p] = gn;
+        return;
+    }
+    const int Lp = Lv[p], lf = Lf[p];
     if (lf > Lp) {
         const int k0 = noff[p];
         for (int l = Lp + 1; l <= lf; ++l) {
@@ -683,7 +692,7 @@ __global__ __launch_bounds__(256) void k_group_emit(
     int64_t n, const int32_t *__restrict__ cnt, const int32_t *__restrict__ goff,
     const int32_t *__restrict__ gnode, const int4 *__restrict__ ninfo,
     const int32_t *__restrict__ noff, const int64_t *__restrict__ off, int clouds, int G,
-    int4 *groups, const int32_t *flags)
+    int mode, int4 *groups, const int32_t *flags)
 {
     if (*flags) return;
     const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -691,8 +700,10 @@ __global__ __launch_bounds__(256) void k_group_emit(
     const int ng = cnt[p];
     if (ng == 0) return;
     const int k = gnode[p];
-    const int c = ninfo[k].y;
-    const int root = noff[off[cloud_of(off, clouds, p)]];
+    const int cl = cloud_of(off, clouds, p);
+    const int root = noff[off[cl]];
+    // particles left to cut from p on: the node's (node groups) or the cloud's (chunks)
+    const int c = mode == UCP_GROUP_CHUNK ? (int)(off[cl + 1] - p) : ninfo[k].y;
     for (int j = 0; j < ng; ++j) {
         const int gc = min(G, c - j * G);
         groups[goff[p] + j] = make_int4((int)p + j * G, gc, k, root);
@@ -808,14 +819,14 @@ void launch_build(Ctx *c, const double *x, const double *q, const int64_t *offse
     hipLaunchKernelGGL(k_group_count, grid_for(n + 1, 256), dim3(256), 0, s, n,
                        (const int8_t *)c->d_L, (const int8_t *)c->d_leaf,
                        (const int32_t *)c->d_noff, (const int4 *)c->d_ninfo,
-                       (const int32_t *)c->d_npar, G, c->d_cnt, c->d_gnode,
-                       (const int32_t *)c->d_flags);
+                       (const int32_t *)c->d_npar, (const int64_t *)c->d_off, clouds, G,
+                       c->p.group_mode, c->d_cnt, c->d_gnode, (const int32_t *)c->d_flags);
     scan_excl((const int32_t *)c->d_cnt, c->d_goff, n + 1, c->d_scanblk, s);
     hipLaunchKernelGGL(k_group_emit, grid_for(n, 256), dim3(256), 0, s, n,
                        (const int32_t *)c->d_cnt, (const int32_t *)c->d_goff,
                        (const int32_t *)c->d_gnode, (const int4 *)c->d_ninfo,
                        (const int32_t *)c->d_noff, (const int64_t *)c->d_off, clouds, G,
-                       c->d_groups, (const int32_t *)c->d_flags);
+                       c->p.group_mode, c->d_groups, (const int32_t *)c->d_flags);
 }
 
 }  // namespace ucp

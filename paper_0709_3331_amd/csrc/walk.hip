@@ -23,13 +23,13 @@
 // Precision (template PREC):
 //   UCP_FP64  -- staged entries are FP64 (absolute box centres and positions),
 //                the interaction arithmetic is FP64 (r = x_i - c, x_i - x_j).
-//   UCP_SPLIT -- staged entries are FP32 offsets from the group box centre
-//                c_g, formed in FP64 and rounded once (box centre - c_g,
-//                source - c_g), with FP32 moments rounded from the FP64 ones;
-//                the target offset x_i - c_g is also formed in FP64 and
-//                rounded once.  The interaction arithmetic is FP32; partial
-//                sums of each flushed list are FP32 and are accumulated into
-//                FP64 per-lane accumulators.
+//   UCP_SPLIT -- staged entries are FP32 offsets from c_g, the centre of the
+//                members' bounding box, formed in FP64 and rounded once (box
+//                centre - c_g, source - c_g), with FP32 moments rounded from
+//                the FP64 ones; the target offset x_i - c_g is also formed in
+//                FP64 and rounded once.  The interaction arithmetic is FP32;
+//                partial sums of each flushed list are FP32 and are
+//                accumulated into FP64 per-lane accumulators.
 //
 // No divergent branch encloses a wave-level operation or the loop heads of
 // the persistent loop: list staging writes one value per lane, idle lanes
@@ -335,7 +335,13 @@ __global__ __launch_bounds__(256) void k_walk(WalkArgs a)
         const bool act = t < c;
         const int i = gfirst + (act ? t : 0);
         const double4 xi = a.xq[i];
-        const double4 cg = *(const double4 *)(a.nrec + 8 * (int64_t)gnode);
+        // bounding box of the members; its centre c_g is the origin of the
+        // FP32 offsets
+        const double bminx = wave_fmin(act ? xi.x : INFINITY), bmaxx = wave_fmax(act ? xi.x : -INFINITY);
+        const double bminy = wave_fmin(act ? xi.y : INFINITY), bmaxy = wave_fmax(act ? xi.y : -INFINITY);
+        const double bminz = wave_fmin(act ? xi.z : INFINITY), bmaxz = wave_fmax(act ? xi.z : -INFINITY);
+        const double4 cg = make_double4(0.5 * (bminx + bmaxx), 0.5 * (bminy + bmaxy),
+                                        0.5 * (bminz + bmaxz), 0.0);
         T tx, ty, tz;
         if constexpr (PREC == UCP_SPLIT) {
             tx = (float)(xi.x - cg.x);
@@ -346,10 +352,6 @@ __global__ __launch_bounds__(256) void k_walk(WalkArgs a)
             ty = xi.y;
             tz = xi.z;
         }
-        // bounding box of the members (lane m * lpt holds member m)
-        const double bminx = wave_fmin(act ? xi.x : INFINITY), bmaxx = wave_fmax(act ? xi.x : -INFINITY);
-        const double bminy = wave_fmin(act ? xi.y : INFINITY), bmaxy = wave_fmax(act ? xi.y : -INFINITY);
-        const double bminz = wave_fmin(act ? xi.z : INFINITY), bmaxz = wave_fmax(act ? xi.z : -INFINITY);
         stk[0] = make_int2(root, min(((const int *)(a.nrec + 8 * (int64_t)root + 2))[0], nn));
         int sp = 1;
         wave_sync();

@@ -37,14 +37,14 @@ def test_oracle_is_not_linked_into_the_library():
 def test_default_params_and_version():
     p = L.default_params()
     assert p.theta == 0.5 and p.key_bits == 63 and p.leaf_cap == 8 and p.group_size == 64
-    assert p.precision == L.UCP_SPLIT
+    assert p.precision == L.UCP_SPLIT and p.group_mode == L.UCP_GROUP_CHUNK
     assert L.ucp_version() >= 100
 
 
 @pytest.mark.parametrize("over", [dict(theta=-0.1), dict(theta=1.2), dict(eps=0.0),
                                   dict(key_bits=32), dict(leaf_cap=0), dict(leaf_cap=65),
                                   dict(group_size=0), dict(group_size=65), dict(list_len=8), dict(list_len=600),
-                                  dict(precision=3)])
+                                  dict(precision=3), dict(group_mode=2), dict(group_mode=-1)])
 def test_create_rejects_bad_params_without_gpu(over):
     p = L.default_params(**over)
     with pytest.raises(L.UcpError) as ei:

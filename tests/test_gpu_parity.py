@@ -72,28 +72,34 @@ def check_moments(ts, t, x, q):
     assert np.all(np.abs(got - ref) <= 1e-13 * scale)
 
 
+NODE, CHUNK = L.UCP_GROUP_NODE, L.UCP_GROUP_CHUNK
 CASES = [
-    # id, n, seed, theta, eps, leaf_cap, G, key_bits, halo
-    ("small", 4096, 0, 0.5, 0.01, 8, 64, 63, 0.0),
-    ("ragged", 3002, 1, 0.6, 0.01, 4, 32, 30, 0.0),
-    ("per-particle", 1000, 2, 0.7, 0.02, 1, 1, 63, 0.0),
-    ("halo", 20000, 3, 0.5, 0.005, 8, 64, 63, 0.05),
-    ("tiles", 70002, 4, 0.3, 0.005, 16, 48, 63, 0.0),
+    # id, n, seed, theta, eps, leaf_cap, G, key_bits, halo, group_mode
+    ("small", 4096, 0, 0.5, 0.01, 8, 64, 63, 0.0, NODE),
+    ("ragged", 3002, 1, 0.6, 0.01, 4, 32, 30, 0.0, NODE),
+    ("per-particle", 1000, 2, 0.7, 0.02, 1, 1, 63, 0.0, NODE),
+    ("halo", 20000, 3, 0.5, 0.005, 8, 64, 63, 0.05, NODE),
+    ("tiles", 70002, 4, 0.3, 0.005, 16, 48, 63, 0.0, NODE),
+    ("chunk-small", 4096, 0, 0.5, 0.01, 8, 64, 63, 0.0, CHUNK),
+    ("chunk-ragged", 3002, 1, 0.6, 0.01, 4, 24, 30, 0.0, CHUNK),
+    ("chunk-halo", 20000, 3, 0.5, 0.005, 8, 32, 63, 0.05, CHUNK),
+    ("chunk-per-particle", 1000, 2, 0.7, 0.02, 1, 1, 63, 0.0, CHUNK),
 ]
 
 
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
 def test_tree_parity(case):
-    name, n, seed, theta, eps, cap, G, kb, halo = case
-    say(f"[parity] case={name} n={n} seed={seed} theta={theta} G={G} leaf_cap={cap} bits={kb}")
+    name, n, seed, theta, eps, cap, G, kb, halo, gm = case
+    say(f"[parity] case={name} n={n} seed={seed} theta={theta} G={G} leaf_cap={cap} bits={kb} "
+        f"group_mode={gm}")
     cl = inputs.gaussian_cloud(n, 1.0, 1e-3, 1e-5, seed, halo_frac=halo)
     b = 21 if kb == 63 else 10
-    t = oracle.Tree(cl.x, cl.q, theta, eps, b=b, leaf_cap=cap, G=G)
+    t = oracle.Tree(cl.x, cl.q, theta, eps, b=b, leaf_cap=cap, G=G, group_mode=gm)
     ref = t.eval(group_counts=True)
     x, q = dev(cl.x), dev(cl.q)
     for prec, tol in ((L.UCP_FP64, TOL_FP64), (L.UCP_SPLIT, TOL_SPLIT)):
         ts = TreeSolver(n, 1, theta=theta, eps=eps, leaf_cap=cap, group_size=G, key_bits=kb,
-                        precision=prec, list_len=64)
+                        precision=prec, list_len=64, group_mode=gm)
         f, phi = ts.tree_forces(x, q, want_phi=True)
         st = ts.stats()
         say(f"[parity]   prec={prec} nodes={st['nodes']} groups={st['groups']} "
@@ -169,9 +175,10 @@ def test_nonfinite_input_is_flagged():
     ts.close()
 
 
-def test_batched_clouds_match_independent_clouds():
+@pytest.mark.parametrize("gm", [NODE, CHUNK])
+def test_batched_clouds_match_independent_clouds(gm):
     sizes = [100, 0, 2000, 74, 4096, 2]
-    say(f"[parity] batched clouds sizes={sizes}")
+    say(f"[parity] batched clouds sizes={sizes} group_mode={gm}")
     parts = [inputs.gaussian_cloud(s, 0.5 + 0.3 * k, 1e-3, 1e-5, 100 + k) if s else None
              for k, s in enumerate(sizes)]
     x = np.concatenate([p.x for p in parts if p is not None])
@@ -179,7 +186,8 @@ def test_batched_clouds_match_independent_clouds():
     off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
     n = int(off[-1])
     for prec, tol in ((L.UCP_FP64, TOL_FP64), (L.UCP_SPLIT, TOL_SPLIT)):
-        ts = TreeSolver(n, len(sizes), theta=0.5, eps=0.01, precision=prec, group_size=32)
+        ts = TreeSolver(n, len(sizes), theta=0.5, eps=0.01, precision=prec, group_size=32,
+                        group_mode=gm)
         f, phi = ts.tree_forces(dev(x), dev(q), offsets=torch.from_numpy(off).cuda(), want_phi=True)
         st = ts.stats()
         f, phi = f.cpu().numpy(), phi.cpu().numpy()
@@ -187,7 +195,7 @@ def test_batched_clouds_match_independent_clouds():
             if p is None:
                 continue
             a, b = off[k], off[k + 1]
-            ref = oracle.tree_forces(p.x, p.q, 0.5, 0.01, G=32)
+            ref = oracle.tree_forces(p.x, p.q, 0.5, 0.01, G=32, group_mode=gm)
             assert relrms(f[a:b], ref["f"]) < tol, k
             assert relrms(phi[a:b], ref["phi"]) < tol, k
         cube = ts.debug("cube")
@@ -197,6 +205,14 @@ def test_batched_clouds_match_independent_clouds():
                 np.testing.assert_array_equal(cube[k, :3], lo)
                 assert cube[k, 3] == e
         assert st["clouds"] == len(sizes)
+        # groups: each cloud's own groups, shifted by the cloud's offset
+        gr = ts.debug("groups")
+        want = []
+        for k, p in enumerate(parts):
+            if p is not None:
+                gf, gc, _ = oracle.Tree(p.x, p.q, 0.5, 0.01, G=32, group_mode=gm).groups()
+                want += [(off[k] + a, c) for a, c in zip(gf, gc)]
+        assert [tuple(r) for r in gr[:, :2].tolist()] == [tuple(w) for w in np.array(want).tolist()]
         ts.close()
 
 
@@ -273,12 +289,13 @@ def test_graph_replay_matches_eager_steps():
     ts.close()
 
 
-def test_full_size_metric_cloud():
+@pytest.mark.parametrize("gm,G", [(NODE, 64), (CHUNK, 64), (CHUNK, 32)])
+def test_full_size_metric_cloud(gm, G):
     c, prm = inputs.metric(0)
     n = c.n
-    say(f"[parity] metric cloud n={n} theta={prm['theta']}")
-    t = oracle.Tree(c.x, c.q, prm["theta"], prm["eps"], G=64)
-    ts = TreeSolver(n, theta=prm["theta"], eps=prm["eps"])
+    say(f"[parity] metric cloud n={n} theta={prm['theta']} group_mode={gm} G={G}")
+    t = oracle.Tree(c.x, c.q, prm["theta"], prm["eps"], G=G, group_mode=gm)
+    ts = TreeSolver(n, theta=prm["theta"], eps=prm["eps"], group_size=G, group_mode=gm)
     x, q = dev(c.x), dev(c.q)
     f = ts.tree_forces(x, q)
     st = ts.stats()

@@ -185,7 +185,7 @@ def test_sort_is_stable_library_order():
 # --------------------------------------------------------------------------
 def test_tiny_tree_golden():
     g = _gold("tiny_tree.json")
-    t = oracle.Tree(g["x"], g["q"], 0.5, 0.01, b=g["b"], leaf_cap=g["leaf_cap"], G=1)
+    t = oracle.Tree(g["x"], g["q"], 0.5, 0.01, b=g["b"], leaf_cap=g["leaf_cap"], G=1, group_mode=0)
     lo, e = t.cube()
     assert list(lo) == g["lo"] and e == g["e"]
     assert [int(v) for v in oracle.keys(g["x"], lo, e, g["b"])] == g["keys"]
@@ -197,9 +197,14 @@ def test_tiny_tree_golden():
     assert list(t.arch_series()) == g["arch_series"]
     gf, gc, gn = t.groups()
     assert [list(v) for v in zip(gf, gc, gn)] == g["groups_G1"]
-    t2 = oracle.Tree(g["x"], g["q"], 0.5, 0.01, b=g["b"], leaf_cap=g["leaf_cap"], G=2)
+    t2 = oracle.Tree(g["x"], g["q"], 0.5, 0.01, b=g["b"], leaf_cap=g["leaf_cap"], G=2, group_mode=0)
     gf, gc, gn = t2.groups()
     assert [list(v) for v in zip(gf, gc, gn)] == g["groups_G2"]
+    for G in (2, 3):
+        tc = oracle.Tree(g["x"], g["q"], 0.5, 0.01, b=g["b"], leaf_cap=g["leaf_cap"], G=G,
+                         group_mode=1)
+        gf, gc, gn = tc.groups()
+        assert [list(v) for v in zip(gf, gc, gn)] == g[f"groups_chunk_G{G}"]
     m = t.moments()[3]
     ref = g["moments_node3"]
     assert m[0] == ref["Q"]
@@ -258,14 +263,14 @@ def _check_tree_invariants(t, x, leaf_cap, G):
 @pytest.mark.parametrize("leaf_cap,G,b", [(1, 1, 21), (8, 64, 21), (4, 16, 10), (16, 8, 21)])
 def test_tree_invariants_random(leaf_cap, G, b):
     cl = _rand_cloud(2000, 11)
-    t = oracle.Tree(cl.x, cl.q, 0.5, 0.01, b=b, leaf_cap=leaf_cap, G=G)
+    t = oracle.Tree(cl.x, cl.q, 0.5, 0.01, b=b, leaf_cap=leaf_cap, G=G, group_mode=0)
     _check_tree_invariants(t, cl.x, leaf_cap, G)
 
 
 def test_tree_coincident_particles():
     x = np.zeros((40, 3)); x[20:] = 1.0
     q = np.ones(40)
-    t = oracle.Tree(x, q, 0.5, 0.01, b=21, leaf_cap=8, G=16)
+    t = oracle.Tree(x, q, 0.5, 0.01, b=21, leaf_cap=8, G=16, group_mode=0)
     _check_tree_invariants(t, x, 8, 16)
     lv, fi, co, sk = t.nodes()
     assert lv.max() == 21 and co[lv == 21].tolist() == [20, 20]
