@@ -22,7 +22,7 @@ sys.path.insert(0, ROOT)
 # algorithmic FLOPs per interaction, counted from the FP32 evaluation code
 # (add, sub, mul = 1; fma = 2; rsqrt = 1); forces only (no potential)
 P2P_FLOPS = 19
-M2P_FLOPS = 68
+M2P_FLOPS = 63
 PEAK_FP32_TFLOPS = 157.3      # MI355X vector FP32 (packed) -- published peak
 PEAK_FP64_TFLOPS = 78.6
 WALK_SOURCES = ["paper_0709_3331_amd/csrc/walk.hip", "paper_0709_3331_amd/csrc/internal.h"]
@@ -62,6 +62,8 @@ def main():
     ap.add_argument("--group-mode", choices=["node", "chunk"], default="chunk")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 comparator run")
+    ap.add_argument("--no-theta-sweep", action="store_true",
+                    help="skip the theta = 0.3 / 0.7 accuracy and cost lines")
     ap.add_argument("--profile", action="store_true", help="short run for rocprofv3 (no extras)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 256 MiB device-to-device copy (counter calibration)")
@@ -173,6 +175,29 @@ def main():
         fd, _ = oracle.direct_targets(xs, qs, eps, tg)
         result["rel_force_err_vs_direct_sampled"] = float(
             np.linalg.norm(fs[tg] - fd) / np.linalg.norm(fd))
+        if not args.no_theta_sweep:
+            # the other opening parameters of the same workload: walk time,
+            # interactions per particle, error against the sampled direct sum
+            sweep = {}
+            for th in (0.3, 0.5, 0.7):
+                tt = TreeSolver(n, theta=th, eps=eps, precision=prec, group_size=args.group_size,
+                                list_len=args.list_len, group_mode=gm)
+                ft = tt.tree_forces(x, q)
+                tt.timing(True)
+                torch.cuda.synchronize()
+                for _ in range(3):
+                    tt.tree_forces(x, q)
+                torch.cuda.synchronize()
+                wm, wc = tt.timing_read()
+                stt = tt.stats()
+                fa = ft.cpu().numpy()
+                sweep[f"{th:g}"] = {
+                    "walk_ms": wm / max(wc, 1),
+                    "interactions_per_particle": (stt["p2p"] + stt["m2p"]) / n,
+                    "rel_force_err_vs_direct_sampled":
+                        float(np.linalg.norm(fa[tg] - fd) / np.linalg.norm(fd))}
+                tt.close()
+            result["theta_sweep"] = sweep
         c0 = time.perf_counter()
         ot = oracle.Tree(xs, qs, theta, eps, G=args.group_size, group_mode=gm)
         ro = ot.eval(want_phi=False)

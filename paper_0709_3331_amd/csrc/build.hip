@@ -10,12 +10,13 @@
 //      key and the level of the leaf holding it; the nodes that start at a
 //      position are the levels in between, so a scan numbers all nodes in
 //      preorder (node order = (first particle, level)),
-//   5. node records (extent by galloping search over the sorted keys, skip
-//      link = first node after the subtree, parent, box centre),
-//   6. moments (Q, p, S about the box centre, FP64) bottom-up: a leaf sums its
-//      particles, the last child to arrive at a parent sums the children in
-//      octant order with the exact shift of origin (deterministic),
-//   7. walk groups (a node with <= G particles whose parent has more).
+//   5. node records (box centre, side, first particle, level),
+//   6. moments (Q, p, S about the box centre, FP64), one level per launch from
+//      the deepest up: a leaf sums its particles, an internal node sums its
+//      children in octant order with the exact shift of origin; the same pass
+//      finds each node's particle count, skip link (first node after the
+//      subtree) and its children's parent,
+//   7. walk groups (node groups or consecutive runs of G particles).
 // Every kernel first checks the device flag word and does nothing once a
 // problem (capacity, non-finite input, bad offsets) has been flagged.
 #include "internal.h"
@@ -298,8 +299,42 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_down(const int32_t *__restr
     }
 }
 
+// one block scans a short array whose length is a multiple of 4: thread j
+// holds elements [64 j, 64 j + 64) in registers (16-byte loads), the thread
+// sums are scanned across the block, and the prefixes are written back
+__global__ __launch_bounds__(kScanBlock) void k_scan_small(const int4 *__restrict__ in, int4 *out,
+                                                          int n4)
+{
+    __shared__ int tot;
+    constexpr int V = kScanSmallItems / 4;
+    const int b0 = threadIdx.x * V;
+    int4 v[V];
+    int sum = 0;
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+        v[j] = b0 + j < n4 ? in[b0 + j] : make_int4(0, 0, 0, 0);
+        sum += v[j].x + v[j].y + v[j].z + v[j].w;
+    }
+    int ex = block_excl_scan(sum, &tot);
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+        int4 o;
+        o.x = ex;
+        o.y = o.x + v[j].x;
+        o.z = o.y + v[j].y;
+        o.w = o.z + v[j].z;
+        ex = o.w + v[j].w;
+        if (b0 + j < n4) out[b0 + j] = o;
+    }
+}
+
 static void scan_excl(const int32_t *in, int32_t *out, int64_t n, int32_t *blk, hipStream_t s)
 {
+    if (n <= kScanSmallLimit && n % 4 == 0) {
+        hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(kScanBlock), 0, s, (const int4 *)in,
+                           (int4 *)out, (int)(n / 4));
+        return;
+    }
     const int64_t per = (int64_t)kScanBlock * kScanItems;
     int nb = (int)((n + per - 1) / per);
     hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanBlock), 0, s, in, n, blk);
@@ -309,11 +344,13 @@ static void scan_excl(const int32_t *in, int32_t *out, int64_t n, int32_t *blk, 
 }
 
 // ---------------------------------------------------------------------------
-// 3. stable LSD radix sort of (key, index), 8-bit digits.  A tile of
-//    kSortTile elements is processed in rounds of 256; inside a round each
-//    wave ranks equal digits with ballots, waves are ordered through LDS, and
-//    a running count per digit carries the order across rounds.  The last
-//    pass(es) of a multi-cloud build sort by cloud, restoring the clouds'
+// 3. stable LSD radix sort of (key, index), 8-bit digits.  Per pass: a
+//    per-tile digit histogram (digit-major), its exclusive scan (the output
+//    offset of each (digit, tile)), and the scatter.  The scatter processes a
+//    tile of kSortTile elements in rounds of kSortThreads; inside a round each
+//    wave ranks equal digits with ballots, the 16 waves are ordered through
+//    LDS, and a running count per digit carries the order across rounds.  The
+//    last pass(es) of a multi-cloud build sort by cloud, restoring the clouds'
 //    contiguity while keeping key order inside each cloud.
 // ---------------------------------------------------------------------------
 template <bool CLOUD>
@@ -331,7 +368,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(
 {
     __shared__ uint32_t h[256];
     if (*flags) return;
-    h[threadIdx.x] = 0;
+    if (threadIdx.x < 256) h[threadIdx.x] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
     for (int it = 0; it < kSortItems; ++it) {
@@ -342,7 +379,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(
         }
     }
     __syncthreads();
-    hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
+    if (threadIdx.x < 256) hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
 }
 
 template <bool CLOUD>
@@ -351,18 +388,23 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     uint32_t *vout, int64_t n, int shift, const int64_t *__restrict__ off, int clouds,
     const uint32_t *__restrict__ hscan, int ntiles, const int32_t *flags)
 {
+    constexpr int NW = kSortThreads / 64;
     __shared__ uint32_t run[256];
-    __shared__ uint32_t wh[kSortThreads / 64][256];
+    __shared__ uint32_t wh[2][NW][256];   // per-wave digit counts, double-buffered by round
     __shared__ uint32_t boff[256];
     if (*flags) return;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    run[tid] = 0;
-    boff[tid] = hscan[(int64_t)tid * ntiles + blockIdx.x];
+    if (tid < 256) {
+        run[tid] = 0;
+        boff[tid] = hscan[(int64_t)tid * ntiles + blockIdx.x];
+    }
+    for (int j = tid; j < NW * 256; j += kSortThreads) wh[0][j / 256][j % 256] = 0;
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    __syncthreads();
     for (int it = 0; it < kSortItems; ++it) {
-        for (int ww = 0; ww < kSortThreads / 64; ++ww) wh[ww][tid] = 0;
-        __syncthreads();
+        uint32_t(*cw)[256] = wh[it & 1];
+        uint32_t(*nw)[256] = wh[(it + 1) & 1];
         const int64_t e = base + it * kSortThreads + tid;
         const bool valid = e < n;
         uint64_t k = 0;
@@ -378,24 +420,25 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
             peers &= ((d >> bit) & 1u) ? bb : ~bb;
         }
         const uint32_t lrank = (uint32_t)__popcll(peers & lt);
-        if (valid && lrank == 0) wh[w][d] = (uint32_t)__popcll(peers);
+        if (valid && lrank == 0) cw[w][d] = (uint32_t)__popcll(peers);
         __syncthreads();
-        {
+        if (tid < 256) {
+            // order the waves for digit tid; clear the other buffer for the next round
             uint32_t r = run[tid];
-            for (int ww = 0; ww < kSortThreads / 64; ++ww) {
-                uint32_t c = wh[ww][tid];
-                wh[ww][tid] = r;
+            for (int ww = 0; ww < NW; ++ww) {
+                const uint32_t c = cw[ww][tid];
+                cw[ww][tid] = r;
                 r += c;
+                nw[ww][tid] = 0;
             }
             run[tid] = r;
         }
         __syncthreads();
         if (valid) {
-            uint32_t dst = boff[d] + wh[w][d] + lrank;
+            const uint32_t dst = boff[d] + cw[w][d] + lrank;
             kout[dst] = k;
             vout[dst] = v;
         }
-        __syncthreads();
     }
 }
 
@@ -474,64 +517,41 @@ __global__ __launch_bounds__(kLvlTile) void k_levels(const uint64_t *__restrict_
 }
 
 // ---------------------------------------------------------------------------
-// 5. node records
+// 5. node records: the nodes starting at position p are the boxes of levels
+//    L(p)+1 .. leaf(p) holding p, numbered noff[p] + (l - L(p) - 1) in
+//    preorder.  This kernel writes what follows from p and l alone (box
+//    centre, side^2, first particle, level and leaf flag); the particle count,
+//    the skip link and the parent are found by the moments pass below, which
+//    visits each node's children in order anyway.
 // ---------------------------------------------------------------------------
-// first position t in (p, ce] whose key prefix (key >> sh) differs from P
-__device__ __forceinline__ int64_t gallop_end(const uint64_t *__restrict__ key, int64_t p,
-                                              int64_t ce, int sh, uint64_t P)
-{
-    int64_t m = p, nm, step = 1;
-    for (;;) {
-        int64_t cand = m + step;
-        if (cand >= ce) { nm = ce; break; }
-        if ((key[cand] >> sh) == P) { m = cand; step <<= 1; }
-        else { nm = cand; break; }
-    }
-    while (nm - m > 1) {
-        int64_t mid = m + ((nm - m) >> 1);
-        if ((key[mid] >> sh) == P) m = mid;
-        else nm = mid;
-    }
-    return nm;
-}
-
-// first position s in [cs, p] whose key prefix equals P (key[p] has it)
-__device__ __forceinline__ int64_t gallop_start(const uint64_t *__restrict__ key, int64_t p,
-                                                int64_t cs, int sh, uint64_t P)
-{
-    int64_t m = p, nm, step = 1;
-    for (;;) {
-        int64_t cand = m - step;
-        if (cand < cs) { nm = cs - 1; break; }
-        if ((key[cand] >> sh) == P) { m = cand; step <<= 1; }
-        else { nm = cand; break; }
-    }
-    while (m - nm > 1) {
-        int64_t mid = nm + ((m - nm) >> 1);
-        if ((key[mid] >> sh) == P) m = mid;
-        else nm = mid;
-    }
-    return m;
-}
-
 __global__ __launch_bounds__(256) void k_nodes(
     const uint64_t *__restrict__ key, int64_t n, const int64_t *__restrict__ off, int clouds,
     const double4 *__restrict__ cube, int b, const int8_t *__restrict__ Lv,
     const int8_t *__restrict__ Lf, const int32_t *__restrict__ noff, int64_t node_cap,
-    double4 *ngeo, int4 *ninfo, int32_t *npar, float4 *nrec, unsigned long long *ctr,
-    int32_t *flags)
+    double4 *ngeo, int4 *ninfo, int32_t *npar, unsigned long long *ctr, int32_t *flags)
 {
     if (*flags) return;
     const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (p >= n) return;
     if ((int64_t)noff[n] > node_cap) {
         if (p == 0) atomicOr(flags, UCP_FLAG_NODE_OVERFLOW);
         return;
     }
-    const int Lp = Lv[p], lf = Lf[p];
-    if (lf <= Lp) return;
+    const int Lp = p < n ? (int)Lv[p] : 0, lf = p < n ? (int)Lf[p] : 0;
+    // deepest leaf level: reduced over the block, then one atomic only if it
+    // raises the running maximum (same-address atomics serialise)
+    __shared__ int wmax[4];
+    int lmax = lf > Lp ? lf : 0;
+    for (int o = 32; o > 0; o >>= 1) lmax = max(lmax, __shfl_xor(lmax, o));
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = lmax;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int bm = max(max(wmax[0], wmax[1]), max(wmax[2], wmax[3]));
+        if ((unsigned long long)bm > __hip_atomic_load(&ctr[CTR_MAXLEVEL], __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT))
+            atomicMax(&ctr[CTR_MAXLEVEL], (unsigned long long)bm);
+    }
+    if (p >= n || lf <= Lp) return;
     const int c = cloud_of(off, clouds, p);
-    const int64_t cs = off[c], ce = off[c + 1];
     const uint64_t kp = key[p];
     const double4 c0 = cube[2 * c];
     const int e = (int)cube[2 * c + 1].y;
@@ -539,38 +559,29 @@ __global__ __launch_bounds__(256) void k_nodes(
     const int k0 = noff[p];
     for (int l = Lp + 1; l <= lf; ++l) {
         const int k = k0 + (l - Lp - 1);
-        const int sh = 3 * (b - l);
-        int64_t t = (l == 0) ? ce : gallop_end(key, p, ce, sh, kp >> sh);
-        int parent;
-        if (l == 0) {
-            parent = -1;
-        } else if (l - 1 > Lp) {
-            parent = k - 1;
-        } else {
-            int64_t s = gallop_start(key, p, cs, sh + 3, kp >> (sh + 3));
-            parent = noff[s] + (l - 1 - (int)Lv[s] - 1);
-        }
         // box centre c_d = lo_d + (2 k_d + 1) 2^(e - l - 1); the product is exact
         const double h = ldexp(1.0, e - l - 1);
         const double cx = c0.x + (double)(2 * (X >> (b - l)) + 1) * h;
         const double cy = c0.y + (double)(2 * (Y >> (b - l)) + 1) * h;
         const double cz = c0.z + (double)(2 * (Z >> (b - l)) + 1) * h;
-        const double4 geo = make_double4(cx, cy, cz, ldexp(1.0, 2 * (e - l)));
-        const int4 inf = make_int4((int)p, (int)(t - p), noff[t], l | (l == lf ? 256 : 0));
-        ngeo[k] = geo;
-        ninfo[k] = inf;
-        npar[k] = parent;
-        *(double4 *)(nrec + 8 * (int64_t)k) = geo;
-        *(int4 *)(nrec + 8 * (int64_t)k + 2) = make_int4(inf.z, inf.x, inf.y, inf.w);
+        ngeo[k] = make_double4(cx, cy, cz, ldexp(1.0, 2 * (e - l)));
+        ninfo[k] = make_int4((int)p, 0, 0, l | (l == lf ? 256 : 0));
+        if (l == 0) npar[k] = -1;   // other parents are set by the moments pass
     }
-    atomicMax(&ctr[CTR_MAXLEVEL], (unsigned long long)lf);
 }
 
 // ---------------------------------------------------------------------------
 // 6. moments about the box centre, one level at a time from the deepest up:
-//    the node (p, l) exists iff L(p) < l <= leaf(p); a leaf sums its
-//    particles, an internal node sums its children (one level deeper, written
-//    by the previous launch) in octant order with the exact shift of origin.
+//    the node (p, l) exists iff L(p) < l <= leaf(p).  A leaf holds the
+//    positions p .. t-1 with t the first later position whose L(t) < l (L is
+//    -1 at every cloud edge and at n).  An internal node k's children, in
+//    octant order, are k + 1 and then each child's skip link for as long as
+//    that node is one level deeper than k (a node of level l + 1 right after
+//    a child's subtree has the same parent); their counts and skip links were
+//    written by the previous launch.  The node then sums its particles (leaf)
+//    or its children's moments with the exact shift of origin (internal), and
+//    records its count, its skip link (that of its last child, or noff[t] for
+//    a leaf) and each child's parent.
 //    Record per node, FP64 (16 doubles): cx cy cz Q px py pz trS Sxx Syy Szz
 //    Sxy Sxz Syz 0 0; FP32 copy in the second line of the walk record:
 //    Q px py pz, 1.5 trS Sxx Syy Szz, Sxy Sxz Syz 0.
@@ -593,20 +604,26 @@ __device__ __forceinline__ void store_moments(double *mom64, float4 *nrec, int k
 __global__ __launch_bounds__(256) void k_moments_level(
     int level, const double4 *__restrict__ xq, int64_t n, const int8_t *__restrict__ Lv,
     const int8_t *__restrict__ Lf, const int32_t *__restrict__ noff,
-    const double4 *__restrict__ ngeo, const int4 *__restrict__ ninfo, double *mom64, float4 *nrec,
-    const int32_t *flags)
+    const double4 *__restrict__ ngeo, int4 *ninfo, int32_t *npar, double *mom64, float4 *nrec,
+    const unsigned long long *__restrict__ ctr, int32_t *flags)
 {
     if (*flags) return;
+    if ((unsigned long long)level > ctr[CTR_MAXLEVEL]) return;   // no node this deep
     const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (p >= n) return;
     const int Lp = Lv[p], lf = Lf[p];
     if (!(Lp < level && level <= lf)) return;
     const int k = noff[p] + (level - Lp - 1);
     const double4 g = ngeo[k];
-    const int4 inf = ninfo[k];
+    const int info = level | (level == lf ? 256 : 0);
     double m[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    int64_t t;
+    int skip;
     if (level == lf) {
-        for (int j = inf.x; j < inf.x + inf.y; ++j) {
+        t = p + 1;
+        while ((int)Lv[t] >= level) ++t;   // Lv[n] = -1 ends the scan
+        skip = noff[t];
+        for (int64_t j = p; j < t; ++j) {
             const double4 a = xq[j];
             const double r0 = a.x - g.x, r1 = a.y - g.y, r2 = a.z - g.z, qq = a.w;
             m[0] += qq;
@@ -623,8 +640,16 @@ __global__ __launch_bounds__(256) void k_moments_level(
     } else {
         const double qd = 0.25 * sqrt(g.w);   // |child centre - parent centre| per axis
         const int nn = noff[n];
-        const int chend = min(inf.z, nn);
-        for (int ch = k + 1; ch < chend; ch = max(ninfo[ch].z, ch + 1)) {
+        int ch = k + 1;
+        int4 ci = ch < nn ? ninfo[ch] : make_int4(0, 0, 0, 0);
+        for (int j = 0;; ++j) {
+            if (j == 8 || ci.y < 1 || ci.z <= ch || (ci.w & 255) != level + 1) {
+                atomicOr(flags, UCP_FLAG_INTERNAL);   // inconsistent records: stop
+                return;
+            }
+            npar[ch] = k;
+            t = (int64_t)ci.x + ci.y;
+            skip = ci.z;
             const double4 cg = ngeo[ch];
             const double d0 = cg.x > g.x ? qd : -qd;
             const double d1 = cg.y > g.y ? qd : -qd;
@@ -642,8 +667,17 @@ __global__ __launch_bounds__(256) void k_moments_level(
             m[7] += c[11] + p0 * d1 + d0 * p1 + Q * d0 * d1;
             m[8] += c[12] + p0 * d2 + d0 * p2 + Q * d0 * d2;
             m[9] += c[13] + p1 * d2 + d1 * p2 + Q * d1 * d2;
+            if (skip >= nn) break;
+            const int4 si = ninfo[skip];
+            if ((si.w & 255) != level + 1) break;   // no further sibling
+            ch = skip;
+            ci = si;
         }
     }
+    const int cnt = (int)(t - p);
+    ninfo[k] = make_int4((int)p, cnt, skip, info);
+    *(double4 *)(nrec + 8 * (int64_t)k) = g;
+    *(int4 *)(nrec + 8 * (int64_t)k + 2) = make_int4(skip, (int)p, cnt, info);
     store_moments(mom64, nrec, k, g, m);
 }
 
@@ -807,14 +841,14 @@ void launch_build(Ctx *c, const double *x, const double *q, const int64_t *offse
                        (const int64_t *)c->d_off, clouds, (const double4 *)c->d_cube, b,
                        (const int8_t *)c->d_L, (const int8_t *)c->d_leaf,
                        (const int32_t *)c->d_noff, c->node_cap, c->d_ngeo, c->d_ninfo, c->d_npar,
-                       c->d_nrec, c->d_ctr, c->d_flags);
+                       c->d_ctr, c->d_flags);
     // 6. moments, deepest level first
     for (int l = b; l >= 0; --l)
         hipLaunchKernelGGL(k_moments_level, grid_for(n, 256), dim3(256), 0, s, l,
                            (const double4 *)c->d_xq, n, (const int8_t *)c->d_L,
                            (const int8_t *)c->d_leaf, (const int32_t *)c->d_noff,
-                           (const double4 *)c->d_ngeo, (const int4 *)c->d_ninfo, c->d_mom64,
-                           c->d_nrec, (const int32_t *)c->d_flags);
+                           (const double4 *)c->d_ngeo, c->d_ninfo, c->d_npar, c->d_mom64,
+                           c->d_nrec, (const unsigned long long *)c->d_ctr, c->d_flags);
     // 7. groups
     hipLaunchKernelGGL(k_group_count, grid_for(n + 1, 256), dim3(256), 0, s, n,
                        (const int8_t *)c->d_L, (const int8_t *)c->d_leaf,

@@ -17,9 +17,13 @@ constexpr int kMaxGroup = 64;      // one target particle per lane
 constexpr int kMaxLeafCap = 64;
 constexpr int kScanBlock = 1024;   // threads per scan block
 constexpr int kScanItems = 4;      // elements per thread in the scan
-constexpr int kSortThreads = 256;
-constexpr int kSortItems = 16;
+constexpr int kSortThreads = 1024;  // 16 waves per sort block
+constexpr int kSortItems = 2;       // rounds of kSortThreads elements per tile
 constexpr int kSortTile = kSortThreads * kSortItems;
+constexpr int kScanSmallItems = 64;            // elements per thread, one-block scan
+// one block streams at most a few KB efficiently; longer arrays take the
+// three-kernel scan
+constexpr int64_t kScanSmallLimit = 4096;
 
 // device counter slots (unsigned long long)
 enum { CTR_P2P = 0, CTR_M2P = 1, CTR_MAXLEVEL = 2, CTR_QUEUE = 3, CTR_NCTR = 8 };

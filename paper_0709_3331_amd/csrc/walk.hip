@@ -399,8 +399,9 @@ __global__ __launch_bounds__(256) void k_walk(WalkArgs a)
                 const double dx = xi.x - readlane_d(geo.x, bl);
                 const double dy = xi.y - readlane_d(geo.y, bl);
                 const double dz = xi.z - readlane_d(geo.z, bl);
+                const double s2 = readlane_d(geo.w, bl);
                 const double d2 = fma(dz, dz, fma(dy, dy, dx * dx));
-                const bool fail = act && !(readlane_d(geo.w, bl) < th2 * d2);
+                const bool fail = act && !(s2 < th2 * d2);
                 const bool ok = __ballot(fail) == 0ull;
                 acc = lane == bl ? ok : acc;
             }
