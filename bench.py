@@ -50,6 +50,59 @@ def traffic_from_profile(precision):
     return d.get("hbm_bytes_per_launch")
 
 
+def bench_ensemble(args, prec, dev):
+    """64 independent clouds (N_c = 2 U[4096, 65536], sigma_c = U[0.5, 2]) built
+    and walked together: one batched build and one persistent walk per Verlet
+    step, the steps replayed from a hipGraph.  (G, L, group rule) come from the
+    autotuner, run on this input."""
+    import torch
+
+    from paper_0709_3331_amd import autotune, inputs
+    from paper_0709_3331_amd.tree import TreeSolver
+
+    ens, off, eprm = inputs.ensemble()
+    clouds = len(off) - 1
+    n = int(off[-1])
+    x = torch.from_numpy(ens.x).to(dev)
+    v = torch.from_numpy(ens.v).to(dev)
+    q = torch.from_numpy(ens.q).to(dev)
+    m = torch.from_numpy(ens.m).to(dev)
+    offs = torch.from_numpy(off).to(dev)
+    print(f"bench: ensemble of {clouds} clouds, N={n}: tuning", file=sys.stderr, flush=True)
+    tuned = autotune.tune(x, q, offs, theta=eprm["theta"], eps=eprm["eps"], precision=prec,
+                          candidates={"group_size": (32, 64), "list_len": (64, 128),
+                                      "group_mode": (1, 0)},
+                          reps=2, use_cache=False)
+    ts = TreeSolver(n, clouds, theta=eprm["theta"], eps=eprm["eps"], precision=prec,
+                    group_size=tuned["group_size"], list_len=tuned["list_len"],
+                    group_mode=tuned["group_mode"])
+    f = ts.tree_forces(x, q, offs)
+    st = ts.stats()
+    ts.step(x, v, f, q, m, eprm["dt"], 2, offsets=offs)
+    torch.cuda.synchronize()
+    ts.timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ts.step(x, v, f, q, m, eprm["dt"], args.ensemble_steps, offsets=offs)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wms, wc = ts.timing_read()
+    ts.stats()
+    ts.close()
+    el = t1 - t0
+    return {"clouds": clouds, "n_total": n, "steps": args.ensemble_steps,
+            "particles_per_s": n * args.ensemble_steps / el,
+            "ms_per_step": 1e3 * el / args.ensemble_steps,
+            "walk_ms": wms / max(wc, 1),
+            "interactions_per_particle": (st["p2p"] + st["m2p"]) / n,
+            "tuned": {"group_size": tuned["group_size"], "list_len": tuned["list_len"],
+                      "group_mode": "chunk" if tuned["group_mode"] == 1 else "node",
+                      "rel_force_diff_vs_per_particle_fp64":
+                          tuned.get("rel_force_diff_vs_per_particle_fp64"),
+                      "candidates_walk_ms": {f"{r['group_mode']}/{r['group_size']}/{r['list_len']}":
+                                             round(r["walk_ms"], 4) for r in tuned["candidates"]}}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -64,6 +117,9 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 comparator run")
     ap.add_argument("--no-theta-sweep", action="store_true",
                     help="skip the theta = 0.3 / 0.7 accuracy and cost lines")
+    ap.add_argument("--no-ensemble", action="store_true",
+                    help="skip the batched 64-cloud ensemble measurement")
+    ap.add_argument("--ensemble-steps", type=int, default=10)
     ap.add_argument("--profile", action="store_true", help="short run for rocprofv3 (no extras)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 256 MiB device-to-device copy (counter calibration)")
@@ -209,6 +265,8 @@ def main():
             "kind": "oracle",
             "sample": "one full FP64 oracle tree-force evaluation (build + walk, OpenMP over "
                       "groups) of the same N=524288 cloud at the same parameters; %.2f s" % (c1 - c0)}
+    if not args.profile and not args.no_ensemble:
+        result["ensemble"] = bench_ensemble(args, prec, dev)
     if args.calib_copy:
         a = torch.ones(64 << 20, dtype=torch.float32, device=dev)   # 256 MiB
         b = torch.empty_like(a)

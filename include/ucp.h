@@ -166,9 +166,21 @@ ucp_status ucp_energy(ucp_ctx *c, const double *x, const double *v, const double
 
 /* Vector-Jacobian product of the tree forces of the last build with respect
  * to positions, xbar = (dF/dx)^T u, with the cube, topology, box centres and
- * interaction lists of that build held fixed.  u, xbar: [n][3] (caller
- * order).  Needs the positions of the last build to be unchanged.
- * Errors: UCP_ENOTBUILT.                                                    */
+ * interaction lists of that build held fixed (they are piecewise constant in
+ * x; the forces are those of Sec. 3 under the expansion of ucp_compute_forces).
+ * The walk of the last build is repeated, giving the same lists; each
+ * accepted box contributes through the target position and through its
+ * dipole and quadrupole (their derivatives with respect to the box's
+ * particles), each particle pair through both positions.
+ * u, xbar: device [n][3] FP64 (caller order), owned by the caller; u may not
+ * alias xbar.  The positions given to the last build must be unchanged.
+ * Precision as for the forces (UCP_SPLIT: FP32 arithmetic on offsets formed
+ * in FP64, FP64 accumulation).  Contributions of different walk groups to one
+ * box or particle are added with FP64 atomics, so xbar is reproducible to
+ * rounding, not bitwise.  The first call allocates the adjoint scratch
+ * (48 bytes per particle, 80 per node slot).
+ * Errors: UCP_EINVAL (NULL argument), UCP_ENOTBUILT, UCP_ENOMEM, UCP_EHIP;
+ * device flags as for ucp_compute_forces.                                   */
 ucp_status ucp_force_vjp(ucp_ctx *c, const double *u, double *xbar, void *stream);
 
 /* Synchronise `stream`, read the device counters and flags.  Returns

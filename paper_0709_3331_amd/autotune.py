@@ -1,0 +1,124 @@
+"""Autotuner for the walk's group size G, list length L and group rule.
+
+G and the group rule decide which targets share one traversal, so they change
+the accepted sets (and the force error at truncation level), not only the
+speed; L changes only the FP64 summation order.  The tuner therefore times the
+walk for every candidate on the caller's own workload, keeps the fastest, and
+reports that setting's force difference from the FP64 per-particle walk
+(G = 1, the walk of Sec. 3) on the same input, so the choice can be judged on
+accuracy as well.
+
+Timing uses the library's own HIP events around each walk launch
+(ucp_set_timing / ucp_timing_read).  Results are cached in a JSON file keyed by
+device, particle count, cloud count, theta, eps and precision.
+"""
+from __future__ import annotations
+
+import json
+import os
+
+import torch
+
+from . import _lib as L
+from .tree import TreeSolver
+
+DEFAULT_CANDIDATES = {
+    "group_size": (32, 48, 64),
+    "list_len": (64, 128, 256),
+    "group_mode": (L.UCP_GROUP_CHUNK, L.UCP_GROUP_NODE),
+}
+
+
+def default_cache_path():
+    return os.environ.get("UCP_TUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "ucptree", "tune.json"))
+
+
+def _key(n, clouds, theta, eps, precision):
+    dev = torch.cuda.get_device_name(torch.cuda.current_device())
+    return f"{dev}|n={n}|clouds={clouds}|theta={theta:g}|eps={eps:g}|precision={precision}"
+
+
+def _load(path):
+    try:
+        with open(path) as fh:
+            return json.load(fh)
+    except (OSError, ValueError):
+        return {}
+
+
+def _time_walk(x, q, offsets, reps, **params):
+    n = x.shape[0]
+    clouds = 1 if offsets is None else offsets.numel() - 1
+    ts = TreeSolver(n, clouds, **params)
+    try:
+        ts.tree_forces(x, q, offsets)          # warm-up (and graph-free first build)
+        ts.stats()
+        ts.timing(True)
+        torch.cuda.synchronize()
+        for _ in range(reps):
+            ts.tree_forces(x, q, offsets)
+        torch.cuda.synchronize()
+        ms, cnt = ts.timing_read()
+        st = ts.stats()
+        ts.timing(False)
+    finally:
+        ts.close()
+    return ms / max(cnt, 1), (st["p2p"] + st["m2p"]) / max(n, 1)
+
+
+def tune(x, q, offsets=None, *, theta, eps, precision=L.UCP_SPLIT, candidates=None, reps=3,
+         cache_path=None, use_cache=True, reference=True):
+    """Pick (group_size, list_len, group_mode) for this workload.
+
+    x, q: float64 GPU tensors ((N, 3), (N,)); offsets: int64 GPU tensor of
+    cloud offsets or None.  Returns a dict with the chosen parameters, the
+    timing of every candidate, and (reference=True) the relative RMS force
+    difference of the chosen setting from the FP64 per-particle walk."""
+    n = x.shape[0]
+    clouds = 1 if offsets is None else offsets.numel() - 1
+    path = cache_path or default_cache_path()
+    key = _key(n, clouds, theta, eps, precision)
+    cache = _load(path) if use_cache else {}
+    if use_cache and key in cache:
+        return dict(cache[key], cached=True)
+    cand = dict(DEFAULT_CANDIDATES)
+    cand.update(candidates or {})
+    rows = []
+    for gm in cand["group_mode"]:
+        for G in cand["group_size"]:
+            for Lq in cand["list_len"]:
+                ms, ipp = _time_walk(x, q, offsets, reps, theta=theta, eps=eps,
+                                     precision=precision, group_size=G, list_len=Lq,
+                                     group_mode=gm)
+                rows.append({"group_size": G, "list_len": Lq, "group_mode": gm, "walk_ms": ms,
+                             "interactions_per_particle": ipp})
+    best = min(rows, key=lambda r: r["walk_ms"])
+    out = {"group_size": best["group_size"], "list_len": best["list_len"],
+           "group_mode": best["group_mode"], "walk_ms": best["walk_ms"], "candidates": rows}
+    if reference:
+        clouds_max = max(clouds, 1)
+        tb = TreeSolver(n, clouds_max, theta=theta, eps=eps, precision=precision,
+                        group_size=best["group_size"], list_len=best["list_len"],
+                        group_mode=best["group_mode"])
+        tr = TreeSolver(n, clouds_max, theta=theta, eps=eps, precision=L.UCP_FP64, group_size=1,
+                        group_mode=L.UCP_GROUP_CHUNK)
+        try:
+            fb = tb.tree_forces(x, q, offsets)
+            fr = tr.tree_forces(x, q, offsets)
+            tb.stats()
+            tr.stats()
+            out["rel_force_diff_vs_per_particle_fp64"] = float(
+                torch.linalg.norm(fb - fr) / torch.linalg.norm(fr))
+        finally:
+            tb.close()
+            tr.close()
+    if use_cache:
+        cache = _load(path)
+        cache[key] = out
+        os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+        tmp = path + ".tmp"
+        with open(tmp, "w") as fh:
+            json.dump(cache, fh, indent=1)
+        os.replace(tmp, path)
+    return dict(out, cached=False)

@@ -62,7 +62,8 @@ void free_all(Ctx *c)
                     c->d_val[1], c->d_hist, c->d_histscan, c->d_xq, c->d_L,
                     c->d_leaf, c->d_cnt,    c->d_noff,  c->d_goff,   c->d_gnode,  c->d_scanblk,
                     c->d_ngeo, c->d_ninfo,  c->d_npar,  c->d_mom64,  c->d_nrec,
-                    c->d_groups, c->d_gstat, c->d_acc,  c->d_ctr,    c->d_flags,  c->d_epart};
+                    c->d_groups, c->d_gstat, c->d_acc,  c->d_ctr,    c->d_flags,  c->d_epart,
+                    c->d_leafof, c->d_w,    c->d_xsrc,  c->d_cbar};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
@@ -216,6 +217,7 @@ ucp_status ucp_create(ucp_ctx **out, int64_t n_max, int32_t clouds_max, const uc
     ALLOC(c->d_groups, N);
     ALLOC(c->d_gstat, N);
     ALLOC(c->d_acc, N + 64);   // 64 spare slots for the walk's inactive lanes
+    ALLOC(c->d_leafof, N);
     ALLOC(c->d_ctr, ucp::CTR_NCTR);
     ALLOC(c->d_flags, 4);
     ALLOC(c->d_epart, 4 * 256);
@@ -365,8 +367,25 @@ ucp_status ucp_force_vjp(ucp_ctx *c, const double *u, double *xbar, void *stream
     if (!c->built) return fail(c, UCP_ENOTBUILT, "ucp_force_vjp: no tree has been built");
     if (c->n == 0) return UCP_OK;
     if (!u || !xbar) return fail(c, UCP_EINVAL, "ucp_force_vjp: NULL argument");
-    (void)stream;
-    return fail(c, UCP_EINVAL, "ucp_force_vjp: the adjoint walk is not available in this build");
+    if (!c->d_w) {
+        // the adjoint buffers are allocated on first use
+        hipError_t e = hipMalloc((void **)&c->d_w, (size_t)c->n_max * sizeof(double4) + 256);
+        if (e == hipSuccess) e = hipMalloc((void **)&c->d_xsrc, (size_t)c->n_max * 4 * sizeof(double) + 256);
+        if (e == hipSuccess) e = hipMalloc((void **)&c->d_cbar, (size_t)c->node_cap * 10 * sizeof(double) + 256);
+        if (e != hipSuccess) {
+            (void)hipFree(c->d_w);
+            (void)hipFree(c->d_xsrc);
+            (void)hipFree(c->d_cbar);
+            c->d_w = nullptr;
+            c->d_xsrc = nullptr;
+            c->d_cbar = nullptr;
+            return fail(c, e == hipErrorOutOfMemory ? UCP_ENOMEM : UCP_EHIP,
+                        std::string("ucp_force_vjp: ") + hipGetErrorString(e));
+        }
+    }
+    ucp::launch_vjp(c, u, xbar, (hipStream_t)stream);
+    HIP_TRY(c, hipGetLastError());
+    return UCP_OK;
 }
 
 ucp_status ucp_get_stats(ucp_ctx *c, ucp_stats *out, void *stream)

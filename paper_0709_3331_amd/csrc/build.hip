@@ -605,7 +605,7 @@ __global__ __launch_bounds__(256) void k_moments_level(
     int level, const double4 *__restrict__ xq, int64_t n, const int8_t *__restrict__ Lv,
     const int8_t *__restrict__ Lf, const int32_t *__restrict__ noff,
     const double4 *__restrict__ ngeo, int4 *ninfo, int32_t *npar, double *mom64, float4 *nrec,
-    const unsigned long long *__restrict__ ctr, int32_t *flags)
+    int32_t *leafof, const unsigned long long *__restrict__ ctr, int32_t *flags)
 {
     if (*flags) return;
     if ((unsigned long long)level > ctr[CTR_MAXLEVEL]) return;   // no node this deep
@@ -624,6 +624,7 @@ __global__ __launch_bounds__(256) void k_moments_level(
         while ((int)Lv[t] >= level) ++t;   // Lv[n] = -1 ends the scan
         skip = noff[t];
         for (int64_t j = p; j < t; ++j) {
+            leafof[j] = k;
             const double4 a = xq[j];
             const double r0 = a.x - g.x, r1 = a.y - g.y, r2 = a.z - g.z, qq = a.w;
             m[0] += qq;
@@ -848,7 +849,7 @@ void launch_build(Ctx *c, const double *x, const double *q, const int64_t *offse
                            (const double4 *)c->d_xq, n, (const int8_t *)c->d_L,
                            (const int8_t *)c->d_leaf, (const int32_t *)c->d_noff,
                            (const double4 *)c->d_ngeo, c->d_ninfo, c->d_npar, c->d_mom64,
-                           c->d_nrec, (const unsigned long long *)c->d_ctr, c->d_flags);
+                           c->d_nrec, c->d_leafof, (const unsigned long long *)c->d_ctr, c->d_flags);
     // 7. groups
     hipLaunchKernelGGL(k_group_count, grid_for(n + 1, 256), dim3(256), 0, s, n,
                        (const int8_t *)c->d_L, (const int8_t *)c->d_leaf,

@@ -101,8 +101,13 @@ struct Ctx {
     // groups
     int4 *d_groups = nullptr;               // [n_max] first, count, node, root
     int2 *d_gstat = nullptr;                // [n_max] accepted boxes, P2P sources
+    int32_t *d_leafof = nullptr;            // [n_max] leaf holding each sorted position
     // results (sorted order)
     double4 *d_acc = nullptr;               // [n_max] E xyz, phi
+    // adjoint, allocated by the first ucp_force_vjp
+    double4 *d_w = nullptr;                 // [n_max] q_i u_i, sorted
+    double *d_xsrc = nullptr;               // [n_max][4] source-side P2P cotangent
+    double *d_cbar = nullptr;               // [node_cap][10] cell cotangents
     // counters, flags
     unsigned long long *d_ctr = nullptr;    // [CTR_NCTR]
     int32_t *d_flags = nullptr;             // [1]

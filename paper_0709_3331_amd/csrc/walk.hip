@@ -40,8 +40,14 @@
 
 namespace ucp {
 
+// what a walk launch computes
+enum { kWalkForce = 0, kWalkForcePhi = 1, kWalkVjp = 2 };
+
 struct WalkArgs {
     const double4 *xq;
+    const double4 *w;       // adjoint: sorted target cotangents q_i u_i
+    double *cbar;           // adjoint: per node pbar[3], (Sbar + Sbar^T)[6], pad (10 doubles)
+    double *xsrc;           // adjoint: per particle source-side P2P cotangent (4 doubles)
     const float4 *nrec;
     const double *mom64;
     const int4 *groups;
@@ -189,22 +195,144 @@ __device__ __forceinline__ void m2p_rec(const T *r, T tx, T ty, T tz, T eps2, T 
     }
 }
 
+// ---------------------------------------------------------------------------
+// adjoint of one accepted box (frozen lists).  With w the target's cotangent
+// (q_i times the cotangent of F_i), r = target - centre and h^2 = |r|^2 + eps^2:
+//   target side  g = d(w.E)/dr = alpha r + beta w + 3 (w.r) h^-5 p
+//                    + 15 (w.r) h^-7 S r - 3 h^-5 S w,
+//     alpha = (w.r)(-3 Q h^-5 - 15 (p.r) h^-7 - 52.5 (r.S.r) h^-9 + 7.5 trS h^-7)
+//             + 3 (w.p) h^-5 + 15 (w.S.r) h^-7,
+//     beta  = Q h^-3 + 3 (p.r) h^-5 + 7.5 (r.S.r) h^-7 - 1.5 trS h^-5;
+//   source side  pbar += 3 (w.r) h^-5 r - h^-3 w,
+//                sym  += 15 (w.r) h^-7 r r^T - 3 (w.r) h^-5 I - 3 h^-5 (w r^T + r w^T),
+// sym being Sbar + Sbar^T; a particle j of the box then receives
+// q_j (pbar + sym (x_j - c)).
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void m2p_adj_target(T rx, T ry, T rz, T Q, T px, T py, T pz, T Sxx,
+                                               T Syy, T Szz, T Sxy, T Sxz, T Syz, T trS15, T wx,
+                                               T wy, T wz, T eps2, T &gx, T &gy, T &gz)
+{
+    const T h2 = fma(rx, rx, fma(ry, ry, fma(rz, rz, eps2)));
+    T ih;
+    if constexpr (sizeof(T) == 4) ih = __builtin_amdgcn_rsqf(h2);
+    else ih = 1.0 / sqrt(h2);
+    const T ih2 = ih * ih, ih3 = ih2 * ih, ih5 = ih3 * ih2, ih7 = ih5 * ih2, ih9 = ih7 * ih2;
+    const T Srx = fma(Sxx, rx, fma(Sxy, ry, Sxz * rz));
+    const T Sry = fma(Sxy, rx, fma(Syy, ry, Syz * rz));
+    const T Srz = fma(Sxz, rx, fma(Syz, ry, Szz * rz));
+    const T Swx = fma(Sxx, wx, fma(Sxy, wy, Sxz * wz));
+    const T Swy = fma(Sxy, wx, fma(Syy, wy, Syz * wz));
+    const T Swz = fma(Sxz, wx, fma(Syz, wy, Szz * wz));
+    const T ur = fma(wx, rx, fma(wy, ry, wz * rz));
+    const T pr = fma(px, rx, fma(py, ry, pz * rz));
+    const T up = fma(wx, px, fma(wy, py, wz * pz));
+    const T rSr = fma(rx, Srx, fma(ry, Sry, rz * Srz));
+    const T uSr = fma(wx, Srx, fma(wy, Sry, wz * Srz));
+    const T alpha = ur * (-(T)3 * Q * ih5 - (T)15 * pr * ih7 - (T)52.5 * rSr * ih9 +
+                          (T)5 * trS15 * ih7) +
+                    (T)3 * up * ih5 + (T)15 * uSr * ih7;
+    const T beta = Q * ih3 + (T)3 * pr * ih5 + (T)7.5 * rSr * ih7 - trS15 * ih5;
+    const T cp = (T)3 * ur * ih5, cs = (T)15 * ur * ih7, cw = (T)3 * ih5;
+    gx += alpha * rx + beta * wx + cp * px + cs * Srx - cw * Swx;
+    gy += alpha * ry + beta * wy + cp * py + cs * Sry - cw * Swy;
+    gz += alpha * rz + beta * wz + cp * pz + cs * Srz - cw * Swz;
+}
+
+template <typename T>
+__device__ __forceinline__ void m2p_adj_source(T rx, T ry, T rz, T wx, T wy, T wz, T eps2, T *cb)
+{
+    const T h2 = fma(rx, rx, fma(ry, ry, fma(rz, rz, eps2)));
+    T ih;
+    if constexpr (sizeof(T) == 4) ih = __builtin_amdgcn_rsqf(h2);
+    else ih = 1.0 / sqrt(h2);
+    const T ih2 = ih * ih, ih3 = ih2 * ih, ih5 = ih3 * ih2, ih7 = ih5 * ih2;
+    const T ur = fma(wx, rx, fma(wy, ry, wz * rz));
+    const T a5 = (T)3 * ur * ih5, a7 = (T)15 * ur * ih7, c5 = (T)3 * ih5;
+    cb[0] += a5 * rx - ih3 * wx;
+    cb[1] += a5 * ry - ih3 * wy;
+    cb[2] += a5 * rz - ih3 * wz;
+    cb[3] += a7 * rx * rx - a5 - (T)2 * c5 * wx * rx;
+    cb[4] += a7 * ry * ry - a5 - (T)2 * c5 * wy * ry;
+    cb[5] += a7 * rz * rz - a5 - (T)2 * c5 * wz * rz;
+    cb[6] += a7 * rx * ry - c5 * (wx * ry + rx * wy);
+    cb[7] += a7 * rx * rz - c5 * (wx * rz + rx * wz);
+    cb[8] += a7 * ry * rz - c5 * (wy * rz + ry * wz);
+}
+
+// adjoint of one particle pair: d(w.K)/dr with K = r h^-3 is w h^-3 - 3 (w.r) r h^-5
+template <typename T>
+__device__ __forceinline__ void p2p_adj(T rx, T ry, T rz, T sq, T wx, T wy, T wz, T eps2, T &gx,
+                                        T &gy, T &gz)
+{
+    const T h2 = fma(rx, rx, fma(ry, ry, fma(rz, rz, eps2)));
+    T ih;
+    if constexpr (sizeof(T) == 4) ih = __builtin_amdgcn_rsqf(h2);
+    else ih = 1.0 / sqrt(h2);
+    const T ih3 = ih * ih * ih;
+    const T c3 = sq * ih3, c5 = (T)3 * sq * fma(wx, rx, fma(wy, ry, wz * rz)) * ih3 * ih * ih;
+    gx += c3 * wx - c5 * rx;
+    gy += c3 * wy - c5 * ry;
+    gz += c3 * wz - c5 * rz;
+}
+
+__device__ __forceinline__ float readlane_t(float v, int src)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+}
+__device__ __forceinline__ double readlane_t(double v, int src) { return readlane_d(v, src); }
+
+// record fields of a staged M2P entry (see m2p_rec for the two layouts)
+template <typename T>
+struct CellRec {
+    T cx, cy, cz, Q, px, py, pz, trS15, Sxx, Syy, Szz, Sxy, Sxz, Syz;
+};
+template <typename T>
+__device__ __forceinline__ CellRec<T> load_rec(const T *r)
+{
+    CellRec<T> c;
+    if constexpr (sizeof(T) == 4) {
+        const float4 a = ((const float4 *)r)[0], b = ((const float4 *)r)[1];
+        const float4 d = ((const float4 *)r)[2], e = ((const float4 *)r)[3];
+        c = {a.x, a.y, a.z, b.x, b.y, b.z, b.w, d.x, d.y, d.z, d.w, e.x, e.y, e.z};
+    } else {
+        c = {r[0], r[1], r[2], r[3], r[4], r[5], r[6], r[7], r[8], r[9], r[10], r[11], r[12], r[13]};
+    }
+    return c;
+}
+
+// Per-target state of a group in the walk: target offset (or position),
+// cotangent (adjoint mode), and the FP64 per-lane accumulators.
+template <typename T>
+struct Target {
+    T tx, ty, tz, wx, wy, wz;
+    double px, py, pz;           // FP64 position (adjoint P2P differences)
+    int i;                       // sorted index of the lane's target
+    double E0, E1, E2, PH;       // field and potential, or the target-side adjoint
+};
+
 // Evaluate the M2P and P2P index lists of a group.  Entries are staged into
 // LDS 64 at a time (one per lane), then the lpt lanes of each target take the
-// staged entries round-robin.
-template <int PREC, bool PHI, typename T>
+// staged entries round-robin.  In adjoint mode a second pass over the same
+// staged entries gives each lane one entry, loops over the group's targets
+// (broadcast from their lanes) and adds the entry's source-side cotangent to
+// the global per-cell or per-particle arrays.
+template <int PREC, int MODE, typename T>
 __device__ __forceinline__ void flush_lists(const WalkArgs &a, const int4 *ml, int nm,
-                                            const int2 *pl, int np, T *stage, int *pfx, int *lfirst, int lane,
-                                            int sub, int lpt, const double4 &cg, T tx, T ty, T tz,
-                                            int i, double &E0, double &E1, double &E2, double &PH)
+                                            const int2 *pl, int np, T *stage, int *pfx,
+                                            int *lfirst, int lane, int sub, int lpt, int c,
+                                            int gfirst, const double4 &cg, Target<T> &tg)
 {
+    constexpr bool PHI = MODE == kWalkForcePhi;
+    constexpr bool ADJ = MODE == kWalkVjp;
     const T eps2 = PREC == UCP_SPLIT ? (T)a.eps2f : (T)a.eps2;
+    const T tx = tg.tx, ty = tg.ty, tz = tg.tz;
     wave_sync();   // the lists were written by other lanes
     for (int base = 0; base < nm; base += 64) {
         const int cnt = min(64, nm - base);
+        const int4 ent = ml[base + (lane < cnt ? lane : cnt - 1)];
+        const int k = ent.x;
         {
-            const int4 ent = ml[base + (lane < cnt ? lane : cnt - 1)];
-            const int k = ent.x;
             T *rec = stage + kRec * lane;
             if constexpr (PREC == UCP_SPLIT) {
                 const float4 *m4 = a.nrec + 8 * (int64_t)k + 4;
@@ -223,21 +351,47 @@ __device__ __forceinline__ void flush_lists(const WalkArgs &a, const int4 *ml, i
             }
         }
         wave_sync();
-        // two independent partial sums (records e and e + lpt) for ILP
-        T ex = 0, ey = 0, ez = 0, ph = 0, fx = 0, fy = 0, fz = 0, fp = 0;
-        int e = sub;
-        for (; e + lpt < cnt; e += 2 * lpt) {
-            m2p_rec<T, PHI>(stage + kRec * e, tx, ty, tz, eps2, ex, ey, ez, ph);
-            m2p_rec<T, PHI>(stage + kRec * (e + lpt), tx, ty, tz, eps2, fx, fy, fz, fp);
+        if constexpr (!ADJ) {
+            // two independent partial sums (records e and e + lpt) for ILP
+            T ex = 0, ey = 0, ez = 0, ph = 0, fx = 0, fy = 0, fz = 0, fp = 0;
+            int e = sub;
+            for (; e + lpt < cnt; e += 2 * lpt) {
+                m2p_rec<T, PHI>(stage + kRec * e, tx, ty, tz, eps2, ex, ey, ez, ph);
+                m2p_rec<T, PHI>(stage + kRec * (e + lpt), tx, ty, tz, eps2, fx, fy, fz, fp);
+            }
+            if (e < cnt) m2p_rec<T, PHI>(stage + kRec * e, tx, ty, tz, eps2, ex, ey, ez, ph);
+            tg.E0 += (double)(ex + fx);
+            tg.E1 += (double)(ey + fy);
+            tg.E2 += (double)(ez + fz);
+            tg.PH += (double)(ph + fp);
+        } else {
+            T gx = 0, gy = 0, gz = 0;
+            for (int e = sub; e < cnt; e += lpt) {
+                const CellRec<T> r = load_rec(stage + kRec * e);
+                m2p_adj_target<T>(tx - r.cx, ty - r.cy, tz - r.cz, r.Q, r.px, r.py, r.pz, r.Sxx,
+                                  r.Syy, r.Szz, r.Sxy, r.Sxz, r.Syz, r.trS15, tg.wx, tg.wy,
+                                  tg.wz, eps2, gx, gy, gz);
+            }
+            tg.E0 += (double)gx;
+            tg.E1 += (double)gy;
+            tg.E2 += (double)gz;
+            // source side: lane e owns staged record e
+            const CellRec<T> r = load_rec(stage + kRec * lane);
+            T cb[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+            for (int t = 0; t < c; ++t) {
+                const int src = t * lpt;
+                m2p_adj_source<T>(readlane_t(tx, src) - r.cx, readlane_t(ty, src) - r.cy,
+                                  readlane_t(tz, src) - r.cz, readlane_t(tg.wx, src),
+                                  readlane_t(tg.wy, src), readlane_t(tg.wz, src), eps2, cb);
+            }
+            if (lane < cnt)
+                for (int q = 0; q < 9; ++q) atomicAdd(a.cbar + 10 * (int64_t)k + q, (double)cb[q]);
         }
-        if (e < cnt) m2p_rec<T, PHI>(stage + kRec * e, tx, ty, tz, eps2, ex, ey, ez, ph);
-        E0 += (double)(ex + fx);
-        E1 += (double)(ey + fy);
-        E2 += (double)(ez + fz);
-        PH += (double)(ph + fp);
         wave_sync();
     }
-    int *sidx = (int *)(stage + 4 * 64);
+    // staged sources are 16 bytes (FP32 offsets) or 32 bytes (FP64 positions)
+    constexpr int kSrcBytes = (PREC == UCP_SPLIT && !ADJ) ? 16 : 32;
+    int *sidx = (int *)((char *)stage + 64 * kSrcBytes);
     for (int base = 0; base < np; base += 64) {
         const int cntL = min(64, np - base);
         const int2 lf = pl[base + (lane < cntL ? lane : cntL - 1)];
@@ -260,45 +414,72 @@ __device__ __forceinline__ void flush_lists(const WalkArgs &a, const int4 *ml, i
             const int j = lfirst[hi] + P;
             const double4 s = a.xq[j];
             T *st = stage + 4 * lane;
-            if constexpr (PREC == UCP_SPLIT) {
+            // the adjoint's pair terms grow as h^-3, so its pair differences
+            // x_i - x_j are formed in FP64 (FP64 staging) and rounded once
+            if constexpr (PREC == UCP_SPLIT && !ADJ) {
                 *(float4 *)st = make_float4((float)(s.x - cg.x), (float)(s.y - cg.y),
                                             (float)(s.z - cg.z), (float)s.w);
             } else {
-                *(double4 *)st = s;
+                *(double4 *)((double *)stage + 4 * lane) = s;
             }
             sidx[lane] = j;
             wave_sync();
             T ex = 0, ey = 0, ez = 0, ph = 0;
             for (int e = sub; e < ncur; e += lpt) {
-                T sx, sy, sz, sq;
-                if constexpr (sizeof(T) == 4) {
-                    const float4 v = ((const float4 *)stage)[e];
-                    sx = v.x; sy = v.y; sz = v.z; sq = v.w;
-                } else {
+                if constexpr (ADJ) {
                     const double4 v = ((const double4 *)stage)[e];
-                    sx = v.x; sy = v.y; sz = v.z; sq = v.w;
+                    if (sidx[e] != tg.i)
+                        p2p_adj<T>((T)(tg.px - v.x), (T)(tg.py - v.y), (T)(tg.pz - v.z), (T)v.w,
+                                   tg.wx, tg.wy, tg.wz, eps2, ex, ey, ez);
+                } else {
+                    T sx, sy, sz, sq;
+                    if constexpr (sizeof(T) == 4) {
+                        const float4 v = ((const float4 *)stage)[e];
+                        sx = v.x; sy = v.y; sz = v.z; sq = v.w;
+                    } else {
+                        const double4 v = ((const double4 *)stage)[e];
+                        sx = v.x; sy = v.y; sz = v.z; sq = v.w;
+                    }
+                    const T rx = tx - sx, ry = ty - sy, rz = tz - sz;
+                    const T h2 = fma(rx, rx, fma(ry, ry, fma(rz, rz, eps2)));
+                    T ih;
+                    if constexpr (sizeof(T) == 4) ih = __builtin_amdgcn_rsqf(h2);
+                    else ih = 1.0 / sqrt(h2);
+                    const T w = sq * (ih * ih * ih);
+                    ex = fma(w, rx, ex);
+                    ey = fma(w, ry, ey);
+                    ez = fma(w, rz, ez);
+                    if (PHI) ph += (sidx[e] != tg.i) ? sq * ih : (T)0;
                 }
-                const T rx = tx - sx, ry = ty - sy, rz = tz - sz;
-                const T h2 = fma(rx, rx, fma(ry, ry, fma(rz, rz, eps2)));
-                T ih;
-                if constexpr (sizeof(T) == 4) ih = __builtin_amdgcn_rsqf(h2);
-                else ih = 1.0 / sqrt(h2);
-                const T w = sq * (ih * ih * ih);
-                ex = fma(w, rx, ex);
-                ey = fma(w, ry, ey);
-                ez = fma(w, rz, ez);
-                if (PHI) ph += (sidx[e] != i) ? sq * ih : (T)0;
             }
-            E0 += (double)ex;
-            E1 += (double)ey;
-            E2 += (double)ez;
-            PH += (double)ph;
+            tg.E0 += (double)ex;
+            tg.E1 += (double)ey;
+            tg.E2 += (double)ez;
+            tg.PH += (double)ph;
+            if constexpr (ADJ) {
+                // source side: lane e owns staged source e (position s)
+                T gx = 0, gy = 0, gz = 0;
+                for (int t = 0; t < c; ++t) {
+                    const int src = t * lpt;
+                    const T rx = (T)(readlane_d(tg.px, src) - s.x);
+                    const T ry = (T)(readlane_d(tg.py, src) - s.y);
+                    const T rz = (T)(readlane_d(tg.pz, src) - s.z);
+                    const T wx = readlane_t(tg.wx, src), wy = readlane_t(tg.wy, src),
+                            wz = readlane_t(tg.wz, src);
+                    if (gfirst + t != j) p2p_adj<T>(rx, ry, rz, (T)s.w, wx, wy, wz, eps2, gx, gy, gz);
+                }
+                if (lane < ncur) {
+                    atomicAdd(a.xsrc + 4 * (int64_t)j + 0, -(double)gx);
+                    atomicAdd(a.xsrc + 4 * (int64_t)j + 1, -(double)gy);
+                    atomicAdd(a.xsrc + 4 * (int64_t)j + 2, -(double)gz);
+                }
+            }
             wave_sync();
         }
     }
 }
 
-template <int PREC, bool PHI>
+template <int PREC, int MODE>
 __global__ __launch_bounds__(256) void k_walk(WalkArgs a)
 {
     using T = typename std::conditional<PREC == UCP_SPLIT, float, double>::type;
@@ -342,27 +523,38 @@ __global__ __launch_bounds__(256) void k_walk(WalkArgs a)
         const double bminz = wave_fmin(act ? xi.z : INFINITY), bmaxz = wave_fmax(act ? xi.z : -INFINITY);
         const double4 cg = make_double4(0.5 * (bminx + bmaxx), 0.5 * (bminy + bmaxy),
                                         0.5 * (bminz + bmaxz), 0.0);
-        T tx, ty, tz;
+        Target<T> tg;
         if constexpr (PREC == UCP_SPLIT) {
-            tx = (float)(xi.x - cg.x);
-            ty = (float)(xi.y - cg.y);
-            tz = (float)(xi.z - cg.z);
+            tg.tx = (float)(xi.x - cg.x);
+            tg.ty = (float)(xi.y - cg.y);
+            tg.tz = (float)(xi.z - cg.z);
         } else {
-            tx = xi.x;
-            ty = xi.y;
-            tz = xi.z;
+            tg.tx = xi.x;
+            tg.ty = xi.y;
+            tg.tz = xi.z;
         }
+        tg.wx = tg.wy = tg.wz = (T)0;
+        if constexpr (MODE == kWalkVjp) {
+            const double4 wi = a.w[i];
+            tg.wx = act ? (T)wi.x : (T)0;   // idle lanes carry no cotangent
+            tg.wy = act ? (T)wi.y : (T)0;
+            tg.wz = act ? (T)wi.z : (T)0;
+        }
+        tg.px = xi.x;
+        tg.py = xi.y;
+        tg.pz = xi.z;
+        tg.i = i;
+        tg.E0 = tg.E1 = tg.E2 = tg.PH = 0.0;
         stk[0] = make_int2(root, min(((const int *)(a.nrec + 8 * (int64_t)root + 2))[0], nn));
         int sp = 1;
         wave_sync();
-        double E0 = 0.0, E1 = 0.0, E2 = 0.0, PH = 0.0;
         int nm = 0, np = 0, my_m = 0, my_src = 0;
         bool overflow = false;
         const double th2 = a.th2;
         while (sp > 0) {
             if (nm > L - 64 || np > L - 64) {
-                flush_lists<PREC, PHI>(a, ml, nm, pl, np, stage, pfx, lfirst, lane, sub, lpt, cg,
-                                       tx, ty, tz, i, E0, E1, E2, PH);
+                flush_lists<PREC, MODE>(a, ml, nm, pl, np, stage, pfx, lfirst, lane, sub, lpt, c,
+                                        gfirst, cg, tg);
                 nm = np = 0;
             }
             const int B = min(min(64, sp), max(1, kStackSoft - sp));
@@ -437,14 +629,14 @@ __global__ __launch_bounds__(256) void k_walk(WalkArgs a)
             wave_sync();
         }
         if (overflow) atomicOr(a.flags_rw, lane == 0 ? UCP_FLAG_WALK_STACK : 0);
-        flush_lists<PREC, PHI>(a, ml, nm, pl, np, stage, pfx, lfirst, lane, sub, lpt, cg, tx, ty,
-                               tz, i, E0, E1, E2, PH);
+        flush_lists<PREC, MODE>(a, ml, nm, pl, np, stage, pfx, lfirst, lane, sub, lpt, c, gfirst,
+                                cg, tg);
         // sum the lpt partial results of each target in fixed lane order
         double *red = (double *)stage;   // 64 x 4 doubles
-        red[4 * lane + 0] = E0;
-        red[4 * lane + 1] = E1;
-        red[4 * lane + 2] = E2;
-        red[4 * lane + 3] = PH;
+        red[4 * lane + 0] = tg.E0;
+        red[4 * lane + 1] = tg.E1;
+        red[4 * lane + 2] = tg.E2;
+        red[4 * lane + 3] = tg.PH;
         wave_sync();
         double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
         for (int s = 0; s < lpt; ++s) {
@@ -497,36 +689,112 @@ __global__ __launch_bounds__(256) void k_scatter(const double4 *__restrict__ acc
     if (phi) phi[i] = e.w;
 }
 
-template <int PREC, bool PHI>
+// ---------------------------------------------------------------------------
+// adjoint: prepare the sorted cotangents and clear the accumulators
+//   w_p = q_p u_{perm[p]},  xsrc = 0,  cbar = 0 (nodes read from the device)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_vjp_prep(const double *__restrict__ u,
+                                                 const double4 *__restrict__ xq,
+                                                 const uint32_t *__restrict__ perm, int64_t n,
+                                                 const int32_t *__restrict__ nnodes, double4 *w,
+                                                 double *xsrc, double *cbar, const int32_t *flags)
+{
+    if (*flags) return;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    for (int64_t p = t0; p < n; p += stride) {
+        const int64_t i = perm[p];
+        const double qq = xq[p].w;
+        w[p] = make_double4(qq * u[3 * i], qq * u[3 * i + 1], qq * u[3 * i + 2], 0.0);
+        *(double4 *)(xsrc + 4 * p) = make_double4(0.0, 0.0, 0.0, 0.0);
+    }
+    const int64_t nc = 10 * (int64_t)*nnodes;
+    for (int64_t e = t0; e < nc; e += stride) cbar[e] = 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// adjoint: per particle j (sorted), the target side (walk accumulators), the
+// P2P source side, and the cell cotangents of every box holding j:
+//   xbar_j = g_j + xsrc_j + q_j sum_{C holding j} (pbar_C + sym_C (x_j - c_C)),
+// then back to the caller's order.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_vjp_down(const double4 *__restrict__ acc,
+                                                 const double *__restrict__ xsrc,
+                                                 const double *__restrict__ cbar,
+                                                 const double4 *__restrict__ xq,
+                                                 const double4 *__restrict__ ngeo,
+                                                 const int32_t *__restrict__ npar,
+                                                 const int32_t *__restrict__ leafof,
+                                                 const int32_t *__restrict__ nnodes,
+                                                 const uint32_t *__restrict__ perm, int64_t n,
+                                                 double *xbar, int32_t *flags)
+{
+    if (*flags) return;
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const double4 x = xq[p];
+    const double4 g = acc[p];
+    double bx = 0.0, by = 0.0, bz = 0.0;
+    const int nn = *nnodes;
+    int k = leafof[p];
+    for (int depth = 0; k >= 0; ++depth) {
+        if (k >= nn || depth > 64) {   // inconsistent records
+            atomicOr(flags, UCP_FLAG_INTERNAL);
+            return;
+        }
+        const double *cb = cbar + 10 * (int64_t)k;
+        const double4 c = ngeo[k];
+        const double rx = x.x - c.x, ry = x.y - c.y, rz = x.z - c.z;
+        bx += cb[0] + cb[3] * rx + cb[6] * ry + cb[7] * rz;
+        by += cb[1] + cb[6] * rx + cb[4] * ry + cb[8] * rz;
+        bz += cb[2] + cb[7] * rx + cb[8] * ry + cb[5] * rz;
+        k = npar[k];
+    }
+    const int64_t i = perm[p];
+    xbar[3 * i + 0] = g.x + xsrc[4 * p + 0] + x.w * bx;
+    xbar[3 * i + 1] = g.y + xsrc[4 * p + 1] + x.w * by;
+    xbar[3 * i + 2] = g.z + xsrc[4 * p + 2] + x.w * bz;
+}
+
+template <int PREC, int MODE>
 static void launch_walk_t(Ctx *c, const WalkArgs &wa, hipStream_t s)
 {
     const int waves_per_cu = c->p_built.walk_waves > 0 ? c->p_built.walk_waves : 32;
     const int blocks = (c->num_cu * waves_per_cu + 3) / 4;
     const size_t lds = (size_t)4 * walk_wave_bytes<PREC>(wa.L);
-    hipLaunchKernelGGL((k_walk<PREC, PHI>), dim3(blocks), dim3(256), lds, s, wa);
+    hipLaunchKernelGGL((k_walk<PREC, MODE>), dim3(blocks), dim3(256), lds, s, wa);
 }
 
-void launch_forces(Ctx *c, double *f, double *phi, hipStream_t s)
+static WalkArgs walk_args(Ctx *c)
 {
-    const int64_t n = c->n;
     WalkArgs wa;
     wa.xq = c->d_xq;
+    wa.w = nullptr;
+    wa.cbar = nullptr;
+    wa.xsrc = nullptr;
     wa.nrec = c->d_nrec;
     wa.mom64 = c->d_mom64;
     wa.groups = c->d_groups;
-    wa.ngroups = c->d_goff + n;
-    wa.nnodes = c->d_noff + n;
+    wa.ngroups = c->d_goff + c->n;
+    wa.nnodes = c->d_noff + c->n;
     wa.gstat = c->d_gstat;
     wa.acc = c->d_acc;
     wa.ctr = c->d_ctr;
     wa.flags = c->d_flags;
     wa.flags_rw = c->d_flags;
-    wa.n = n;
+    wa.n = c->n;
     wa.n_spare = c->n_max;
     wa.th2 = c->p_built.theta * c->p_built.theta;
     wa.eps2 = c->p_built.eps * c->p_built.eps;
     wa.eps2f = (float)wa.eps2;
     wa.L = c->p_built.list_len;
+    return wa;
+}
+
+void launch_forces(Ctx *c, double *f, double *phi, hipStream_t s)
+{
+    const int64_t n = c->n;
+    const WalkArgs wa = walk_args(c);
     hipLaunchKernelGGL(k_walk_reset, dim3(1), dim3(64), 0, s, c->d_ctr);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (c->timing) {
@@ -544,16 +812,37 @@ void launch_forces(Ctx *c, double *f, double *phi, hipStream_t s)
     }
     const bool want_phi = phi != nullptr || f == nullptr;
     if (c->p_built.precision == UCP_SPLIT) {
-        if (want_phi) launch_walk_t<UCP_SPLIT, true>(c, wa, s);
-        else launch_walk_t<UCP_SPLIT, false>(c, wa, s);
+        if (want_phi) launch_walk_t<UCP_SPLIT, kWalkForcePhi>(c, wa, s);
+        else launch_walk_t<UCP_SPLIT, kWalkForce>(c, wa, s);
     } else {
-        if (want_phi) launch_walk_t<UCP_FP64, true>(c, wa, s);
-        else launch_walk_t<UCP_FP64, false>(c, wa, s);
+        if (want_phi) launch_walk_t<UCP_FP64, kWalkForcePhi>(c, wa, s);
+        else launch_walk_t<UCP_FP64, kWalkForce>(c, wa, s);
     }
     if (c->timing) (void)hipEventRecord(e1, s);
     hipLaunchKernelGGL(k_scatter, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
                        (const double4 *)c->d_acc, (const double4 *)c->d_xq,
                        (const uint32_t *)c->d_perm, n, f, phi, (const int32_t *)c->d_flags);
+}
+
+void launch_vjp(Ctx *c, const double *u, double *xbar, hipStream_t s)
+{
+    const int64_t n = c->n;
+    WalkArgs wa = walk_args(c);
+    wa.w = c->d_w;
+    wa.cbar = c->d_cbar;
+    wa.xsrc = c->d_xsrc;
+    hipLaunchKernelGGL(k_vjp_prep, dim3(1024), dim3(256), 0, s, u, (const double4 *)c->d_xq,
+                       (const uint32_t *)c->d_perm, n, (const int32_t *)(c->d_noff + n), c->d_w,
+                       c->d_xsrc, c->d_cbar, (const int32_t *)c->d_flags);
+    hipLaunchKernelGGL(k_walk_reset, dim3(1), dim3(64), 0, s, c->d_ctr);
+    if (c->p_built.precision == UCP_SPLIT) launch_walk_t<UCP_SPLIT, kWalkVjp>(c, wa, s);
+    else launch_walk_t<UCP_FP64, kWalkVjp>(c, wa, s);
+    hipLaunchKernelGGL(k_vjp_down, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                       (const double4 *)c->d_acc, (const double *)c->d_xsrc,
+                       (const double *)c->d_cbar, (const double4 *)c->d_xq,
+                       (const double4 *)c->d_ngeo, (const int32_t *)c->d_npar,
+                       (const int32_t *)c->d_leafof, (const int32_t *)(c->d_noff + n),
+                       (const uint32_t *)c->d_perm, n, xbar, c->d_flags);
 }
 
 }  // namespace ucp

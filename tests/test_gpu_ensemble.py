@@ -1,0 +1,72 @@
+"""The batched ensemble at full size and the walk autotuner, on the GPU.
+
+The 64-cloud ensemble (N_c = 2 U[4096, 65536], sigma_c = U[0.5, 2]) is built
+and walked in one batched call; a sample of its clouds is compared with the
+FP64 oracle tree of each cloud alone.  The autotuner must return one of its
+candidates, the fastest it measured, and read it back from its cache.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_0709_3331_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_0709_3331_amd import _lib as L  # noqa: E402
+from paper_0709_3331_amd import autotune  # noqa: E402
+from paper_0709_3331_amd.tree import TreeSolver  # noqa: E402
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def relrms(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def test_full_ensemble_sampled_clouds_match_oracle():
+    ens, off, prm = inputs.ensemble()
+    n, clouds = int(off[-1]), len(off) - 1
+    say(f"[ensemble] clouds={clouds} n={n}")
+    x, q = torch.from_numpy(ens.x).cuda(), torch.from_numpy(ens.q).cuda()
+    offs = torch.from_numpy(off).cuda()
+    sizes = np.diff(off)
+    pick = [int(np.argmin(sizes)), 7, int(np.argmax(sizes))]
+    for prec, tol in ((L.UCP_FP64, 1e-12), (L.UCP_SPLIT, 1e-5)):
+        ts = TreeSolver(n, clouds, theta=prm["theta"], eps=prm["eps"], precision=prec)
+        f = ts.tree_forces(x, q, offs).cpu().numpy()
+        st = ts.stats()
+        assert st["clouds"] == clouds
+        for c in pick:
+            a, b = off[c], off[c + 1]
+            ref = oracle.tree_forces(ens.x[a:b], ens.q[a:b], prm["theta"], prm["eps"], G=64)
+            e = relrms(f[a:b], ref["f"])
+            say(f"[ensemble]   prec={prec} cloud {c} (N={b - a}) rel RMS {e:.3e}")
+            assert e < tol
+        ts.close()
+
+
+def test_autotune_picks_fastest_candidate_and_caches(tmp_path):
+    sizes = [6000, 10000]
+    parts = [inputs.gaussian_cloud(s, 1.0, 1e-3, 1e-5, 40 + k) for k, s in enumerate(sizes)]
+    x = torch.from_numpy(np.concatenate([p.x for p in parts])).cuda()
+    q = torch.from_numpy(np.concatenate([p.q for p in parts])).cuda()
+    offs = torch.tensor([0, sizes[0], sum(sizes)], dtype=torch.int64, device="cuda")
+    cache = str(tmp_path / "tune.json")
+    cand = {"group_size": (32, 64), "list_len": (64, 128), "group_mode": (L.UCP_GROUP_CHUNK,)}
+    r = autotune.tune(x, q, offs, theta=0.5, eps=0.01, candidates=cand, reps=2, cache_path=cache)
+    say(f"[autotune] chose G={r['group_size']} L={r['list_len']} "
+        f"diff vs per-particle FP64 {r['rel_force_diff_vs_per_particle_fp64']:.3e}")
+    assert not r["cached"]
+    assert len(r["candidates"]) == 4
+    assert r["walk_ms"] == min(c["walk_ms"] for c in r["candidates"])
+    assert (r["group_size"], r["list_len"]) in [(G, Lq) for G in (32, 64) for Lq in (64, 128)]
+    assert 0.0 < r["rel_force_diff_vs_per_particle_fp64"] < 1e-2
+    r2 = autotune.tune(x, q, offs, theta=0.5, eps=0.01, candidates=cand, cache_path=cache)
+    assert r2["cached"] and r2["group_size"] == r["group_size"] and r2["list_len"] == r["list_len"]
