@@ -12,6 +12,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -70,12 +71,12 @@ def bench_ensemble(args, prec, dev):
     offs = torch.from_numpy(off).to(dev)
     print(f"bench: ensemble of {clouds} clouds, N={n}: tuning", file=sys.stderr, flush=True)
     tuned = autotune.tune(x, q, offs, theta=eprm["theta"], eps=eprm["eps"], precision=prec,
-                          candidates={"group_size": (32, 64), "list_len": (64, 128),
-                                      "group_mode": (1, 0)},
+                          candidates={"group_size": (32, 64), "list_len": (128,),
+                                      "group_mode": (1, 0), "leaf_cap": (8, 16, 24, 32)},
                           reps=2, use_cache=False)
     ts = TreeSolver(n, clouds, theta=eprm["theta"], eps=eprm["eps"], precision=prec,
                     group_size=tuned["group_size"], list_len=tuned["list_len"],
-                    group_mode=tuned["group_mode"])
+                    group_mode=tuned["group_mode"], leaf_cap=tuned["leaf_cap"])
     f = ts.tree_forces(x, q, offs)
     st = ts.stats()
     ts.step(x, v, f, q, m, eprm["dt"], 2, offsets=offs)
@@ -96,11 +97,81 @@ def bench_ensemble(args, prec, dev):
             "walk_ms": wms / max(wc, 1),
             "interactions_per_particle": (st["p2p"] + st["m2p"]) / n,
             "tuned": {"group_size": tuned["group_size"], "list_len": tuned["list_len"],
+                      "leaf_cap": tuned["leaf_cap"],
                       "group_mode": "chunk" if tuned["group_mode"] == 1 else "node",
                       "rel_force_diff_vs_per_particle_fp64":
                           tuned.get("rel_force_diff_vs_per_particle_fp64"),
-                      "candidates_walk_ms": {f"{r['group_mode']}/{r['group_size']}/{r['list_len']}":
+                      "candidates_walk_ms": {f"{r['group_mode']}/{r['group_size']}/{r['list_len']}/"
+                                             f"{r['leaf_cap']}":
                                              round(r["walk_ms"], 4) for r in tuned["candidates"]}}}
+
+
+def _finite(v):
+    """JSON has no NaN or infinity: report those as null."""
+    return v if isinstance(v, float) and math.isfinite(v) else None
+
+
+def bench_adjoint(prec, dev):
+    """Differentiable rollout of the N = 65,536 cloud (theta = 0.5, eps = 0.01,
+    dt = 1e-4, checkpoint every 20 steps); loss = final ion kinetic energy;
+    gradient with respect to sigma (x0 = sigma z) through the adjoint walk.
+    For horizons of 5, 20 and 200 steps the central difference in sigma
+    (h = 1e-7) is reported beside the gradient, not asserted: the stated time
+    step does not resolve electrons bound in the softened ion wells, so long
+    rollouts grow unstable, and along the perturbed path the opening decisions
+    can differ from the frozen lists.  Times are for the 200-step rollout."""
+    import torch
+
+    from paper_0709_3331_amd import adjoint, inputs
+    from paper_0709_3331_amd.tree import TreeSolver
+
+    cl, prm = inputs.adjoint(0)
+    n = cl.n
+    z = torch.from_numpy(cl.x).to(dev)
+    q = torch.from_numpy(cl.q).to(dev)
+    m = torch.from_numpy(cl.m).to(dev)
+    v0n = torch.from_numpy(cl.v).to(dev)
+    ts = None
+
+    def loss_of(sigma, v0, steps):
+        xT, vT = adjoint.rollout(ts, sigma * z, v0, q, m, prm["dt"], steps,
+                                 checkpoint_every=prm["ckpt"])
+        return adjoint.ion_kinetic_energy(vT, q, m)
+
+    out = {"n": n, "checkpoint_every": prm["ckpt"], "horizons": {}}
+    h = 1e-7
+    # (theta, steps): the configured theta at 5, 20 and 200 steps; theta = 0
+    # (direct sum, a smooth force map) at 5 and 20 steps separates the
+    # conditioning of the rollout from changes of the interaction lists
+    for th, steps in ((prm["theta"], 5), (prm["theta"], 20), (prm["theta"], prm["steps"]),
+                      (0.0, 5), (0.0, 20)):
+        if ts is None or ts.params.theta != th:
+            if ts is not None:
+                ts.close()
+            ts = TreeSolver(n, theta=th, eps=prm["eps"], precision=prec)
+        print(f"bench: adjoint rollout N={n} theta={th} steps={steps}", file=sys.stderr, flush=True)
+        sigma = torch.tensor(1.0, dtype=torch.float64, device=dev, requires_grad=True)
+        v0 = v0n.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        loss = loss_of(sigma, v0, steps)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        loss.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        with torch.no_grad():
+            lp = loss_of(torch.tensor(1.0 + h, dtype=torch.float64, device=dev), v0n, steps).item()
+            lm = loss_of(torch.tensor(1.0 - h, dtype=torch.float64, device=dev), v0n, steps).item()
+        fd = (lp - lm) / (2 * h)
+        g = sigma.grad.item()
+        out["horizons"][f"theta={th:g},steps={steps}"] = {
+            "loss": _finite(loss.item()), "dL_dsigma": _finite(g),
+            "dL_dsigma_central_difference": _finite(fd),
+            "rel_diff": _finite(abs(g - fd) / abs(fd)) if fd != 0 else None,
+            "forward_s": t1 - t0, "backward_s": t2 - t1}
+    ts.close()
+    return out
 
 
 def main():
@@ -112,6 +183,8 @@ def main():
     ap.add_argument("--theta", type=float, default=0.5)
     ap.add_argument("--group-size", type=int, default=64)
     ap.add_argument("--list-len", type=int, default=128)
+    ap.add_argument("--leaf-cap", type=int, default=24)
+    ap.add_argument("--walk-waves", type=int, default=0)
     ap.add_argument("--group-mode", choices=["node", "chunk"], default="chunk")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 comparator run")
@@ -120,6 +193,8 @@ def main():
     ap.add_argument("--no-ensemble", action="store_true",
                     help="skip the batched 64-cloud ensemble measurement")
     ap.add_argument("--ensemble-steps", type=int, default=10)
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the differentiable 200-step rollout measurement")
     ap.add_argument("--profile", action="store_true", help="short run for rocprofv3 (no extras)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 256 MiB device-to-device copy (counter calibration)")
@@ -148,7 +223,8 @@ def main():
     m = torch.from_numpy(cl.m).to(dev)
     gm = L.UCP_GROUP_CHUNK if args.group_mode == "chunk" else L.UCP_GROUP_NODE
     ts = TreeSolver(n, theta=theta, eps=eps, precision=prec, group_size=args.group_size,
-                    list_len=args.list_len, group_mode=gm)
+                    list_len=args.list_len, group_mode=gm, leaf_cap=args.leaf_cap,
+                    walk_waves=args.walk_waves)
     print(f"bench: N={n} theta={theta} precision={args.precision}", file=sys.stderr, flush=True)
 
     # initial forces; interaction counts of one evaluation
@@ -193,7 +269,7 @@ def main():
         "config": {"workload": f"single two-component Gaussian cloud N=524288 (sigma=1, 5% halo "
                                f"shell 2-3 sigma), theta={theta:g}, eps=0.005, G={args.group_size} "
                                f"({args.group_mode} groups), "
-                               f"leaf_cap=8, 63-bit keys, one KDK Verlet step dt=5e-5",
+                               f"leaf_cap={args.leaf_cap}, 63-bit keys, one KDK Verlet step dt=5e-5",
                    "n": n, "theta": theta, "precision": args.precision,
                    "group_size": args.group_size, "group_mode": args.group_mode},
         "interactions_per_s": inter / (walk_avg_ms * 1e-3),
@@ -208,7 +284,8 @@ def main():
         # against the FP64 oracle direct sum on sampled targets
         f_split = ts.tree_forces(x, q)
         ts64 = TreeSolver(n, theta=theta, eps=eps, precision=L.UCP_FP64,
-                          group_size=args.group_size, list_len=args.list_len, group_mode=gm)
+                          group_size=args.group_size, list_len=args.list_len, group_mode=gm,
+                          leaf_cap=args.leaf_cap, walk_waves=args.walk_waves)
         f64 = ts64.tree_forces(x, q)
         ts64.timing(True)
         torch.cuda.synchronize()
@@ -237,7 +314,8 @@ def main():
             sweep = {}
             for th in (0.3, 0.5, 0.7):
                 tt = TreeSolver(n, theta=th, eps=eps, precision=prec, group_size=args.group_size,
-                                list_len=args.list_len, group_mode=gm)
+                                list_len=args.list_len, group_mode=gm, leaf_cap=args.leaf_cap,
+                                walk_waves=args.walk_waves)
                 ft = tt.tree_forces(x, q)
                 tt.timing(True)
                 torch.cuda.synchronize()
@@ -255,7 +333,8 @@ def main():
                 tt.close()
             result["theta_sweep"] = sweep
         c0 = time.perf_counter()
-        ot = oracle.Tree(xs, qs, theta, eps, G=args.group_size, group_mode=gm)
+        ot = oracle.Tree(xs, qs, theta, eps, G=args.group_size, group_mode=gm,
+                         leaf_cap=args.leaf_cap)
         ro = ot.eval(want_phi=False)
         c1 = time.perf_counter()
         result["rel_force_err_vs_oracle_tree"] = float(
@@ -267,6 +346,8 @@ def main():
                       "groups) of the same N=524288 cloud at the same parameters; %.2f s" % (c1 - c0)}
     if not args.profile and not args.no_ensemble:
         result["ensemble"] = bench_ensemble(args, prec, dev)
+    if not args.profile and not args.no_adjoint:
+        result["adjoint"] = bench_adjoint(prec, dev)
     if args.calib_copy:
         a = torch.ones(64 << 20, dtype=torch.float32, device=dev)   # 256 MiB
         b = torch.empty_like(a)

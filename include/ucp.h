@@ -102,7 +102,7 @@ typedef struct {
 #define UCP_FLAG_INTERNAL       16   /* inconsistent tree records (a library defect) */
 #define UCP_FLAG_WALK_STACK     32   /* a walk group overflowed its traversal stack     */
 
-/* Default parameters: theta 0.5, eps 0.005, 63-bit keys, leaf_cap 8, G 64,
+/* Default parameters: theta 0.5, eps 0.005, 63-bit keys, leaf_cap 24, G 64,
  * list_len 128, UCP_SPLIT, walk_waves 0, UCP_GROUP_CHUNK.                    */
 void ucp_default_params(ucp_params *p);
 

@@ -158,7 +158,7 @@ class Tree:
     group_mode 0: node groups (a node of at most G particles whose parent holds
     more); group_mode 1: consecutive runs of G key-sorted particles."""
 
-    def __init__(self, x, q, theta, eps, b=21, leaf_cap=8, G=64, keep_lists=False, group_mode=1):
+    def __init__(self, x, q, theta, eps, b=21, leaf_cap=24, G=64, keep_lists=False, group_mode=1):
         lib = _load()
         self.x = _f64(x, (-1, 3)); self.q = _f64(q)
         self.n = self.x.shape[0]
@@ -293,7 +293,7 @@ def rebuild(series, cap):
     return par[:m], nch[:m]
 
 
-def tree_forces(x, q, theta, eps, b=21, leaf_cap=8, G=64, want_phi=True, group_mode=1):
+def tree_forces(x, q, theta, eps, b=21, leaf_cap=24, G=64, want_phi=True, group_mode=1):
     """Convenience: build the oracle tree and evaluate it."""
     t = Tree(x, q, theta, eps, b, leaf_cap, G, group_mode=group_mode)
     r = t.eval(want_phi=want_phi)
@@ -305,7 +305,7 @@ def tree_forces(x, q, theta, eps, b=21, leaf_cap=8, G=64, want_phi=True, group_m
 # --------------------------------------------------------------------------
 # C-3 Verlet and energies.
 # --------------------------------------------------------------------------
-def verlet(x, v, q, m, dt, nsteps, eps, mode="direct", theta=0.5, b=21, leaf_cap=8, G=64,
+def verlet(x, v, q, m, dt, nsteps, eps, mode="direct", theta=0.5, b=21, leaf_cap=24, G=64,
            f=None, group_mode=1):
     """KDK velocity Verlet; returns (x, v, f) after nsteps (copies)."""
     x = _f64(x, (-1, 3)).copy(); v = _f64(v, (-1, 3)).copy()

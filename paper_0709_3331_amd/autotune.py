@@ -1,12 +1,14 @@
-"""Autotuner for the walk's group size G, list length L and group rule.
+"""Autotuner for the walk's group size G, list length L, group rule and leaf
+capacity.
 
-G and the group rule decide which targets share one traversal, so they change
-the accepted sets (and the force error at truncation level), not only the
-speed; L changes only the FP64 summation order.  The tuner therefore times the
+G, the group rule and the leaf capacity decide which targets share one
+traversal and where the near field starts, so they change the accepted sets
+(and the force error at truncation level), not only the speed; L changes only
+the FP64 summation order.  The tuner therefore times the
 walk for every candidate on the caller's own workload, keeps the fastest, and
-reports that setting's force difference from the FP64 per-particle walk
-(G = 1, the walk of Sec. 3) on the same input, so the choice can be judged on
-accuracy as well.
+reports that setting's force difference from the FP64 per-particle walk over
+a tree of single-particle leaves (G = 1, leaf capacity 1: the tree and walk of
+Sec. 3) on the same input, so the choice can be judged on accuracy as well.
 
 Timing uses the library's own HIP events around each walk launch
 (ucp_set_timing / ucp_timing_read).  Results are cached in a JSON file keyed by
@@ -26,6 +28,7 @@ DEFAULT_CANDIDATES = {
     "group_size": (32, 48, 64),
     "list_len": (64, 128, 256),
     "group_mode": (L.UCP_GROUP_CHUNK, L.UCP_GROUP_NODE),
+    "leaf_cap": (8, 16, 24, 32),
 }
 
 
@@ -69,7 +72,7 @@ def _time_walk(x, q, offsets, reps, **params):
 
 def tune(x, q, offsets=None, *, theta, eps, precision=L.UCP_SPLIT, candidates=None, reps=3,
          cache_path=None, use_cache=True, reference=True):
-    """Pick (group_size, list_len, group_mode) for this workload.
+    """Pick (group_size, list_len, group_mode, leaf_cap) for this workload.
 
     x, q: float64 GPU tensors ((N, 3), (N,)); offsets: int64 GPU tensor of
     cloud offsets or None.  Returns a dict with the chosen parameters, the
@@ -85,24 +88,27 @@ def tune(x, q, offsets=None, *, theta, eps, precision=L.UCP_SPLIT, candidates=No
     cand = dict(DEFAULT_CANDIDATES)
     cand.update(candidates or {})
     rows = []
-    for gm in cand["group_mode"]:
-        for G in cand["group_size"]:
-            for Lq in cand["list_len"]:
-                ms, ipp = _time_walk(x, q, offsets, reps, theta=theta, eps=eps,
-                                     precision=precision, group_size=G, list_len=Lq,
-                                     group_mode=gm)
-                rows.append({"group_size": G, "list_len": Lq, "group_mode": gm, "walk_ms": ms,
-                             "interactions_per_particle": ipp})
+    for lc in cand["leaf_cap"]:
+        for gm in cand["group_mode"]:
+            for G in cand["group_size"]:
+                for Lq in cand["list_len"]:
+                    ms, ipp = _time_walk(x, q, offsets, reps, theta=theta, eps=eps,
+                                         precision=precision, group_size=G, list_len=Lq,
+                                         group_mode=gm, leaf_cap=lc)
+                    rows.append({"group_size": G, "list_len": Lq, "group_mode": gm,
+                                 "leaf_cap": lc, "walk_ms": ms,
+                                 "interactions_per_particle": ipp})
     best = min(rows, key=lambda r: r["walk_ms"])
     out = {"group_size": best["group_size"], "list_len": best["list_len"],
-           "group_mode": best["group_mode"], "walk_ms": best["walk_ms"], "candidates": rows}
+           "group_mode": best["group_mode"], "leaf_cap": best["leaf_cap"],
+           "walk_ms": best["walk_ms"], "candidates": rows}
     if reference:
         clouds_max = max(clouds, 1)
         tb = TreeSolver(n, clouds_max, theta=theta, eps=eps, precision=precision,
                         group_size=best["group_size"], list_len=best["list_len"],
-                        group_mode=best["group_mode"])
+                        group_mode=best["group_mode"], leaf_cap=best["leaf_cap"])
         tr = TreeSolver(n, clouds_max, theta=theta, eps=eps, precision=L.UCP_FP64, group_size=1,
-                        group_mode=L.UCP_GROUP_CHUNK)
+                        group_mode=L.UCP_GROUP_CHUNK, leaf_cap=1)
         try:
             fb = tb.tree_forces(x, q, offsets)
             fr = tr.tree_forces(x, q, offsets)

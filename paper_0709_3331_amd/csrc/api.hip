@@ -154,7 +154,7 @@ void ucp_default_params(ucp_params *p)
     p->theta = 0.5;
     p->eps = 0.005;
     p->key_bits = 63;
-    p->leaf_cap = 8;
+    p->leaf_cap = 24;
     p->group_size = 64;
     p->list_len = 128;
     p->precision = UCP_SPLIT;

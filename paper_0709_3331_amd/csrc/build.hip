@@ -601,15 +601,13 @@ __device__ __forceinline__ void store_moments(double *mom64, float4 *nrec, int k
     f4[2] = make_float4((float)m[7], (float)m[8], (float)m[9], 0.f);
 }
 
-__global__ __launch_bounds__(256) void k_moments_level(
-    int level, const double4 *__restrict__ xq, int64_t n, const int8_t *__restrict__ Lv,
+// the node of `level` starting at position p, if there is one
+__device__ __forceinline__ void moments_node(
+    int64_t p, int level, const double4 *__restrict__ xq, int64_t n, const int8_t *__restrict__ Lv,
     const int8_t *__restrict__ Lf, const int32_t *__restrict__ noff,
     const double4 *__restrict__ ngeo, int4 *ninfo, int32_t *npar, double *mom64, float4 *nrec,
-    int32_t *leafof, const unsigned long long *__restrict__ ctr, int32_t *flags)
+    int32_t *leafof, int32_t *flags)
 {
-    if (*flags) return;
-    if ((unsigned long long)level > ctr[CTR_MAXLEVEL]) return;   // no node this deep
-    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (p >= n) return;
     const int Lp = Lv[p], lf = Lf[p];
     if (!(Lp < level && level <= lf)) return;
@@ -680,6 +678,23 @@ __global__ __launch_bounds__(256) void k_moments_level(
     *(double4 *)(nrec + 8 * (int64_t)k) = g;
     *(int4 *)(nrec + 8 * (int64_t)k + 2) = make_int4(skip, (int)p, cnt, info);
     store_moments(mom64, nrec, k, g, m);
+}
+
+// one launch per level, one thread per position (several positions per
+// thread serialise their child chains and are slower)
+constexpr int kMomThreads = 256, kMomPer = 1;
+__global__ __launch_bounds__(kMomThreads) void k_moments_level(
+    int level, const double4 *__restrict__ xq, int64_t n, const int8_t *__restrict__ Lv,
+    const int8_t *__restrict__ Lf, const int32_t *__restrict__ noff,
+    const double4 *__restrict__ ngeo, int4 *ninfo, int32_t *npar, double *mom64, float4 *nrec,
+    int32_t *leafof, const unsigned long long *__restrict__ ctr, int32_t *flags)
+{
+    if (*flags) return;
+    if ((unsigned long long)level > ctr[CTR_MAXLEVEL]) return;   // no node this deep
+    const int64_t base = (int64_t)blockIdx.x * kMomThreads * kMomPer + threadIdx.x;
+    for (int r = 0; r < kMomPer; ++r)
+        moments_node(base + (int64_t)r * kMomThreads, level, xq, n, Lv, Lf, noff, ngeo, ninfo,
+                     npar, mom64, nrec, leafof, flags);
 }
 
 // ---------------------------------------------------------------------------
@@ -845,7 +860,8 @@ void launch_build(Ctx *c, const double *x, const double *q, const int64_t *offse
                        c->d_ctr, c->d_flags);
     // 6. moments, deepest level first
     for (int l = b; l >= 0; --l)
-        hipLaunchKernelGGL(k_moments_level, grid_for(n, 256), dim3(256), 0, s, l,
+        hipLaunchKernelGGL(k_moments_level, grid_for(n, kMomThreads * kMomPer), dim3(kMomThreads),
+                           0, s, l,
                            (const double4 *)c->d_xq, n, (const int8_t *)c->d_L,
                            (const int8_t *)c->d_leaf, (const int32_t *)c->d_noff,
                            (const double4 *)c->d_ngeo, c->d_ninfo, c->d_npar, c->d_mom64,

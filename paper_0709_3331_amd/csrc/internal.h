@@ -26,7 +26,7 @@ constexpr int kScanSmallItems = 64;            // elements per thread, one-block
 constexpr int64_t kScanSmallLimit = 4096;
 
 // device counter slots (unsigned long long)
-enum { CTR_P2P = 0, CTR_M2P = 1, CTR_MAXLEVEL = 2, CTR_QUEUE = 3, CTR_NCTR = 8 };
+enum { CTR_P2P = 0, CTR_M2P = 1, CTR_MAXLEVEL = 2, CTR_QUEUE = 3, CTR_VJPMAX = 4, CTR_NCTR = 8 };
 
 struct Ctx;
 

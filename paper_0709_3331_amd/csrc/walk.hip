@@ -690,21 +690,68 @@ __global__ __launch_bounds__(256) void k_scatter(const double4 *__restrict__ acc
 }
 
 // ---------------------------------------------------------------------------
+// adjoint: the cotangents are scaled by a power of two s >= max |q_i u_i| so
+// that the FP32 arithmetic of the split walk cannot overflow however large
+// they grow (a rollout's cotangents grow with its instability); s is exact,
+// and the result is scaled back in FP64.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_vjp_max(const double *__restrict__ u,
+                                                const double4 *__restrict__ xq,
+                                                const uint32_t *__restrict__ perm, int64_t n,
+                                                unsigned long long *ctr, const int32_t *flags)
+{
+    __shared__ double red[4];
+    if (*flags) return;
+    double mx = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n; p += stride) {
+        const double a = fabs(xq[p].w);
+        const int64_t i = perm[p];
+        mx = fmax(mx, fmax(a * fabs(u[3 * i]), fmax(a * fabs(u[3 * i + 1]), a * fabs(u[3 * i + 2]))));
+    }
+    for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        mx = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+        // non-negative doubles order like their bit patterns (NaN is largest)
+        atomicMax(&ctr[CTR_VJPMAX], (unsigned long long)__double_as_longlong(mx));
+    }
+}
+
+__device__ __forceinline__ double vjp_scale(const unsigned long long *ctr)
+{
+    const double mx = __longlong_as_double((long long)ctr[CTR_VJPMAX]);
+    if (!(mx > 0.0) || !isfinite(mx)) return 1.0;
+    int e;
+    frexp(mx, &e);
+    return ldexp(1.0, e);   // power of two > mx
+}
+
+__global__ void k_vjp_reset(unsigned long long *ctr)
+{
+    if (threadIdx.x == 0) ctr[CTR_VJPMAX] = 0ull;
+}
+
+// ---------------------------------------------------------------------------
 // adjoint: prepare the sorted cotangents and clear the accumulators
-//   w_p = q_p u_{perm[p]},  xsrc = 0,  cbar = 0 (nodes read from the device)
+//   w_p = q_p u_{perm[p]} / s,  xsrc = 0,  cbar = 0 (nodes read from the device)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_vjp_prep(const double *__restrict__ u,
                                                  const double4 *__restrict__ xq,
                                                  const uint32_t *__restrict__ perm, int64_t n,
-                                                 const int32_t *__restrict__ nnodes, double4 *w,
-                                                 double *xsrc, double *cbar, const int32_t *flags)
+                                                 const int32_t *__restrict__ nnodes,
+                                                 const unsigned long long *__restrict__ ctr,
+                                                 double4 *w, double *xsrc, double *cbar,
+                                                 const int32_t *flags)
 {
     if (*flags) return;
+    const double inv = 1.0 / vjp_scale(ctr);
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     for (int64_t p = t0; p < n; p += stride) {
         const int64_t i = perm[p];
-        const double qq = xq[p].w;
+        const double qq = xq[p].w * inv;
         w[p] = make_double4(qq * u[3 * i], qq * u[3 * i + 1], qq * u[3 * i + 2], 0.0);
         *(double4 *)(xsrc + 4 * p) = make_double4(0.0, 0.0, 0.0, 0.0);
     }
@@ -727,9 +774,11 @@ __global__ __launch_bounds__(256) void k_vjp_down(const double4 *__restrict__ ac
                                                  const int32_t *__restrict__ leafof,
                                                  const int32_t *__restrict__ nnodes,
                                                  const uint32_t *__restrict__ perm, int64_t n,
+                                                 const unsigned long long *__restrict__ ctr,
                                                  double *xbar, int32_t *flags)
 {
     if (*flags) return;
+    const double sc = vjp_scale(ctr);
     const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (p >= n) return;
     const double4 x = xq[p];
@@ -751,9 +800,9 @@ __global__ __launch_bounds__(256) void k_vjp_down(const double4 *__restrict__ ac
         k = npar[k];
     }
     const int64_t i = perm[p];
-    xbar[3 * i + 0] = g.x + xsrc[4 * p + 0] + x.w * bx;
-    xbar[3 * i + 1] = g.y + xsrc[4 * p + 1] + x.w * by;
-    xbar[3 * i + 2] = g.z + xsrc[4 * p + 2] + x.w * bz;
+    xbar[3 * i + 0] = sc * (g.x + xsrc[4 * p + 0] + x.w * bx);
+    xbar[3 * i + 1] = sc * (g.y + xsrc[4 * p + 1] + x.w * by);
+    xbar[3 * i + 2] = sc * (g.z + xsrc[4 * p + 2] + x.w * bz);
 }
 
 template <int PREC, int MODE>
@@ -831,9 +880,13 @@ void launch_vjp(Ctx *c, const double *u, double *xbar, hipStream_t s)
     wa.w = c->d_w;
     wa.cbar = c->d_cbar;
     wa.xsrc = c->d_xsrc;
+    hipLaunchKernelGGL(k_vjp_reset, dim3(1), dim3(64), 0, s, c->d_ctr);
+    hipLaunchKernelGGL(k_vjp_max, dim3(256), dim3(256), 0, s, u, (const double4 *)c->d_xq,
+                       (const uint32_t *)c->d_perm, n, c->d_ctr, (const int32_t *)c->d_flags);
     hipLaunchKernelGGL(k_vjp_prep, dim3(1024), dim3(256), 0, s, u, (const double4 *)c->d_xq,
-                       (const uint32_t *)c->d_perm, n, (const int32_t *)(c->d_noff + n), c->d_w,
-                       c->d_xsrc, c->d_cbar, (const int32_t *)c->d_flags);
+                       (const uint32_t *)c->d_perm, n, (const int32_t *)(c->d_noff + n),
+                       (const unsigned long long *)c->d_ctr, c->d_w, c->d_xsrc, c->d_cbar,
+                       (const int32_t *)c->d_flags);
     hipLaunchKernelGGL(k_walk_reset, dim3(1), dim3(64), 0, s, c->d_ctr);
     if (c->p_built.precision == UCP_SPLIT) launch_walk_t<UCP_SPLIT, kWalkVjp>(c, wa, s);
     else launch_walk_t<UCP_FP64, kWalkVjp>(c, wa, s);
@@ -842,7 +895,8 @@ void launch_vjp(Ctx *c, const double *u, double *xbar, hipStream_t s)
                        (const double *)c->d_cbar, (const double4 *)c->d_xq,
                        (const double4 *)c->d_ngeo, (const int32_t *)c->d_npar,
                        (const int32_t *)c->d_leafof, (const int32_t *)(c->d_noff + n),
-                       (const uint32_t *)c->d_perm, n, xbar, c->d_flags);
+                       (const uint32_t *)c->d_perm, n, (const unsigned long long *)c->d_ctr, xbar,
+                       c->d_flags);
 }
 
 }  // namespace ucp

@@ -36,7 +36,7 @@ def test_oracle_is_not_linked_into_the_library():
 
 def test_default_params_and_version():
     p = L.default_params()
-    assert p.theta == 0.5 and p.key_bits == 63 and p.leaf_cap == 8 and p.group_size == 64
+    assert p.theta == 0.5 and p.key_bits == 63 and p.leaf_cap == 24 and p.group_size == 64
     assert p.precision == L.UCP_SPLIT and p.group_mode == L.UCP_GROUP_CHUNK
     assert L.ucp_version() >= 100
 

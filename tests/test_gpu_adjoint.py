@@ -153,3 +153,22 @@ def test_rollout_checkpointing_matches_stored_graph():
     assert out[0][1] == pytest.approx(out[1][1], rel=1e-9)
     torch.testing.assert_close(out[0][2], out[1][2], rtol=1e-9, atol=1e-12)
     ts.close()
+
+
+def test_vjp_is_linear_and_finite_for_huge_cotangents():
+    # the split walk computes in FP32; the library scales the cotangent by a
+    # power of two first, so u * 1e30 gives 1e30 times the result, not inf
+    n = 2000
+    cl = inputs.gaussian_cloud(n, 1.0, 1e-3, 1e-5, 27)
+    u = np.random.default_rng(6).normal(size=(n, 3))
+    ts = TreeSolver(n, theta=0.5, eps=0.01, precision=L.UCP_SPLIT)
+    ts.build(dev(cl.x), dev(cl.q))
+    a = ts.vjp(dev(u)).cpu().numpy()
+    b = ts.vjp(dev(u * 1e30)).cpu().numpy()
+    c = ts.vjp(dev(u * 1e-30)).cpu().numpy()
+    assert np.isfinite(b).all() and np.isfinite(c).all()
+    assert relrms(b, 1e30 * a) < 1e-6
+    assert relrms(c, 1e-30 * a) < 1e-6
+    z = ts.vjp(dev(np.zeros((n, 3)))).cpu().numpy()
+    assert np.all(z == 0.0)
+    ts.close()

@@ -59,7 +59,8 @@ def test_autotune_picks_fastest_candidate_and_caches(tmp_path):
     q = torch.from_numpy(np.concatenate([p.q for p in parts])).cuda()
     offs = torch.tensor([0, sizes[0], sum(sizes)], dtype=torch.int64, device="cuda")
     cache = str(tmp_path / "tune.json")
-    cand = {"group_size": (32, 64), "list_len": (64, 128), "group_mode": (L.UCP_GROUP_CHUNK,)}
+    cand = {"group_size": (32, 64), "list_len": (64, 128), "group_mode": (L.UCP_GROUP_CHUNK,),
+            "leaf_cap": (24,)}
     r = autotune.tune(x, q, offs, theta=0.5, eps=0.01, candidates=cand, reps=2, cache_path=cache)
     say(f"[autotune] chose G={r['group_size']} L={r['list_len']} "
         f"diff vs per-particle FP64 {r['rel_force_diff_vs_per_particle_fp64']:.3e}")

@@ -150,7 +150,7 @@ def test_degenerate_inputs():
     # 100 coincident particles (one max-depth leaf chain) + 100 at another point
     xx = np.zeros((200, 3)); xx[100:] = [0.5, 0.25, -0.125]
     qq = np.where(np.arange(200) % 2 == 0, 1.0, -1.0)
-    t = oracle.Tree(xx, qq, 0.5, 0.01, leaf_cap=8, G=64)
+    t = oracle.Tree(xx, qq, 0.5, 0.01, G=64)
     ref = t.eval()
     f, phi = ts.tree_forces(dev(xx), dev(qq), want_phi=True)
     check_topology(ts, t)
