@@ -63,7 +63,7 @@ void free_all(Ctx *c)
                     c->d_leaf, c->d_cnt,    c->d_noff,  c->d_goff,   c->d_gnode,  c->d_scanblk,
                     c->d_ngeo, c->d_ninfo,  c->d_npar,  c->d_mom64,  c->d_nrec,
                     c->d_groups, c->d_gstat, c->d_acc,  c->d_ctr,    c->d_flags,  c->d_epart,
-                    c->d_leafof, c->d_w,    c->d_xsrc,  c->d_cbar};
+                    c->d_leafof, c->d_w,    c->d_xsrc,  c->d_cbar,  c->d_wq};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
@@ -219,6 +219,7 @@ ucp_status ucp_create(ucp_ctx **out, int64_t n_max, int32_t clouds_max, const uc
     ALLOC(c->d_acc, N + 64);   // 64 spare slots for the walk's inactive lanes
     ALLOC(c->d_leafof, N);
     ALLOC(c->d_ctr, ucp::CTR_NCTR);
+    ALLOC(c->d_wq, ucp::kWalkQueues * ucp::kQStride);
     ALLOC(c->d_flags, 4);
     ALLOC(c->d_epart, 4 * 256);
 #undef ALLOC

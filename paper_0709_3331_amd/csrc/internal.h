@@ -26,7 +26,9 @@ constexpr int kScanSmallItems = 64;            // elements per thread, one-block
 constexpr int64_t kScanSmallLimit = 4096;
 
 // device counter slots (unsigned long long)
-enum { CTR_P2P = 0, CTR_M2P = 1, CTR_MAXLEVEL = 2, CTR_QUEUE = 3, CTR_VJPMAX = 4, CTR_NCTR = 8 };
+enum { CTR_P2P = 0, CTR_M2P = 1, CTR_MAXLEVEL = 2, CTR_VJPMAX = 4, CTR_NCTR = 8 };
+// walk work queues: one per XCD, each on its own 128-byte line
+constexpr int kWalkQueues = 8, kQStride = 16;
 
 struct Ctx;
 
@@ -110,6 +112,7 @@ struct Ctx {
     double *d_cbar = nullptr;               // [node_cap][10] cell cotangents
     // counters, flags
     unsigned long long *d_ctr = nullptr;    // [CTR_NCTR]
+    unsigned long long *d_wq = nullptr;     // [kWalkQueues * kQStride] walk queue heads
     int32_t *d_flags = nullptr;             // [1]
     // energy partials
     double *d_epart = nullptr;              // [256][8]

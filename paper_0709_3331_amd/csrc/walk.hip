@@ -56,6 +56,7 @@ struct WalkArgs {
     int2 *gstat;
     double4 *acc;
     unsigned long long *ctr;
+    unsigned long long *wq;     // queue heads (kWalkQueues, kQStride apart)
     const int32_t *flags;
     int32_t *flags_rw;
     int64_t n;
@@ -497,13 +498,27 @@ __global__ __launch_bounds__(256) void k_walk(WalkArgs a)
     // every loop below is bounded by these totals, whatever the records hold
     const int ng = min(*a.ngroups, (int)a.n);
     const int nn = *a.nnodes;
-    // No divergent branch anywhere around the queue: every lane executes the
+    // Groups are split into kWalkQueues contiguous ranges, one per XCD (work
+    // groups are dispatched to the XCDs in turn, so block b runs on XCD
+    // b mod 8): neighbouring groups share most of their lists, and keeping
+    // them on one XCD keeps those nodes in that XCD's L2.  A wave whose
+    // queue is exhausted moves on to the next one, so all finish together.
+    // No divergent branch anywhere around a queue: every lane executes the
     // atomic, only lane 0 adds 1, so lane 0 receives the value before its own
-    // increment.
+    // increment.  Queue heads only grow, so each wave passes each exhausted
+    // queue once and the loop ends.
+    int qx = (int)(blockIdx.x % kWalkQueues), exhausted = 0;
     for (;;) {
-        const unsigned long long old = atomicAdd(&a.ctr[CTR_QUEUE], lane == 0 ? 1ull : 0ull);
-        const int g = uni((int)old);
-        if (g >= ng) break;
+        const unsigned long long old =
+            atomicAdd(&a.wq[kQStride * qx], lane == 0 ? 1ull : 0ull);
+        const int g0 = (int)(((int64_t)ng * qx) / kWalkQueues);
+        const int g1 = (int)(((int64_t)ng * (qx + 1)) / kWalkQueues);
+        const int g = g0 + uni((int)min(old, (unsigned long long)ng));
+        if (g >= g1) {
+            if (++exhausted == kWalkQueues) break;
+            qx = qx + 1 == kWalkQueues ? 0 : qx + 1;
+            continue;
+        }
         const int4 gr = a.groups[g];
         const int gfirst = uni(gr.x), c = uni(gr.y), gnode = uni(gr.z), root = uni(gr.w);
         if (gfirst < 0 || c < 1 || c > kMaxGroup || (int64_t)gfirst + c > a.n || gnode < 0 ||
@@ -660,13 +675,13 @@ __global__ __launch_bounds__(256) void k_walk(WalkArgs a)
     }
 }
 
-__global__ void k_walk_reset(unsigned long long *ctr)
+__global__ void k_walk_reset(unsigned long long *ctr, unsigned long long *wq)
 {
     if (threadIdx.x == 0) {
-        ctr[CTR_QUEUE] = 0;
         ctr[CTR_P2P] = 0;
         ctr[CTR_M2P] = 0;
     }
+    if (threadIdx.x < kWalkQueues) wq[kQStride * threadIdx.x] = 0;
 }
 
 // F_i = q_i E_i and phi_i back to the caller's order
@@ -829,6 +844,7 @@ static WalkArgs walk_args(Ctx *c)
     wa.gstat = c->d_gstat;
     wa.acc = c->d_acc;
     wa.ctr = c->d_ctr;
+    wa.wq = c->d_wq;
     wa.flags = c->d_flags;
     wa.flags_rw = c->d_flags;
     wa.n = c->n;
@@ -844,7 +860,7 @@ void launch_forces(Ctx *c, double *f, double *phi, hipStream_t s)
 {
     const int64_t n = c->n;
     const WalkArgs wa = walk_args(c);
-    hipLaunchKernelGGL(k_walk_reset, dim3(1), dim3(64), 0, s, c->d_ctr);
+    hipLaunchKernelGGL(k_walk_reset, dim3(1), dim3(64), 0, s, c->d_ctr, c->d_wq);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (c->timing) {
         if ((int64_t)c->ev.size() < 2 * (c->ev_used + 1)) {
@@ -887,7 +903,7 @@ void launch_vjp(Ctx *c, const double *u, double *xbar, hipStream_t s)
                        (const uint32_t *)c->d_perm, n, (const int32_t *)(c->d_noff + n),
                        (const unsigned long long *)c->d_ctr, c->d_w, c->d_xsrc, c->d_cbar,
                        (const int32_t *)c->d_flags);
-    hipLaunchKernelGGL(k_walk_reset, dim3(1), dim3(64), 0, s, c->d_ctr);
+    hipLaunchKernelGGL(k_walk_reset, dim3(1), dim3(64), 0, s, c->d_ctr, c->d_wq);
     if (c->p_built.precision == UCP_SPLIT) launch_walk_t<UCP_SPLIT, kWalkVjp>(c, wa, s);
     else launch_walk_t<UCP_FP64, kWalkVjp>(c, wa, s);
     hipLaunchKernelGGL(k_vjp_down, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
