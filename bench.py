@@ -121,10 +121,13 @@ def bench_adjoint(prec, dev):
       - a resolved control, dt = 1e-6, theta = 0.5, 200 steps, several h.
     The stated dt does not resolve electrons bound in the softened ion wells
     (omega dt ~ 4), so perturbations grow ~18x per step there and the finite
-    differences stop being linear within a few steps; in the resolved control
-    they are.  Nothing here is asserted; the gradient checks are tests."""
+    differences stop being linear within a few steps unless h is tiny; in the
+    resolved control they are.  Finite differences use the FP64 path; the
+    stated 200-step workload is also timed in the benchmark precision.
+    Nothing here is asserted; the gradient checks are tests."""
     import torch
 
+    from paper_0709_3331_amd import _lib as L
     from paper_0709_3331_amd import adjoint, inputs
     from paper_0709_3331_amd.tree import TreeSolver
 
@@ -140,14 +143,20 @@ def bench_adjoint(prec, dev):
         xT, vT = adjoint.rollout(ts, sigma * z, v0, q, m, dt, steps, checkpoint_every=prm["ckpt"])
         return adjoint.ion_kinetic_energy(vT, q, m)
 
-    cases = [(prm["theta"], prm["dt"], 5, (1e-7,)), (prm["theta"], prm["dt"], 20, (1e-7,)),
-             (prm["theta"], prm["dt"], prm["steps"], (1e-7,)), (0.0, prm["dt"], 5, (1e-7, 1e-9, 1e-11)),
-             (prm["theta"], 1e-6, prm["steps"], (1e-7, 1e-9))]
+    # (theta, dt, steps, finite-difference steps h, precision); the finite
+    # differences need the FP64 path: FP32 arithmetic makes the loss noisy at
+    # the 1e-7 level, far above what 2h resolves
+    fp64 = L.UCP_FP64
+    cases = [(prm["theta"], prm["dt"], prm["steps"], (), prec),
+             (prm["theta"], prm["dt"], 5, (1e-7, 1e-9, 1e-11), fp64),
+             (prm["theta"], prm["dt"], 20, (1e-9, 1e-11), fp64),
+             (0.0, prm["dt"], 5, (1e-7, 1e-9, 1e-11), fp64),
+             (prm["theta"], 1e-6, prm["steps"], (1e-7, 1e-9), fp64)]
     out = {"n": n, "eps": prm["eps"], "checkpoint_every": prm["ckpt"], "cases": {}}
-    for th, dt, steps, hs in cases:
-        if th not in solvers:
-            solvers[th] = TreeSolver(n, theta=th, eps=prm["eps"], precision=prec)
-        ts = solvers[th]
+    for th, dt, steps, hs, pr in cases:
+        if (th, pr) not in solvers:
+            solvers[(th, pr)] = TreeSolver(n, theta=th, eps=prm["eps"], precision=pr)
+        ts = solvers[(th, pr)]
         print(f"bench: adjoint rollout N={n} theta={th} dt={dt} steps={steps}", file=sys.stderr,
               flush=True)
         sigma = torch.tensor(1.0, dtype=torch.float64, device=dev, requires_grad=True)
@@ -171,7 +180,8 @@ def bench_adjoint(prec, dev):
             fd = (lp - lm) / (2 * h)
             fds[f"{h:g}"] = {"central_difference": _finite(fd),
                              "rel_diff": _finite(abs(g - fd) / abs(fd)) if fd != 0 else None}
-        out["cases"][f"theta={th:g},dt={dt:g},steps={steps}"] = {
+        name = "split" if pr == L.UCP_SPLIT else "fp64"
+        out["cases"][f"theta={th:g},dt={dt:g},steps={steps},{name}"] = {
             "loss": _finite(loss.item()), "dL_dsigma": _finite(g), "fd": fds,
             "forward_s": t1 - t0, "backward_s": t2 - t1}
     for ts in solvers.values():

@@ -57,6 +57,7 @@ def _load():
         "orc_tree_moments": (None, [vp, _dp, _dp, _dp]),
         "orc_tree_eval": (None, [vp, _dp, _dp, _dp, vp, vp, vp, vp]),
         "orc_tree_vjp": (i32, [vp, _dp, _dp, _dp, _dp]),
+        "orc_tree_eval_groups": (i32, [vp, _dp, _dp, i64, _i64p, _dp, vp, vp, vp]),
         "orc_tree_arch_series": (i64, [vp, _i64p]),
         "orc_rebuild": (i64, [i64, _i64p, i64, _i64p, _i64p]),
         "orc_verlet": (i32, [i64, _dp, _dp, _dp, _dp, i32, dbl, dbl, i32, i32, i32, i32, dbl,
@@ -241,6 +242,21 @@ class Tree:
         if group_counts:
             out["gm2p"], out["gp2p"] = gm, gp
         return out
+
+    def eval_groups(self, gsel, x=None, want_phi=False):
+        """Tree forces of the members of the selected groups only.  Returns
+        dict f, phi (caller order; rows of other particles are NaN) and the
+        per-selected-group list lengths gm2p, gp2p."""
+        x = self.x if x is None else _f64(x, (-1, 3))
+        gsel = np.ascontiguousarray(gsel, dtype=np.int64)
+        f = np.full((self.n, 3), np.nan)
+        phi = np.full(self.n, np.nan) if want_phi else None
+        gm = np.zeros(gsel.size, dtype=np.int64)
+        gp = np.zeros(gsel.size, dtype=np.int64)
+        if _lib.orc_tree_eval_groups(self._h, x, self.q, gsel.size, gsel, f, _ptr(phi), _ptr(gm),
+                                     _ptr(gp)) != 0:
+            raise ValueError("group index out of range")
+        return {"f": f, "phi": phi, "gm2p": gm, "gp2p": gp}
 
     def vjp(self, u, x=None):
         """Frozen-list (dF/dx)^T u; needs keep_lists=True."""

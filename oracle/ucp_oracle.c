@@ -606,8 +606,63 @@ void orc_tree_moments(const orc_tree *t, const double *x, const double *q, doubl
 /* stats[1] = M2P interactions.  gm2p/gp2p (optional, length ng) receive the  */
 /* per-group number of accepted cells and of P2P source particles.           */
 /* ------------------------------------------------------------------------- */
-void orc_tree_eval(const orc_tree *t, const double *x, const double *q, double *f, double *phi,
-                   int64_t *stats, int64_t *gm2p, int64_t *gp2p)
+/* Forces and potentials of the members of group g (C-2.8), written in the   */
+/* caller's order; returns the group's list lengths (cells, P2P sources).    */
+static void eval_group(const orc_tree *t, const double *xs, const double *qs, const double *mom,
+                       double eps2, int64_t g, ivec *M, ivec *P, double *f, double *phi,
+                       int64_t *mn_out, int64_t *nsrc_out)
+{
+    const int64_t *mv, *pv;
+    int64_t mn, pn;
+    if (t->keep_lists) {
+        mv = t->m2p[g]; mn = t->nm2p[g];
+        pv = t->p2p[g]; pn = t->np2p[g];
+    } else {
+        tree_walk_group(t, xs, g, M, P);
+        mv = M->v; mn = M->n;
+        pv = P->v; pn = P->n;
+    }
+    int64_t nsrc = 0;
+    for (int64_t a = 0; a < pn; ++a) nsrc += t->count[pv[a]];
+    *mn_out = mn;
+    *nsrc_out = nsrc;
+    for (int64_t a = 0; a < t->gcount[g]; ++a) {
+        int64_t i = t->gfirst[g] + a;
+        const double *xi = xs + 3 * i;
+        nsum E[3] = {{0, 0}, {0, 0}, {0, 0}}, ph = {0, 0};
+        for (int64_t m = 0; m < mn; ++m) {
+            int64_t k = mv[m];
+            const double *c = t->centre + 3 * k;
+            double r[3] = {xi[0] - c[0], xi[1] - c[1], xi[2] - c[2]};
+            double Ec[3], pc;
+            cell_field(mom + 10 * k, r, eps2, Ec, &pc);
+            for (int d = 0; d < 3; ++d) nadd(&E[d], Ec[d]);
+            nadd(&ph, pc);
+        }
+        for (int64_t m = 0; m < pn; ++m) {
+            int64_t k = pv[m];
+            for (int64_t j = t->first[k]; j < t->first[k] + t->count[k]; ++j) {
+                double r[3] = {xi[0] - xs[3 * j], xi[1] - xs[3 * j + 1], xi[2] - xs[3 * j + 2]};
+                double h2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2] + eps2;
+                double h = sqrt(h2);
+                double w = qs[j] / (h2 * h);
+                for (int d = 0; d < 3; ++d) nadd(&E[d], w * r[d]);
+                if (j != i) nadd(&ph, qs[j] / h);
+            }
+        }
+        int64_t ci = t->perm[i];
+        for (int d = 0; d < 3; ++d) f[3 * ci + d] = qs[i] * nval(E[d]);
+        if (phi) phi[ci] = nval(ph);
+    }
+}
+
+/* Tree forces of the groups gsel[0 .. ngs-1] only (all groups when gsel is  */
+/* NULL); members of other groups are left untouched in f and phi.  gm2p and */
+/* gp2p, when given, receive the list lengths per evaluated group, in the    */
+/* order evaluated.                                                          */
+static void eval_groups(const orc_tree *t, const double *x, const double *q, int64_t ngs,
+                        const int64_t *gsel, double *f, double *phi, int64_t *stats, int64_t *gm2p,
+                        int64_t *gp2p)
 {
     int64_t n = t->n;
     if (stats) { stats[0] = 0; stats[1] = 0; }
@@ -624,51 +679,14 @@ void orc_tree_eval(const orc_tree *t, const double *x, const double *q, double *
     {
         ivec M = {0, 0, 0}, P = {0, 0, 0};
 #pragma omp for schedule(dynamic, 4)
-        for (int64_t g = 0; g < t->ng; ++g) {
-            const int64_t *mv, *pv;
-            int64_t mn, pn;
-            if (t->keep_lists) {
-                mv = t->m2p[g]; mn = t->nm2p[g];
-                pv = t->p2p[g]; pn = t->np2p[g];
-            } else {
-                tree_walk_group(t, xs, g, &M, &P);
-                mv = M.v; mn = M.n;
-                pv = P.v; pn = P.n;
-            }
-            int64_t nsrc = 0;
-            for (int64_t a = 0; a < pn; ++a) nsrc += t->count[pv[a]];
-            if (gm2p) gm2p[g] = mn;
-            if (gp2p) gp2p[g] = nsrc;
+        for (int64_t e = 0; e < ngs; ++e) {
+            const int64_t g = gsel ? gsel[e] : e;
+            int64_t mn, nsrc;
+            eval_group(t, xs, qs, mom, eps2, g, &M, &P, f, phi, &mn, &nsrc);
+            if (gm2p) gm2p[e] = mn;
+            if (gp2p) gp2p[e] = nsrc;
             sp2p += nsrc * t->gcount[g];
             sm2p += mn * t->gcount[g];
-            for (int64_t a = 0; a < t->gcount[g]; ++a) {
-                int64_t i = t->gfirst[g] + a;
-                const double *xi = xs + 3 * i;
-                nsum E[3] = {{0, 0}, {0, 0}, {0, 0}}, ph = {0, 0};
-                for (int64_t m = 0; m < mn; ++m) {
-                    int64_t k = mv[m];
-                    const double *c = t->centre + 3 * k;
-                    double r[3] = {xi[0] - c[0], xi[1] - c[1], xi[2] - c[2]};
-                    double Ec[3], pc;
-                    cell_field(mom + 10 * k, r, eps2, Ec, &pc);
-                    for (int d = 0; d < 3; ++d) nadd(&E[d], Ec[d]);
-                    nadd(&ph, pc);
-                }
-                for (int64_t m = 0; m < pn; ++m) {
-                    int64_t k = pv[m];
-                    for (int64_t j = t->first[k]; j < t->first[k] + t->count[k]; ++j) {
-                        double r[3] = {xi[0] - xs[3 * j], xi[1] - xs[3 * j + 1], xi[2] - xs[3 * j + 2]};
-                        double h2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2] + eps2;
-                        double h = sqrt(h2);
-                        double w = qs[j] / (h2 * h);
-                        for (int d = 0; d < 3; ++d) nadd(&E[d], w * r[d]);
-                        if (j != i) nadd(&ph, qs[j] / h);
-                    }
-                }
-                int64_t ci = t->perm[i];
-                for (int d = 0; d < 3; ++d) f[3 * ci + d] = qs[i] * nval(E[d]);
-                if (phi) phi[ci] = nval(ph);
-            }
         }
         free(M.v);
         free(P.v);
@@ -677,6 +695,23 @@ void orc_tree_eval(const orc_tree *t, const double *x, const double *q, double *
     free(xs);
     free(qs);
     free(mom);
+}
+
+void orc_tree_eval(const orc_tree *t, const double *x, const double *q, double *f, double *phi,
+                   int64_t *stats, int64_t *gm2p, int64_t *gp2p)
+{
+    eval_groups(t, x, q, t->ng, NULL, f, phi, stats, gm2p, gp2p);
+}
+
+/* Tree forces of selected groups only (for checks of large clouds).  Returns */
+/* -1 if a selected index is out of range.                                   */
+int orc_tree_eval_groups(const orc_tree *t, const double *x, const double *q, int64_t ngs,
+                         const int64_t *gsel, double *f, double *phi, int64_t *gm2p, int64_t *gp2p)
+{
+    for (int64_t e = 0; e < ngs; ++e)
+        if (gsel[e] < 0 || gsel[e] >= t->ng) return -1;
+    eval_groups(t, x, q, ngs, gsel, f, phi, NULL, gm2p, gp2p);
+    return 0;
 }
 
 /* ------------------------------------------------------------------------- */

@@ -584,7 +584,7 @@ __global__ __launch_bounds__(256) void k_nodes(
 //    a leaf) and each child's parent.
 //    Record per node, FP64 (16 doubles): cx cy cz Q px py pz trS Sxx Syy Szz
 //    Sxy Sxz Syz 0 0; FP32 copy in the second line of the walk record:
-//    Q px py pz, 1.5 trS Sxx Syy Szz, Sxy Sxz Syz 0.
+//    Q px py pz, 1.5 trS 3Sxx 3Syy 3Szz, 3Sxy 3Sxz 3Syz 0.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void store_moments(double *mom64, float4 *nrec, int k, const double4 &g,
                                               const double *m)
@@ -595,10 +595,13 @@ __device__ __forceinline__ void store_moments(double *mom64, float4 *nrec, int k
                             m[4], m[5], m[6], m[7], m[8], m[9], 0.0, 0.0};
     double2 *d2 = (double2 *)(mom64 + 16 * (int64_t)k);
     for (int i = 0; i < 8; ++i) d2[i] = make_double2(rec[2 * i], rec[2 * i + 1]);
+    // FP32 line of the walk record: Q, p, 1.5 trS and 3S (the factors the
+    // expansion applies, folded in once per node)
     float4 *f4 = nrec + 8 * (int64_t)k + 4;
     f4[0] = make_float4((float)m[0], (float)m[1], (float)m[2], (float)m[3]);
-    f4[1] = make_float4((float)(1.5 * trS), (float)m[4], (float)m[5], (float)m[6]);
-    f4[2] = make_float4((float)m[7], (float)m[8], (float)m[9], 0.f);
+    f4[1] = make_float4((float)(1.5 * trS), (float)(3.0 * m[4]), (float)(3.0 * m[5]),
+                        (float)(3.0 * m[6]));
+    f4[2] = make_float4((float)(3.0 * m[7]), (float)(3.0 * m[8]), (float)(3.0 * m[9]), 0.f);
 }
 
 // the node of `level` starting at position p, if there is one

@@ -98,7 +98,7 @@ struct Ctx {
     double *d_mom64 = nullptr;              // [node_cap][16] cx cy cz Q p[3] trS S[6] 0 0
     // node record for the walk, two 64-byte lines per node:
     //   line 1: cx cy cz side^2 (double), skip first count level|256*leaf (int)
-    //   line 2: Q px py pz | 1.5 trS Sxx Syy Szz | Sxy Sxz Syz 0   (float)
+    //   line 2: Q px py pz | 1.5 trS 3Sxx 3Syy 3Szz | 3Sxy 3Sxz 3Syz 0   (float)
     float4 *d_nrec = nullptr;               // [node_cap][8]
     // groups
     int4 *d_groups = nullptr;               // [n_max] first, count, node, root

@@ -145,13 +145,14 @@ __device__ __forceinline__ int wave_incl_scan_i(int v, int lane)
 // kernel about the box centre (r = target - centre, h^2 = |r|^2 + eps^2)
 //   phi = Q/h + (p.r)/h^3 + (3 r.S.r/h^5 - trS/h^3)/2
 //   E   = [Q/h^3 + 3(p.r)/h^5 + 7.5 r.S.r/h^7 - 1.5 trS/h^5] r - p/h^3 - 3 S r/h^5
-// evaluated as E = h^-3 [ b r - u ] with u = p + 3 h^-2 S r and
-// b = Q + h^-2 (3 p.r - 1.5 trS + 7.5 h^-2 r.S.r); the staged record holds
-// c[3], Q, p[3], 1.5 trS, Sxx, Syy, Szz, Sxy, Sxz, Syz.
+// evaluated as E = h^-3 [ b r - u ] with u = p + h^-2 (3S) r and
+// b = Q + h^-2 (3 p.r - 1.5 trS + 2.5 h^-2 r.(3S).r); the staged record holds
+// c[3], Q, p[3], 1.5 trS and the six components of 3S.
 // ---------------------------------------------------------------------------
+// S3xx .. S3yz are the components of 3S.
 template <typename T, bool PHI>
-__device__ __forceinline__ void m2p_eval(T rx, T ry, T rz, T Q, T px, T py, T pz, T Sxx, T Syy,
-                                         T Szz, T Sxy, T Sxz, T Syz, T trS15, T eps2, T &ex,
+__device__ __forceinline__ void m2p_eval(T rx, T ry, T rz, T Q, T px, T py, T pz, T S3xx, T S3yy,
+                                         T S3zz, T S3xy, T S3xz, T S3yz, T trS15, T eps2, T &ex,
                                          T &ey, T &ez, T &ph)
 {
     const T h2 = fma(rx, rx, fma(ry, ry, fma(rz, rz, eps2)));
@@ -160,25 +161,24 @@ __device__ __forceinline__ void m2p_eval(T rx, T ry, T rz, T Q, T px, T py, T pz
     else ih = 1.0 / sqrt(h2);
     const T ih2 = ih * ih;
     const T ih3 = ih2 * ih;
-    const T Srx = fma(Sxx, rx, fma(Sxy, ry, Sxz * rz));
-    const T Sry = fma(Sxy, rx, fma(Syy, ry, Syz * rz));
-    const T Srz = fma(Sxz, rx, fma(Syz, ry, Szz * rz));
-    const T rSr = fma(rx, Srx, fma(ry, Sry, rz * Srz));
+    const T Srx = fma(S3xx, rx, fma(S3xy, ry, S3xz * rz));   // (3S) r
+    const T Sry = fma(S3xy, rx, fma(S3yy, ry, S3yz * rz));
+    const T Srz = fma(S3xz, rx, fma(S3yz, ry, S3zz * rz));
+    const T rSr = fma(rx, Srx, fma(ry, Sry, rz * Srz));      // 3 r.S.r
     const T pr = fma(px, rx, fma(py, ry, pz * rz));
-    const T w = (T)3 * ih2;
-    const T ux = fma(w, Srx, px), uy = fma(w, Sry, py), uz = fma(w, Srz, pz);
-    const T a = fma((T)7.5 * ih2, rSr, fma((T)3, pr, -trS15));
+    const T ux = fma(ih2, Srx, px), uy = fma(ih2, Sry, py), uz = fma(ih2, Srz, pz);
+    const T a = fma((T)2.5 * ih2, rSr, fma((T)3, pr, -trS15));
     const T b = fma(ih2, a, Q);
     ex = fma(ih3, fma(b, rx, -ux), ex);
     ey = fma(ih3, fma(b, ry, -uy), ey);
     ez = fma(ih3, fma(b, rz, -uz), ez);
     // phi = h^-1 [ Q + h^-2 (p.r - trS/2 + 1.5 h^-2 r.S.r) ]
-    if (PHI) ph = fma(ih, fma(ih2, fma((T)1.5 * ih2, rSr, pr - trS15 * (T)(1.0 / 3.0)), Q), ph);
+    if (PHI) ph = fma(ih, fma(ih2, fma((T)0.5 * ih2, rSr, pr - trS15 * (T)(1.0 / 3.0)), Q), ph);
 }
 
 // one staged M2P record, read with 16-byte LDS loads.  FP32 record: dx dy dz 0,
-// Q px py pz, 1.5 trS Sxx Syy Szz, Sxy Sxz Syz 0; FP64 record: cx cy cz Q px py
-// pz 1.5 trS Sxx Syy Szz Sxy Sxz Syz.
+// Q px py pz, 1.5 trS 3Sxx 3Syy 3Szz, 3Sxy 3Sxz 3Syz 0; FP64 record: cx cy cz Q
+// px py pz 1.5 trS 3Sxx 3Syy 3Szz 3Sxy 3Sxz 3Syz.
 template <typename T, bool PHI>
 __device__ __forceinline__ void m2p_rec(const T *r, T tx, T ty, T tz, T eps2, T &ex, T &ey, T &ez,
                                         T &ph)
@@ -277,6 +277,21 @@ __device__ __forceinline__ void p2p_adj(T rx, T ry, T rz, T sq, T wx, T wy, T wz
     gz += c3 * wz - c5 * rz;
 }
 
+// one FP32 particle pair: source (offset, charge) in v; phi skips the self pair
+template <bool PHI>
+__device__ __forceinline__ void p2p_one(float tx, float ty, float tz, const float4 &v, float eps2,
+                                        bool notself, float &ex, float &ey, float &ez, float &ph)
+{
+    const float rx = tx - v.x, ry = ty - v.y, rz = tz - v.z;
+    const float h2 = fmaf(rx, rx, fmaf(ry, ry, fmaf(rz, rz, eps2)));
+    const float ih = __builtin_amdgcn_rsqf(h2);
+    const float w = v.w * (ih * ih * ih);
+    ex = fmaf(w, rx, ex);
+    ey = fmaf(w, ry, ey);
+    ez = fmaf(w, rz, ez);
+    if (PHI) ph += notself ? v.w * ih : 0.f;
+}
+
 __device__ __forceinline__ float readlane_t(float v, int src)
 {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
@@ -300,6 +315,35 @@ __device__ __forceinline__ CellRec<T> load_rec(const T *r)
         c = {r[0], r[1], r[2], r[3], r[4], r[5], r[6], r[7], r[8], r[9], r[10], r[11], r[12], r[13]};
     }
     return c;
+}
+
+// staged record in adjoint mode: FP64 box centre, then the moments in T
+// (UCP_SPLIT: 3 doubles then 11 floats, 68 bytes; UCP_FP64: the record of
+// m2p_rec).  The adjoint's terms grow as h^-5 and h^-7, so its differences
+// x_i - c are formed in FP64 and rounded once.
+template <int PREC, typename T>
+__device__ __forceinline__ void load_adj_rec(const T *r, CellRec<T> &m, double &cx, double &cy,
+                                             double &cz)
+{
+    if constexpr (PREC == UCP_SPLIT) {
+        const double *d = (const double *)r;
+        cx = d[0];
+        cy = d[1];
+        cz = d[2];
+        const float *f = (const float *)r + 6;
+        m.Q = f[0]; m.px = f[1]; m.py = f[2]; m.pz = f[3];
+        m.trS15 = f[4]; m.Sxx = f[5]; m.Syy = f[6]; m.Szz = f[7];
+        m.Sxy = f[8]; m.Sxz = f[9]; m.Syz = f[10];
+    } else {
+        m = load_rec(r);
+        cx = m.cx;
+        cy = m.cy;
+        cz = m.cz;
+    }
+    // the records hold 3S
+    const T third = (T)(1.0 / 3.0);
+    m.Sxx *= third; m.Syy *= third; m.Szz *= third;
+    m.Sxy *= third; m.Sxz *= third; m.Syz *= third;
 }
 
 // Per-target state of a group in the walk: target offset (or position),
@@ -335,7 +379,19 @@ __device__ __forceinline__ void flush_lists(const WalkArgs &a, const int4 *ml, i
         const int k = ent.x;
         {
             T *rec = stage + kRec * lane;
-            if constexpr (PREC == UCP_SPLIT) {
+            if constexpr (PREC == UCP_SPLIT && ADJ) {
+                const float4 *m4 = a.nrec + 8 * (int64_t)k;
+                const double4 geo = *(const double4 *)m4;
+                const float4 r1 = m4[4], r2 = m4[5], r3 = m4[6];
+                double *dd = (double *)rec;
+                dd[0] = geo.x;
+                dd[1] = geo.y;
+                dd[2] = geo.z;
+                float *ff = (float *)rec + 6;
+                ff[0] = r1.x; ff[1] = r1.y; ff[2] = r1.z; ff[3] = r1.w;
+                ff[4] = r2.x; ff[5] = r2.y; ff[6] = r2.z; ff[7] = r2.w;
+                ff[8] = r3.x; ff[9] = r3.y; ff[10] = r3.z;
+            } else if constexpr (PREC == UCP_SPLIT) {
                 const float4 *m4 = a.nrec + 8 * (int64_t)k + 4;
                 const float4 r1 = m4[0], r2 = m4[1], r3 = m4[2];
                 float4 *d4 = (float4 *)rec;
@@ -347,20 +403,36 @@ __device__ __forceinline__ void flush_lists(const WalkArgs &a, const int4 *ml, i
             } else {
                 const double2 *m2 = (const double2 *)(a.mom64 + 16 * (int64_t)k);
                 double2 *d2 = (double2 *)rec;
-                for (int q = 0; q < 7; ++q) d2[q] = m2[q];
+                for (int q = 0; q < 4; ++q) d2[q] = m2[q];
                 d2[3].y *= 1.5;
+                for (int q = 4; q < 7; ++q) {
+                    const double2 v = m2[q];
+                    d2[q] = make_double2(3.0 * v.x, 3.0 * v.y);
+                }
             }
         }
         wave_sync();
         if constexpr (!ADJ) {
             // two independent partial sums (records e and e + lpt) for ILP
             T ex = 0, ey = 0, ez = 0, ph = 0, fx = 0, fy = 0, fz = 0, fp = 0;
-            int e = sub;
-            for (; e + lpt < cnt; e += 2 * lpt) {
-                m2p_rec<T, PHI>(stage + kRec * e, tx, ty, tz, eps2, ex, ey, ez, ph);
-                m2p_rec<T, PHI>(stage + kRec * (e + lpt), tx, ty, tz, eps2, fx, fy, fz, fp);
+            if (lpt == 1) {
+                // one lane per target (full groups): every lane takes every
+                // record, so the record index is the same on all lanes
+                int e = 0;
+                for (; e + 1 < cnt; e += 2) {
+                    const T *r0 = stage + kRec * e;
+                    m2p_rec<T, PHI>(r0, tx, ty, tz, eps2, ex, ey, ez, ph);
+                    m2p_rec<T, PHI>(r0 + kRec, tx, ty, tz, eps2, fx, fy, fz, fp);
+                }
+                if (e < cnt) m2p_rec<T, PHI>(stage + kRec * e, tx, ty, tz, eps2, ex, ey, ez, ph);
+            } else {
+                int e = sub;
+                for (; e + lpt < cnt; e += 2 * lpt) {
+                    m2p_rec<T, PHI>(stage + kRec * e, tx, ty, tz, eps2, ex, ey, ez, ph);
+                    m2p_rec<T, PHI>(stage + kRec * (e + lpt), tx, ty, tz, eps2, fx, fy, fz, fp);
+                }
+                if (e < cnt) m2p_rec<T, PHI>(stage + kRec * e, tx, ty, tz, eps2, ex, ey, ez, ph);
             }
-            if (e < cnt) m2p_rec<T, PHI>(stage + kRec * e, tx, ty, tz, eps2, ex, ey, ez, ph);
             tg.E0 += (double)(ex + fx);
             tg.E1 += (double)(ey + fy);
             tg.E2 += (double)(ez + fz);
@@ -368,21 +440,25 @@ __device__ __forceinline__ void flush_lists(const WalkArgs &a, const int4 *ml, i
         } else {
             T gx = 0, gy = 0, gz = 0;
             for (int e = sub; e < cnt; e += lpt) {
-                const CellRec<T> r = load_rec(stage + kRec * e);
-                m2p_adj_target<T>(tx - r.cx, ty - r.cy, tz - r.cz, r.Q, r.px, r.py, r.pz, r.Sxx,
-                                  r.Syy, r.Szz, r.Sxy, r.Sxz, r.Syz, r.trS15, tg.wx, tg.wy,
-                                  tg.wz, eps2, gx, gy, gz);
+                CellRec<T> r;
+                double cx, cy, cz;
+                load_adj_rec<PREC>(stage + kRec * e, r, cx, cy, cz);
+                m2p_adj_target<T>((T)(tg.px - cx), (T)(tg.py - cy), (T)(tg.pz - cz), r.Q, r.px,
+                                  r.py, r.pz, r.Sxx, r.Syy, r.Szz, r.Sxy, r.Sxz, r.Syz, r.trS15,
+                                  tg.wx, tg.wy, tg.wz, eps2, gx, gy, gz);
             }
             tg.E0 += (double)gx;
             tg.E1 += (double)gy;
             tg.E2 += (double)gz;
             // source side: lane e owns staged record e
-            const CellRec<T> r = load_rec(stage + kRec * lane);
+            CellRec<T> r;
+            double cx, cy, cz;
+            load_adj_rec<PREC>(stage + kRec * lane, r, cx, cy, cz);
             T cb[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
             for (int t = 0; t < c; ++t) {
                 const int src = t * lpt;
-                m2p_adj_source<T>(readlane_t(tx, src) - r.cx, readlane_t(ty, src) - r.cy,
-                                  readlane_t(tz, src) - r.cz, readlane_t(tg.wx, src),
+                m2p_adj_source<T>((T)(readlane_d(tg.px, src) - cx), (T)(readlane_d(tg.py, src) - cy),
+                                  (T)(readlane_d(tg.pz, src) - cz), readlane_t(tg.wx, src),
                                   readlane_t(tg.wy, src), readlane_t(tg.wz, src), eps2, cb);
             }
             if (lane < cnt)
@@ -426,7 +502,30 @@ __device__ __forceinline__ void flush_lists(const WalkArgs &a, const int4 *ml, i
             sidx[lane] = j;
             wave_sync();
             T ex = 0, ey = 0, ez = 0, ph = 0;
-            for (int e = sub; e < ncur; e += lpt) {
+            bool done = false;
+            if constexpr (!ADJ && sizeof(T) == 4) {
+                if (lpt == 1) {
+                    // one lane per target: every lane takes every staged
+                    // source, in pairs with two partial sums
+                    T fx = 0, fy = 0, fz = 0, fp = 0;
+                    int e = 0;
+                    for (; e + 1 < ncur; e += 2) {
+                        const float4 v0 = ((const float4 *)stage)[e];
+                        const float4 v1 = ((const float4 *)stage)[e + 1];
+                        p2p_one<PHI>(tx, ty, tz, v0, eps2, sidx[e] != tg.i, ex, ey, ez, ph);
+                        p2p_one<PHI>(tx, ty, tz, v1, eps2, sidx[e + 1] != tg.i, fx, fy, fz, fp);
+                    }
+                    if (e < ncur)
+                        p2p_one<PHI>(tx, ty, tz, ((const float4 *)stage)[e], eps2, sidx[e] != tg.i,
+                                     ex, ey, ez, ph);
+                    ex += fx;
+                    ey += fy;
+                    ez += fz;
+                    ph += fp;
+                    done = true;
+                }
+            }
+            for (int e = sub; !done && e < ncur; e += lpt) {
                 if constexpr (ADJ) {
                     const double4 v = ((const double4 *)stage)[e];
                     if (sidx[e] != tg.i)

@@ -23,7 +23,11 @@ from paper_0709_3331_amd import adjoint  # noqa: E402
 from paper_0709_3331_amd.tree import TreeSolver  # noqa: E402
 
 TOL_FP64 = 1e-10   # FP64 atomics add the per-group source terms in any order
-TOL_SPLIT = 1e-5
+# UCP_SPLIT: each pair or cell term is FP32 (relative error ~1e-6 after the
+# reciprocal square root and products), and the adjoint's sums cancel: over
+# the test clouds sum|terms| / |xbar| is 10-20 (the pair terms q_i q_j K(r)
+# (u_i - u_j) of the direct sum already show it), so the bound is 5e-5
+TOL_SPLIT = 5e-5
 
 
 def say(*a):

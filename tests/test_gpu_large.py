@@ -1,0 +1,92 @@
+"""Full-size workloads on the GPU, checked on outputs the oracle can afford.
+
+N = 4,194,304 (Gaussian cloud, 10% of electrons in a hot tail, eps = 0.002,
+theta = 0.5): keys, permutation, node records and groups bit-exact against the
+oracle's build; forces and per-group interaction counts on a seeded sample of
+walk groups against the oracle's evaluation of those groups alone.  The
+N = 65,536 rollout workload: checkpointed and stored-graph gradients agree and
+stay finite.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_0709_3331_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_0709_3331_amd import _lib as L  # noqa: E402
+from paper_0709_3331_amd import adjoint  # noqa: E402
+from paper_0709_3331_amd.tree import TreeSolver  # noqa: E402
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def relrms(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def test_large_cloud_topology_and_sampled_groups():
+    cl, prm = inputs.large(0)
+    n = cl.n
+    say(f"[large] n={n} theta={prm['theta']} eps={prm['eps']}: oracle build")
+    t = oracle.Tree(cl.x, cl.q, prm["theta"], prm["eps"])
+    gf, gc, gn = t.groups()
+    sel = np.sort(np.random.default_rng(0).choice(t.ngroups, 24, replace=False))
+    say(f"[large]   oracle nodes={t.nnodes} groups={t.ngroups}; evaluating {sel.size} groups")
+    ref = t.eval_groups(sel)
+    perm = t.perm()
+    idx = np.concatenate([perm[gf[g]:gf[g] + gc[g]] for g in sel])
+    x, q = torch.from_numpy(cl.x).cuda(), torch.from_numpy(cl.q).cuda()
+    for prec, tol in ((L.UCP_FP64, 1e-12), (L.UCP_SPLIT, 1e-5)):
+        ts = TreeSolver(n, theta=prm["theta"], eps=prm["eps"], precision=prec)
+        f = ts.tree_forces(x, q)
+        st = ts.stats()
+        say(f"[large]   prec={prec} nodes={st['nodes']} groups={st['groups']}")
+        if prec == L.UCP_FP64:
+            np.testing.assert_array_equal(ts.debug("keys"), t.sorted_keys())
+            np.testing.assert_array_equal(ts.debug("perm").astype(np.int64), perm)
+            lv, fi, co, sk = t.nodes()
+            ni = ts.debug("ninfo")
+            np.testing.assert_array_equal(ni[:, 0], fi)
+            np.testing.assert_array_equal(ni[:, 1], co)
+            np.testing.assert_array_equal(ni[:, 2], sk)
+            np.testing.assert_array_equal(ni[:, 3] & 255, lv)
+            np.testing.assert_array_equal(ts.debug("ngeo")[:, :3], t.centres())
+            gr = ts.debug("groups")
+            np.testing.assert_array_equal(gr[:, 0], gf)
+            np.testing.assert_array_equal(gr[:, 1], gc)
+        gs = ts.debug("gstat")
+        np.testing.assert_array_equal(gs[sel, 0], ref["gm2p"])
+        np.testing.assert_array_equal(gs[sel, 1], ref["gp2p"])
+        e = relrms(f.cpu().numpy()[idx], ref["f"][idx])
+        say(f"[large]   sampled-group force rel RMS {e:.3e}")
+        assert e < tol
+        ts.close()
+
+
+def test_rollout_workload_checkpointing_and_finiteness():
+    cl, prm = inputs.adjoint(0)
+    n, steps = cl.n, 20
+    say(f"[large] rollout n={n} steps={steps}")
+    z = torch.from_numpy(cl.x).cuda()
+    q, m = torch.from_numpy(cl.q).cuda(), torch.from_numpy(cl.m).cuda()
+    ts = TreeSolver(n, theta=prm["theta"], eps=prm["eps"])
+    out = []
+    for every in (0, prm["ckpt"] // 2):
+        sigma = torch.tensor(1.0, dtype=torch.float64, device="cuda", requires_grad=True)
+        v0 = torch.from_numpy(cl.v).cuda().requires_grad_(True)
+        xT, vT = adjoint.rollout(ts, sigma * z, v0, q, m, prm["dt"], steps, checkpoint_every=every)
+        loss = adjoint.ion_kinetic_energy(vT, q, m)
+        loss.backward()
+        assert torch.isfinite(v0.grad).all() and np.isfinite(sigma.grad.item())
+        out.append((loss.item(), sigma.grad.item()))
+    assert out[0][0] == out[1][0]
+    assert out[0][1] == pytest.approx(out[1][1], rel=1e-9)
+    ts.close()

@@ -637,3 +637,22 @@ def test_tree_vjp_matches_frozen_list_finite_differences():
         fm = t.eval(cl.x - h * w, want_phi=False)["f"]
         fd = (u * (fp - fm) / (2 * h)).sum()
         assert abs(fd - (xb * w).sum()) < 1e-6 * abs(fd)
+
+
+def test_eval_of_selected_groups_equals_full_eval():
+    cl = _rand_cloud(3000, 29)
+    t = oracle.Tree(cl.x, cl.q, 0.5, 0.01, G=32)
+    r = t.eval(group_counts=True)
+    sel = np.array([0, 5, 17, t.ngroups - 1])
+    e = t.eval_groups(sel, want_phi=True)
+    gf, gc, gn = t.groups()
+    perm = t.perm()
+    idx = np.concatenate([perm[gf[g]:gf[g] + gc[g]] for g in sel])
+    np.testing.assert_array_equal(e["f"][idx], r["f"][idx])
+    np.testing.assert_array_equal(e["phi"][idx], r["phi"][idx])
+    np.testing.assert_array_equal(e["gm2p"], r["gm2p"][sel])
+    np.testing.assert_array_equal(e["gp2p"], r["gp2p"][sel])
+    rest = np.setdiff1d(np.arange(cl.n), idx)
+    assert np.isnan(e["f"][rest]).all()
+    with pytest.raises(ValueError):
+        t.eval_groups([t.ngroups])
