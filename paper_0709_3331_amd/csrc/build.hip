@@ -57,11 +57,12 @@ void launch_fill_f64(double *p, double v, int64_t n, hipStream_t s)
 
 // reset of the per-build state: min/max slots, counters, flag word
 __global__ void k_build_reset(unsigned long long *mm, int clouds, unsigned long long *ctr,
-                              int32_t *flags)
+                              uint32_t *sortctl, int32_t *flags)
 {
     int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < clouds * 6) mm[t] = (t % 6 < 3) ? ~0ull : 0ull;
     if (t < CTR_NCTR) ctr[t] = 0;
+    if (t < kSortTickets) sortctl[t] = 0;
     if (t == 0) *flags = 0;
 }
 
@@ -345,8 +346,8 @@ static void scan_excl(const int32_t *in, int32_t *out, int64_t n, int32_t *blk, 
 
 // ---------------------------------------------------------------------------
 // 3. stable LSD radix sort of (key, index), 8-bit digits.  Per pass: a
-//    per-tile digit histogram (digit-major), its exclusive scan (the output
-//    offset of each (digit, tile)), and the scatter.  The scatter processes a
+//    per-tile digit histogram whose exclusive prefix over the tiles is found
+//    by a decoupled look-back (below), and the scatter.  The scatter processes a
 //    tile of kSortTile elements in rounds of kSortThreads; inside a round each
 //    wave ranks equal digits with ballots, the 16 waves are ordered through
 //    LDS, and a running count per digit carries the order across rounds.  The
@@ -361,16 +362,31 @@ __device__ __forceinline__ uint32_t sort_digit(uint64_t k, uint32_t v, int shift
     return (uint32_t)(k >> shift) & 255u;
 }
 
+// Per-tile digit counts and their exclusive prefix over the tiles, in one
+// kernel.  Blocks take tiles in the order they start (a ticket), count their
+// tile's digits, publish the counts at once (flag AGG), then walk back over
+// the earlier tiles adding published counts until one of them has published
+// its inclusive prefix (flag INCL), and publish their own.  A tile only waits
+// for tiles that started before it and that publish before waiting, so every
+// wait ends; a bounded spin turns a lost tile into an internal-error flag
+// rather than a hang.  Status word: flag (2 bits) | count (30 bits).
+constexpr uint32_t kStAgg = 1u << 30, kStIncl = 2u << 30, kStMask = (1u << 30) - 1;
+constexpr int kLookbackSpin = 1 << 18;
+
 template <bool CLOUD>
 __global__ __launch_bounds__(kSortThreads) void k_radix_hist(
     const uint64_t *__restrict__ key, const uint32_t *__restrict__ val, int64_t n, int shift,
-    const int64_t *__restrict__ off, int clouds, uint32_t *hist, int ntiles, const int32_t *flags)
+    const int64_t *__restrict__ off, int clouds, uint32_t *status, uint32_t *excl_out,
+    uint32_t *ticket, int32_t *flags)
 {
     __shared__ uint32_t h[256];
+    __shared__ int tile_sh;
     if (*flags) return;
+    if (threadIdx.x == 0) tile_sh = (int)atomicAdd(ticket, 1u);
     if (threadIdx.x < 256) h[threadIdx.x] = 0;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    const int tile = tile_sh;
+    const int64_t base = (int64_t)tile * kSortTile;
     for (int it = 0; it < kSortItems; ++it) {
         int64_t e = base + it * kSortThreads + threadIdx.x;
         if (e < n) {
@@ -379,24 +395,61 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(
         }
     }
     __syncthreads();
-    if (threadIdx.x < 256) hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
+    if (threadIdx.x < 256) {
+        const int d = threadIdx.x;
+        const uint32_t agg = h[d];
+        uint32_t *st = status + (int64_t)tile * 256 + d;
+        uint32_t excl = 0;
+        if (tile == 0) {
+            __hip_atomic_store(st, kStIncl | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            __hip_atomic_store(st, kStAgg | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            int j = tile - 1, spins = 0;
+            for (;;) {
+                const uint32_t v = __hip_atomic_load(status + (int64_t)j * 256 + d, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+                if ((v & ~kStMask) == 0) {
+                    if (++spins > kLookbackSpin) {
+                        atomicOr(flags, UCP_FLAG_INTERNAL);
+                        break;
+                    }
+                    continue;
+                }
+                excl += v & kStMask;
+                if ((v & kStIncl) || j == 0) break;
+                --j;
+            }
+            __hip_atomic_store(st, kStIncl | (excl + agg), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
+        excl_out[(int64_t)tile * 256 + d] = excl;
+    }
 }
 
 template <bool CLOUD>
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint64_t *kout,
     uint32_t *vout, int64_t n, int shift, const int64_t *__restrict__ off, int clouds,
-    const uint32_t *__restrict__ hscan, int ntiles, const int32_t *flags)
+    const uint32_t *__restrict__ status, const uint32_t *__restrict__ excl, uint32_t *status_next,
+    int ntiles, const int32_t *flags)
 {
     constexpr int NW = kSortThreads / 64;
     __shared__ uint32_t run[256];
     __shared__ uint32_t wh[2][NW][256];   // per-wave digit counts, double-buffered by round
     __shared__ uint32_t boff[256];
+    __shared__ int btot;
     if (*flags) return;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    if (tid < 256) {
-        run[tid] = 0;
-        boff[tid] = hscan[(int64_t)tid * ntiles + blockIdx.x];
+    // digit totals are the last tile's inclusive prefixes; this tile's output
+    // offset of digit d is the total of all smaller digits plus its prefix
+    {
+        const uint32_t tot = tid < 256 ? (status[(int64_t)(ntiles - 1) * 256 + tid] & kStMask) : 0u;
+        const int below = block_excl_scan((int)tot, &btot);
+        if (tid < 256) {
+            run[tid] = 0;
+            boff[tid] = (uint32_t)below + excl[(int64_t)blockIdx.x * 256 + tid];
+            status_next[(int64_t)blockIdx.x * 256 + tid] = 0u;   // the next pass's status
+        }
     }
     for (int j = tid; j < NW * 256; j += kSortThreads) wh[0][j / 256][j % 256] = 0;
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -464,7 +517,8 @@ __device__ __forceinline__ int lcp_level(uint64_t a, uint64_t b2, int b)
 __global__ __launch_bounds__(kLvlTile) void k_levels(const uint64_t *__restrict__ key, int64_t n,
                                                     const int64_t *__restrict__ off, int clouds,
                                                     int b, int cap, int8_t *Lout, int8_t *leafout,
-                                                    int32_t *cnt, const int32_t *flags)
+                                                    int32_t *cnt, int32_t *lend,
+                                                    const int32_t *flags)
 {
     __shared__ int8_t sL[kLvlTile + 2 * kMaxLeafCap + 2];
     const int64_t base = (int64_t)blockIdx.x * kLvlTile;
@@ -490,23 +544,33 @@ __global__ __launch_bounds__(kLvlTile) void k_levels(const uint64_t *__restrict_
         return;
     }
     auto Lw = [&](int64_t j) -> int { return (int)sL[j - wlo]; };
-    auto ok = [&](int lv) -> bool {
+    // does the box of level lv holding p hold at most cap particles?  If so,
+    // tend is the position after its last particle
+    auto ok = [&](int lv, int64_t &tend) -> bool {
         int64_t s = p;
         while (s > p - cap + 1 && Lw(s) >= lv) --s;
         if (Lw(s) >= lv) return false;
         int64_t t = p + 1;
         while (t < s + cap && Lw(t) >= lv) ++t;
+        tend = t;
         return Lw(t) < lv;
     };
     int leaf;
-    if (!ok(b)) {
+    int64_t tleaf = -1;   // -1: a max-depth leaf beyond the window, found by a scan
+    if (!ok(b, tleaf)) {
         leaf = b;
+        tleaf = -1;
     } else {
         int lo = -1, hi = b;   // ok(hi) holds; ok(lo) is taken as false
         while (hi - lo > 1) {
             int mid = (lo + hi) >> 1;
-            if (ok(mid)) hi = mid;
-            else lo = mid;
+            int64_t tm;
+            if (ok(mid, tm)) {
+                hi = mid;
+                tleaf = tm;
+            } else {
+                lo = mid;
+            }
         }
         leaf = hi;
     }
@@ -514,6 +578,7 @@ __global__ __launch_bounds__(kLvlTile) void k_levels(const uint64_t *__restrict_
     Lout[p] = (int8_t)Lp;
     leafout[p] = (int8_t)leaf;
     cnt[p] = leaf > Lp ? leaf - Lp : 0;
+    lend[p] = (int32_t)tleaf;
 }
 
 // ---------------------------------------------------------------------------
@@ -528,7 +593,8 @@ __global__ __launch_bounds__(256) void k_nodes(
     const uint64_t *__restrict__ key, int64_t n, const int64_t *__restrict__ off, int clouds,
     const double4 *__restrict__ cube, int b, const int8_t *__restrict__ Lv,
     const int8_t *__restrict__ Lf, const int32_t *__restrict__ noff, int64_t node_cap,
-    double4 *ngeo, int4 *ninfo, int32_t *npar, unsigned long long *ctr, int32_t *flags)
+    double4 *ngeo, int4 *ninfo, int32_t *npar, uint8_t *nlev, unsigned long long *ctr,
+    int32_t *flags)
 {
     if (*flags) return;
     const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -566,22 +632,20 @@ __global__ __launch_bounds__(256) void k_nodes(
         const double cz = c0.z + (double)(2 * (Z >> (b - l)) + 1) * h;
         ngeo[k] = make_double4(cx, cy, cz, ldexp(1.0, 2 * (e - l)));
         ninfo[k] = make_int4((int)p, 0, 0, l | (l == lf ? 256 : 0));
+        nlev[k] = (uint8_t)(l | (l == lf ? kLeafBit : 0));
         if (l == 0) npar[k] = -1;   // other parents are set by the moments pass
     }
 }
 
 // ---------------------------------------------------------------------------
-// 6. moments about the box centre, one level at a time from the deepest up:
-//    the node (p, l) exists iff L(p) < l <= leaf(p).  A leaf holds the
-//    positions p .. t-1 with t the first later position whose L(t) < l (L is
-//    -1 at every cloud edge and at n).  An internal node k's children, in
-//    octant order, are k + 1 and then each child's skip link for as long as
-//    that node is one level deeper than k (a node of level l + 1 right after
-//    a child's subtree has the same parent); their counts and skip links were
-//    written by the previous launch.  The node then sums its particles (leaf)
-//    or its children's moments with the exact shift of origin (internal), and
-//    records its count, its skip link (that of its last child, or noff[t] for
-//    a leaf) and each child's parent.
+// 6. moments about the box centre: the node (p, l) exists iff
+//    L(p) < l <= leaf(p).  A leaf holds the positions p .. t-1 with t the
+//    first later position whose L(t) < l (L is -1 at every cloud edge and at
+//    n); it sums its particles.  An internal node sums its children's moments
+//    with the exact shift of origin, so the internal levels are done from the
+//    deepest up.  Each node records its count and its skip link (noff[t] for a
+//    leaf, that of its last child otherwise); internal nodes also record each
+//    child's parent.
 //    Record per node, FP64 (16 doubles): cx cy cz Q px py pz trS Sxx Syy Szz
 //    Sxy Sxz Syz 0 0; FP32 copy in the second line of the walk record:
 //    Q px py pz, 1.5 trS 3Sxx 3Syy 3Szz, 3Sxy 3Sxz 3Syz 0.
@@ -604,30 +668,39 @@ __device__ __forceinline__ void store_moments(double *mom64, float4 *nrec, int k
     f4[2] = make_float4((float)(3.0 * m[7]), (float)(3.0 * m[8]), (float)(3.0 * m[9]), 0.f);
 }
 
-// the node of `level` starting at position p, if there is one
-__device__ __forceinline__ void moments_node(
-    int64_t p, int level, const double4 *__restrict__ xq, int64_t n, const int8_t *__restrict__ Lv,
-    const int8_t *__restrict__ Lf, const int32_t *__restrict__ noff,
-    const double4 *__restrict__ ngeo, int4 *ninfo, int32_t *npar, double *mom64, float4 *nrec,
-    int32_t *leafof, int32_t *flags)
+// The leaf starting at position p, if there is one (every level at once: a
+// leaf depends on nothing but its particles).  Its end was found by the level
+// pass, or is -1 for a max-depth leaf wider than that pass's window.
+constexpr int kLeafThreads = 256, kP2MBatch = 4;
+__global__ __launch_bounds__(kLeafThreads) void k_leaf_moments(
+    const double4 *__restrict__ xq, int64_t n, const int8_t *__restrict__ Lv,
+    const int8_t *__restrict__ Lf, const int32_t *__restrict__ lend,
+    const int32_t *__restrict__ noff, const double4 *__restrict__ ngeo, int4 *ninfo,
+    double *mom64, float4 *nrec, int32_t *leafof, const int32_t *flags)
 {
+    if (*flags) return;
+    const int64_t p = blockIdx.x * (int64_t)kLeafThreads + threadIdx.x;
     if (p >= n) return;
     const int Lp = Lv[p], lf = Lf[p];
-    if (!(Lp < level && level <= lf)) return;
-    const int k = noff[p] + (level - Lp - 1);
+    if (lf <= Lp) return;
+    const int k = noff[p] + (lf - Lp - 1);
     const double4 g = ngeo[k];
-    const int info = level | (level == lf ? 256 : 0);
-    double m[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    int64_t t;
-    int skip;
-    if (level == lf) {
+    int64_t t = lend[p];
+    if (t < 0) {
         t = p + 1;
-        while ((int)Lv[t] >= level) ++t;   // Lv[n] = -1 ends the scan
-        skip = noff[t];
-        for (int64_t j = p; j < t; ++j) {
-            leafof[j] = k;
-            const double4 a = xq[j];
-            const double r0 = a.x - g.x, r1 = a.y - g.y, r2 = a.z - g.z, qq = a.w;
+        while ((int)Lv[t] >= lf) ++t;   // Lv[n] = -1 ends the scan
+    }
+    double m[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    // particles in order; the loads of a batch are issued together
+    for (int64_t j0 = p; j0 < t; j0 += kP2MBatch) {
+        double4 a[kP2MBatch];
+#pragma unroll
+        for (int u = 0; u < kP2MBatch; ++u) a[u] = xq[j0 + u < t ? j0 + u : t - 1];
+#pragma unroll
+        for (int u = 0; u < kP2MBatch; ++u) {
+            if (j0 + u >= t) break;
+            leafof[j0 + u] = k;
+            const double r0 = a[u].x - g.x, r1 = a[u].y - g.y, r2 = a[u].z - g.z, qq = a[u].w;
             m[0] += qq;
             m[1] += qq * r0;
             m[2] += qq * r1;
@@ -639,9 +712,161 @@ __device__ __forceinline__ void moments_node(
             m[8] += qq * r0 * r2;
             m[9] += qq * r1 * r2;
         }
+    }
+    const int cnt = (int)(t - p), skip = noff[t], info = lf | 256;
+    ninfo[k] = make_int4((int)p, cnt, skip, info);
+    *(double4 *)(nrec + 8 * (int64_t)k) = g;
+    *(int4 *)(nrec + 8 * (int64_t)k + 2) = make_int4(skip, (int)p, cnt, info);
+    store_moments(mom64, nrec, k, g, m);
+}
+
+// one child's moments shifted from its centre to the parent's centre g and
+// added: p' = p + Q d, S' = S + p d^T + d p^T + Q d d^T with d = c_child - g
+// (each component +-qd)
+__device__ __forceinline__ void add_child(double *m, const double4 &g, double qd,
+                                          const double4 &cg, const double *c)
+{
+    const double d0 = cg.x > g.x ? qd : -qd;
+    const double d1 = cg.y > g.y ? qd : -qd;
+    const double d2 = cg.z > g.z ? qd : -qd;
+    const double Q = c[0], p0 = c[1], p1 = c[2], p2 = c[3];
+    m[0] += Q;
+    m[1] += p0 + Q * d0;
+    m[2] += p1 + Q * d1;
+    m[3] += p2 + Q * d2;
+    m[4] += c[5] + 2.0 * p0 * d0 + Q * d0 * d0;
+    m[5] += c[6] + 2.0 * p1 * d1 + Q * d1 * d1;
+    m[6] += c[7] + 2.0 * p2 * d2 + Q * d2 * d2;
+    m[7] += c[8] + p0 * d1 + d0 * p1 + Q * d0 * d1;
+    m[8] += c[9] + p0 * d2 + d0 * p2 + Q * d0 * d2;
+    m[9] += c[10] + p1 * d2 + d1 * p2 + Q * d1 * d2;
+}
+
+// Q p S of node ch (the FP64 record holds cx cy cz Q px py pz trS S[6])
+__device__ __forceinline__ void load_child(const double *mom64, int ch, double *c)
+{
+    const double *r = mom64 + 16 * (int64_t)ch + 3;
+#pragma unroll
+    for (int i = 0; i < 11; ++i) c[i] = r[i];
+}
+
+// High bit of each byte of x set where that byte (taken mod 128) is < v,
+// for 0 < v <= 127; the bias 0x80 per byte keeps borrows inside each byte.
+__device__ __forceinline__ uint32_t bytes_below(uint32_t x, uint32_t v)
+{
+    return ~((x & 0x7F7F7F7Fu) + 0x80808080u - v * 0x01010101u) & 0x80808080u;
+}
+// the four byte flags (bits 7, 15, 23, 31) gathered into bits 0..3
+__device__ __forceinline__ uint32_t gather4(uint32_t m)
+{
+    return ((m >> 7) & 1u) | ((m >> 14) & 2u) | ((m >> 21) & 4u) | ((m >> 28) & 8u);
+}
+
+// Direct children of internal node k (level l) from the level bytes of the
+// kWin nodes after it: in preorder they are the nodes of level l + 1 before
+// the first node of level <= l (or nn).  On return bit i of *cm marks node
+// k + 1 + i as a child and *end is the offset of that first node; false if
+// the subtree runs past the window.
+constexpr int kWin = 64;
+__device__ __forceinline__ bool children_in_window(int k, int level, int nn,
+                                                   const uint8_t *__restrict__ nlev,
+                                                   uint64_t *cm, int *end)
+{
+    const int base = (k + 1) & ~15, off = k + 1 - base;
+    const uint4 *w4 = (const uint4 *)(nlev + base);
+    // 80 bytes from base: flags of "level == l + 1" and "level <= l", one bit
+    // per byte
+    uint64_t clo = 0, slo = 0;
+    uint32_t chi = 0, shi = 0;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        const uint4 v = w4[i];
+        const uint32_t d[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t le = bytes_below(d[q], (uint32_t)level + 1);
+            const uint32_t eq = bytes_below(d[q], (uint32_t)level + 2) & ~le;
+            const int sh = 4 * (4 * i + q);   // bit position of this dword's first byte
+            if (sh < 64) {
+                clo |= (uint64_t)gather4(eq) << sh;
+                slo |= (uint64_t)gather4(le) << sh;
+            } else {
+                chi |= gather4(eq) << (sh - 64);
+                shi |= gather4(le) << (sh - 64);
+            }
+        }
+    }
+    // shift to offsets 0 .. 63 after k
+    uint64_t child = (clo >> off) | (off ? (uint64_t)chi << (64 - off) : 0ull);
+    uint64_t stop = (slo >> off) | (off ? (uint64_t)shi << (64 - off) : 0ull);
+    // nodes past nn end the subtree
+    const int room = nn - (k + 1);   // >= 0
+    if (room < kWin) stop |= ~0ull << room;
+    if (stop == 0) return false;
+    const int e = __builtin_ctzll(stop);
+    *end = e;
+    *cm = child & ((1ull << e) - 1);
+    return true;
+}
+
+// the internal node k of `level`, first position p: its children's moments
+// shifted to its centre, summed in octant order (preorder).  The children are
+// read from the level bytes when the subtree is short, else by following the
+// skip links from k + 1.
+__device__ __forceinline__ void moments_internal(
+    int k, int64_t p, int level, int nn, const uint8_t *__restrict__ nlev,
+    const double4 *__restrict__ ngeo, int4 *ninfo, int32_t *npar, double *mom64, float4 *nrec,
+    int32_t *flags)
+{
+    const double4 g = ngeo[k];
+    double m[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    const double qd = 0.25 * sqrt(g.w);   // |child centre - parent centre| per axis
+    int64_t t;
+    int skip;
+    uint64_t cm;
+    int end;
+    if (children_in_window(k, level, nn, nlev, &cm, &end)) {
+        // two children per round of loads
+        int last = -1, nch = 0;
+        bool bad = (cm & 1ull) == 0;   // the first child is k + 1
+        while (cm != 0 && !bad) {
+            const int c0 = k + 1 + __builtin_ctzll(cm);
+            cm &= cm - 1;
+            const int c1 = cm != 0 ? k + 1 + __builtin_ctzll(cm) : -1;
+            if (c1 >= 0) cm &= cm - 1;
+            const int4 i0 = ninfo[c0];
+            const double4 g0 = ngeo[c0];
+            double r0[11], r1[11];
+            load_child(mom64, c0, r0);
+            int4 i1 = make_int4(0, 1, 0, 0);
+            double4 g1 = g0;
+            if (c1 >= 0) {
+                i1 = ninfo[c1];
+                g1 = ngeo[c1];
+                load_child(mom64, c1, r1);
+            }
+            bad = bad || i0.y < 1 || i1.y < 1;
+            add_child(m, g, qd, g0, r0);
+            npar[c0] = k;
+            last = c0;
+            t = (int64_t)i0.x + i0.y;
+            skip = i0.z;
+            ++nch;
+            if (c1 >= 0) {
+                add_child(m, g, qd, g1, r1);
+                npar[c1] = k;
+                last = c1;
+                t = (int64_t)i1.x + i1.y;
+                skip = i1.z;
+                ++nch;
+            }
+        }
+        // the last child's skip link is the first node after k's subtree
+        if (bad || last < 0 || nch > 8 || skip != k + 1 + end) {
+            atomicOr(flags, UCP_FLAG_INTERNAL);   // inconsistent records: stop
+            return;
+        }
     } else {
-        const double qd = 0.25 * sqrt(g.w);   // |child centre - parent centre| per axis
-        const int nn = noff[n];
         int ch = k + 1;
         int4 ci = ch < nn ? ninfo[ch] : make_int4(0, 0, 0, 0);
         for (int j = 0;; ++j) {
@@ -652,52 +877,140 @@ __device__ __forceinline__ void moments_node(
             npar[ch] = k;
             t = (int64_t)ci.x + ci.y;
             skip = ci.z;
-            const double4 cg = ngeo[ch];
-            const double d0 = cg.x > g.x ? qd : -qd;
-            const double d1 = cg.y > g.y ? qd : -qd;
-            const double d2 = cg.z > g.z ? qd : -qd;
-            const double *c = mom64 + 16 * (int64_t)ch;
-            const double Q = c[3], p0 = c[4], p1 = c[5], p2 = c[6];
-            // shift of origin by d: p' = p + Q d, S' = S + p d^T + d p^T + Q d d^T
-            m[0] += Q;
-            m[1] += p0 + Q * d0;
-            m[2] += p1 + Q * d1;
-            m[3] += p2 + Q * d2;
-            m[4] += c[8] + 2.0 * p0 * d0 + Q * d0 * d0;
-            m[5] += c[9] + 2.0 * p1 * d1 + Q * d1 * d1;
-            m[6] += c[10] + 2.0 * p2 * d2 + Q * d2 * d2;
-            m[7] += c[11] + p0 * d1 + d0 * p1 + Q * d0 * d1;
-            m[8] += c[12] + p0 * d2 + d0 * p2 + Q * d0 * d2;
-            m[9] += c[13] + p1 * d2 + d1 * p2 + Q * d1 * d2;
-            if (skip >= nn) break;
-            const int4 si = ninfo[skip];
-            if ((si.w & 255) != level + 1) break;   // no further sibling
+            // the next candidate sibling's record, loaded with this child's
+            const int4 si = skip < nn ? ninfo[skip] : make_int4(0, 0, 0, 0);
+            double r[11];
+            load_child(mom64, ch, r);
+            add_child(m, g, qd, ngeo[ch], r);
+            if (skip >= nn || (si.w & 255) != level + 1) break;   // no further sibling
             ch = skip;
             ci = si;
         }
     }
-    const int cnt = (int)(t - p);
+    const int cnt = (int)(t - p), info = level;
     ninfo[k] = make_int4((int)p, cnt, skip, info);
     *(double4 *)(nrec + 8 * (int64_t)k) = g;
     *(int4 *)(nrec + 8 * (int64_t)k + 2) = make_int4(skip, (int)p, cnt, info);
     store_moments(mom64, nrec, k, g, m);
 }
 
-// one launch per level, one thread per position (several positions per
-// thread serialise their child chains and are slower)
-constexpr int kMomThreads = 256, kMomPer = 1;
-__global__ __launch_bounds__(kMomThreads) void k_moments_level(
-    int level, const double4 *__restrict__ xq, int64_t n, const int8_t *__restrict__ Lv,
-    const int8_t *__restrict__ Lf, const int32_t *__restrict__ noff,
+// Internal nodes by level.  nlev[k] is the level of node k, with kLeafBit
+// set for a leaf; a pass over level l takes the nodes whose byte equals l.
+// The nodes of one level are spread over the whole preorder.
+__device__ __forceinline__ void internal_node(
+    int k, int level, int64_t n, int nn, const uint8_t *__restrict__ nlev,
     const double4 *__restrict__ ngeo, int4 *ninfo, int32_t *npar, double *mom64, float4 *nrec,
-    int32_t *leafof, const unsigned long long *__restrict__ ctr, int32_t *flags)
+    int32_t *flags)
+{
+    const int p = ninfo[k].x;
+    if (p < 0 || (int64_t)p >= n) {
+        atomicOr(flags, UCP_FLAG_INTERNAL);
+        return;
+    }
+    moments_internal(k, p, level, nn, nlev, ngeo, ninfo, npar, mom64, nrec, flags);
+}
+
+// Internal level maxl - 1 - j, with maxl the deepest leaf level: the
+// deepest internal levels hold most internal nodes, and each node reads its
+// children's records with loads that no two lanes share, so each of them
+// takes a launch over the whole chip, one node per thread.
+constexpr int kDeepThreads = 256, kDeepLevels = 4;
+__global__ __launch_bounds__(kDeepThreads) void k_moments_level(
+    int j, int64_t n, const int32_t *__restrict__ noff, const uint8_t *__restrict__ nlev,
+    const double4 *__restrict__ ngeo, int4 *ninfo, int32_t *npar, double *mom64, float4 *nrec,
+    const unsigned long long *__restrict__ ctr, int32_t *flags)
 {
     if (*flags) return;
-    if ((unsigned long long)level > ctr[CTR_MAXLEVEL]) return;   // no node this deep
-    const int64_t base = (int64_t)blockIdx.x * kMomThreads * kMomPer + threadIdx.x;
-    for (int r = 0; r < kMomPer; ++r)
-        moments_node(base + (int64_t)r * kMomThreads, level, xq, n, Lv, Lf, noff, ngeo, ninfo,
-                     npar, mom64, nrec, leafof, flags);
+    const int l = (int)ctr[CTR_MAXLEVEL] - 1 - j;
+    if (l < 0) return;
+    const int nn = noff[n];
+    for (int64_t k = blockIdx.x * (int64_t)kDeepThreads + threadIdx.x; k < nn;
+         k += (int64_t)gridDim.x * kDeepThreads)
+        if ((int)nlev[k] == l)
+            internal_node((int)k, l, n, nn, nlev, ngeo, ninfo, npar, mom64, nrec, flags);
+}
+
+// Grid-wide barrier of a launch whose blocks are all resident at once (one
+// block per CU).  Thread 0 of each block publishes the block's writes, counts
+// itself in and waits for the count to reach `target`; the wait is bounded and
+// returns false when the bound is hit.
+constexpr int kBarrierSpin = 1 << 21;
+__device__ __forceinline__ bool grid_barrier(unsigned long long *bar, unsigned long long target)
+{
+    __shared__ int ok;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        atomicAdd(bar, 1ull);
+        int spins = 0;
+        while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target &&
+               spins <= kBarrierSpin) {
+            __builtin_amdgcn_s_sleep(2);
+            ++spins;
+        }
+        ok = spins <= kBarrierSpin;
+        __threadfence();
+    }
+    __syncthreads();
+    return ok != 0;
+}
+
+// The internal levels above those, from the deepest up, in one launch of
+// kUpBlocks blocks with a grid barrier between levels (these levels hold few
+// nodes, so a kernel launch per level would cost more than its work).  Every block passes every barrier, whatever it finds, so that the
+// count of arrivals stays exact; a block whose wait times out flags the build
+// and stops waiting.  Few blocks keep the barrier cheap: each block's release
+// writes back its L2.
+constexpr int kUpThreads = 512, kUpBlocks = 16, kUpScan = 16;   // level bytes per thread
+constexpr int kUpChunk = kUpThreads * kUpScan;
+__global__ __launch_bounds__(kUpThreads) void k_moments_up(
+    int64_t n, const int32_t *__restrict__ noff, const uint8_t *__restrict__ nlev,
+    const double4 *__restrict__ ngeo, int4 *ninfo, int32_t *npar, double *mom64, float4 *nrec,
+    unsigned long long *ctr, int32_t *flags)
+{
+    // the matching nodes of one chunk of the preorder, gathered so that the
+    // block's threads share them evenly
+    __shared__ int match[kUpChunk];
+    __shared__ int nmatch, go_s;
+    const int maxl = (int)ctr[CTR_MAXLEVEL];   // deepest leaf; internal nodes lie above it
+    const int nn = noff[n];
+    unsigned long long target = 0;
+    bool wait = true;
+    for (int l = maxl - 1 - kDeepLevels; l >= 0; --l) {
+        // one reading of the flags for the whole block, so that its threads
+        // agree on every loop bound below
+        if (threadIdx.x == 0)
+            go_s = __hip_atomic_load(flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
+        __syncthreads();
+        const bool go = go_s != 0;
+        __syncthreads();
+        for (int64_t cb = (int64_t)blockIdx.x * kUpChunk; go && cb < nn;
+             cb += (int64_t)gridDim.x * kUpChunk) {
+            if (threadIdx.x == 0) nmatch = 0;
+            __syncthreads();
+            const int64_t k0 = cb + (int64_t)threadIdx.x * kUpScan;
+            if (k0 < nn) {
+                const uint4 v = *(const uint4 *)(nlev + k0);
+                const uint32_t d[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int b = 0; b < kUpScan; ++b) {
+                    const int64_t k = k0 + b;
+                    if (k < nn && (int)((d[b >> 2] >> (8 * (b & 3))) & 255u) == l)
+                        match[atomicAdd(&nmatch, 1)] = (int)k;
+                }
+            }
+            __syncthreads();
+            for (int i = threadIdx.x; i < nmatch; i += kUpThreads)
+                internal_node(match[i], l, n, nn, nlev, ngeo, ninfo, npar, mom64, nrec, flags);
+            __syncthreads();
+        }
+        if (l == 0 || !wait) continue;
+        target += gridDim.x;
+        if (!grid_barrier(&ctr[CTR_BARRIER], target)) {
+            if (threadIdx.x == 0) atomicOr(flags, UCP_FLAG_INTERNAL);
+            wait = false;
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -788,8 +1101,9 @@ void launch_build(Ctx *c, const double *x, const double *q, const int64_t *offse
     const int cap = c->p.leaf_cap;
     const int G = c->p.group_size;
 
-    hipLaunchKernelGGL(k_build_reset, grid_for(6 * (int64_t)clouds + CTR_NCTR, 256), dim3(256), 0, s,
-                       c->d_mm, clouds, c->d_ctr, c->d_flags);
+    hipLaunchKernelGGL(k_build_reset,
+                       grid_for(6 * (int64_t)clouds + CTR_NCTR + kSortTickets, 256),
+                       dim3(256), 0, s, c->d_mm, clouds, c->d_ctr, c->d_sortctl, c->d_flags);
     if (offsets_in)
         hipLaunchKernelGGL(k_offsets_copy, dim3(1), dim3(256), 0, s, c->d_off, offsets_in, clouds,
                            n, c->d_flags);
@@ -809,34 +1123,37 @@ void launch_build(Ctx *c, const double *x, const double *q, const int64_t *offse
     // 3. sort
     const int ntiles = (int)((n + kSortTile - 1) / kSortTile);
     const int nhist = 256 * ntiles;
-    int cur = 0;
+    int cur = 0, npass = 0;
+    uint32_t *status[2] = {c->d_hist, c->d_histscan};
+    launch_fill_i32((int32_t *)status[0], 0, nhist, s);
     auto pass = [&](bool cloud_pass, int shift) {
+        uint32_t *st = status[npass & 1], *st_next = status[(npass + 1) & 1];
+        uint32_t *ticket = c->d_sortctl + npass;
         if (cloud_pass) {
             hipLaunchKernelGGL(k_radix_hist<true>, dim3(ntiles), dim3(kSortThreads), 0, s,
                                (const uint64_t *)c->d_key[cur], (const uint32_t *)c->d_val[cur], n,
-                               shift, (const int64_t *)c->d_off, clouds, c->d_hist, ntiles,
+                               shift, (const int64_t *)c->d_off, clouds, st, c->d_hexcl, ticket,
+                               c->d_flags);
+            hipLaunchKernelGGL(k_radix_scatter<true>, dim3(ntiles), dim3(kSortThreads), 0, s,
+                               (const uint64_t *)c->d_key[cur], (const uint32_t *)c->d_val[cur],
+                               c->d_key[cur ^ 1], c->d_val[cur ^ 1], n, shift,
+                               (const int64_t *)c->d_off, clouds, (const uint32_t *)st,
+                               (const uint32_t *)c->d_hexcl, st_next, ntiles,
                                (const int32_t *)c->d_flags);
         } else {
             hipLaunchKernelGGL(k_radix_hist<false>, dim3(ntiles), dim3(kSortThreads), 0, s,
                                (const uint64_t *)c->d_key[cur], (const uint32_t *)c->d_val[cur], n,
-                               shift, (const int64_t *)c->d_off, clouds, c->d_hist, ntiles,
-                               (const int32_t *)c->d_flags);
-        }
-        scan_excl((const int32_t *)c->d_hist, (int32_t *)c->d_histscan, nhist, c->d_scanblk, s);
-        if (cloud_pass) {
-            hipLaunchKernelGGL(k_radix_scatter<true>, dim3(ntiles), dim3(kSortThreads), 0, s,
-                               (const uint64_t *)c->d_key[cur], (const uint32_t *)c->d_val[cur],
-                               c->d_key[cur ^ 1], c->d_val[cur ^ 1], n, shift,
-                               (const int64_t *)c->d_off, clouds, (const uint32_t *)c->d_histscan,
-                               ntiles, (const int32_t *)c->d_flags);
-        } else {
+                               shift, (const int64_t *)c->d_off, clouds, st, c->d_hexcl, ticket,
+                               c->d_flags);
             hipLaunchKernelGGL(k_radix_scatter<false>, dim3(ntiles), dim3(kSortThreads), 0, s,
                                (const uint64_t *)c->d_key[cur], (const uint32_t *)c->d_val[cur],
                                c->d_key[cur ^ 1], c->d_val[cur ^ 1], n, shift,
-                               (const int64_t *)c->d_off, clouds, (const uint32_t *)c->d_histscan,
-                               ntiles, (const int32_t *)c->d_flags);
+                               (const int64_t *)c->d_off, clouds, (const uint32_t *)st,
+                               (const uint32_t *)c->d_hexcl, st_next, ntiles,
+                               (const int32_t *)c->d_flags);
         }
         cur ^= 1;
+        ++npass;
     };
     const int key_passes = (3 * b + 7) / 8;
     for (int ps = 0; ps < key_passes; ++ps) pass(false, 8 * ps);
@@ -853,22 +1170,31 @@ void launch_build(Ctx *c, const double *x, const double *q, const int64_t *offse
     // 4. levels and node numbering
     hipLaunchKernelGGL(k_levels, grid_for(n + 1, kLvlTile), dim3(kLvlTile), 0, s,
                        (const uint64_t *)c->d_skey, n, (const int64_t *)c->d_off, clouds, b, cap,
-                       c->d_L, c->d_leaf, c->d_cnt, (const int32_t *)c->d_flags);
+                       c->d_L, c->d_leaf, c->d_cnt, c->d_lend, (const int32_t *)c->d_flags);
     scan_excl((const int32_t *)c->d_cnt, c->d_noff, n + 1, c->d_scanblk, s);
     // 5. nodes
     hipLaunchKernelGGL(k_nodes, grid_for(n, 256), dim3(256), 0, s, (const uint64_t *)c->d_skey, n,
                        (const int64_t *)c->d_off, clouds, (const double4 *)c->d_cube, b,
                        (const int8_t *)c->d_L, (const int8_t *)c->d_leaf,
                        (const int32_t *)c->d_noff, c->node_cap, c->d_ngeo, c->d_ninfo, c->d_npar,
-                       c->d_ctr, c->d_flags);
-    // 6. moments, deepest level first
-    for (int l = b; l >= 0; --l)
-        hipLaunchKernelGGL(k_moments_level, grid_for(n, kMomThreads * kMomPer), dim3(kMomThreads),
-                           0, s, l,
-                           (const double4 *)c->d_xq, n, (const int8_t *)c->d_L,
-                           (const int8_t *)c->d_leaf, (const int32_t *)c->d_noff,
+                       c->d_nlev, c->d_ctr, c->d_flags);
+    // 6. moments: every leaf, then the internal levels from the deepest up
+    hipLaunchKernelGGL(k_leaf_moments, grid_for(n, kLeafThreads), dim3(kLeafThreads), 0, s,
+                       (const double4 *)c->d_xq, n, (const int8_t *)c->d_L,
+                       (const int8_t *)c->d_leaf, (const int32_t *)c->d_lend,
+                       (const int32_t *)c->d_noff, (const double4 *)c->d_ngeo, c->d_ninfo,
+                       c->d_mom64, c->d_nrec, c->d_leafof, (const int32_t *)c->d_flags);
+    const int deep_blocks = (int)std::min<int64_t>((c->node_cap + kDeepThreads - 1) / kDeepThreads,
+                                                   16384);
+    for (int j = 0; j < kDeepLevels; ++j)
+        hipLaunchKernelGGL(k_moments_level, dim3(deep_blocks), dim3(kDeepThreads), 0, s, j, n,
+                           (const int32_t *)c->d_noff, (const uint8_t *)c->d_nlev,
                            (const double4 *)c->d_ngeo, c->d_ninfo, c->d_npar, c->d_mom64,
-                           c->d_nrec, c->d_leafof, (const unsigned long long *)c->d_ctr, c->d_flags);
+                           c->d_nrec, (const unsigned long long *)c->d_ctr, c->d_flags);
+    hipLaunchKernelGGL(k_moments_up, dim3(std::min(kUpBlocks, std::max(c->num_cu, 1))),
+                       dim3(kUpThreads), 0, s, n, (const int32_t *)c->d_noff,
+                       (const uint8_t *)c->d_nlev, (const double4 *)c->d_ngeo, c->d_ninfo,
+                       c->d_npar, c->d_mom64, c->d_nrec, c->d_ctr, c->d_flags);
     // 7. groups
     hipLaunchKernelGGL(k_group_count, grid_for(n + 1, 256), dim3(256), 0, s, n,
                        (const int8_t *)c->d_L, (const int8_t *)c->d_leaf,

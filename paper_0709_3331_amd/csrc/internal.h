@@ -20,13 +20,15 @@ constexpr int kScanItems = 4;      // elements per thread in the scan
 constexpr int kSortThreads = 1024;  // 16 waves per sort block
 constexpr int kSortItems = 2;       // rounds of kSortThreads elements per tile
 constexpr int kSortTile = kSortThreads * kSortItems;
+constexpr int kSortTickets = 32;
 constexpr int kScanSmallItems = 64;            // elements per thread, one-block scan
 // one block streams at most a few KB efficiently; longer arrays take the
 // three-kernel scan
 constexpr int64_t kScanSmallLimit = 4096;
+constexpr uint8_t kLeafBit = 0x80;             // leaf flag of the per-node level byte
 
 // device counter slots (unsigned long long)
-enum { CTR_P2P = 0, CTR_M2P = 1, CTR_MAXLEVEL = 2, CTR_VJPMAX = 4, CTR_NCTR = 8 };
+enum { CTR_P2P = 0, CTR_M2P = 1, CTR_MAXLEVEL = 2, CTR_BARRIER = 3, CTR_VJPMAX = 4, CTR_NCTR = 8 };
 // walk work queues: one per XCD, each on its own 128-byte line
 constexpr int kWalkQueues = 8, kQStride = 16;
 
@@ -77,8 +79,13 @@ struct Ctx {
     // sort
     uint64_t *d_key[2] = {nullptr, nullptr};
     uint32_t *d_val[2] = {nullptr, nullptr};
-    uint32_t *d_hist = nullptr;             // [256 * tiles]
-    uint32_t *d_histscan = nullptr;
+    // radix sort: per-(tile, digit) status words of the decoupled look-back
+    // (two arrays, alternating by pass), each tile's exclusive digit prefixes,
+    // and one ticket counter per pass
+    uint32_t *d_hist = nullptr;             // [256 * tiles] status, even passes
+    uint32_t *d_histscan = nullptr;         // [256 * tiles] status, odd passes
+    uint32_t *d_hexcl = nullptr;            // [256 * tiles]
+    uint32_t *d_sortctl = nullptr;          // [kSortTickets]
     uint64_t *d_skey = nullptr;             // sorted keys (points into d_key[])
     uint32_t *d_perm = nullptr;             // sorted position -> caller index
     // sorted particles
@@ -87,6 +94,7 @@ struct Ctx {
     int8_t *d_L = nullptr;                  // [n_max + 1] common-prefix level with predecessor
     int8_t *d_leaf = nullptr;               // [n_max + 1] level of the leaf holding the position
     int32_t *d_cnt = nullptr;               // [n_max + 1] per-position counts to scan
+    int32_t *d_lend = nullptr;              // [n_max + 1] end of the leaf starting there (-1: scan)
     int32_t *d_noff = nullptr;              // [n_max + 1] first node starting at the position
     int32_t *d_goff = nullptr;              // [n_max + 1] first group starting at the position
     int32_t *d_gnode = nullptr;             // [n_max]
@@ -95,6 +103,7 @@ struct Ctx {
     double4 *d_ngeo = nullptr;              // [node_cap] centre xyz, side^2
     int4 *d_ninfo = nullptr;                // [node_cap] first, count, skip, level | 256*leaf
     int32_t *d_npar = nullptr;              // [node_cap] parent (-1 for a root)
+    uint8_t *d_nlev = nullptr;              // [node_cap + 128] level of each node, | kLeafBit for a leaf
     double *d_mom64 = nullptr;              // [node_cap][16] cx cy cz Q p[3] trS S[6] 0 0
     // node record for the walk, two 64-byte lines per node:
     //   line 1: cx cy cz side^2 (double), skip first count level|256*leaf (int)
