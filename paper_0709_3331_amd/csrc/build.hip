@@ -500,8 +500,8 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
 //    L(p): number of leading key digits shared with position p-1 (-1 at a
 //    cloud edge).  A boundary at level l lies before p iff L(p) < l.
 //    leaf(p): smallest level l at which the box holding p has <= leaf_cap
-//    particles (b if none) -- found by bisection on l, each probe looking for
-//    boundaries s <= p < t at level l with t - s <= leaf_cap.
+//    particles (b if none) -- found from running minima of L over the
+//    leaf_cap positions on either side of p.
 //    nodes starting at p: levels L(p)+1 .. leaf(p).
 // ---------------------------------------------------------------------------
 constexpr int kLvlTile = 256;
@@ -521,6 +521,7 @@ __global__ __launch_bounds__(kLvlTile) void k_levels(const uint64_t *__restrict_
                                                     const int32_t *flags)
 {
     __shared__ int8_t sL[kLvlTile + 2 * kMaxLeafCap + 2];
+    __shared__ int8_t sBM[kMaxLeafCap * kLvlTile];   // BM[j] of thread x at [j][x]
     const int64_t base = (int64_t)blockIdx.x * kLvlTile;
     const int64_t wlo = base - cap;                 // sL[j - wlo] = L(j)
     const int wn = kLvlTile + 2 * cap + 1;
@@ -544,35 +545,29 @@ __global__ __launch_bounds__(kLvlTile) void k_levels(const uint64_t *__restrict_
         return;
     }
     auto Lw = [&](int64_t j) -> int { return (int)sL[j - wlo]; };
-    // does the box of level lv holding p hold at most cap particles?  If so,
-    // tend is the position after its last particle
-    auto ok = [&](int lv, int64_t &tend) -> bool {
-        int64_t s = p;
-        while (s > p - cap + 1 && Lw(s) >= lv) --s;
-        if (Lw(s) >= lv) return false;
-        int64_t t = p + 1;
-        while (t < s + cap && Lw(t) >= lv) ++t;
-        tend = t;
-        return Lw(t) < lv;
-    };
-    int leaf;
+    // The box of level l holding p starts j* positions back (the first
+    // j >= 0 with L(p - j) < l) and ends i* positions on (the first i >= 1
+    // with L(p + i) < l); it holds at most cap particles iff j* + i* <= cap.
+    // With BM[j] the least L over p - j .. p and FM[i] the least L over
+    // p + 1 .. p + i, both non-increasing, that holds iff l > M with
+    // M = min over j in [0, cap) of max(BM[j], FM[cap - j]).  The leaf is the
+    // least such level, else the deepest.
+    int run = 127;
+    for (int j = 0; j < cap; ++j) {
+        run = min(run, Lw(p - j));
+        sBM[j * kLvlTile + threadIdx.x] = (int8_t)run;
+    }
+    int M = 127, fm = 127;
+    for (int i = 1; i <= cap; ++i) {
+        fm = min(fm, Lw(p + i));
+        M = min(M, max((int)sBM[(cap - i) * kLvlTile + threadIdx.x], fm));
+    }
+    const int leaf = min(M + 1, b);
     int64_t tleaf = -1;   // -1: a max-depth leaf beyond the window, found by a scan
-    if (!ok(b, tleaf)) {
-        leaf = b;
-        tleaf = -1;
-    } else {
-        int lo = -1, hi = b;   // ok(hi) holds; ok(lo) is taken as false
-        while (hi - lo > 1) {
-            int mid = (lo + hi) >> 1;
-            int64_t tm;
-            if (ok(mid, tm)) {
-                hi = mid;
-                tleaf = tm;
-            } else {
-                lo = mid;
-            }
-        }
-        leaf = hi;
+    if (M + 1 <= b) {
+        int64_t t = p + 1;
+        while (Lw(t) >= leaf) ++t;   // i* <= cap - j*, inside the window
+        tleaf = t;
     }
     const int Lp = Lw(p);
     Lout[p] = (int8_t)Lp;
@@ -813,6 +808,7 @@ __device__ __forceinline__ bool children_in_window(int k, int level, int nn,
 // shifted to its centre, summed in octant order (preorder).  The children are
 // read from the level bytes when the subtree is short, else by following the
 // skip links from k + 1.
+template <int BATCH>
 __device__ __forceinline__ void moments_internal(
     int k, int64_t p, int level, int nn, const uint8_t *__restrict__ nlev,
     const double4 *__restrict__ ngeo, int4 *ninfo, int32_t *npar, double *mom64, float4 *nrec,
@@ -826,45 +822,37 @@ __device__ __forceinline__ void moments_internal(
     uint64_t cm;
     int end;
     if (children_in_window(k, level, nn, nlev, &cm, &end)) {
-        // two children per round of loads
+        // BATCH children per round of loads
         int last = -1, nch = 0;
         bool bad = (cm & 1ull) == 0;   // the first child is k + 1
         while (cm != 0 && !bad) {
-            const int c0 = k + 1 + __builtin_ctzll(cm);
-            cm &= cm - 1;
-            const int c1 = cm != 0 ? k + 1 + __builtin_ctzll(cm) : -1;
-            if (c1 >= 0) cm &= cm - 1;
-            const int4 i0 = ninfo[c0];
-            const double4 g0 = ngeo[c0];
-            double r0[11], r1[11];
-            load_child(mom64, c0, r0);
-            int4 i1 = make_int4(0, 1, 0, 0);
-            double4 g1 = g0;
-            if (c1 >= 0) {
-                i1 = ninfo[c1];
-                g1 = ngeo[c1];
-                load_child(mom64, c1, r1);
+            int c[BATCH];
+#pragma unroll
+            for (int u = 0; u < BATCH; ++u) {
+                c[u] = cm != 0 ? k + 1 + __builtin_ctzll(cm) : -1;
+                if (cm != 0) cm &= cm - 1;
             }
-            bad = bad || i0.y < 1 || i1.y < 1;
-            add_child(m, g, qd, g0, r0);
-            npar[c0] = k;
-            last = c0;
-            t = (int64_t)i0.x + i0.y;
-            skip = i0.z;
-            ++nch;
-            if (c1 >= 0) {
-                add_child(m, g, qd, g1, r1);
-                npar[c1] = k;
-                last = c1;
-                t = (int64_t)i1.x + i1.y;
-                skip = i1.z;
+            int4 ic[BATCH];
+            double4 gc[BATCH];
+            double rc[BATCH][11];
+#pragma unroll
+            for (int u = 0; u < BATCH; ++u) {
+                const int cu = c[u] >= 0 ? c[u] : c[0];
+                ic[u] = ninfo[cu];
+                gc[u] = ngeo[cu];
+                load_child(mom64, cu, rc[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < BATCH; ++u) {
+                if (c[u] < 0) break;
+                bad = bad || ic[u].y < 1;
+                add_child(m, g, qd, gc[u], rc[u]);
+                npar[c[u]] = k;
+                last = c[u];
+                t = (int64_t)ic[u].x + ic[u].y;
+                skip = ic[u].z;
                 ++nch;
             }
-        }
-        // the last child's skip link is the first node after k's subtree
-        if (bad || last < 0 || nch > 8 || skip != k + 1 + end) {
-            atomicOr(flags, UCP_FLAG_INTERNAL);   // inconsistent records: stop
-            return;
         }
     } else {
         int ch = k + 1;
@@ -897,6 +885,7 @@ __device__ __forceinline__ void moments_internal(
 // Internal nodes by level.  nlev[k] is the level of node k, with kLeafBit
 // set for a leaf; a pass over level l takes the nodes whose byte equals l.
 // The nodes of one level are spread over the whole preorder.
+template <int BATCH>
 __device__ __forceinline__ void internal_node(
     int k, int level, int64_t n, int nn, const uint8_t *__restrict__ nlev,
     const double4 *__restrict__ ngeo, int4 *ninfo, int32_t *npar, double *mom64, float4 *nrec,
@@ -907,7 +896,7 @@ __device__ __forceinline__ void internal_node(
         atomicOr(flags, UCP_FLAG_INTERNAL);
         return;
     }
-    moments_internal(k, p, level, nn, nlev, ngeo, ninfo, npar, mom64, nrec, flags);
+    moments_internal<BATCH>(k, p, level, nn, nlev, ngeo, ninfo, npar, mom64, nrec, flags);
 }
 
 // Internal level maxl - 1 - j, with maxl the deepest leaf level: the
@@ -927,7 +916,7 @@ __global__ __launch_bounds__(kDeepThreads) void k_moments_level(
     for (int64_t k = blockIdx.x * (int64_t)kDeepThreads + threadIdx.x; k < nn;
          k += (int64_t)gridDim.x * kDeepThreads)
         if ((int)nlev[k] == l)
-            internal_node((int)k, l, n, nn, nlev, ngeo, ninfo, npar, mom64, nrec, flags);
+            internal_node<4>((int)k, l, n, nn, nlev, ngeo, ninfo, npar, mom64, nrec, flags);
 }
 
 // Grid-wide barrier of a launch whose blocks are all resident at once (one
@@ -1001,7 +990,7 @@ __global__ __launch_bounds__(kUpThreads) void k_moments_up(
             }
             __syncthreads();
             for (int i = threadIdx.x; i < nmatch; i += kUpThreads)
-                internal_node(match[i], l, n, nn, nlev, ngeo, ninfo, npar, mom64, nrec, flags);
+                internal_node<2>(match[i], l, n, nn, nlev, ngeo, ninfo, npar, mom64, nrec, flags);
             __syncthreads();
         }
         if (l == 0 || !wait) continue;
