@@ -56,14 +56,19 @@ void launch_fill_f64(double *p, double v, int64_t n, hipStream_t s)
 }
 
 // reset of the per-build state: min/max slots, counters, flag word
+// per-build state: cloud extents, counters, flags, the sort's tickets, digit
+// counts and the first pass's look-back status words
 __global__ void k_build_reset(unsigned long long *mm, int clouds, unsigned long long *ctr,
-                              uint32_t *sortctl, int32_t *flags)
+                              uint32_t *sortctl, uint32_t *ghist, uint32_t *status0,
+                              int64_t nstatus, int32_t *flags)
 {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < clouds * 6) mm[t] = (t % 6 < 3) ? ~0ull : 0ull;
-    if (t < CTR_NCTR) ctr[t] = 0;
-    if (t < kSortTickets) sortctl[t] = 0;
-    if (t == 0) *flags = 0;
+    const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t0 < clouds * 6) mm[t0] = (t0 % 6 < 3) ? ~0ull : 0ull;
+    if (t0 < CTR_NCTR) ctr[t0] = 0;
+    if (t0 < kSortTickets) sortctl[t0] = 0;
+    if (t0 < kSortPassesMax * 256) ghist[t0] = 0;
+    if (t0 == 0) *flags = 0;
+    for (int64_t t = t0; t < nstatus; t += (int64_t)gridDim.x * blockDim.x) status0[t] = 0;
 }
 
 // cloud offsets: {0, n} for one cloud, or a checked copy of the caller's
@@ -345,14 +350,15 @@ static void scan_excl(const int32_t *in, int32_t *out, int64_t n, int32_t *blk, 
 }
 
 // ---------------------------------------------------------------------------
-// 3. stable LSD radix sort of (key, index), 8-bit digits.  Per pass: a
-//    per-tile digit histogram whose exclusive prefix over the tiles is found
-//    by a decoupled look-back (below), and the scatter.  The scatter processes a
-//    tile of kSortTile elements in rounds of kSortThreads; inside a round each
-//    wave ranks equal digits with ballots, the 16 waves are ordered through
-//    LDS, and a running count per digit carries the order across rounds.  The
-//    last pass(es) of a multi-cloud build sort by cloud, restoring the clouds'
-//    contiguity while keeping key order inside each cloud.
+// 3. stable LSD radix sort of (key, index), 8-bit digits.  The digit counts
+//    of every pass are found first, in one kernel (they do not depend on the
+//    order).  Then each pass is one kernel: a tile of kSortTile elements is
+//    ranked (inside a round of kSortThreads each wave ranks equal digits with
+//    ballots, and the waves and rounds are ordered through LDS), its digit
+//    counts are published, its digit prefixes over the earlier tiles are found
+//    by a decoupled look-back, and the tile is scattered.  The last pass(es)
+//    of a multi-cloud build sort by cloud, restoring the clouds' contiguity
+//    while keeping key order inside each cloud.
 // ---------------------------------------------------------------------------
 template <bool CLOUD>
 __device__ __forceinline__ uint32_t sort_digit(uint64_t k, uint32_t v, int shift,
@@ -362,137 +368,131 @@ __device__ __forceinline__ uint32_t sort_digit(uint64_t k, uint32_t v, int shift
     return (uint32_t)(k >> shift) & 255u;
 }
 
-// Per-tile digit counts and their exclusive prefix over the tiles, in one
-// kernel.  Blocks take tiles in the order they start (a ticket), count their
-// tile's digits, publish the counts at once (flag AGG), then walk back over
-// the earlier tiles adding published counts until one of them has published
-// its inclusive prefix (flag INCL), and publish their own.  A tile only waits
-// for tiles that started before it and that publish before waiting, so every
-// wait ends; a bounded spin turns a lost tile into an internal-error flag
-// rather than a hang.  Status word: flag (2 bits) | count (30 bits).
+// digit counts of all passes: key passes first, then cloud passes (the
+// values are still the identity here, so element e is particle e)
+__global__ __launch_bounds__(kSortThreads) void k_radix_counts(
+    const uint64_t *__restrict__ key, int64_t n, int key_passes, int cloud_passes,
+    const int64_t *__restrict__ off, int clouds, uint32_t *ghist, const int32_t *flags)
+{
+    __shared__ uint32_t h[kSortPassesMax * 256];
+    if (*flags) return;
+    const int np = key_passes + cloud_passes;
+    for (int j = threadIdx.x; j < np * 256; j += kSortThreads) h[j] = 0;
+    __syncthreads();
+    for (int64_t e = blockIdx.x * (int64_t)kSortThreads + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * kSortThreads) {
+        const uint64_t k = key[e];
+        for (int ps = 0; ps < key_passes; ++ps)
+            atomicAdd(&h[ps * 256 + (uint32_t)((k >> (8 * ps)) & 255u)], 1u);
+        if (cloud_passes > 0) {
+            const uint32_t cl = (uint32_t)cloud_of(off, clouds, e);
+            for (int ps = 0; ps < cloud_passes; ++ps)
+                atomicAdd(&h[(key_passes + ps) * 256 + ((cl >> (8 * ps)) & 255u)], 1u);
+        }
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < np * 256; j += kSortThreads)
+        if (h[j] != 0) atomicAdd(&ghist[j], h[j]);
+}
+
+// Status word of a (tile, digit): flag (2 bits) | count (30 bits).  A tile
+// publishes its own count at once (flag AGG), then walks back over the earlier
+// tiles adding published counts until one of them has published its inclusive
+// prefix (flag INCL), and publishes its own.  Blocks take tiles in the order
+// they start (a ticket), so a tile only waits for tiles that started before
+// it and that publish before waiting: every wait ends.  A bounded spin turns a
+// lost tile into an internal-error flag rather than a hang.
 constexpr uint32_t kStAgg = 1u << 30, kStIncl = 2u << 30, kStMask = (1u << 30) - 1;
 constexpr int kLookbackSpin = 1 << 18;
 
 template <bool CLOUD>
-__global__ __launch_bounds__(kSortThreads) void k_radix_hist(
-    const uint64_t *__restrict__ key, const uint32_t *__restrict__ val, int64_t n, int shift,
-    const int64_t *__restrict__ off, int clouds, uint32_t *status, uint32_t *excl_out,
+__global__ __launch_bounds__(kSortThreads) void k_radix_pass(
+    const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint64_t *kout,
+    uint32_t *vout, int64_t n, int shift, const int64_t *__restrict__ off, int clouds,
+    const uint32_t *__restrict__ ghist, uint32_t *status, uint32_t *status_next,
     uint32_t *ticket, int32_t *flags)
 {
-    __shared__ uint32_t h[256];
-    __shared__ int tile_sh;
+    constexpr int NW = kSortThreads / 64;
+    __shared__ uint32_t wh[kSortItems][NW][256];   // per-(round, wave) digit counts, then offsets
+    __shared__ uint32_t boff[256];
+    __shared__ int btot, tile_sh;
     if (*flags) return;
-    if (threadIdx.x == 0) tile_sh = (int)atomicAdd(ticket, 1u);
-    if (threadIdx.x < 256) h[threadIdx.x] = 0;
-    __syncthreads();
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    if (tid == 0) tile_sh = (int)atomicAdd(ticket, 1u);
+    for (int j = tid; j < kSortItems * NW * 256; j += kSortThreads) (&wh[0][0][0])[j] = 0;
+    // digit totals of this pass and their exclusive prefix over the digits
+    const uint32_t tot = tid < 256 ? ghist[tid] : 0u;
+    const int below = block_excl_scan((int)tot, &btot);   // synchronises the block
     const int tile = tile_sh;
     const int64_t base = (int64_t)tile * kSortTile;
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    uint64_t k[kSortItems];
+    uint32_t v[kSortItems], d[kSortItems], lrank[kSortItems];
+    bool valid[kSortItems];
+#pragma unroll
     for (int it = 0; it < kSortItems; ++it) {
-        int64_t e = base + it * kSortThreads + threadIdx.x;
-        if (e < n) {
-            uint32_t d = sort_digit<CLOUD>(CLOUD ? 0 : key[e], CLOUD ? val[e] : 0, shift, off, clouds);
-            atomicAdd(&h[d], 1u);
+        const int64_t e = base + it * kSortThreads + tid;
+        valid[it] = e < n;
+        k[it] = valid[it] ? kin[e] : 0ull;
+        v[it] = valid[it] ? vin[e] : 0u;
+        d[it] = valid[it] ? sort_digit<CLOUD>(k[it], v[it], shift, off, clouds) : 0u;
+    }
+    // rank equal digits inside each wave and round
+#pragma unroll
+    for (int it = 0; it < kSortItems; ++it) {
+        uint64_t peers = __ballot(valid[it]);
+        for (int bit = 0; bit < 8; ++bit) {
+            const uint64_t bb = __ballot((d[it] >> bit) & 1u);
+            peers &= ((d[it] >> bit) & 1u) ? bb : ~bb;
         }
+        lrank[it] = (uint32_t)__popcll(peers & lt);
+        if (valid[it] && lrank[it] == 0) wh[it][w][d[it]] = (uint32_t)__popcll(peers);
     }
     __syncthreads();
-    if (threadIdx.x < 256) {
-        const int d = threadIdx.x;
-        const uint32_t agg = h[d];
-        uint32_t *st = status + (int64_t)tile * 256 + d;
+    if (tid < 256) {
+        // the tile's count of digit tid, and each (round, wave)'s offset inside it
+        uint32_t r = 0;
+        for (int it = 0; it < kSortItems; ++it)
+            for (int ww = 0; ww < NW; ++ww) {
+                const uint32_t c = wh[it][ww][tid];
+                wh[it][ww][tid] = r;
+                r += c;
+            }
+        uint32_t *st = status + (int64_t)tile * 256 + tid;
         uint32_t excl = 0;
         if (tile == 0) {
-            __hip_atomic_store(st, kStIncl | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(st, kStIncl | r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         } else {
-            __hip_atomic_store(st, kStAgg | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(st, kStAgg | r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             int j = tile - 1, spins = 0;
             for (;;) {
-                const uint32_t v = __hip_atomic_load(status + (int64_t)j * 256 + d, __ATOMIC_RELAXED,
-                                                     __HIP_MEMORY_SCOPE_AGENT);
-                if ((v & ~kStMask) == 0) {
+                const uint32_t sv = __hip_atomic_load(status + (int64_t)j * 256 + tid,
+                                                      __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if ((sv & ~kStMask) == 0) {
                     if (++spins > kLookbackSpin) {
                         atomicOr(flags, UCP_FLAG_INTERNAL);
                         break;
                     }
                     continue;
                 }
-                excl += v & kStMask;
-                if ((v & kStIncl) || j == 0) break;
+                excl += sv & kStMask;
+                if ((sv & kStIncl) || j == 0) break;
                 --j;
             }
-            __hip_atomic_store(st, kStIncl | (excl + agg), __ATOMIC_RELAXED,
+            __hip_atomic_store(st, kStIncl | (excl + r), __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
         }
-        excl_out[(int64_t)tile * 256 + d] = excl;
+        boff[tid] = (uint32_t)below + excl;
+        status_next[(int64_t)tile * 256 + tid] = 0u;   // the next pass's status
     }
-}
-
-template <bool CLOUD>
-__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
-    const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint64_t *kout,
-    uint32_t *vout, int64_t n, int shift, const int64_t *__restrict__ off, int clouds,
-    const uint32_t *__restrict__ status, const uint32_t *__restrict__ excl, uint32_t *status_next,
-    int ntiles, const int32_t *flags)
-{
-    constexpr int NW = kSortThreads / 64;
-    __shared__ uint32_t run[256];
-    __shared__ uint32_t wh[2][NW][256];   // per-wave digit counts, double-buffered by round
-    __shared__ uint32_t boff[256];
-    __shared__ int btot;
-    if (*flags) return;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    // digit totals are the last tile's inclusive prefixes; this tile's output
-    // offset of digit d is the total of all smaller digits plus its prefix
-    {
-        const uint32_t tot = tid < 256 ? (status[(int64_t)(ntiles - 1) * 256 + tid] & kStMask) : 0u;
-        const int below = block_excl_scan((int)tot, &btot);
-        if (tid < 256) {
-            run[tid] = 0;
-            boff[tid] = (uint32_t)below + excl[(int64_t)blockIdx.x * 256 + tid];
-            status_next[(int64_t)blockIdx.x * 256 + tid] = 0u;   // the next pass's status
-        }
-    }
-    for (int j = tid; j < NW * 256; j += kSortThreads) wh[0][j / 256][j % 256] = 0;
-    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const int64_t base = (int64_t)blockIdx.x * kSortTile;
     __syncthreads();
-    for (int it = 0; it < kSortItems; ++it) {
-        uint32_t(*cw)[256] = wh[it & 1];
-        uint32_t(*nw)[256] = wh[(it + 1) & 1];
-        const int64_t e = base + it * kSortThreads + tid;
-        const bool valid = e < n;
-        uint64_t k = 0;
-        uint32_t v = 0, d = 0;
-        if (valid) {
-            k = kin[e];
-            v = vin[e];
-            d = sort_digit<CLOUD>(k, v, shift, off, clouds);
+#pragma unroll
+    for (int it = 0; it < kSortItems; ++it)
+        if (valid[it]) {
+            const uint32_t dst = boff[d[it]] + wh[it][w][d[it]] + lrank[it];
+            kout[dst] = k[it];
+            vout[dst] = v[it];
         }
-        uint64_t peers = __ballot(valid);
-        for (int bit = 0; bit < 8; ++bit) {
-            uint64_t bb = __ballot((d >> bit) & 1u);
-            peers &= ((d >> bit) & 1u) ? bb : ~bb;
-        }
-        const uint32_t lrank = (uint32_t)__popcll(peers & lt);
-        if (valid && lrank == 0) cw[w][d] = (uint32_t)__popcll(peers);
-        __syncthreads();
-        if (tid < 256) {
-            // order the waves for digit tid; clear the other buffer for the next round
-            uint32_t r = run[tid];
-            for (int ww = 0; ww < NW; ++ww) {
-                const uint32_t c = cw[ww][tid];
-                cw[ww][tid] = r;
-                r += c;
-                nw[ww][tid] = 0;
-            }
-            run[tid] = r;
-        }
-        __syncthreads();
-        if (valid) {
-            const uint32_t dst = boff[d] + cw[w][d] + lrank;
-            kout[dst] = k;
-            vout[dst] = v;
-        }
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -517,11 +517,12 @@ __device__ __forceinline__ int lcp_level(uint64_t a, uint64_t b2, int b)
 __global__ __launch_bounds__(kLvlTile) void k_levels(const uint64_t *__restrict__ key, int64_t n,
                                                     const int64_t *__restrict__ off, int clouds,
                                                     int b, int cap, int8_t *Lout, int8_t *leafout,
-                                                    int32_t *cnt, int32_t *lend,
+                                                    int32_t *cnt, int32_t *lend, int32_t *blkmax,
                                                     const int32_t *flags)
 {
     __shared__ int8_t sL[kLvlTile + 2 * kMaxLeafCap + 2];
     __shared__ int8_t sBM[kMaxLeafCap * kLvlTile];   // BM[j] of thread x at [j][x]
+    __shared__ int wmax[kLvlTile / kWave];
     const int64_t base = (int64_t)blockIdx.x * kLvlTile;
     const int64_t wlo = base - cap;                 // sL[j - wlo] = L(j)
     const int wn = kLvlTile + 2 * cap + 1;
@@ -537,43 +538,52 @@ __global__ __launch_bounds__(kLvlTile) void k_levels(const uint64_t *__restrict_
     }
     __syncthreads();
     const int64_t p = base + threadIdx.x;
-    if (p > n) return;
-    if (p == n || stop) {
+    int leaf = 0;   // deepest leaf level over the block, reduced below
+    if (p < n && !stop) {
+        auto Lw = [&](int64_t j) -> int { return (int)sL[j - wlo]; };
+        // The box of level l holding p starts j* positions back (the first
+        // j >= 0 with L(p - j) < l) and ends i* positions on (the first i >= 1
+        // with L(p + i) < l); it holds at most cap particles iff j* + i* <= cap.
+        // With BM[j] the least L over p - j .. p and FM[i] the least L over
+        // p + 1 .. p + i, both non-increasing, that holds iff l > M with
+        // M = min over j in [0, cap) of max(BM[j], FM[cap - j]).  The leaf is the
+        // least such level, else the deepest.
+        int run = 127;
+        for (int j = 0; j < cap; ++j) {
+            run = min(run, Lw(p - j));
+            sBM[j * kLvlTile + threadIdx.x] = (int8_t)run;
+        }
+        int M = 127, fm = 127;
+        for (int i = 1; i <= cap; ++i) {
+            fm = min(fm, Lw(p + i));
+            M = min(M, max((int)sBM[(cap - i) * kLvlTile + threadIdx.x], fm));
+        }
+        leaf = min(M + 1, b);
+        int64_t tleaf = -1;   // -1: a max-depth leaf beyond the window, found by a scan
+        if (M + 1 <= b) {
+            int64_t t = p + 1;
+            while (Lw(t) >= leaf) ++t;   // i* <= cap - j*, inside the window
+            tleaf = t;
+        }
+        const int Lp = Lw(p);
+        Lout[p] = (int8_t)Lp;
+        leafout[p] = (int8_t)leaf;
+        cnt[p] = leaf > Lp ? leaf - Lp : 0;
+        lend[p] = (int32_t)tleaf;
+    } else if (p <= n) {
         cnt[p] = 0;
-        if (p < n) { Lout[p] = -1; leafout[p] = -1; }
-        else Lout[p] = -1;
-        return;
+        Lout[p] = -1;
+        if (p < n) leafout[p] = -1;
     }
-    auto Lw = [&](int64_t j) -> int { return (int)sL[j - wlo]; };
-    // The box of level l holding p starts j* positions back (the first
-    // j >= 0 with L(p - j) < l) and ends i* positions on (the first i >= 1
-    // with L(p + i) < l); it holds at most cap particles iff j* + i* <= cap.
-    // With BM[j] the least L over p - j .. p and FM[i] the least L over
-    // p + 1 .. p + i, both non-increasing, that holds iff l > M with
-    // M = min over j in [0, cap) of max(BM[j], FM[cap - j]).  The leaf is the
-    // least such level, else the deepest.
-    int run = 127;
-    for (int j = 0; j < cap; ++j) {
-        run = min(run, Lw(p - j));
-        sBM[j * kLvlTile + threadIdx.x] = (int8_t)run;
+    // every position lies in one leaf, whose level its leaf(p) is
+    for (int o = kWave / 2; o > 0; o >>= 1) leaf = max(leaf, __shfl_xor(leaf, o));
+    if ((threadIdx.x & (kWave - 1)) == 0) wmax[threadIdx.x / kWave] = leaf;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int bm = 0;
+        for (int w = 0; w < kLvlTile / kWave; ++w) bm = max(bm, wmax[w]);
+        blkmax[blockIdx.x] = bm;
     }
-    int M = 127, fm = 127;
-    for (int i = 1; i <= cap; ++i) {
-        fm = min(fm, Lw(p + i));
-        M = min(M, max((int)sBM[(cap - i) * kLvlTile + threadIdx.x], fm));
-    }
-    const int leaf = min(M + 1, b);
-    int64_t tleaf = -1;   // -1: a max-depth leaf beyond the window, found by a scan
-    if (M + 1 <= b) {
-        int64_t t = p + 1;
-        while (Lw(t) >= leaf) ++t;   // i* <= cap - j*, inside the window
-        tleaf = t;
-    }
-    const int Lp = Lw(p);
-    Lout[p] = (int8_t)Lp;
-    leafout[p] = (int8_t)leaf;
-    cnt[p] = leaf > Lp ? leaf - Lp : 0;
-    lend[p] = (int32_t)tleaf;
 }
 
 // ---------------------------------------------------------------------------
@@ -588,8 +598,8 @@ __global__ __launch_bounds__(256) void k_nodes(
     const uint64_t *__restrict__ key, int64_t n, const int64_t *__restrict__ off, int clouds,
     const double4 *__restrict__ cube, int b, const int8_t *__restrict__ Lv,
     const int8_t *__restrict__ Lf, const int32_t *__restrict__ noff, int64_t node_cap,
-    double4 *ngeo, int4 *ninfo, int32_t *npar, uint8_t *nlev, unsigned long long *ctr,
-    int32_t *flags)
+    double4 *ngeo, int4 *ninfo, int32_t *npar, uint8_t *nlev, const int32_t *__restrict__ blkmax,
+    int nlvlblk, unsigned long long *ctr, int32_t *flags)
 {
     if (*flags) return;
     const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -598,18 +608,16 @@ __global__ __launch_bounds__(256) void k_nodes(
         return;
     }
     const int Lp = p < n ? (int)Lv[p] : 0, lf = p < n ? (int)Lf[p] : 0;
-    // deepest leaf level: reduced over the block, then one atomic only if it
-    // raises the running maximum (same-address atomics serialise)
-    __shared__ int wmax[4];
-    int lmax = lf > Lp ? lf : 0;
-    for (int o = 32; o > 0; o >>= 1) lmax = max(lmax, __shfl_xor(lmax, o));
-    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = lmax;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const int bm = max(max(wmax[0], wmax[1]), max(wmax[2], wmax[3]));
-        if ((unsigned long long)bm > __hip_atomic_load(&ctr[CTR_MAXLEVEL], __ATOMIC_RELAXED,
-                                                        __HIP_MEMORY_SCOPE_AGENT))
-            atomicMax(&ctr[CTR_MAXLEVEL], (unsigned long long)bm);
+    // deepest leaf level: the maximum of the level pass's block maxima
+    if (blockIdx.x == 0) {
+        __shared__ int wmax[4];
+        int lmax = 0;
+        for (int i = threadIdx.x; i < nlvlblk; i += blockDim.x) lmax = max(lmax, blkmax[i]);
+        for (int o = 32; o > 0; o >>= 1) lmax = max(lmax, __shfl_xor(lmax, o));
+        if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = lmax;
+        __syncthreads();
+        if (threadIdx.x == 0)
+            ctr[CTR_MAXLEVEL] = (unsigned long long)max(max(wmax[0], wmax[1]), max(wmax[2], wmax[3]));
     }
     if (p >= n || lf <= Lp) return;
     const int c = cloud_of(off, clouds, p);
@@ -1090,9 +1098,13 @@ void launch_build(Ctx *c, const double *x, const double *q, const int64_t *offse
     const int cap = c->p.leaf_cap;
     const int G = c->p.group_size;
 
+    const int64_t nstatus = 256 * ((n + kSortTile - 1) / kSortTile);
     hipLaunchKernelGGL(k_build_reset,
-                       grid_for(6 * (int64_t)clouds + CTR_NCTR + kSortTickets, 256),
-                       dim3(256), 0, s, c->d_mm, clouds, c->d_ctr, c->d_sortctl, c->d_flags);
+                       grid_for(std::max<int64_t>({6 * (int64_t)clouds + CTR_NCTR,
+                                                   (int64_t)kSortPassesMax * 256, 1}),
+                                256),
+                       dim3(256), 0, s, c->d_mm, clouds, c->d_ctr, c->d_sortctl, c->d_ghist,
+                       c->d_hist, nstatus, c->d_flags);
     if (offsets_in)
         hipLaunchKernelGGL(k_offsets_copy, dim3(1), dim3(256), 0, s, c->d_off, offsets_in, clouds,
                            n, c->d_flags);
@@ -1111,46 +1123,40 @@ void launch_build(Ctx *c, const double *x, const double *q, const int64_t *offse
                        (const int32_t *)c->d_flags);
     // 3. sort
     const int ntiles = (int)((n + kSortTile - 1) / kSortTile);
-    const int nhist = 256 * ntiles;
-    int cur = 0, npass = 0;
-    uint32_t *status[2] = {c->d_hist, c->d_histscan};
-    launch_fill_i32((int32_t *)status[0], 0, nhist, s);
-    auto pass = [&](bool cloud_pass, int shift) {
-        uint32_t *st = status[npass & 1], *st_next = status[(npass + 1) & 1];
-        uint32_t *ticket = c->d_sortctl + npass;
-        if (cloud_pass) {
-            hipLaunchKernelGGL(k_radix_hist<true>, dim3(ntiles), dim3(kSortThreads), 0, s,
-                               (const uint64_t *)c->d_key[cur], (const uint32_t *)c->d_val[cur], n,
-                               shift, (const int64_t *)c->d_off, clouds, st, c->d_hexcl, ticket,
-                               c->d_flags);
-            hipLaunchKernelGGL(k_radix_scatter<true>, dim3(ntiles), dim3(kSortThreads), 0, s,
-                               (const uint64_t *)c->d_key[cur], (const uint32_t *)c->d_val[cur],
-                               c->d_key[cur ^ 1], c->d_val[cur ^ 1], n, shift,
-                               (const int64_t *)c->d_off, clouds, (const uint32_t *)st,
-                               (const uint32_t *)c->d_hexcl, st_next, ntiles,
-                               (const int32_t *)c->d_flags);
-        } else {
-            hipLaunchKernelGGL(k_radix_hist<false>, dim3(ntiles), dim3(kSortThreads), 0, s,
-                               (const uint64_t *)c->d_key[cur], (const uint32_t *)c->d_val[cur], n,
-                               shift, (const int64_t *)c->d_off, clouds, st, c->d_hexcl, ticket,
-                               c->d_flags);
-            hipLaunchKernelGGL(k_radix_scatter<false>, dim3(ntiles), dim3(kSortThreads), 0, s,
-                               (const uint64_t *)c->d_key[cur], (const uint32_t *)c->d_val[cur],
-                               c->d_key[cur ^ 1], c->d_val[cur ^ 1], n, shift,
-                               (const int64_t *)c->d_off, clouds, (const uint32_t *)st,
-                               (const uint32_t *)c->d_hexcl, st_next, ntiles,
-                               (const int32_t *)c->d_flags);
-        }
-        cur ^= 1;
-        ++npass;
-    };
     const int key_passes = (3 * b + 7) / 8;
-    for (int ps = 0; ps < key_passes; ++ps) pass(false, 8 * ps);
+    int cloud_passes = 0;
     if (clouds > 1) {
         int cbits = 0;
         while ((1 << cbits) < clouds) ++cbits;
-        for (int ps = 0; ps < (cbits + 7) / 8; ++ps) pass(true, 8 * ps);
+        cloud_passes = (cbits + 7) / 8;
     }
+    hipLaunchKernelGGL(k_radix_counts, dim3(std::max(1, std::min(ntiles, c->num_cu))),
+                       dim3(kSortThreads), 0, s, (const uint64_t *)c->d_key[0], n, key_passes,
+                       cloud_passes, (const int64_t *)c->d_off, clouds, c->d_ghist,
+                       (const int32_t *)c->d_flags);
+    int cur = 0, npass = 0;
+    uint32_t *status[2] = {c->d_hist, c->d_histscan};
+    auto pass = [&](bool cloud_pass, int shift) {
+        uint32_t *st = status[npass & 1], *st_next = status[(npass + 1) & 1];
+        uint32_t *ticket = c->d_sortctl + npass;
+        const uint32_t *gh = c->d_ghist + 256 * npass;
+        if (cloud_pass)
+            hipLaunchKernelGGL(k_radix_pass<true>, dim3(ntiles), dim3(kSortThreads), 0, s,
+                               (const uint64_t *)c->d_key[cur], (const uint32_t *)c->d_val[cur],
+                               c->d_key[cur ^ 1], c->d_val[cur ^ 1], n, shift,
+                               (const int64_t *)c->d_off, clouds, gh, st, st_next, ticket,
+                               c->d_flags);
+        else
+            hipLaunchKernelGGL(k_radix_pass<false>, dim3(ntiles), dim3(kSortThreads), 0, s,
+                               (const uint64_t *)c->d_key[cur], (const uint32_t *)c->d_val[cur],
+                               c->d_key[cur ^ 1], c->d_val[cur ^ 1], n, shift,
+                               (const int64_t *)c->d_off, clouds, gh, st, st_next, ticket,
+                               c->d_flags);
+        cur ^= 1;
+        ++npass;
+    };
+    for (int ps = 0; ps < key_passes; ++ps) pass(false, 8 * ps);
+    for (int ps = 0; ps < cloud_passes; ++ps) pass(true, 8 * ps);
     c->d_skey = c->d_key[cur];
     c->d_perm = c->d_val[cur];
     // gather
@@ -1159,14 +1165,16 @@ void launch_build(Ctx *c, const double *x, const double *q, const int64_t *offse
     // 4. levels and node numbering
     hipLaunchKernelGGL(k_levels, grid_for(n + 1, kLvlTile), dim3(kLvlTile), 0, s,
                        (const uint64_t *)c->d_skey, n, (const int64_t *)c->d_off, clouds, b, cap,
-                       c->d_L, c->d_leaf, c->d_cnt, c->d_lend, (const int32_t *)c->d_flags);
+                       c->d_L, c->d_leaf, c->d_cnt, c->d_lend, c->d_lvlmax,
+                       (const int32_t *)c->d_flags);
     scan_excl((const int32_t *)c->d_cnt, c->d_noff, n + 1, c->d_scanblk, s);
     // 5. nodes
     hipLaunchKernelGGL(k_nodes, grid_for(n, 256), dim3(256), 0, s, (const uint64_t *)c->d_skey, n,
                        (const int64_t *)c->d_off, clouds, (const double4 *)c->d_cube, b,
                        (const int8_t *)c->d_L, (const int8_t *)c->d_leaf,
                        (const int32_t *)c->d_noff, c->node_cap, c->d_ngeo, c->d_ninfo, c->d_npar,
-                       c->d_nlev, c->d_ctr, c->d_flags);
+                       c->d_nlev, (const int32_t *)c->d_lvlmax,
+                       (int)((n + 1 + kLvlTile - 1) / kLvlTile), c->d_ctr, c->d_flags);
     // 6. moments: every leaf, then the internal levels from the deepest up
     hipLaunchKernelGGL(k_leaf_moments, grid_for(n, kLeafThreads), dim3(kLeafThreads), 0, s,
                        (const double4 *)c->d_xq, n, (const int8_t *)c->d_L,

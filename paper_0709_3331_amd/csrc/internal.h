@@ -21,6 +21,7 @@ constexpr int kSortThreads = 1024;  // 16 waves per sort block
 constexpr int kSortItems = 2;       // rounds of kSortThreads elements per tile
 constexpr int kSortTile = kSortThreads * kSortItems;
 constexpr int kSortTickets = 32;
+constexpr int kSortPassesMax = 12;   // 8 key passes (63-bit keys) + up to 4 cloud passes
 constexpr int kScanSmallItems = 64;            // elements per thread, one-block scan
 // one block streams at most a few KB efficiently; longer arrays take the
 // three-kernel scan
@@ -80,11 +81,11 @@ struct Ctx {
     uint64_t *d_key[2] = {nullptr, nullptr};
     uint32_t *d_val[2] = {nullptr, nullptr};
     // radix sort: per-(tile, digit) status words of the decoupled look-back
-    // (two arrays, alternating by pass), each tile's exclusive digit prefixes,
-    // and one ticket counter per pass
+    // (two arrays, alternating by pass), the digit counts of every pass, and
+    // one ticket counter per pass
     uint32_t *d_hist = nullptr;             // [256 * tiles] status, even passes
     uint32_t *d_histscan = nullptr;         // [256 * tiles] status, odd passes
-    uint32_t *d_hexcl = nullptr;            // [256 * tiles]
+    uint32_t *d_ghist = nullptr;            // [kSortPassesMax * 256]
     uint32_t *d_sortctl = nullptr;          // [kSortTickets]
     uint64_t *d_skey = nullptr;             // sorted keys (points into d_key[])
     uint32_t *d_perm = nullptr;             // sorted position -> caller index
@@ -95,6 +96,7 @@ struct Ctx {
     int8_t *d_leaf = nullptr;               // [n_max + 1] level of the leaf holding the position
     int32_t *d_cnt = nullptr;               // [n_max + 1] per-position counts to scan
     int32_t *d_lend = nullptr;              // [n_max + 1] end of the leaf starting there (-1: scan)
+    int32_t *d_lvlmax = nullptr;            // [n_max / 256 + 2] deepest leaf level per level-pass block
     int32_t *d_noff = nullptr;              // [n_max + 1] first node starting at the position
     int32_t *d_goff = nullptr;              // [n_max + 1] first group starting at the position
     int32_t *d_gnode = nullptr;             // [n_max]
