@@ -189,6 +189,74 @@ def bench_adjoint(prec, dev):
     return out
 
 
+def opening_study(dev, dt=1e-6):
+    """Opening-parameter study after Sec. 5.2 (Fig. 9): a cloud of 5e4 ions and
+    5e4 electrons (sigma = 1, T_e = 1e-3, T_i = 1e-5, eps = 0.01) advanced
+    1000 Verlet steps at each theta, its total energy E(t) = K + U (U from the
+    tree potential at that theta) compared every 50 steps with the all-pairs
+    run (theta = 0: no box is ever accepted) in FP64, and the cost of the
+    steps set against theta = 0.1.  The default dt = 1e-6 is the resolved
+    control: omega dt = 0.043 for an electron bound in a softened ion well
+    (omega^2 = 1836 / eps^3), so the integrator's own energy error stays
+    below the tree's; at dt = 1e-5 (omega dt = 0.43) the all-pairs run
+    itself drifts by ~4% in 1000 steps."""
+    import torch
+
+    from paper_0709_3331_amd import _lib as L
+    from paper_0709_3331_amd import inputs
+    from paper_0709_3331_amd.tree import TreeSolver
+
+    cl = inputs.gaussian_cloud(100000, 1.0, 1e-3, 1e-5, 0)
+    eps, dt, steps, every = 0.01, dt, 1000, 50
+    q = torch.from_numpy(cl.q).to(dev)
+    m = torch.from_numpy(cl.m).to(dev)
+
+    def run(theta, prec):
+        ts = TreeSolver(cl.n, theta=theta, eps=eps, precision=prec)
+        x = torch.from_numpy(cl.x).to(dev)
+        v = torch.from_numpy(cl.v).to(dev)
+        f = ts.tree_forces(x, q)
+        st = ts.stats()
+        ipp = (st["p2p"] + st["m2p"]) / cl.n
+        e0 = ts.energy(x, v, q, m).cpu().tolist()
+        energies = [e0[2]]
+        step_s = 0.0
+        for _ in range(steps // every):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ts.step(x, v, f, q, m, dt, every)
+            torch.cuda.synchronize()
+            step_s += time.perf_counter() - t0
+            energies.append(ts.energy(x, v, q, m)[2].item())
+        ts.stats()
+        ts.close()
+        print(f"opening study: theta={theta:g} done, {1e3 * step_s / steps:.3f} ms/step",
+              file=sys.stderr, flush=True)
+        return energies, step_s / steps, ipp, e0
+
+    e_ref, t_ref, _, c_ref = run(0.0, L.UCP_FP64)
+    out = {"study": "opening parameter (Sec. 5.2, Fig. 9)", "n": cl.n, "eps": eps, "dt": dt,
+           "steps": steps, "energy_every": every, "precision": "split",
+           "reference": {"theta": 0.0, "precision": "fp64", "ms_per_step": 1e3 * t_ref,
+                         "K_U_E_at_t0": c_ref[:3],
+                         "energy_drift_max": _finite(max(abs(e - e_ref[0]) for e in e_ref)
+                                                     / abs(e_ref[0]))},
+           "theta": {}}
+    base = None
+    for th in (0.1, 0.2, 0.3, 0.4, 0.5, 0.6, 0.7):
+        e, t, ipp, _ = run(th, L.UCP_SPLIT)
+        err = [abs(a - b) / abs(b) for a, b in zip(e, e_ref)]
+        base = base or t
+        out["theta"][f"{th:g}"] = {
+            "ms_per_step": 1e3 * t, "cost_vs_theta_0.1": t / base,
+            "interactions_per_particle": ipp,
+            "energy_err_vs_all_pairs_t0_pct": _finite(100 * err[0]),
+            "energy_err_vs_all_pairs_max_pct": _finite(100 * max(err)),
+            "energy_err_vs_all_pairs_final_pct": _finite(100 * err[-1]),
+            "energy_drift_max_pct": _finite(100 * max(abs(a - e[0]) for a in e) / abs(e[0]))}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -213,6 +281,9 @@ def main():
     ap.add_argument("--profile", action="store_true", help="short run for rocprofv3 (no extras)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 256 MiB device-to-device copy (counter calibration)")
+    ap.add_argument("--study", choices=["opening"],
+                    help="run a study instead of the benchmark and print its JSON line")
+    ap.add_argument("--study-dt", type=float, default=1e-6, help="time step of the study")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the method is not "
@@ -228,6 +299,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     dev = torch.device("cuda:0")
+    if args.study == "opening":
+        print(json.dumps(opening_study(dev, args.study_dt)), flush=True)
+        return
     cl, prm = inputs.metric(0)
     n = cl.n
     theta, eps, dt = args.theta, prm["eps"], prm["dt"]
