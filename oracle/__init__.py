@@ -39,6 +39,8 @@ def _load():
         "orc_max_threads": (i32, []),
         "orc_set_threads": (None, [i32]),
         "orc_direct": (None, [i64, _dp, _dp, dbl, _dp, vp]),
+        "orc_direct_pair": (i32, [i64, _dp, _dp, dbl, i32, dbl, _dp, vp]),
+        "orc_tree_set_pair": (i32, [vp, i32, dbl]),
         "orc_direct_targets": (None, [i64, _dp, _dp, dbl, i64, _i64p, _dp, vp]),
         "orc_direct_vjp": (None, [i64, _dp, _dp, dbl, _dp, _dp]),
         "orc_cube": (i32, [i64, _dp, _dp, C.POINTER(C.c_int)]),
@@ -106,6 +108,23 @@ def direct(x, q, eps):
     return f, phi
 
 
+PAIR_PLUMMER, PAIR_KELBG = 0, 1
+
+
+def direct_pair(x, q, eps, pair_law=PAIR_PLUMMER, lambda_ei=0.0):
+    """Direct-sum F and phi under a pair law (Sec. 2.1): PAIR_PLUMMER applies the
+    softened Coulomb law to every pair; PAIR_KELBG applies the modified law of
+    Eq. (3) with length lambda_ei to electron-ion pairs and the softened
+    Coulomb law (eps = 0: bare) to like pairs."""
+    x = _f64(x, (-1, 3)); q = _f64(q)
+    n = x.shape[0]
+    f = np.zeros((n, 3)); phi = np.zeros(n)
+    if _load().orc_direct_pair(n, x, q, float(eps), int(pair_law), float(lambda_ei), f,
+                               _ptr(phi)) != 0:
+        raise ValueError("oracle direct_pair: invalid pair law")
+    return f, phi
+
+
 def direct_targets(x, q, eps, targets):
     """Direct-sum F and phi for the particles listed in ``targets`` only."""
     x = _f64(x, (-1, 3)); q = _f64(q)
@@ -159,7 +178,8 @@ class Tree:
     group_mode 0: node groups (a node of at most G particles whose parent holds
     more); group_mode 1: consecutive runs of G key-sorted particles."""
 
-    def __init__(self, x, q, theta, eps, b=21, leaf_cap=24, G=64, keep_lists=False, group_mode=1):
+    def __init__(self, x, q, theta, eps, b=21, leaf_cap=24, G=64, keep_lists=False, group_mode=1,
+                 pair_law=PAIR_PLUMMER, lambda_ei=0.0):
         lib = _load()
         self.x = _f64(x, (-1, 3)); self.q = _f64(q)
         self.n = self.x.shape[0]
@@ -171,6 +191,9 @@ class Tree:
             raise ValueError("oracle tree: invalid parameters or non-finite input")
         self._h = h
         self.keep_lists = keep_lists
+        self.pair_law, self.lambda_ei = pair_law, lambda_ei
+        if lib.orc_tree_set_pair(h, int(pair_law), float(lambda_ei)) != 0:
+            raise ValueError("oracle tree: invalid pair law")
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -264,7 +287,7 @@ class Tree:
         u = _f64(u, (-1, 3))
         xb = np.zeros_like(x)
         if _lib.orc_tree_vjp(self._h, x, self.q, u, xb) != 0:
-            raise ValueError("tree vjp needs keep_lists=True")
+            raise ValueError("tree vjp needs keep_lists=True and the Plummer pair law")
         return xb
 
     def lists(self, g):
@@ -309,9 +332,11 @@ def rebuild(series, cap):
     return par[:m], nch[:m]
 
 
-def tree_forces(x, q, theta, eps, b=21, leaf_cap=24, G=64, want_phi=True, group_mode=1):
+def tree_forces(x, q, theta, eps, b=21, leaf_cap=24, G=64, want_phi=True, group_mode=1,
+                pair_law=PAIR_PLUMMER, lambda_ei=0.0):
     """Convenience: build the oracle tree and evaluate it."""
-    t = Tree(x, q, theta, eps, b, leaf_cap, G, group_mode=group_mode)
+    t = Tree(x, q, theta, eps, b, leaf_cap, G, group_mode=group_mode, pair_law=pair_law,
+             lambda_ei=lambda_ei)
     r = t.eval(want_phi=want_phi)
     r["nodes"] = t.nnodes
     r["groups"] = t.ngroups

@@ -51,28 +51,82 @@ static inline void nadd(nsum *a, double v)
 static inline double nval(nsum a) { return a.s + a.c; }
 
 /* ------------------------------------------------------------------------- */
+/* Pair laws (Sec. 2.1).  ORC_PAIR_PLUMMER: every pair interacts through the  */
+/* softened Coulomb potential q_i q_j / h, h^2 = r^2 + eps^2.                */
+/* ORC_PAIR_KELBG: an electron-ion pair (q_i q_j < 0) through the modified   */
+/* potential of Eq. (3), V = q_i q_j (1 - exp(-r/lambda)) / r; like pairs     */
+/* through the softened Coulomb potential (eps = 0: bare, as in Sec. 2.1).   */
+/* pair_factors gives the field factor a and the potential factor b of the   */
+/* pair, E_i += q_j a (x_i - x_j) and phi_i += q_j b.  For the Kelbg pair,    */
+/* -dV/dr gives a = (1 - e^{-u}(1 + u)) / r^3 and b = (1 - e^{-u}) / r with   */
+/* u = r / lambda.  Both brackets cancel to O(u^2) and O(u) as u -> 0, so    */
+/* below u = 1/4 they are taken from their Taylor series,                    */
+/*   1 - e^{-u}(1+u) = sum_{m>=2} (-1)^m (m-1) u^m / m!,                      */
+/*   1 - e^{-u}      = sum_{m>=1} (-1)^(m+1) u^m / m!,                        */
+/* summed to m = 18 (the next term is below 1e-16 of the sum).  At r = 0 the  */
+/* electron-ion pair exerts no force (a r = 0 by symmetry) and b = 1/lambda. */
+/* ------------------------------------------------------------------------- */
+enum { ORC_PAIR_PLUMMER = 0, ORC_PAIR_KELBG = 1 };
+typedef struct { int law; double eps2, lambda; } orc_pair;
+
+static void kelbg_brackets(double u, double *g, double *p)
+{
+    if (u < 0.25) {
+        double term = u, sg = 0.0, sp = 0.0;   /* term = u^m / m! */
+        for (int m = 1; m <= 18; ++m) {
+            const double sgn = (m % 2) ? 1.0 : -1.0;   /* (-1)^(m+1) */
+            sp += sgn * term;
+            if (m >= 2) sg += -sgn * (double)(m - 1) * term;
+            term *= u / (double)(m + 1);
+        }
+        *g = sg;
+        *p = sp;
+    } else {
+        const double e = exp(-u);
+        *g = 1.0 - e * (1.0 + u);
+        *p = 1.0 - e;
+    }
+}
+
+static void pair_factors(const orc_pair *pl, double qi, double qj, double r2, double *a, double *b)
+{
+    if (pl->law == ORC_PAIR_KELBG && qi * qj < 0.0) {
+        if (r2 == 0.0) { *a = 0.0; *b = 1.0 / pl->lambda; return; }
+        const double r = sqrt(r2);
+        double g, p;
+        kelbg_brackets(r / pl->lambda, &g, &p);
+        *a = g / (r2 * r);
+        *b = p / r;
+        return;
+    }
+    const double h2 = r2 + pl->eps2;
+    const double h = sqrt(h2);
+    *a = 1.0 / (h2 * h);
+    *b = 1.0 / h;
+}
+
+/* ------------------------------------------------------------------------- */
 /* C-1  Direct sum.  Eq. (1)-(2) with e^2/(4 pi eps0) = 1 and softening:     */
 /*   F_i   = q_i sum_{j!=i} q_j (x_i - x_j) / (|x_i - x_j|^2 + eps^2)^{3/2}  */
 /*   phi_i =     sum_{j!=i} q_j / (|x_i - x_j|^2 + eps^2)^{1/2}              */
 /* x is [n][3] row-major; f is [n][3]; phi may be NULL.                      */
 /* ------------------------------------------------------------------------- */
-static void direct_one(int64_t n, const double *x, const double *q, double eps,
+static void direct_one(int64_t n, const double *x, const double *q, const orc_pair *pl,
                        int64_t i, double *fi, double *phii)
 {
     nsum ex = {0, 0}, ey = {0, 0}, ez = {0, 0}, ph = {0, 0};
-    const double eps2 = eps * eps;
     for (int64_t j = 0; j < n; ++j) {
         if (j == i) continue;
         double rx = x[3 * i + 0] - x[3 * j + 0];
         double ry = x[3 * i + 1] - x[3 * j + 1];
         double rz = x[3 * i + 2] - x[3 * j + 2];
-        double h2 = rx * rx + ry * ry + rz * rz + eps2;
-        double h = sqrt(h2);
-        double w = q[j] / (h2 * h);
+        double a, b;
+        pair_factors(pl, q[i], q[j], rx * rx + ry * ry + rz * rz, &a, &b);
+        double w = q[j] * a;
         nadd(&ex, w * rx);
         nadd(&ey, w * ry);
         nadd(&ez, w * rz);
-        nadd(&ph, q[j] / h);
+        nadd(&ph, q[j] * b);
     }
     fi[0] = q[i] * nval(ex);
     fi[1] = q[i] * nval(ey);
@@ -83,18 +137,34 @@ static void direct_one(int64_t n, const double *x, const double *q, double eps,
 void orc_direct(int64_t n, const double *x, const double *q, double eps,
                 double *f, double *phi)
 {
+    const orc_pair pl = {ORC_PAIR_PLUMMER, eps * eps, 0.0};
 #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t i = 0; i < n; ++i)
-        direct_one(n, x, q, eps, i, f + 3 * i, phi ? phi + i : NULL);
+        direct_one(n, x, q, &pl, i, f + 3 * i, phi ? phi + i : NULL);
+}
+
+/* Direct sum under a given pair law (law: ORC_PAIR_*; lambda > 0 for Kelbg). */
+int orc_direct_pair(int64_t n, const double *x, const double *q, double eps, int law,
+                    double lambda, double *f, double *phi)
+{
+    if ((law != ORC_PAIR_PLUMMER && law != ORC_PAIR_KELBG) ||
+        (law == ORC_PAIR_KELBG && !(lambda > 0.0)))
+        return -1;
+    const orc_pair pl = {law, eps * eps, lambda};
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n; ++i)
+        direct_one(n, x, q, &pl, i, f + 3 * i, phi ? phi + i : NULL);
+    return 0;
 }
 
 /* Direct sum for a subset of targets (all n particles are sources).          */
 void orc_direct_targets(int64_t n, const double *x, const double *q, double eps,
                         int64_t nt, const int64_t *targets, double *f, double *phi)
 {
+    const orc_pair pl = {ORC_PAIR_PLUMMER, eps * eps, 0.0};
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t t = 0; t < nt; ++t)
-        direct_one(n, x, q, eps, targets[t], f + 3 * t, phi ? phi + t : NULL);
+        direct_one(n, x, q, &pl, targets[t], f + 3 * t, phi ? phi + t : NULL);
 }
 
 /* Direct-sum vector-Jacobian product of the force map F(x):                 */
@@ -243,6 +313,8 @@ void orc_sort(int64_t n, const uint64_t *key, int64_t *perm)
 struct orc_tree {
     int64_t n;
     double theta, eps;
+    int pair_law;          /* ORC_PAIR_*: the near-field (P2P) pair law           */
+    double lambda;         /* Kelbg length (ORC_PAIR_KELBG)                       */
     int b, leaf_cap, G;
     double lo[3];
     int e;
@@ -557,6 +629,18 @@ void orc_tree_free(orc_tree *t)
 
 int64_t orc_tree_nnodes(const orc_tree *t) { return t->M; }
 int64_t orc_tree_ngroups(const orc_tree *t) { return t->ng; }
+/* Near-field pair law of the tree's P2P terms (ORC_PAIR_*; lambda > 0 for  */
+/* Kelbg); the far field is the softened expansion either way.              */
+int orc_tree_set_pair(orc_tree *t, int law, double lambda)
+{
+    if ((law != ORC_PAIR_PLUMMER && law != ORC_PAIR_KELBG) ||
+        (law == ORC_PAIR_KELBG && !(lambda > 0.0)))
+        return -1;
+    t->pair_law = law;
+    t->lambda = lambda;
+    return 0;
+}
+
 void orc_tree_cube(const orc_tree *t, double *lo, int *e)
 {
     for (int d = 0; d < 3; ++d) lo[d] = t->lo[d];
@@ -609,8 +693,8 @@ void orc_tree_moments(const orc_tree *t, const double *x, const double *q, doubl
 /* Forces and potentials of the members of group g (C-2.8), written in the   */
 /* caller's order; returns the group's list lengths (cells, P2P sources).    */
 static void eval_group(const orc_tree *t, const double *xs, const double *qs, const double *mom,
-                       double eps2, int64_t g, ivec *M, ivec *P, double *f, double *phi,
-                       int64_t *mn_out, int64_t *nsrc_out)
+                       double eps2, const orc_pair *pl, int64_t g, ivec *M, ivec *P, double *f,
+                       double *phi, int64_t *mn_out, int64_t *nsrc_out)
 {
     const int64_t *mv, *pv;
     int64_t mn, pn;
@@ -643,11 +727,12 @@ static void eval_group(const orc_tree *t, const double *xs, const double *qs, co
             int64_t k = pv[m];
             for (int64_t j = t->first[k]; j < t->first[k] + t->count[k]; ++j) {
                 double r[3] = {xi[0] - xs[3 * j], xi[1] - xs[3 * j + 1], xi[2] - xs[3 * j + 2]};
-                double h2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2] + eps2;
-                double h = sqrt(h2);
-                double w = qs[j] / (h2 * h);
+                if (j == i) continue;   /* the self pair: r = 0, no field, no potential */
+                double a, b;
+                pair_factors(pl, qs[i], qs[j], r[0] * r[0] + r[1] * r[1] + r[2] * r[2], &a, &b);
+                double w = qs[j] * a;
                 for (int d = 0; d < 3; ++d) nadd(&E[d], w * r[d]);
-                if (j != i) nadd(&ph, qs[j] / h);
+                nadd(&ph, qs[j] * b);
             }
         }
         int64_t ci = t->perm[i];
@@ -674,6 +759,7 @@ static void eval_groups(const orc_tree *t, const double *x, const double *q, int
 #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t k = 0; k < t->M; ++k) node_moments(t, k, xs, qs, t->centre + 3 * k, mom + 10 * k);
     const double eps2 = t->eps * t->eps;
+    const orc_pair pl = {t->pair_law, eps2, t->lambda};
     int64_t sp2p = 0, sm2p = 0;
 #pragma omp parallel reduction(+ : sp2p, sm2p)
     {
@@ -682,7 +768,7 @@ static void eval_groups(const orc_tree *t, const double *x, const double *q, int
         for (int64_t e = 0; e < ngs; ++e) {
             const int64_t g = gsel ? gsel[e] : e;
             int64_t mn, nsrc;
-            eval_group(t, xs, qs, mom, eps2, g, &M, &P, f, phi, &mn, &nsrc);
+            eval_group(t, xs, qs, mom, eps2, &pl, g, &M, &P, f, phi, &mn, &nsrc);
             if (gm2p) gm2p[e] = mn;
             if (gp2p) gp2p[e] = nsrc;
             sp2p += nsrc * t->gcount[g];
@@ -756,7 +842,7 @@ int orc_tree_vjp(const orc_tree *t, const double *x, const double *q, const doub
 {
     int64_t n = t->n;
     if (n == 0) return 0;
-    if (!t->keep_lists) return -1;
+    if (!t->keep_lists || t->pair_law != ORC_PAIR_PLUMMER) return -1;
     double *xs = (double *)malloc((size_t)n * 3 * sizeof(double));
     double *qs = (double *)malloc((size_t)n * sizeof(double));
     double *us = (double *)malloc((size_t)n * 3 * sizeof(double));
