@@ -189,6 +189,49 @@ def bench_adjoint(prec, dev):
     return out
 
 
+def bench_kelbg(args, prec, x, q, cl, plummer_walk_ms):
+    """The same cloud and opening parameter under the Kelbg pair law of
+    Eq. (3): electron-ion pairs through q q (1 - exp(-r/lambda)) / r with
+    lambda = 0.005 (the length the Plummer runs use for eps), like pairs bare
+    Coulomb (eps = 0) as in Sec. 2.1.  Walk time, interactions/s, the cost
+    against the Plummer walk, and the force difference from the FP64 oracle
+    tree on every 97th walk group."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_0709_3331_amd import _lib as L
+    from paper_0709_3331_amd.tree import TreeSolver
+
+    lam = 0.005
+    gm = L.UCP_GROUP_CHUNK if args.group_mode == "chunk" else L.UCP_GROUP_NODE
+    ts = TreeSolver(cl.n, theta=args.theta, eps=0.0, precision=prec, group_size=args.group_size,
+                    list_len=args.list_len, group_mode=gm, leaf_cap=args.leaf_cap,
+                    walk_waves=args.walk_waves, pair_law=L.UCP_PAIR_KELBG, lambda_ei=lam)
+    f = ts.tree_forces(x, q)
+    ts.timing(True)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        ts.tree_forces(x, q)
+    torch.cuda.synchronize()
+    wm, wc = ts.timing_read()
+    st = ts.stats()
+    ts.close()
+    walk = wm / max(wc, 1)
+    xs = x.cpu().numpy()   # the positions after the timed steps
+    t = oracle.Tree(xs, cl.q, args.theta, 0.0, G=args.group_size, group_mode=gm,
+                    leaf_cap=args.leaf_cap, pair_law=oracle.PAIR_KELBG, lambda_ei=lam)
+    ref = t.eval_groups(np.arange(0, t.ngroups, 97))["f"]
+    mask = ~np.isnan(ref[:, 0])
+    fa = f.cpu().numpy()
+    return {"lambda_ei": lam, "eps_like_pairs": 0.0, "walk_ms": walk,
+            "interactions_per_s": (st["p2p"] + st["m2p"]) / (walk * 1e-3),
+            "walk_cost_vs_plummer": walk / plummer_walk_ms,
+            "rel_force_err_vs_oracle_tree_sampled": float(
+                np.linalg.norm(fa[mask] - ref[mask]) / np.linalg.norm(ref[mask])),
+            "sampled_particles": int(mask.sum())}
+
+
 def opening_study(dev, dt=1e-6):
     """Opening-parameter study after Sec. 5.2 (Fig. 9): a cloud of 5e4 ions and
     5e4 electrons (sigma = 1, T_e = 1e-3, T_i = 1e-5, eps = 0.01) advanced
@@ -276,6 +319,8 @@ def main():
     ap.add_argument("--no-ensemble", action="store_true",
                     help="skip the batched 64-cloud ensemble measurement")
     ap.add_argument("--ensemble-steps", type=int, default=10)
+    ap.add_argument("--no-kelbg", action="store_true",
+                    help="skip the Kelbg pair-law measurement")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the differentiable 200-step rollout measurement")
     ap.add_argument("--profile", action="store_true", help="short run for rocprofv3 (no extras)")
@@ -433,6 +478,8 @@ def main():
             "kind": "oracle",
             "sample": "one full FP64 oracle tree-force evaluation (build + walk, OpenMP over "
                       "groups) of the same N=524288 cloud at the same parameters; %.2f s" % (c1 - c0)}
+    if not args.profile and not args.no_kelbg:
+        result["kelbg"] = bench_kelbg(args, prec, x, q, cl, walk_avg_ms)
     if not args.profile and not args.no_ensemble:
         result["ensemble"] = bench_ensemble(args, prec, dev)
     if not args.profile and not args.no_adjoint:

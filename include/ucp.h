@@ -62,6 +62,20 @@ typedef enum {
                               cloud; the last run of a cloud holds the remainder     */
 } ucp_group_mode;
 
+/* Pair law of the particle-particle (near-field) terms, Sec. 2.1.
+ * UCP_PAIR_PLUMMER: every pair through q_i q_j / h, h^2 = r^2 + eps^2.
+ * UCP_PAIR_KELBG: an electron-ion pair (q_i q_j < 0) through the modified
+ *   potential of Eq. (3), q_i q_j (1 - exp(-r/lambda_ei)) / r, whose force is
+ *   q_i q_j (1 - exp(-u)(1 + u)) r_ij / r^3 with u = r/lambda_ei (no force and
+ *   potential q_i q_j / lambda_ei at r = 0); like pairs through the softened
+ *   Coulomb law with eps (eps = 0: the bare law of Sec. 2.1).  The far field
+ *   (accepted boxes) keeps the expansion of the softened kernel, which for
+ *   boxes far beyond lambda_ei is the Coulomb far field.                     */
+typedef enum {
+    UCP_PAIR_PLUMMER = 0,
+    UCP_PAIR_KELBG = 1
+} ucp_pair_law;
+
 /* Method parameters.  The opening test is Eq. (5), s/theta + delta < d, with
  * the pseudo-particle expanded about the box centre (delta = 0), s the box
  * side and d the distance from the target to the box centre; it is evaluated
@@ -69,7 +83,8 @@ typedef enum {
  * its members fails the test.                                                */
 typedef struct {
     double theta;          /* opening parameter, 0 <= theta < 2/sqrt(3); 0 => direct sum */
-    double eps;            /* Plummer softening, > 0                                      */
+    double eps;            /* Plummer softening, > 0 (>= 0 under UCP_PAIR_KELBG, where it
+                              softens the like pairs and the far-field expansion only)   */
     int32_t key_bits;      /* 30 or 63 (key depth b = 10 or 21 levels)                   */
     int32_t leaf_cap;      /* a box holding more particles is split (Sec. 3 uses 1); 1..64 */
     int32_t group_size;    /* G: largest walk group, 1..64; see group_mode            */
@@ -79,6 +94,8 @@ typedef struct {
     int32_t walk_waves;    /* resident waves per CU for the persistent walk, 0 = auto    */
     int32_t group_mode;    /* ucp_group_mode: how the sorted particles are cut into
                               walk groups                                                */
+    int32_t pair_law;      /* ucp_pair_law: the pair law of the particle-particle terms  */
+    double lambda_ei;      /* Kelbg length lambda_ei of Eq. (4), > 0 (UCP_PAIR_KELBG)     */
 } ucp_params;
 
 typedef struct ucp_ctx ucp_ctx;   /* opaque */
@@ -103,7 +120,8 @@ typedef struct {
 #define UCP_FLAG_WALK_STACK     32   /* a walk group overflowed its traversal stack     */
 
 /* Default parameters: theta 0.5, eps 0.005, 63-bit keys, leaf_cap 24, G 64,
- * list_len 128, UCP_SPLIT, walk_waves 0, UCP_GROUP_CHUNK.                    */
+ * list_len 128, UCP_SPLIT, walk_waves 0, UCP_GROUP_CHUNK, UCP_PAIR_PLUMMER,
+ * lambda_ei 0.                                                              */
 void ucp_default_params(ucp_params *p);
 
 /* Create a context on the current HIP device able to hold n_max particles in
@@ -179,8 +197,9 @@ ucp_status ucp_energy(ucp_ctx *c, const double *x, const double *v, const double
  * box or particle are added with FP64 atomics, so xbar is reproducible to
  * rounding, not bitwise.  The first call allocates the adjoint scratch
  * (48 bytes per particle, 80 per node slot).
- * Errors: UCP_EINVAL (NULL argument), UCP_ENOTBUILT, UCP_ENOMEM, UCP_EHIP;
- * device flags as for ucp_compute_forces.                                   */
+ * Errors: UCP_EINVAL (NULL argument, or a pair law other than
+ * UCP_PAIR_PLUMMER: only that law has an adjoint), UCP_ENOTBUILT, UCP_ENOMEM,
+ * UCP_EHIP; device flags as for ucp_compute_forces.                         */
 ucp_status ucp_force_vjp(ucp_ctx *c, const double *u, double *xbar, void *stream);
 
 /* Synchronise `stream`, read the device counters and flags.  Returns

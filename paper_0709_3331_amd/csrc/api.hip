@@ -36,7 +36,23 @@ bool validate(const ucp_params *p, std::string &why)
         why = "theta must satisfy 0 <= theta < 2/sqrt(3)";
         return false;
     }
-    if (!(p->eps > 0.0) || !(p->eps < 1e30)) { why = "eps must be > 0 and finite"; return false; }
+    if (p->pair_law != UCP_PAIR_PLUMMER && p->pair_law != UCP_PAIR_KELBG) {
+        why = "pair_law must be UCP_PAIR_PLUMMER or UCP_PAIR_KELBG";
+        return false;
+    }
+    if (p->pair_law == UCP_PAIR_KELBG) {
+        if (!(p->lambda_ei > 0.0) || !(p->lambda_ei < 1e30)) {
+            why = "lambda_ei must be > 0 and finite under UCP_PAIR_KELBG";
+            return false;
+        }
+        if (!(p->eps >= 0.0) || !(p->eps < 1e30)) {
+            why = "eps must be >= 0 and finite under UCP_PAIR_KELBG";
+            return false;
+        }
+    } else if (!(p->eps > 0.0) || !(p->eps < 1e30)) {
+        why = "eps must be > 0 and finite";
+        return false;
+    }
     if (p->key_bits != 30 && p->key_bits != 63) { why = "key_bits must be 30 or 63"; return false; }
     if (p->leaf_cap < 1 || p->leaf_cap > ucp::kMaxLeafCap) { why = "leaf_cap must be in 1..64"; return false; }
     if (p->group_size < 1 || p->group_size > ucp::kMaxGroup) { why = "group_size must be in 1..64"; return false; }
@@ -113,8 +129,9 @@ ucp_status run_steps(Ctx *c, double *x, double *v, double *f, const double *q, c
     }
     uint64_t dtb;
     memcpy(&dtb, &dt, sizeof dtb);
-    uint64_t pb[6];
-    memcpy(pb, &c->p, sizeof pb < sizeof c->p ? sizeof pb : sizeof c->p);
+    // every parameter byte is part of the key
+    uint64_t pb[(sizeof(ucp_params) + 7) / 8] = {};
+    memcpy(pb, &c->p, sizeof c->p);
     std::vector<uintptr_t> key = {(uintptr_t)x, (uintptr_t)v, (uintptr_t)f, (uintptr_t)q,
                                   (uintptr_t)m, (uintptr_t)offsets, (uintptr_t)clouds,
                                   (uintptr_t)n, (uintptr_t)dtb};
@@ -161,6 +178,8 @@ void ucp_default_params(ucp_params *p)
     p->precision = UCP_SPLIT;
     p->walk_waves = 0;
     p->group_mode = UCP_GROUP_CHUNK;
+    p->pair_law = UCP_PAIR_PLUMMER;
+    p->lambda_ei = 0.0;
 }
 
 const char *ucp_last_error(const ucp_ctx *c)
@@ -268,6 +287,8 @@ ucp_status ucp_set_params(ucp_ctx *c, const ucp_params *p)
         c->p_built.list_len = p->list_len;
         c->p_built.precision = p->precision;
         c->p_built.walk_waves = p->walk_waves;
+        c->p_built.pair_law = p->pair_law;
+        c->p_built.lambda_ei = p->lambda_ei;
     }
     drop_graph(c);
     return UCP_OK;
@@ -374,6 +395,8 @@ ucp_status ucp_force_vjp(ucp_ctx *c, const double *u, double *xbar, void *stream
     if (!c->built) return fail(c, UCP_ENOTBUILT, "ucp_force_vjp: no tree has been built");
     if (c->n == 0) return UCP_OK;
     if (!u || !xbar) return fail(c, UCP_EINVAL, "ucp_force_vjp: NULL argument");
+    if (c->p_built.pair_law != UCP_PAIR_PLUMMER)
+        return fail(c, UCP_EINVAL, "ucp_force_vjp: only the Plummer pair law has an adjoint");
     if (!c->d_w) {
         // the adjoint buffers are allocated on first use
         hipError_t e = hipMalloc((void **)&c->d_w, (size_t)c->n_max * sizeof(double4) + 256);

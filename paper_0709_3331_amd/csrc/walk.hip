@@ -64,6 +64,8 @@ struct WalkArgs {
     double th2;
     double eps2;
     float eps2f;
+    double inv_lambda;      // 1 / lambda_ei under the Kelbg pair law
+    float inv_lambdaf;
     int L;
 };
 
@@ -292,6 +294,66 @@ __device__ __forceinline__ void p2p_one(float tx, float ty, float tz, const floa
     if (PHI) ph += notself ? v.w * ih : 0.f;
 }
 
+// Kelbg electron-ion pair (Eq. (3)), u = r / lambda: the force bracket
+// g = 1 - e^{-u}(1 + u) and the potential bracket p = 1 - e^{-u}.  Both vanish
+// with u (as u^2/2 and u) and the exponential forms cancel there, so below
+// u = 1/2 they are summed from their Taylor series in Horner form,
+//   g = u^2 sum_{m>=2} (-1)^m (m-1)/m! u^(m-2),  p = u sum_{m>=1} (-1)^(m-1) u^(m-1)/m!,
+// to the term below the type's rounding at u = 1/2 (FP32: m = 9 and 8; FP64:
+// m = 16 and 15); above, from the exponential.
+__host__ __device__ constexpr double inv_factorial(int m)
+{
+    double f = 1.0;
+    for (int i = 2; i <= m; ++i) f *= (double)i;
+    return 1.0 / f;
+}
+
+template <typename T>
+__device__ __forceinline__ void kelbg_brackets(T u, T &g, T &p)
+{
+    constexpr int MG = sizeof(T) == 4 ? 9 : 16, MP = sizeof(T) == 4 ? 8 : 15;
+    if (u < (T)0.5) {
+        T sg = (T)((MG - 1) * inv_factorial(MG));
+#pragma unroll
+        for (int m = MG - 1; m >= 2; --m) sg = (T)((m - 1) * inv_factorial(m)) - u * sg;
+        T sp = (T)inv_factorial(MP);
+#pragma unroll
+        for (int m = MP - 1; m >= 1; --m) sp = (T)inv_factorial(m) - u * sp;
+        g = u * u * sg;
+        p = u * sp;
+    } else {
+        T e;
+        if constexpr (sizeof(T) == 4) e = __expf(-u);
+        else e = exp(-u);
+        g = (T)1 - e * ((T)1 + u);
+        p = (T)1 - e;
+    }
+}
+
+// one particle pair under the Kelbg law: the electron-ion pair (q_s q_t < 0)
+// through the brackets above, a like pair through the softened Coulomb law
+// (eps2 may be 0).  A pair at r = 0 exerts no force; its potential is
+// q_s / lambda for an electron-ion pair and nothing for the self pair.
+template <typename T, bool PHI>
+__device__ __forceinline__ void p2p_kelbg(T rx, T ry, T rz, T sq, T qt, T eps2, T inv_lam,
+                                          bool notself, T &ex, T &ey, T &ez, T &ph)
+{
+    const T r2 = fma(rx, rx, fma(ry, ry, rz * rz));
+    const bool ei = sq * qt < (T)0;
+    const T h2 = ei ? r2 : r2 + eps2;
+    const bool live = h2 > (T)0;
+    T ih;
+    if constexpr (sizeof(T) == 4) ih = __builtin_amdgcn_rsqf(live ? h2 : (T)1);
+    else ih = 1.0 / sqrt(live ? h2 : (T)1);
+    T ga = (T)1, pa = (T)1;
+    if (ei) kelbg_brackets<T>(r2 * ih * inv_lam, ga, pa);
+    const T w = live ? sq * ga * (ih * ih * ih) : (T)0;
+    ex = fma(w, rx, ex);
+    ey = fma(w, ry, ey);
+    ez = fma(w, rz, ez);
+    if (PHI) ph += notself ? (live ? sq * pa * ih : (ei ? sq * inv_lam : (T)0)) : (T)0;
+}
+
 __device__ __forceinline__ float readlane_t(float v, int src)
 {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
@@ -351,6 +413,7 @@ __device__ __forceinline__ void load_adj_rec(const T *r, CellRec<T> &m, double &
 template <typename T>
 struct Target {
     T tx, ty, tz, wx, wy, wz;
+    T qt;                        // target charge (the Kelbg law depends on the pair's signs)
     double px, py, pz;           // FP64 position (adjoint P2P differences)
     int i;                       // sorted index of the lane's target
     double E0, E1, E2, PH;       // field and potential, or the target-side adjoint
@@ -362,7 +425,7 @@ struct Target {
 // staged entries gives each lane one entry, loops over the group's targets
 // (broadcast from their lanes) and adds the entry's source-side cotangent to
 // the global per-cell or per-particle arrays.
-template <int PREC, int MODE, typename T>
+template <int PREC, int MODE, bool KELBG, typename T>
 __device__ __forceinline__ void flush_lists(const WalkArgs &a, const int4 *ml, int nm,
                                             const int2 *pl, int np, T *stage, int *pfx,
                                             int *lfirst, int lane, int sub, int lpt, int c,
@@ -371,6 +434,7 @@ __device__ __forceinline__ void flush_lists(const WalkArgs &a, const int4 *ml, i
     constexpr bool PHI = MODE == kWalkForcePhi;
     constexpr bool ADJ = MODE == kWalkVjp;
     const T eps2 = PREC == UCP_SPLIT ? (T)a.eps2f : (T)a.eps2;
+    const T inv_lam = PREC == UCP_SPLIT ? (T)a.inv_lambdaf : (T)a.inv_lambda;
     const T tx = tg.tx, ty = tg.ty, tz = tg.tz;
     wave_sync();   // the lists were written by other lanes
     for (int base = 0; base < nm; base += 64) {
@@ -509,15 +573,20 @@ __device__ __forceinline__ void flush_lists(const WalkArgs &a, const int4 *ml, i
                     // source, in pairs with two partial sums
                     T fx = 0, fy = 0, fz = 0, fp = 0;
                     int e = 0;
+                    auto one = [&](const float4 &v, bool notself, float &sx, float &sy,
+                                   float &sz, float &sp) {
+                        if constexpr (KELBG)
+                            p2p_kelbg<float, PHI>(tx - v.x, ty - v.y, tz - v.z, v.w, tg.qt, eps2,
+                                                  inv_lam, notself, sx, sy, sz, sp);
+                        else p2p_one<PHI>(tx, ty, tz, v, eps2, notself, sx, sy, sz, sp);
+                    };
                     for (; e + 1 < ncur; e += 2) {
                         const float4 v0 = ((const float4 *)stage)[e];
                         const float4 v1 = ((const float4 *)stage)[e + 1];
-                        p2p_one<PHI>(tx, ty, tz, v0, eps2, sidx[e] != tg.i, ex, ey, ez, ph);
-                        p2p_one<PHI>(tx, ty, tz, v1, eps2, sidx[e + 1] != tg.i, fx, fy, fz, fp);
+                        one(v0, sidx[e] != tg.i, ex, ey, ez, ph);
+                        one(v1, sidx[e + 1] != tg.i, fx, fy, fz, fp);
                     }
-                    if (e < ncur)
-                        p2p_one<PHI>(tx, ty, tz, ((const float4 *)stage)[e], eps2, sidx[e] != tg.i,
-                                     ex, ey, ez, ph);
+                    if (e < ncur) one(((const float4 *)stage)[e], sidx[e] != tg.i, ex, ey, ez, ph);
                     ex += fx;
                     ey += fy;
                     ez += fz;
@@ -541,15 +610,20 @@ __device__ __forceinline__ void flush_lists(const WalkArgs &a, const int4 *ml, i
                         sx = v.x; sy = v.y; sz = v.z; sq = v.w;
                     }
                     const T rx = tx - sx, ry = ty - sy, rz = tz - sz;
-                    const T h2 = fma(rx, rx, fma(ry, ry, fma(rz, rz, eps2)));
-                    T ih;
-                    if constexpr (sizeof(T) == 4) ih = __builtin_amdgcn_rsqf(h2);
-                    else ih = 1.0 / sqrt(h2);
-                    const T w = sq * (ih * ih * ih);
-                    ex = fma(w, rx, ex);
-                    ey = fma(w, ry, ey);
-                    ez = fma(w, rz, ez);
-                    if (PHI) ph += (sidx[e] != tg.i) ? sq * ih : (T)0;
+                    if constexpr (KELBG) {
+                        p2p_kelbg<T, PHI>(rx, ry, rz, sq, tg.qt, eps2, inv_lam, sidx[e] != tg.i,
+                                          ex, ey, ez, ph);
+                    } else {
+                        const T h2 = fma(rx, rx, fma(ry, ry, fma(rz, rz, eps2)));
+                        T ih;
+                        if constexpr (sizeof(T) == 4) ih = __builtin_amdgcn_rsqf(h2);
+                        else ih = 1.0 / sqrt(h2);
+                        const T w = sq * (ih * ih * ih);
+                        ex = fma(w, rx, ex);
+                        ey = fma(w, ry, ey);
+                        ez = fma(w, rz, ez);
+                        if (PHI) ph += (sidx[e] != tg.i) ? sq * ih : (T)0;
+                    }
                 }
             }
             tg.E0 += (double)ex;
@@ -579,7 +653,7 @@ __device__ __forceinline__ void flush_lists(const WalkArgs &a, const int4 *ml, i
     }
 }
 
-template <int PREC, int MODE>
+template <int PREC, int MODE, bool KELBG>
 __global__ __launch_bounds__(256) void k_walk(WalkArgs a)
 {
     using T = typename std::conditional<PREC == UCP_SPLIT, float, double>::type;
@@ -657,6 +731,7 @@ __global__ __launch_bounds__(256) void k_walk(WalkArgs a)
         tg.px = xi.x;
         tg.py = xi.y;
         tg.pz = xi.z;
+        tg.qt = (T)xi.w;
         tg.i = i;
         tg.E0 = tg.E1 = tg.E2 = tg.PH = 0.0;
         stk[0] = make_int2(root, min(((const int *)(a.nrec + 8 * (int64_t)root + 2))[0], nn));
@@ -667,7 +742,7 @@ __global__ __launch_bounds__(256) void k_walk(WalkArgs a)
         const double th2 = a.th2;
         while (sp > 0) {
             if (nm > L - 64 || np > L - 64) {
-                flush_lists<PREC, MODE>(a, ml, nm, pl, np, stage, pfx, lfirst, lane, sub, lpt, c,
+                flush_lists<PREC, MODE, KELBG>(a, ml, nm, pl, np, stage, pfx, lfirst, lane, sub, lpt, c,
                                         gfirst, cg, tg);
                 nm = np = 0;
             }
@@ -743,7 +818,7 @@ __global__ __launch_bounds__(256) void k_walk(WalkArgs a)
             wave_sync();
         }
         if (overflow) atomicOr(a.flags_rw, lane == 0 ? UCP_FLAG_WALK_STACK : 0);
-        flush_lists<PREC, MODE>(a, ml, nm, pl, np, stage, pfx, lfirst, lane, sub, lpt, c, gfirst,
+        flush_lists<PREC, MODE, KELBG>(a, ml, nm, pl, np, stage, pfx, lfirst, lane, sub, lpt, c, gfirst,
                                 cg, tg);
         // sum the lpt partial results of each target in fixed lane order
         double *red = (double *)stage;   // 64 x 4 doubles
@@ -919,13 +994,13 @@ __global__ __launch_bounds__(256) void k_vjp_down(const double4 *__restrict__ ac
     xbar[3 * i + 2] = sc * (g.z + xsrc[4 * p + 2] + x.w * bz);
 }
 
-template <int PREC, int MODE>
+template <int PREC, int MODE, bool KELBG = false>
 static void launch_walk_t(Ctx *c, const WalkArgs &wa, hipStream_t s)
 {
     const int waves_per_cu = c->p_built.walk_waves > 0 ? c->p_built.walk_waves : 32;
     const int blocks = (c->num_cu * waves_per_cu + 3) / 4;
     const size_t lds = (size_t)4 * walk_wave_bytes<PREC>(wa.L);
-    hipLaunchKernelGGL((k_walk<PREC, MODE>), dim3(blocks), dim3(256), lds, s, wa);
+    hipLaunchKernelGGL((k_walk<PREC, MODE, KELBG>), dim3(blocks), dim3(256), lds, s, wa);
 }
 
 static WalkArgs walk_args(Ctx *c)
@@ -951,6 +1026,8 @@ static WalkArgs walk_args(Ctx *c)
     wa.th2 = c->p_built.theta * c->p_built.theta;
     wa.eps2 = c->p_built.eps * c->p_built.eps;
     wa.eps2f = (float)wa.eps2;
+    wa.inv_lambda = c->p_built.pair_law == UCP_PAIR_KELBG ? 1.0 / c->p_built.lambda_ei : 0.0;
+    wa.inv_lambdaf = (float)wa.inv_lambda;
     wa.L = c->p_built.list_len;
     return wa;
 }
@@ -975,12 +1052,23 @@ void launch_forces(Ctx *c, double *f, double *phi, hipStream_t s)
         (void)hipEventRecord(e0, s);
     }
     const bool want_phi = phi != nullptr || f == nullptr;
+    const bool kelbg = c->p_built.pair_law == UCP_PAIR_KELBG;
     if (c->p_built.precision == UCP_SPLIT) {
-        if (want_phi) launch_walk_t<UCP_SPLIT, kWalkForcePhi>(c, wa, s);
-        else launch_walk_t<UCP_SPLIT, kWalkForce>(c, wa, s);
+        if (kelbg) {
+            if (want_phi) launch_walk_t<UCP_SPLIT, kWalkForcePhi, true>(c, wa, s);
+            else launch_walk_t<UCP_SPLIT, kWalkForce, true>(c, wa, s);
+        } else {
+            if (want_phi) launch_walk_t<UCP_SPLIT, kWalkForcePhi>(c, wa, s);
+            else launch_walk_t<UCP_SPLIT, kWalkForce>(c, wa, s);
+        }
     } else {
-        if (want_phi) launch_walk_t<UCP_FP64, kWalkForcePhi>(c, wa, s);
-        else launch_walk_t<UCP_FP64, kWalkForce>(c, wa, s);
+        if (kelbg) {
+            if (want_phi) launch_walk_t<UCP_FP64, kWalkForcePhi, true>(c, wa, s);
+            else launch_walk_t<UCP_FP64, kWalkForce, true>(c, wa, s);
+        } else {
+            if (want_phi) launch_walk_t<UCP_FP64, kWalkForcePhi>(c, wa, s);
+            else launch_walk_t<UCP_FP64, kWalkForce>(c, wa, s);
+        }
     }
     if (c->timing) (void)hipEventRecord(e1, s);
     hipLaunchKernelGGL(k_scatter, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,

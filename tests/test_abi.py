@@ -38,13 +38,17 @@ def test_default_params_and_version():
     p = L.default_params()
     assert p.theta == 0.5 and p.key_bits == 63 and p.leaf_cap == 24 and p.group_size == 64
     assert p.precision == L.UCP_SPLIT and p.group_mode == L.UCP_GROUP_CHUNK
+    assert p.pair_law == L.UCP_PAIR_PLUMMER and p.lambda_ei == 0.0
     assert L.ucp_version() >= 100
 
 
 @pytest.mark.parametrize("over", [dict(theta=-0.1), dict(theta=1.2), dict(eps=0.0),
                                   dict(key_bits=32), dict(leaf_cap=0), dict(leaf_cap=65),
                                   dict(group_size=0), dict(group_size=65), dict(list_len=8), dict(list_len=600),
-                                  dict(precision=3), dict(group_mode=2), dict(group_mode=-1)])
+                                  dict(precision=3), dict(group_mode=2), dict(group_mode=-1),
+                                  dict(pair_law=2), dict(pair_law=1, lambda_ei=0.0),
+                                  dict(pair_law=1, lambda_ei=-0.5),
+                                  dict(pair_law=1, lambda_ei=0.1, eps=-1.0)])
 def test_create_rejects_bad_params_without_gpu(over):
     p = L.default_params(**over)
     with pytest.raises(L.UcpError) as ei:
