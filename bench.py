@@ -300,6 +300,66 @@ def opening_study(dev, dt=1e-6):
     return out
 
 
+def relaxation_study(dev, clouds=16, n_c=10000, steps=10000, every=250, dt=2e-5, eps=0.05):
+    """Relaxation of two-component clouds (after Sec. 5.3): `clouds` clouds of
+    n_c particles (sigma = 1, T_e = 1e-3, T_i = 1e-5, seeds 0 .. clouds-1)
+    advanced together by the batched Verlet step, with the tree (theta = 0.5)
+    and with all pairs (theta = 0).  Every `every` steps the electron and ion
+    temperatures T_s = m <|v|^2> / 3 (k_B = 1, mean over each cloud's species,
+    then over clouds with the spread between clouds) are recorded.  eps = 0.05
+    and dt = 2e-5 keep electrons bound in the softened ion wells resolved
+    (omega dt = 0.08 for omega^2 = 1836 / eps^3).  Qualitative: the paper's
+    physical parameters and figure data are not available."""
+    import numpy as np
+    import torch
+
+    from paper_0709_3331_amd import _lib as L
+    from paper_0709_3331_amd import inputs
+    from paper_0709_3331_amd.tree import TreeSolver
+
+    cls = [inputs.gaussian_cloud(n_c, 1.0, 1e-3, 1e-5, s) for s in range(clouds)]
+    x0 = np.concatenate([c.x for c in cls])
+    v0 = np.concatenate([c.v for c in cls])
+    q = torch.from_numpy(np.concatenate([c.q for c in cls])).to(dev)
+    m = torch.from_numpy(np.concatenate([c.m for c in cls])).to(dev)
+    off = torch.arange(0, clouds + 1, device=dev, dtype=torch.int64) * n_c
+    n = clouds * n_c
+    ion = (q > 0).reshape(clouds, n_c)
+
+    def temps(v):
+        k2 = (m * (v * v).sum(dim=1) / 3.0).reshape(clouds, n_c)
+        te = (k2 * (~ion)).sum(dim=1) / (~ion).sum(dim=1)
+        ti = (k2 * ion).sum(dim=1) / ion.sum(dim=1)
+        return te.cpu().numpy(), ti.cpu().numpy()
+
+    def run(theta):
+        ts = TreeSolver(n, clouds, theta=theta, eps=eps, precision=L.UCP_SPLIT)
+        x = torch.from_numpy(x0.copy()).to(dev)
+        v = torch.from_numpy(v0.copy()).to(dev)
+        f = ts.tree_forces(x, q, off)
+        rows = []
+        t0 = time.perf_counter()
+        for k in range(steps // every + 1):
+            if k:
+                ts.step(x, v, f, q, m, dt, every, off)
+            te, ti = temps(v)
+            rows.append({"t": k * every * dt, "T_e": float(te.mean()), "T_e_spread": float(te.std()),
+                         "T_i": float(ti.mean()), "T_i_spread": float(ti.std())})
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ts.stats()
+        ts.close()
+        print(f"relaxation study: theta={theta:g} done, {wall:.1f} s", file=sys.stderr, flush=True)
+        return rows, wall
+
+    tree, wt = run(0.5)
+    pairs, wp = run(0.0)
+    return {"study": "relaxation (Sec. 5.3)", "clouds": clouds, "n_per_cloud": n_c, "eps": eps,
+            "dt": dt, "steps": steps, "record_every": every,
+            "tree_theta_0.5": {"wall_s": wt, "series": tree},
+            "all_pairs": {"wall_s": wp, "series": pairs}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -326,7 +386,7 @@ def main():
     ap.add_argument("--profile", action="store_true", help="short run for rocprofv3 (no extras)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 256 MiB device-to-device copy (counter calibration)")
-    ap.add_argument("--study", choices=["opening"],
+    ap.add_argument("--study", choices=["opening", "relaxation"],
                     help="run a study instead of the benchmark and print its JSON line")
     ap.add_argument("--study-dt", type=float, default=1e-6, help="time step of the study")
     args = ap.parse_args()
@@ -346,6 +406,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.study == "opening":
         print(json.dumps(opening_study(dev, args.study_dt)), flush=True)
+        return
+    if args.study == "relaxation":
+        print(json.dumps(relaxation_study(dev)), flush=True)
         return
     cl, prm = inputs.metric(0)
     n = cl.n
