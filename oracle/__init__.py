@@ -41,6 +41,7 @@ def _load():
         "orc_direct": (None, [i64, _dp, _dp, dbl, _dp, vp]),
         "orc_direct_pair": (i32, [i64, _dp, _dp, dbl, i32, dbl, _dp, vp]),
         "orc_tree_set_pair": (i32, [vp, i32, dbl]),
+        "orc_tree_set_expansion": (i32, [vp, i32]),
         "orc_direct_targets": (None, [i64, _dp, _dp, dbl, i64, _i64p, _dp, vp]),
         "orc_direct_vjp": (None, [i64, _dp, _dp, dbl, _dp, _dp]),
         "orc_cube": (i32, [i64, _dp, _dp, C.POINTER(C.c_int)]),
@@ -109,6 +110,7 @@ def direct(x, q, eps):
 
 
 PAIR_PLUMMER, PAIR_KELBG = 0, 1
+EXP_QUADRUPOLE, EXP_SPECIES = 0, 1
 
 
 def direct_pair(x, q, eps, pair_law=PAIR_PLUMMER, lambda_ei=0.0):
@@ -179,7 +181,7 @@ class Tree:
     more); group_mode 1: consecutive runs of G key-sorted particles."""
 
     def __init__(self, x, q, theta, eps, b=21, leaf_cap=24, G=64, keep_lists=False, group_mode=1,
-                 pair_law=PAIR_PLUMMER, lambda_ei=0.0):
+                 pair_law=PAIR_PLUMMER, lambda_ei=0.0, expansion=EXP_QUADRUPOLE):
         lib = _load()
         self.x = _f64(x, (-1, 3)); self.q = _f64(q)
         self.n = self.x.shape[0]
@@ -194,6 +196,10 @@ class Tree:
         self.pair_law, self.lambda_ei = pair_law, lambda_ei
         if lib.orc_tree_set_pair(h, int(pair_law), float(lambda_ei)) != 0:
             raise ValueError("oracle tree: invalid pair law")
+        self.expansion = expansion
+        if lib.orc_tree_set_expansion(h, int(expansion)) != 0:
+            raise ValueError("oracle tree: invalid expansion (species pseudo-particles do not "
+                             "keep lists)")
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -333,10 +339,10 @@ def rebuild(series, cap):
 
 
 def tree_forces(x, q, theta, eps, b=21, leaf_cap=24, G=64, want_phi=True, group_mode=1,
-                pair_law=PAIR_PLUMMER, lambda_ei=0.0):
+                pair_law=PAIR_PLUMMER, lambda_ei=0.0, expansion=EXP_QUADRUPOLE):
     """Convenience: build the oracle tree and evaluate it."""
     t = Tree(x, q, theta, eps, b, leaf_cap, G, group_mode=group_mode, pair_law=pair_law,
-             lambda_ei=lambda_ei)
+             lambda_ei=lambda_ei, expansion=expansion)
     r = t.eval(want_phi=want_phi)
     r["nodes"] = t.nnodes
     r["groups"] = t.ngroups

@@ -314,6 +314,7 @@ struct orc_tree {
     int64_t n;
     double theta, eps;
     int pair_law;          /* ORC_PAIR_*: the near-field (P2P) pair law           */
+    int expansion;         /* ORC_EXP_*: what an accepted box contributes          */
     double lambda;         /* Kelbg length (ORC_PAIR_KELBG)                       */
     int b, leaf_cap, G;
     double lo[3];
@@ -462,12 +463,90 @@ static int mac_accept(const orc_tree *t, int64_t k, const double *xs, int64_t gf
     return 1;
 }
 
-static void walk_rec(const orc_tree *t, int64_t k, const double *xs, int64_t gf, int64_t gc,
-                     ivec *M, ivec *P)
+/* ------------------------------------------------------------------------- */
+/* Pseudo-particles as Sec. 3 has them (ORC_EXP_SPECIES): a box carries, per  */
+/* species s (q > 0 and q < 0), the charge Q_s = sum q_j of its particles of  */
+/* that sign placed at their centre of charge c_s = sum q_j x_j / Q_s (the    */
+/* charge-ratio interpolation of the positions below it).  Eq. (5) then reads */
+/* s/theta + delta_s < d_s with delta_s = |c_s - c| (c the box centre) and    */
+/* d_s the distance from the member to c_s; the box is accepted for a group  */
+/* iff every member passes for every species the box holds.  Layout per      */
+/* node: Q+, c+[3], Q-, c-[3], delta+, delta- (a species the box does not    */
+/* hold has Q_s = 0).  Sums run about the box centre, brute force over the   */
+/* node's particles.                                                         */
+/* ------------------------------------------------------------------------- */
+enum { ORC_EXP_QUADRUPOLE = 0, ORC_EXP_SPECIES = 1 };
+
+static void node_species(const orc_tree *t, int64_t k, const double *xs, const double *qs,
+                         const double *c, double *ps)
 {
-    if (mac_accept(t, k, xs, gf, gc)) { ivec_push(M, k); return; }
+    nsum Q[2], mu[2][3];
+    memset(Q, 0, sizeof(Q));
+    memset(mu, 0, sizeof(mu));
+    for (int64_t p = t->first[k]; p < t->first[k] + t->count[k]; ++p) {
+        if (qs[p] == 0.0) continue;
+        const int sp = qs[p] > 0.0 ? 0 : 1;
+        nadd(&Q[sp], qs[p]);
+        for (int d = 0; d < 3; ++d) nadd(&mu[sp][d], qs[p] * (xs[3 * p + d] - c[d]));
+    }
+    for (int sp = 0; sp < 2; ++sp) {
+        const double q = nval(Q[sp]);
+        double off[3] = {0.0, 0.0, 0.0};
+        if (q != 0.0)
+            for (int d = 0; d < 3; ++d) off[d] = nval(mu[sp][d]) / q;
+        ps[4 * sp] = q;
+        for (int d = 0; d < 3; ++d) ps[4 * sp + 1 + d] = c[d] + off[d];
+        ps[8 + sp] = sqrt(off[0] * off[0] + off[1] * off[1] + off[2] * off[2]);
+    }
+}
+
+static int mac_accept_species(const orc_tree *t, int64_t k, const double *xs, int64_t gf,
+                              int64_t gc, const double *ps)
+{
+    if (!(t->theta > 0.0)) return 0;
+    const double s = node_side(t, k);
+    for (int sp = 0; sp < 2; ++sp) {
+        if (ps[4 * sp] == 0.0) continue;
+        const double R = s / t->theta + ps[8 + sp];
+        const double *cs = ps + 4 * sp + 1;
+        for (int64_t a = 0; a < gc; ++a) {
+            const double *xi = xs + 3 * (gf + a);
+            double dx = xi[0] - cs[0], dy = xi[1] - cs[1], dz = xi[2] - cs[2];
+            double d2 = fma(dz, dz, fma(dy, dy, dx * dx));
+            if (!(R * R < d2)) return 0;
+        }
+    }
+    return 1;
+}
+
+/* field and potential at x of a box's two pseudo-particles (softened like   */
+/* the pairs)                                                                */
+static void cell_field_species(const double *ps, const double *x, double eps2, double *E,
+                               double *phi)
+{
+    E[0] = E[1] = E[2] = 0.0;
+    *phi = 0.0;
+    for (int sp = 0; sp < 2; ++sp) {
+        const double q = ps[4 * sp];
+        if (q == 0.0) continue;
+        double r[3] = {x[0] - ps[4 * sp + 1], x[1] - ps[4 * sp + 2], x[2] - ps[4 * sp + 3]};
+        double h2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2] + eps2;
+        double h = sqrt(h2);
+        for (int d = 0; d < 3; ++d) E[d] += q * r[d] / (h2 * h);
+        *phi += q / h;
+    }
+}
+
+/* ps: per-node pseudo-particles (ORC_EXP_SPECIES), NULL otherwise            */
+static void walk_rec(const orc_tree *t, int64_t k, const double *xs, int64_t gf, int64_t gc,
+                     const double *ps, ivec *M, ivec *P)
+{
+    const int acc = ps ? mac_accept_species(t, k, xs, gf, gc, ps + 10 * k)
+                       : mac_accept(t, k, xs, gf, gc);
+    if (acc) { ivec_push(M, k); return; }
     if (is_leaf(t, k)) { ivec_push(P, k); return; }
-    for (int64_t ch = k + 1; ch < t->skip[k]; ch = t->skip[ch]) walk_rec(t, ch, xs, gf, gc, M, P);
+    for (int64_t ch = k + 1; ch < t->skip[k]; ch = t->skip[ch])
+        walk_rec(t, ch, xs, gf, gc, ps, M, P);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -528,12 +607,13 @@ static void cell_field(const double *mom, const double *r, double eps2, double *
 /* ------------------------------------------------------------------------- */
 /* Tree construction entry point.                                            */
 /* ------------------------------------------------------------------------- */
-static void tree_walk_group(const orc_tree *t, const double *xs, int64_t g, ivec *M, ivec *P)
+static void tree_walk_group(const orc_tree *t, const double *xs, const double *ps, int64_t g,
+                            ivec *M, ivec *P)
 {
     M->n = 0;
     P->n = 0;
     if (t->M == 0) return;
-    walk_rec(t, 0, xs, t->gfirst[g], t->gcount[g], M, P);
+    walk_rec(t, 0, xs, t->gfirst[g], t->gcount[g], ps, M, P);
 }
 
 static void sorted_copy(const orc_tree *t, const double *x, const double *q, double *xs, double *qs)
@@ -591,7 +671,7 @@ orc_tree *orc_tree_new(int64_t n, const double *x, const double *q, double theta
             ivec M = {0, 0, 0}, P = {0, 0, 0};
 #pragma omp for schedule(dynamic, 4)
             for (int64_t g = 0; g < t->ng; ++g) {
-                tree_walk_group(t, xs, g, &M, &P);
+                tree_walk_group(t, xs, NULL, g, &M, &P);
                 t->m2p[g] = (int64_t *)malloc((size_t)(M.n ? M.n : 1) * sizeof(int64_t));
                 t->p2p[g] = (int64_t *)malloc((size_t)(P.n ? P.n : 1) * sizeof(int64_t));
                 memcpy(t->m2p[g], M.v, (size_t)M.n * sizeof(int64_t));
@@ -631,6 +711,17 @@ int64_t orc_tree_nnodes(const orc_tree *t) { return t->M; }
 int64_t orc_tree_ngroups(const orc_tree *t) { return t->ng; }
 /* Near-field pair law of the tree's P2P terms (ORC_PAIR_*; lambda > 0 for  */
 /* Kelbg); the far field is the softened expansion either way.              */
+/* What an accepted box contributes (ORC_EXP_*).  The species pseudo-       */
+/* particles change the lists, so a tree that keeps lists (for the adjoint)  */
+/* takes the expansion only.                                                 */
+int orc_tree_set_expansion(orc_tree *t, int expansion)
+{
+    if (expansion != ORC_EXP_QUADRUPOLE && expansion != ORC_EXP_SPECIES) return -1;
+    if (expansion != ORC_EXP_QUADRUPOLE && t->keep_lists) return -1;
+    t->expansion = expansion;
+    return 0;
+}
+
 int orc_tree_set_pair(orc_tree *t, int law, double lambda)
 {
     if ((law != ORC_PAIR_PLUMMER && law != ORC_PAIR_KELBG) ||
@@ -693,8 +784,8 @@ void orc_tree_moments(const orc_tree *t, const double *x, const double *q, doubl
 /* Forces and potentials of the members of group g (C-2.8), written in the   */
 /* caller's order; returns the group's list lengths (cells, P2P sources).    */
 static void eval_group(const orc_tree *t, const double *xs, const double *qs, const double *mom,
-                       double eps2, const orc_pair *pl, int64_t g, ivec *M, ivec *P, double *f,
-                       double *phi, int64_t *mn_out, int64_t *nsrc_out)
+                       const double *ps, double eps2, const orc_pair *pl, int64_t g, ivec *M,
+                       ivec *P, double *f, double *phi, int64_t *mn_out, int64_t *nsrc_out)
 {
     const int64_t *mv, *pv;
     int64_t mn, pn;
@@ -702,7 +793,7 @@ static void eval_group(const orc_tree *t, const double *xs, const double *qs, co
         mv = t->m2p[g]; mn = t->nm2p[g];
         pv = t->p2p[g]; pn = t->np2p[g];
     } else {
-        tree_walk_group(t, xs, g, M, P);
+        tree_walk_group(t, xs, ps, g, M, P);
         mv = M->v; mn = M->n;
         pv = P->v; pn = P->n;
     }
@@ -719,7 +810,8 @@ static void eval_group(const orc_tree *t, const double *xs, const double *qs, co
             const double *c = t->centre + 3 * k;
             double r[3] = {xi[0] - c[0], xi[1] - c[1], xi[2] - c[2]};
             double Ec[3], pc;
-            cell_field(mom + 10 * k, r, eps2, Ec, &pc);
+            if (ps) cell_field_species(ps + 10 * k, xi, eps2, Ec, &pc);
+            else cell_field(mom + 10 * k, r, eps2, Ec, &pc);
             for (int d = 0; d < 3; ++d) nadd(&E[d], Ec[d]);
             nadd(&ph, pc);
         }
@@ -758,6 +850,13 @@ static void eval_groups(const orc_tree *t, const double *x, const double *q, int
     sorted_copy(t, x, q, xs, qs);
 #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t k = 0; k < t->M; ++k) node_moments(t, k, xs, qs, t->centre + 3 * k, mom + 10 * k);
+    double *ps = NULL;
+    if (t->expansion == ORC_EXP_SPECIES) {
+        ps = (double *)malloc((size_t)t->M * 10 * sizeof(double));
+#pragma omp parallel for schedule(dynamic, 64)
+        for (int64_t k = 0; k < t->M; ++k)
+            node_species(t, k, xs, qs, t->centre + 3 * k, ps + 10 * k);
+    }
     const double eps2 = t->eps * t->eps;
     const orc_pair pl = {t->pair_law, eps2, t->lambda};
     int64_t sp2p = 0, sm2p = 0;
@@ -768,7 +867,7 @@ static void eval_groups(const orc_tree *t, const double *x, const double *q, int
         for (int64_t e = 0; e < ngs; ++e) {
             const int64_t g = gsel ? gsel[e] : e;
             int64_t mn, nsrc;
-            eval_group(t, xs, qs, mom, eps2, &pl, g, &M, &P, f, phi, &mn, &nsrc);
+            eval_group(t, xs, qs, mom, ps, eps2, &pl, g, &M, &P, f, phi, &mn, &nsrc);
             if (gm2p) gm2p[e] = mn;
             if (gp2p) gp2p[e] = nsrc;
             sp2p += nsrc * t->gcount[g];
@@ -781,6 +880,7 @@ static void eval_groups(const orc_tree *t, const double *x, const double *q, int
     free(xs);
     free(qs);
     free(mom);
+    free(ps);
 }
 
 void orc_tree_eval(const orc_tree *t, const double *x, const double *q, double *f, double *phi,
