@@ -379,6 +379,8 @@ def main():
     ap.add_argument("--no-ensemble", action="store_true",
                     help="skip the batched 64-cloud ensemble measurement")
     ap.add_argument("--ensemble-steps", type=int, default=10)
+    ap.add_argument("--no-species", action="store_true",
+                    help="skip the per-species pseudo-particle measurement")
     ap.add_argument("--no-kelbg", action="store_true",
                     help="skip the Kelbg pair-law measurement")
     ap.add_argument("--no-adjoint", action="store_true",
@@ -529,6 +531,31 @@ def main():
                         float(np.linalg.norm(fa[tg] - fd) / np.linalg.norm(fd))}
                 tt.close()
             result["theta_sweep"] = sweep
+        if not args.no_species:
+            # the paper's pseudo-particles (one per sign at its centre of
+            # charge, Eq. (5) with delta) against the quadrupole above
+            spc = {}
+            for th in (0.3, 0.5, 0.7):
+                tt = TreeSolver(n, theta=th, eps=eps, precision=prec, group_size=args.group_size,
+                                list_len=args.list_len, group_mode=gm, leaf_cap=args.leaf_cap,
+                                walk_waves=args.walk_waves, expansion=L.UCP_EXPANSION_SPECIES)
+                ft = tt.tree_forces(x, q)
+                tt.timing(True)
+                torch.cuda.synchronize()
+                for _ in range(3):
+                    tt.tree_forces(x, q)
+                torch.cuda.synchronize()
+                wm, wc = tt.timing_read()
+                stt = tt.stats()
+                fa = ft.cpu().numpy()
+                spc[f"{th:g}"] = {
+                    "walk_ms": wm / max(wc, 1),
+                    "interactions_per_particle": (stt["p2p"] + stt["m2p"]) / n,
+                    "m2p_per_particle": stt["m2p"] / n,
+                    "rel_force_err_vs_direct_sampled":
+                        float(np.linalg.norm(fa[tg] - fd) / np.linalg.norm(fd))}
+                tt.close()
+            result["species_pseudo_particles"] = spc
         c0 = time.perf_counter()
         ot = oracle.Tree(xs, qs, theta, eps, G=args.group_size, group_mode=gm,
                          leaf_cap=args.leaf_cap)

@@ -76,6 +76,22 @@ typedef enum {
     UCP_PAIR_KELBG = 1
 } ucp_pair_law;
 
+/* What an accepted box contributes (its pseudo-particle, Sec. 3).
+ * UCP_EXPANSION_QUADRUPOLE: charge, dipole and quadrupole about the box
+ *   centre (the second-order expansion of the softened kernel), opening test
+ *   s^2 < theta^2 d^2 with d to the box centre (delta = 0 in Eq. (5)).
+ * UCP_EXPANSION_SPECIES: the paper's twig charges, one per sign: the charge
+ *   Q_s of the box's particles of that sign at their centre of charge c_s,
+ *   each evaluated like a particle (softened by eps); the box is accepted
+ *   iff s/theta + delta_s < d_s for every member of the walk group and every
+ *   sign the box holds, with delta_s = |c_s - box centre| and d_s the
+ *   distance from the member to c_s (Eq. (5)).  Costs 96 bytes per node
+ *   slot, allocated when the expansion is first selected.                  */
+typedef enum {
+    UCP_EXPANSION_QUADRUPOLE = 0,
+    UCP_EXPANSION_SPECIES = 1
+} ucp_expansion;
+
 /* Method parameters.  The opening test is Eq. (5), s/theta + delta < d, with
  * the pseudo-particle expanded about the box centre (delta = 0), s the box
  * side and d the distance from the target to the box centre; it is evaluated
@@ -96,6 +112,7 @@ typedef struct {
                               walk groups                                                */
     int32_t pair_law;      /* ucp_pair_law: the pair law of the particle-particle terms  */
     double lambda_ei;      /* Kelbg length lambda_ei of Eq. (4), > 0 (UCP_PAIR_KELBG)     */
+    int32_t expansion;     /* ucp_expansion: what an accepted box contributes            */
 } ucp_params;
 
 typedef struct ucp_ctx ucp_ctx;   /* opaque */
@@ -121,7 +138,7 @@ typedef struct {
 
 /* Default parameters: theta 0.5, eps 0.005, 63-bit keys, leaf_cap 24, G 64,
  * list_len 128, UCP_SPLIT, walk_waves 0, UCP_GROUP_CHUNK, UCP_PAIR_PLUMMER,
- * lambda_ei 0.                                                              */
+ * lambda_ei 0, UCP_EXPANSION_QUADRUPOLE.                                    */
 void ucp_default_params(ucp_params *p);
 
 /* Create a context on the current HIP device able to hold n_max particles in
@@ -198,8 +215,9 @@ ucp_status ucp_energy(ucp_ctx *c, const double *x, const double *v, const double
  * rounding, not bitwise.  The first call allocates the adjoint scratch
  * (48 bytes per particle, 80 per node slot).
  * Errors: UCP_EINVAL (NULL argument, or a pair law other than
- * UCP_PAIR_PLUMMER: only that law has an adjoint), UCP_ENOTBUILT, UCP_ENOMEM,
- * UCP_EHIP; device flags as for ucp_compute_forces.                         */
+ * UCP_PAIR_PLUMMER or an expansion other than UCP_EXPANSION_QUADRUPOLE: only
+ * those have an adjoint), UCP_ENOTBUILT, UCP_ENOMEM, UCP_EHIP; device flags
+ * as for ucp_compute_forces.                                                */
 ucp_status ucp_force_vjp(ucp_ctx *c, const double *u, double *xbar, void *stream);
 
 /* Synchronise `stream`, read the device counters and flags.  Returns

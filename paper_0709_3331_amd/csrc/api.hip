@@ -36,6 +36,10 @@ bool validate(const ucp_params *p, std::string &why)
         why = "theta must satisfy 0 <= theta < 2/sqrt(3)";
         return false;
     }
+    if (p->expansion != UCP_EXPANSION_QUADRUPOLE && p->expansion != UCP_EXPANSION_SPECIES) {
+        why = "expansion must be UCP_EXPANSION_QUADRUPOLE or UCP_EXPANSION_SPECIES";
+        return false;
+    }
     if (p->pair_law != UCP_PAIR_PLUMMER && p->pair_law != UCP_PAIR_KELBG) {
         why = "pair_law must be UCP_PAIR_PLUMMER or UCP_PAIR_KELBG";
         return false;
@@ -80,7 +84,7 @@ void free_all(Ctx *c)
                     c->d_ngeo, c->d_ninfo,  c->d_npar,  c->d_mom64,  c->d_nrec,
                     c->d_groups, c->d_gstat, c->d_acc,  c->d_ctr,    c->d_flags,  c->d_epart,
                     c->d_leafof, c->d_w,    c->d_xsrc,  c->d_cbar,  c->d_wq,
-                    c->d_ghist,  c->d_sortctl, c->d_nlev};
+                    c->d_ghist,  c->d_sortctl, c->d_nlev, c->d_spec};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
@@ -180,6 +184,7 @@ void ucp_default_params(ucp_params *p)
     p->group_mode = UCP_GROUP_CHUNK;
     p->pair_law = UCP_PAIR_PLUMMER;
     p->lambda_ei = 0.0;
+    p->expansion = UCP_EXPANSION_QUADRUPOLE;
 }
 
 const char *ucp_last_error(const ucp_ctx *c)
@@ -237,6 +242,7 @@ ucp_status ucp_create(ucp_ctx **out, int64_t n_max, int32_t clouds_max, const uc
     ALLOC(c->d_ninfo, NC);
     ALLOC(c->d_npar, NC);
     ALLOC(c->d_nlev, NC + 128);
+    if (p->expansion == UCP_EXPANSION_SPECIES) ALLOC(c->d_spec, ucp::kSpecVals * NC);
     ALLOC(c->d_mom64, 16 * NC);
     ALLOC(c->d_nrec, 8 * NC);
     ALLOC(c->d_groups, N);
@@ -276,8 +282,17 @@ ucp_status ucp_set_params(ucp_ctx *c, const ucp_params *p)
     if (!c) return fail(nullptr, UCP_EINVAL, kNoCtx);
     std::string why;
     if (!validate(p, why)) return fail(c, UCP_EINVAL, "ucp_set_params: " + why);
+    // the expansion decides what the build computes, so it needs a new build
     const bool topo = p->key_bits != c->p.key_bits || p->leaf_cap != c->p.leaf_cap ||
-                      p->group_size != c->p.group_size || p->group_mode != c->p.group_mode;
+                      p->group_size != c->p.group_size || p->group_mode != c->p.group_mode ||
+                      p->expansion != c->p.expansion;
+    if (p->expansion == UCP_EXPANSION_SPECIES && !c->d_spec) {
+        const hipError_t e = dalloc(&c->d_spec, (size_t)c->node_cap * ucp::kSpecVals);
+        if (e != hipSuccess) {
+            c->d_spec = nullptr;
+            return fail(c, UCP_ENOMEM, "ucp_set_params: no memory for the species pseudo-particles");
+        }
+    }
     c->p = *p;
     if (topo) c->built = 0;
     else if (c->built) {
@@ -397,6 +412,8 @@ ucp_status ucp_force_vjp(ucp_ctx *c, const double *u, double *xbar, void *stream
     if (!u || !xbar) return fail(c, UCP_EINVAL, "ucp_force_vjp: NULL argument");
     if (c->p_built.pair_law != UCP_PAIR_PLUMMER)
         return fail(c, UCP_EINVAL, "ucp_force_vjp: only the Plummer pair law has an adjoint");
+    if (c->p_built.expansion != UCP_EXPANSION_QUADRUPOLE)
+        return fail(c, UCP_EINVAL, "ucp_force_vjp: only the quadrupole expansion has an adjoint");
     if (!c->d_w) {
         // the adjoint buffers are allocated on first use
         hipError_t e = hipMalloc((void **)&c->d_w, (size_t)c->n_max * sizeof(double4) + 256);

@@ -671,6 +671,47 @@ __device__ __forceinline__ void store_moments(double *mom64, float4 *nrec, int k
     f4[2] = make_float4((float)(3.0 * m[7]), (float)(3.0 * m[8]), (float)(3.0 * m[9]), 0.f);
 }
 
+// Per-species pseudo-particles of a box (Sec. 3, the paper's twig charges):
+// the charge Q_s of its particles of one sign placed at their centre of
+// charge c_s = c + mu_s / Q_s, mu_s = sum q_j (x_j - c) about the box centre c;
+// delta_s = |c_s - c| enters the opening test.  Accumulators: Q+ mu+[3] Q-
+// mu-[3]; record of kSpecVals doubles: c+[3] Q+ c-[3] Q- delta+ delta- 0 0.
+// A box without particles of a sign has Q_s = 0 and c_s = c.
+__device__ __forceinline__ void spec_add(double *sq, double q, double rx, double ry, double rz)
+{
+    if (q == 0.0) return;
+    double *a = sq + (q > 0.0 ? 0 : 4);
+    a[0] += q;
+    a[1] += q * rx;
+    a[2] += q * ry;
+    a[3] += q * rz;
+}
+
+__device__ __forceinline__ void spec_store(double *spec, int k, const double4 &g, const double *sq)
+{
+    double *r = spec + kSpecVals * (int64_t)k;
+    for (int sp = 0; sp < 2; ++sp) {
+        const double Q = sq[4 * sp];
+        const double ox = Q != 0.0 ? sq[4 * sp + 1] / Q : 0.0;
+        const double oy = Q != 0.0 ? sq[4 * sp + 2] / Q : 0.0;
+        const double oz = Q != 0.0 ? sq[4 * sp + 3] / Q : 0.0;
+        *(double4 *)(r + 4 * sp) = make_double4(g.x + ox, g.y + oy, g.z + oz, Q);
+        r[8 + sp] = sqrt(ox * ox + oy * oy + oz * oz);
+    }
+    r[10] = 0.0;
+    r[11] = 0.0;
+}
+
+// a child's pseudo-particles added to its parent's accumulators
+__device__ __forceinline__ void spec_add_child(double *sq, const double *spec, int ch,
+                                               const double4 &g)
+{
+    const double *r = spec + kSpecVals * (int64_t)ch;
+    const double4 a = *(const double4 *)r, b = *(const double4 *)(r + 4);
+    spec_add(sq, a.w, a.x - g.x, a.y - g.y, a.z - g.z);
+    spec_add(sq, b.w, b.x - g.x, b.y - g.y, b.z - g.z);
+}
+
 // The leaf starting at position p, if there is one (every level at once: a
 // leaf depends on nothing but its particles).  Its end was found by the level
 // pass, or is -1 for a max-depth leaf wider than that pass's window.
@@ -679,7 +720,7 @@ __global__ __launch_bounds__(kLeafThreads) void k_leaf_moments(
     const double4 *__restrict__ xq, int64_t n, const int8_t *__restrict__ Lv,
     const int8_t *__restrict__ Lf, const int32_t *__restrict__ lend,
     const int32_t *__restrict__ noff, const double4 *__restrict__ ngeo, int4 *ninfo,
-    double *mom64, float4 *nrec, int32_t *leafof, const int32_t *flags)
+    double *mom64, float4 *nrec, int32_t *leafof, double *spec, const int32_t *flags)
 {
     if (*flags) return;
     const int64_t p = blockIdx.x * (int64_t)kLeafThreads + threadIdx.x;
@@ -694,6 +735,7 @@ __global__ __launch_bounds__(kLeafThreads) void k_leaf_moments(
         while ((int)Lv[t] >= lf) ++t;   // Lv[n] = -1 ends the scan
     }
     double m[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    double sq[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     // particles in order; the loads of a batch are issued together
     for (int64_t j0 = p; j0 < t; j0 += kP2MBatch) {
         double4 a[kP2MBatch];
@@ -714,8 +756,10 @@ __global__ __launch_bounds__(kLeafThreads) void k_leaf_moments(
             m[7] += qq * r0 * r1;
             m[8] += qq * r0 * r2;
             m[9] += qq * r1 * r2;
+            if (spec) spec_add(sq, qq, r0, r1, r2);
         }
     }
+    if (spec) spec_store(spec, k, g, sq);
     const int cnt = (int)(t - p), skip = noff[t], info = lf | 256;
     ninfo[k] = make_int4((int)p, cnt, skip, info);
     *(double4 *)(nrec + 8 * (int64_t)k) = g;
@@ -820,10 +864,11 @@ template <int BATCH>
 __device__ __forceinline__ void moments_internal(
     int k, int64_t p, int level, int nn, const uint8_t *__restrict__ nlev,
     const double4 *__restrict__ ngeo, int4 *ninfo, int32_t *npar, double *mom64, float4 *nrec,
-    int32_t *flags)
+    double *spec, int32_t *flags)
 {
     const double4 g = ngeo[k];
     double m[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    double sq[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     const double qd = 0.25 * sqrt(g.w);   // |child centre - parent centre| per axis
     int64_t t;
     int skip;
@@ -855,6 +900,7 @@ __device__ __forceinline__ void moments_internal(
                 if (c[u] < 0) break;
                 bad = bad || ic[u].y < 1;
                 add_child(m, g, qd, gc[u], rc[u]);
+                if (spec) spec_add_child(sq, spec, c[u], g);
                 npar[c[u]] = k;
                 last = c[u];
                 t = (int64_t)ic[u].x + ic[u].y;
@@ -878,11 +924,13 @@ __device__ __forceinline__ void moments_internal(
             double r[11];
             load_child(mom64, ch, r);
             add_child(m, g, qd, ngeo[ch], r);
+            if (spec) spec_add_child(sq, spec, ch, g);
             if (skip >= nn || (si.w & 255) != level + 1) break;   // no further sibling
             ch = skip;
             ci = si;
         }
     }
+    if (spec) spec_store(spec, k, g, sq);
     const int cnt = (int)(t - p), info = level;
     ninfo[k] = make_int4((int)p, cnt, skip, info);
     *(double4 *)(nrec + 8 * (int64_t)k) = g;
@@ -897,14 +945,14 @@ template <int BATCH>
 __device__ __forceinline__ void internal_node(
     int k, int level, int64_t n, int nn, const uint8_t *__restrict__ nlev,
     const double4 *__restrict__ ngeo, int4 *ninfo, int32_t *npar, double *mom64, float4 *nrec,
-    int32_t *flags)
+    double *spec, int32_t *flags)
 {
     const int p = ninfo[k].x;
     if (p < 0 || (int64_t)p >= n) {
         atomicOr(flags, UCP_FLAG_INTERNAL);
         return;
     }
-    moments_internal<BATCH>(k, p, level, nn, nlev, ngeo, ninfo, npar, mom64, nrec, flags);
+    moments_internal<BATCH>(k, p, level, nn, nlev, ngeo, ninfo, npar, mom64, nrec, spec, flags);
 }
 
 // Internal level maxl - 1 - j, with maxl the deepest leaf level: the
@@ -915,7 +963,7 @@ constexpr int kDeepThreads = 256, kDeepLevels = 4;
 __global__ __launch_bounds__(kDeepThreads) void k_moments_level(
     int j, int64_t n, const int32_t *__restrict__ noff, const uint8_t *__restrict__ nlev,
     const double4 *__restrict__ ngeo, int4 *ninfo, int32_t *npar, double *mom64, float4 *nrec,
-    const unsigned long long *__restrict__ ctr, int32_t *flags)
+    double *spec, const unsigned long long *__restrict__ ctr, int32_t *flags)
 {
     if (*flags) return;
     const int l = (int)ctr[CTR_MAXLEVEL] - 1 - j;
@@ -924,7 +972,7 @@ __global__ __launch_bounds__(kDeepThreads) void k_moments_level(
     for (int64_t k = blockIdx.x * (int64_t)kDeepThreads + threadIdx.x; k < nn;
          k += (int64_t)gridDim.x * kDeepThreads)
         if ((int)nlev[k] == l)
-            internal_node<4>((int)k, l, n, nn, nlev, ngeo, ninfo, npar, mom64, nrec, flags);
+            internal_node<4>((int)k, l, n, nn, nlev, ngeo, ninfo, npar, mom64, nrec, spec, flags);
 }
 
 // Grid-wide barrier of a launch whose blocks are all resident at once (one
@@ -963,7 +1011,7 @@ constexpr int kUpChunk = kUpThreads * kUpScan;
 __global__ __launch_bounds__(kUpThreads) void k_moments_up(
     int64_t n, const int32_t *__restrict__ noff, const uint8_t *__restrict__ nlev,
     const double4 *__restrict__ ngeo, int4 *ninfo, int32_t *npar, double *mom64, float4 *nrec,
-    unsigned long long *ctr, int32_t *flags)
+    double *spec, unsigned long long *ctr, int32_t *flags)
 {
     // the matching nodes of one chunk of the preorder, gathered so that the
     // block's threads share them evenly
@@ -998,7 +1046,8 @@ __global__ __launch_bounds__(kUpThreads) void k_moments_up(
             }
             __syncthreads();
             for (int i = threadIdx.x; i < nmatch; i += kUpThreads)
-                internal_node<2>(match[i], l, n, nn, nlev, ngeo, ninfo, npar, mom64, nrec, flags);
+                internal_node<2>(match[i], l, n, nn, nlev, ngeo, ninfo, npar, mom64, nrec, spec,
+                                 flags);
             __syncthreads();
         }
         if (l == 0 || !wait) continue;
@@ -1176,22 +1225,24 @@ void launch_build(Ctx *c, const double *x, const double *q, const int64_t *offse
                        c->d_nlev, (const int32_t *)c->d_lvlmax,
                        (int)((n + 1 + kLvlTile - 1) / kLvlTile), c->d_ctr, c->d_flags);
     // 6. moments: every leaf, then the internal levels from the deepest up
+    //    (and the per-species pseudo-particles when the walk uses them)
+    double *spec = c->p.expansion == UCP_EXPANSION_SPECIES ? c->d_spec : nullptr;
     hipLaunchKernelGGL(k_leaf_moments, grid_for(n, kLeafThreads), dim3(kLeafThreads), 0, s,
                        (const double4 *)c->d_xq, n, (const int8_t *)c->d_L,
                        (const int8_t *)c->d_leaf, (const int32_t *)c->d_lend,
                        (const int32_t *)c->d_noff, (const double4 *)c->d_ngeo, c->d_ninfo,
-                       c->d_mom64, c->d_nrec, c->d_leafof, (const int32_t *)c->d_flags);
+                       c->d_mom64, c->d_nrec, c->d_leafof, spec, (const int32_t *)c->d_flags);
     const int deep_blocks = (int)std::min<int64_t>((c->node_cap + kDeepThreads - 1) / kDeepThreads,
                                                    16384);
     for (int j = 0; j < kDeepLevels; ++j)
         hipLaunchKernelGGL(k_moments_level, dim3(deep_blocks), dim3(kDeepThreads), 0, s, j, n,
                            (const int32_t *)c->d_noff, (const uint8_t *)c->d_nlev,
                            (const double4 *)c->d_ngeo, c->d_ninfo, c->d_npar, c->d_mom64,
-                           c->d_nrec, (const unsigned long long *)c->d_ctr, c->d_flags);
+                           c->d_nrec, spec, (const unsigned long long *)c->d_ctr, c->d_flags);
     hipLaunchKernelGGL(k_moments_up, dim3(std::min(kUpBlocks, std::max(c->num_cu, 1))),
                        dim3(kUpThreads), 0, s, n, (const int32_t *)c->d_noff,
                        (const uint8_t *)c->d_nlev, (const double4 *)c->d_ngeo, c->d_ninfo,
-                       c->d_npar, c->d_mom64, c->d_nrec, c->d_ctr, c->d_flags);
+                       c->d_npar, c->d_mom64, c->d_nrec, spec, c->d_ctr, c->d_flags);
     // 7. groups
     hipLaunchKernelGGL(k_group_count, grid_for(n + 1, 256), dim3(256), 0, s, n,
                        (const int8_t *)c->d_L, (const int8_t *)c->d_leaf,

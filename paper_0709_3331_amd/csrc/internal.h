@@ -27,6 +27,7 @@ constexpr int kScanSmallItems = 64;            // elements per thread, one-block
 // three-kernel scan
 constexpr int64_t kScanSmallLimit = 4096;
 constexpr uint8_t kLeafBit = 0x80;             // leaf flag of the per-node level byte
+constexpr int kSpecVals = 12;                   // doubles per node of the species pseudo-particles
 
 // device counter slots (unsigned long long)
 enum { CTR_P2P = 0, CTR_M2P = 1, CTR_MAXLEVEL = 2, CTR_BARRIER = 3, CTR_VJPMAX = 4, CTR_NCTR = 8 };
@@ -106,6 +107,9 @@ struct Ctx {
     int4 *d_ninfo = nullptr;                // [node_cap] first, count, skip, level | 256*leaf
     int32_t *d_npar = nullptr;              // [node_cap] parent (-1 for a root)
     uint8_t *d_nlev = nullptr;              // [node_cap + 128] level of each node, | kLeafBit for a leaf
+    // per-species pseudo-particles (UCP_EXPANSION_SPECIES), allocated when that
+    // expansion is first set: c+[3] Q+ c-[3] Q- delta+ delta- 0 0
+    double *d_spec = nullptr;               // [node_cap][kSpecVals]
     double *d_mom64 = nullptr;              // [node_cap][16] cx cy cz Q p[3] trS S[6] 0 0
     // node record for the walk, two 64-byte lines per node:
     //   line 1: cx cy cz side^2 (double), skip first count level|256*leaf (int)

@@ -66,6 +66,8 @@ struct WalkArgs {
     float eps2f;
     double inv_lambda;      // 1 / lambda_ei under the Kelbg pair law
     float inv_lambdaf;
+    const double *spec;     // per-species pseudo-particles (UCP_EXPANSION_SPECIES)
+    double theta;
     int L;
 };
 
@@ -196,6 +198,36 @@ __device__ __forceinline__ void m2p_rec(const T *r, T tx, T ty, T tz, T eps2, T 
         m2p_eval<T, PHI>(tx - a.x, ty - a.y, tz - b.x, b.y, c.x, c.y, d.x, e.x, e.y, f.x, f.y, g.x,
                          g.y, d.y, eps2, ex, ey, ez, ph);
     }
+}
+
+// the two per-species pseudo-particles of an accepted box (staged as c+ Q+
+// c- Q-, offsets in FP32 or positions in FP64), each softened like a pair
+template <typename T, bool PHI>
+__device__ __forceinline__ void m2p_species(const T *r, T tx, T ty, T tz, T eps2, T &ex, T &ey,
+                                            T &ez, T &ph)
+{
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp) {
+        const T *v = r + 4 * sp;
+        const T rx = tx - v[0], ry = ty - v[1], rz = tz - v[2], q = v[3];
+        const T h2 = fma(rx, rx, fma(ry, ry, fma(rz, rz, eps2)));
+        T ih;
+        if constexpr (sizeof(T) == 4) ih = __builtin_amdgcn_rsqf(h2);
+        else ih = 1.0 / sqrt(h2);
+        const T w = q * (ih * ih * ih);
+        ex = fma(w, rx, ex);
+        ey = fma(w, ry, ey);
+        ez = fma(w, rz, ez);
+        if (PHI) ph = fma(q, ih, ph);
+    }
+}
+
+template <typename T, bool PHI, bool SPEC>
+__device__ __forceinline__ void m2p_entry(const T *r, T tx, T ty, T tz, T eps2, T &ex, T &ey,
+                                          T &ez, T &ph)
+{
+    if constexpr (SPEC) m2p_species<T, PHI>(r, tx, ty, tz, eps2, ex, ey, ez, ph);
+    else m2p_rec<T, PHI>(r, tx, ty, tz, eps2, ex, ey, ez, ph);
 }
 
 // ---------------------------------------------------------------------------
@@ -425,7 +457,7 @@ struct Target {
 // staged entries gives each lane one entry, loops over the group's targets
 // (broadcast from their lanes) and adds the entry's source-side cotangent to
 // the global per-cell or per-particle arrays.
-template <int PREC, int MODE, bool KELBG, typename T>
+template <int PREC, int MODE, bool KELBG, bool SPEC, typename T>
 __device__ __forceinline__ void flush_lists(const WalkArgs &a, const int4 *ml, int nm,
                                             const int2 *pl, int np, T *stage, int *pfx,
                                             int *lfirst, int lane, int sub, int lpt, int c,
@@ -443,7 +475,21 @@ __device__ __forceinline__ void flush_lists(const WalkArgs &a, const int4 *ml, i
         const int k = ent.x;
         {
             T *rec = stage + kRec * lane;
-            if constexpr (PREC == UCP_SPLIT && ADJ) {
+            if constexpr (SPEC) {
+                const double *sr = a.spec + kSpecVals * (int64_t)k;
+                const double4 pp = *(const double4 *)sr, pm = *(const double4 *)(sr + 4);
+                if constexpr (PREC == UCP_SPLIT) {
+                    float4 *d4 = (float4 *)rec;
+                    d4[0] = make_float4((float)(pp.x - cg.x), (float)(pp.y - cg.y),
+                                        (float)(pp.z - cg.z), (float)pp.w);
+                    d4[1] = make_float4((float)(pm.x - cg.x), (float)(pm.y - cg.y),
+                                        (float)(pm.z - cg.z), (float)pm.w);
+                } else {
+                    double4 *d4 = (double4 *)rec;
+                    d4[0] = pp;
+                    d4[1] = pm;
+                }
+            } else if constexpr (PREC == UCP_SPLIT && ADJ) {
                 const float4 *m4 = a.nrec + 8 * (int64_t)k;
                 const double4 geo = *(const double4 *)m4;
                 const float4 r1 = m4[4], r2 = m4[5], r3 = m4[6];
@@ -485,17 +531,17 @@ __device__ __forceinline__ void flush_lists(const WalkArgs &a, const int4 *ml, i
                 int e = 0;
                 for (; e + 1 < cnt; e += 2) {
                     const T *r0 = stage + kRec * e;
-                    m2p_rec<T, PHI>(r0, tx, ty, tz, eps2, ex, ey, ez, ph);
-                    m2p_rec<T, PHI>(r0 + kRec, tx, ty, tz, eps2, fx, fy, fz, fp);
+                    m2p_entry<T, PHI, SPEC>(r0, tx, ty, tz, eps2, ex, ey, ez, ph);
+                    m2p_entry<T, PHI, SPEC>(r0 + kRec, tx, ty, tz, eps2, fx, fy, fz, fp);
                 }
-                if (e < cnt) m2p_rec<T, PHI>(stage + kRec * e, tx, ty, tz, eps2, ex, ey, ez, ph);
+                if (e < cnt) m2p_entry<T, PHI, SPEC>(stage + kRec * e, tx, ty, tz, eps2, ex, ey, ez, ph);
             } else {
                 int e = sub;
                 for (; e + lpt < cnt; e += 2 * lpt) {
-                    m2p_rec<T, PHI>(stage + kRec * e, tx, ty, tz, eps2, ex, ey, ez, ph);
-                    m2p_rec<T, PHI>(stage + kRec * (e + lpt), tx, ty, tz, eps2, fx, fy, fz, fp);
+                    m2p_entry<T, PHI, SPEC>(stage + kRec * e, tx, ty, tz, eps2, ex, ey, ez, ph);
+                    m2p_entry<T, PHI, SPEC>(stage + kRec * (e + lpt), tx, ty, tz, eps2, fx, fy, fz, fp);
                 }
-                if (e < cnt) m2p_rec<T, PHI>(stage + kRec * e, tx, ty, tz, eps2, ex, ey, ez, ph);
+                if (e < cnt) m2p_entry<T, PHI, SPEC>(stage + kRec * e, tx, ty, tz, eps2, ex, ey, ez, ph);
             }
             tg.E0 += (double)(ex + fx);
             tg.E1 += (double)(ey + fy);
@@ -653,7 +699,7 @@ __device__ __forceinline__ void flush_lists(const WalkArgs &a, const int4 *ml, i
     }
 }
 
-template <int PREC, int MODE, bool KELBG>
+template <int PREC, int MODE, bool KELBG, bool SPEC>
 __global__ __launch_bounds__(256) void k_walk(WalkArgs a)
 {
     using T = typename std::conditional<PREC == UCP_SPLIT, float, double>::type;
@@ -742,7 +788,7 @@ __global__ __launch_bounds__(256) void k_walk(WalkArgs a)
         const double th2 = a.th2;
         while (sp > 0) {
             if (nm > L - 64 || np > L - 64) {
-                flush_lists<PREC, MODE, KELBG>(a, ml, nm, pl, np, stage, pfx, lfirst, lane, sub, lpt, c,
+                flush_lists<PREC, MODE, KELBG, SPEC>(a, ml, nm, pl, np, stage, pfx, lfirst, lane, sub, lpt, c,
                                         gfirst, cg, tg);
                 nm = np = 0;
             }
@@ -756,19 +802,50 @@ __global__ __launch_bounds__(256) void k_walk(WalkArgs a)
             const float4 *rp = a.nrec + 8 * (int64_t)k;
             const double4 geo = *(const double4 *)rp;
             const int4 inf = *(const int4 *)(rp + 2);   // skip, first, count, level|256*leaf
-            // opening test, Eq. (5): accept iff s^2 < theta^2 d^2 for every member.
+            // distances from the group's bounding box to a point, nearest and
+            // farthest, squared
+            auto box_d2 = [&](double px, double py, double pz, double &dmin2, double &dmax2) {
+                const double nx = fmax(0.0, fmax(bminx - px, px - bmaxx));
+                const double ny = fmax(0.0, fmax(bminy - py, py - bmaxy));
+                const double nz = fmax(0.0, fmax(bminz - pz, pz - bmaxz));
+                const double fx = fmax(fabs(bminx - px), fabs(bmaxx - px));
+                const double fy = fmax(fabs(bminy - py), fabs(bmaxy - py));
+                const double fz = fmax(fabs(bminz - pz), fabs(bmaxz - pz));
+                dmin2 = nx * nx + ny * ny + nz * nz;
+                dmax2 = fx * fx + fy * fy + fz * fz;
+            };
             // The group box bounds decide when a margin far above rounding
             // proves every member agrees; otherwise every member is tested.
-            const double nx = fmax(0.0, fmax(bminx - geo.x, geo.x - bmaxx));
-            const double ny = fmax(0.0, fmax(bminy - geo.y, geo.y - bmaxy));
-            const double nz = fmax(0.0, fmax(bminz - geo.z, geo.z - bmaxz));
-            const double fx = fmax(fabs(bminx - geo.x), fabs(bmaxx - geo.x));
-            const double fy = fmax(fabs(bminy - geo.y), fabs(bmaxy - geo.y));
-            const double fz = fmax(fabs(bminz - geo.z), fabs(bmaxz - geo.z));
-            const double dmin2 = nx * nx + ny * ny + nz * nz;
-            const double dmax2 = fx * fx + fy * fy + fz * fz;
-            const bool sure_acc = geo.w < th2 * dmin2 * (1.0 - 1e-12);
-            const bool sure_open = geo.w >= th2 * dmax2 * (1.0 + 1e-12);
+            bool sure_acc, sure_open;
+            double4 sp_p = make_double4(0, 0, 0, 0), sp_m = sp_p;   // c_s, Q_s
+            double R2p = 0.0, R2m = 0.0;
+            if constexpr (SPEC) {
+                // Eq. (5) per species: accept iff (s/theta + delta_s)^2 < d_s^2
+                // for every member and every sign the box holds (theta = 0:
+                // s/theta is infinite and nothing is accepted)
+                const double *sr = a.spec + kSpecVals * (int64_t)k;
+                sp_p = *(const double4 *)sr;
+                sp_m = *(const double4 *)(sr + 4);
+                const double2 dl = *(const double2 *)(sr + 8);
+                const double sth = sqrt(geo.w) / a.theta;
+                R2p = (sth + dl.x) * (sth + dl.x);
+                R2m = (sth + dl.y) * (sth + dl.y);
+                double pmin2, pmax2, mmin2, mmax2;
+                box_d2(sp_p.x, sp_p.y, sp_p.z, pmin2, pmax2);
+                box_d2(sp_m.x, sp_m.y, sp_m.z, mmin2, mmax2);
+                const bool hp = sp_p.w != 0.0, hm = sp_m.w != 0.0;
+                sure_acc = (!hp || R2p < pmin2 * (1.0 - 1e-12)) &&
+                           (!hm || R2m < mmin2 * (1.0 - 1e-12));
+                sure_open = (hp && R2p >= pmax2 * (1.0 + 1e-12)) ||
+                            (hm && R2m >= mmax2 * (1.0 + 1e-12));
+            } else {
+                // Eq. (5) about the box centre: accept iff s^2 < theta^2 d^2
+                // for every member
+                double dmin2, dmax2;
+                box_d2(geo.x, geo.y, geo.z, dmin2, dmax2);
+                sure_acc = geo.w < th2 * dmin2 * (1.0 - 1e-12);
+                sure_open = geo.w >= th2 * dmax2 * (1.0 + 1e-12);
+            }
             const bool band = have && !sure_acc && !sure_open;
             bool acc = sure_acc;
             // nodes in the band one at a time: the node is broadcast from its
@@ -777,12 +854,27 @@ __global__ __launch_bounds__(256) void k_walk(WalkArgs a)
             while (bandm != 0ull) {
                 const int bl = __builtin_ctzll(bandm);
                 bandm &= bandm - 1ull;
-                const double dx = xi.x - readlane_d(geo.x, bl);
-                const double dy = xi.y - readlane_d(geo.y, bl);
-                const double dz = xi.z - readlane_d(geo.z, bl);
-                const double s2 = readlane_d(geo.w, bl);
-                const double d2 = fma(dz, dz, fma(dy, dy, dx * dx));
-                const bool fail = act && !(s2 < th2 * d2);
+                bool fail;
+                if constexpr (SPEC) {
+                    const double qp = readlane_d(sp_p.w, bl), qm = readlane_d(sp_m.w, bl);
+                    const double px = xi.x - readlane_d(sp_p.x, bl);
+                    const double py = xi.y - readlane_d(sp_p.y, bl);
+                    const double pz = xi.z - readlane_d(sp_p.z, bl);
+                    const double mx = xi.x - readlane_d(sp_m.x, bl);
+                    const double my = xi.y - readlane_d(sp_m.y, bl);
+                    const double mz = xi.z - readlane_d(sp_m.z, bl);
+                    const double rp = readlane_d(R2p, bl), rm = readlane_d(R2m, bl);
+                    const double dp = fma(pz, pz, fma(py, py, px * px));
+                    const double dm = fma(mz, mz, fma(my, my, mx * mx));
+                    fail = act && ((qp != 0.0 && !(rp < dp)) || (qm != 0.0 && !(rm < dm)));
+                } else {
+                    const double dx = xi.x - readlane_d(geo.x, bl);
+                    const double dy = xi.y - readlane_d(geo.y, bl);
+                    const double dz = xi.z - readlane_d(geo.z, bl);
+                    const double s2 = readlane_d(geo.w, bl);
+                    const double d2 = fma(dz, dz, fma(dy, dy, dx * dx));
+                    fail = act && !(s2 < th2 * d2);
+                }
                 const bool ok = __ballot(fail) == 0ull;
                 acc = lane == bl ? ok : acc;
             }
@@ -818,7 +910,7 @@ __global__ __launch_bounds__(256) void k_walk(WalkArgs a)
             wave_sync();
         }
         if (overflow) atomicOr(a.flags_rw, lane == 0 ? UCP_FLAG_WALK_STACK : 0);
-        flush_lists<PREC, MODE, KELBG>(a, ml, nm, pl, np, stage, pfx, lfirst, lane, sub, lpt, c, gfirst,
+        flush_lists<PREC, MODE, KELBG, SPEC>(a, ml, nm, pl, np, stage, pfx, lfirst, lane, sub, lpt, c, gfirst,
                                 cg, tg);
         // sum the lpt partial results of each target in fixed lane order
         double *red = (double *)stage;   // 64 x 4 doubles
@@ -994,13 +1086,36 @@ __global__ __launch_bounds__(256) void k_vjp_down(const double4 *__restrict__ ac
     xbar[3 * i + 2] = sc * (g.z + xsrc[4 * p + 2] + x.w * bz);
 }
 
-template <int PREC, int MODE, bool KELBG = false>
+template <int PREC, int MODE, bool KELBG = false, bool SPEC = false>
 static void launch_walk_t(Ctx *c, const WalkArgs &wa, hipStream_t s)
 {
     const int waves_per_cu = c->p_built.walk_waves > 0 ? c->p_built.walk_waves : 32;
     const int blocks = (c->num_cu * waves_per_cu + 3) / 4;
     const size_t lds = (size_t)4 * walk_wave_bytes<PREC>(wa.L);
-    hipLaunchKernelGGL((k_walk<PREC, MODE, KELBG>), dim3(blocks), dim3(256), lds, s, wa);
+    hipLaunchKernelGGL((k_walk<PREC, MODE, KELBG, SPEC>), dim3(blocks), dim3(256), lds, s, wa);
+}
+
+// the force walks: precision x (forces | forces and potentials) x pair law x
+// expansion
+template <int PREC>
+static void launch_force_walk(Ctx *c, const WalkArgs &wa, bool phi, bool kelbg, bool spec,
+                              hipStream_t s)
+{
+    if (spec) {
+        if (kelbg) {
+            if (phi) launch_walk_t<PREC, kWalkForcePhi, true, true>(c, wa, s);
+            else launch_walk_t<PREC, kWalkForce, true, true>(c, wa, s);
+        } else {
+            if (phi) launch_walk_t<PREC, kWalkForcePhi, false, true>(c, wa, s);
+            else launch_walk_t<PREC, kWalkForce, false, true>(c, wa, s);
+        }
+    } else if (kelbg) {
+        if (phi) launch_walk_t<PREC, kWalkForcePhi, true>(c, wa, s);
+        else launch_walk_t<PREC, kWalkForce, true>(c, wa, s);
+    } else {
+        if (phi) launch_walk_t<PREC, kWalkForcePhi>(c, wa, s);
+        else launch_walk_t<PREC, kWalkForce>(c, wa, s);
+    }
 }
 
 static WalkArgs walk_args(Ctx *c)
@@ -1028,6 +1143,8 @@ static WalkArgs walk_args(Ctx *c)
     wa.eps2f = (float)wa.eps2;
     wa.inv_lambda = c->p_built.pair_law == UCP_PAIR_KELBG ? 1.0 / c->p_built.lambda_ei : 0.0;
     wa.inv_lambdaf = (float)wa.inv_lambda;
+    wa.spec = c->d_spec;
+    wa.theta = c->p_built.theta;
     wa.L = c->p_built.list_len;
     return wa;
 }
@@ -1053,22 +1170,11 @@ void launch_forces(Ctx *c, double *f, double *phi, hipStream_t s)
     }
     const bool want_phi = phi != nullptr || f == nullptr;
     const bool kelbg = c->p_built.pair_law == UCP_PAIR_KELBG;
+    const bool spec = c->p_built.expansion == UCP_EXPANSION_SPECIES;
     if (c->p_built.precision == UCP_SPLIT) {
-        if (kelbg) {
-            if (want_phi) launch_walk_t<UCP_SPLIT, kWalkForcePhi, true>(c, wa, s);
-            else launch_walk_t<UCP_SPLIT, kWalkForce, true>(c, wa, s);
-        } else {
-            if (want_phi) launch_walk_t<UCP_SPLIT, kWalkForcePhi>(c, wa, s);
-            else launch_walk_t<UCP_SPLIT, kWalkForce>(c, wa, s);
-        }
+        launch_force_walk<UCP_SPLIT>(c, wa, want_phi, kelbg, spec, s);
     } else {
-        if (kelbg) {
-            if (want_phi) launch_walk_t<UCP_FP64, kWalkForcePhi, true>(c, wa, s);
-            else launch_walk_t<UCP_FP64, kWalkForce, true>(c, wa, s);
-        } else {
-            if (want_phi) launch_walk_t<UCP_FP64, kWalkForcePhi>(c, wa, s);
-            else launch_walk_t<UCP_FP64, kWalkForce>(c, wa, s);
-        }
+        launch_force_walk<UCP_FP64>(c, wa, want_phi, kelbg, spec, s);
     }
     if (c->timing) (void)hipEventRecord(e1, s);
     hipLaunchKernelGGL(k_scatter, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,

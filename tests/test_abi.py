@@ -39,6 +39,7 @@ def test_default_params_and_version():
     assert p.theta == 0.5 and p.key_bits == 63 and p.leaf_cap == 24 and p.group_size == 64
     assert p.precision == L.UCP_SPLIT and p.group_mode == L.UCP_GROUP_CHUNK
     assert p.pair_law == L.UCP_PAIR_PLUMMER and p.lambda_ei == 0.0
+    assert p.expansion == L.UCP_EXPANSION_QUADRUPOLE
     assert L.ucp_version() >= 100
 
 
@@ -48,7 +49,8 @@ def test_default_params_and_version():
                                   dict(precision=3), dict(group_mode=2), dict(group_mode=-1),
                                   dict(pair_law=2), dict(pair_law=1, lambda_ei=0.0),
                                   dict(pair_law=1, lambda_ei=-0.5),
-                                  dict(pair_law=1, lambda_ei=0.1, eps=-1.0)])
+                                  dict(pair_law=1, lambda_ei=0.1, eps=-1.0),
+                                  dict(expansion=2), dict(expansion=-1)])
 def test_create_rejects_bad_params_without_gpu(over):
     p = L.default_params(**over)
     with pytest.raises(L.UcpError) as ei:
