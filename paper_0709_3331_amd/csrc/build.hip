@@ -490,6 +490,10 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_pass(
     for (int it = 0; it < kSortItems; ++it)
         if (valid[it]) {
             const uint32_t dst = boff[d[it]] + wh[it][w][d[it]] + lrank[it];
+            if ((int64_t)dst >= n) {   // only inconsistent prefixes lead here
+                atomicOr(flags, UCP_FLAG_INTERNAL);
+                continue;
+            }
             kout[dst] = k[it];
             vout[dst] = v[it];
         }
