@@ -80,7 +80,7 @@ void free_all(Ctx *c)
 {
     void *ptrs[] = {c->d_off,  c->d_mm,     c->d_cube,  c->d_key[0], c->d_key[1], c->d_val[0],
                     c->d_val[1], c->d_hist, c->d_histscan, c->d_xq, c->d_L,
-                    c->d_leaf, c->d_cnt,    c->d_lend, c->d_lvlmax, c->d_noff,  c->d_goff,   c->d_gnode,  c->d_scanblk,
+                    c->d_leaf, c->d_cnt,    c->d_lend, c->d_lvlmax, c->d_noff,  c->d_goff,   c->d_gnode,  c->d_gcl, c->d_scanblk,
                     c->d_ngeo, c->d_ninfo,  c->d_npar,  c->d_mom64,  c->d_nrec,
                     c->d_groups, c->d_gstat, c->d_acc,  c->d_ctr,    c->d_flags,  c->d_epart,
                     c->d_leafof, c->d_w,    c->d_xsrc,  c->d_cbar,  c->d_wq,
@@ -218,6 +218,7 @@ ucp_status ucp_create(ucp_ctx **out, int64_t n_max, int32_t clouds_max, const uc
     const size_t N = (size_t)n_max, NC = (size_t)c->node_cap;
 #define ALLOC(ptr, cnt) if (e == hipSuccess) e = dalloc(&(ptr), (size_t)(cnt))
     ALLOC(c->d_off, clouds_max + 1);
+    ALLOC(c->d_gcl, clouds_max + 1);
     ALLOC(c->d_mm, 6 * (size_t)clouds_max);
     ALLOC(c->d_cube, 2 * (size_t)clouds_max);
     ALLOC(c->d_key[0], N);

@@ -1104,6 +1104,56 @@ __global__ __launch_bounds__(256) void k_group_count(
     gnode[p] = gn;
 }
 
+// Chunk groups need no scan over positions: cloud c holds ceil(N_c / G)
+// groups, the g-th from its first particle on.  One block finds each cloud's
+// first group (and the total, read by the walk at goff[n]); then every group
+// is written from its index alone.
+__global__ __launch_bounds__(kScanBlock) void k_group_chunk_count(
+    const int64_t *__restrict__ off, int clouds, int G, int32_t *gcl, int32_t *goff_n,
+    const int32_t *flags)
+{
+    __shared__ int tot;
+    if (*flags) {   // no groups: the walk and the statistics read the total
+        if (threadIdx.x == 0) {
+            gcl[clouds] = 0;
+            *goff_n = 0;
+        }
+        return;
+    }
+    const int per = (clouds + kScanBlock - 1) / kScanBlock;
+    const int c0 = min(clouds, (int)threadIdx.x * per), c1 = min(clouds, c0 + per);
+    int mine = 0;
+    for (int c = c0; c < c1; ++c) mine += (int)((off[c + 1] - off[c] + G - 1) / G);
+    int run = block_excl_scan(mine, &tot);
+    for (int c = c0; c < c1; ++c) {
+        gcl[c] = run;
+        run += (int)((off[c + 1] - off[c] + G - 1) / G);
+    }
+    if (threadIdx.x == 0) {
+        gcl[clouds] = tot;
+        *goff_n = tot;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_group_chunk_emit(
+    const int64_t *__restrict__ off, int clouds, int G, const int32_t *__restrict__ gcl,
+    const int32_t *__restrict__ noff, int4 *groups, const int32_t *flags)
+{
+    if (*flags) return;
+    const int g = blockIdx.x * 256 + threadIdx.x;
+    if (g >= gcl[clouds]) return;
+    // the cloud holding group g: the last c with gcl[c] <= g (it has groups)
+    int lo = 0, hi = clouds;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (gcl[mid] <= g) lo = mid;
+        else hi = mid;
+    }
+    const int64_t p = off[lo] + (int64_t)(g - gcl[lo]) * G;
+    const int root = noff[off[lo]];
+    groups[g] = make_int4((int)p, (int)min<int64_t>(G, off[lo + 1] - p), root, root);
+}
+
 __global__ __launch_bounds__(256) void k_group_emit(
     int64_t n, const int32_t *__restrict__ cnt, const int32_t *__restrict__ goff,
     const int32_t *__restrict__ gnode, const int4 *__restrict__ ninfo,
@@ -1248,6 +1298,16 @@ void launch_build(Ctx *c, const double *x, const double *q, const int64_t *offse
                        (const uint8_t *)c->d_nlev, (const double4 *)c->d_ngeo, c->d_ninfo,
                        c->d_npar, c->d_mom64, c->d_nrec, spec, c->d_ctr, c->d_flags);
     // 7. groups
+    if (c->p.group_mode == UCP_GROUP_CHUNK) {
+        hipLaunchKernelGGL(k_group_chunk_count, dim3(1), dim3(kScanBlock), 0, s,
+                           (const int64_t *)c->d_off, clouds, G, c->d_gcl, c->d_goff + n,
+                           (const int32_t *)c->d_flags);
+        const int64_t gmax = (n + G - 1) / G + clouds;
+        hipLaunchKernelGGL(k_group_chunk_emit, grid_for(gmax, 256), dim3(256), 0, s,
+                           (const int64_t *)c->d_off, clouds, G, (const int32_t *)c->d_gcl,
+                           (const int32_t *)c->d_noff, c->d_groups, (const int32_t *)c->d_flags);
+        return;
+    }
     hipLaunchKernelGGL(k_group_count, grid_for(n + 1, 256), dim3(256), 0, s, n,
                        (const int8_t *)c->d_L, (const int8_t *)c->d_leaf,
                        (const int32_t *)c->d_noff, (const int4 *)c->d_ninfo,

@@ -101,6 +101,7 @@ struct Ctx {
     int32_t *d_noff = nullptr;              // [n_max + 1] first node starting at the position
     int32_t *d_goff = nullptr;              // [n_max + 1] first group starting at the position
     int32_t *d_gnode = nullptr;             // [n_max]
+    int32_t *d_gcl = nullptr;               // [clouds_max + 1] first chunk group of each cloud
     int32_t *d_scanblk = nullptr;           // scan block sums
     // nodes
     double4 *d_ngeo = nullptr;              // [node_cap] centre xyz, side^2
