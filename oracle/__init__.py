@@ -45,9 +45,9 @@ def _load():
         "orc_direct_targets": (None, [i64, _dp, _dp, dbl, i64, _i64p, _dp, vp]),
         "orc_direct_vjp": (None, [i64, _dp, _dp, dbl, _dp, _dp]),
         "orc_cube": (i32, [i64, _dp, _dp, C.POINTER(C.c_int)]),
-        "orc_keys": (None, [i64, _dp, _dp, i32, i32, _u64p]),
+        "orc_keys": (None, [i64, _dp, _dp, i32, i32, i32, _u64p]),
         "orc_sort": (None, [i64, _u64p, _i64p]),
-        "orc_tree_new": (vp, [i64, _dp, _dp, dbl, dbl, i32, i32, i32, i32, i32]),
+        "orc_tree_new": (vp, [i64, _dp, _dp, dbl, dbl, i32, i32, i32, i32, i32, i32]),
         "orc_tree_free": (None, [vp]),
         "orc_tree_nnodes": (i64, [vp]),
         "orc_tree_ngroups": (i64, [vp]),
@@ -63,8 +63,8 @@ def _load():
         "orc_tree_eval_groups": (i32, [vp, _dp, _dp, i64, _i64p, _dp, vp, vp, vp]),
         "orc_tree_arch_series": (i64, [vp, _i64p]),
         "orc_rebuild": (i64, [i64, _i64p, i64, _i64p, _i64p]),
-        "orc_verlet": (i32, [i64, _dp, _dp, _dp, _dp, i32, dbl, dbl, i32, i32, i32, i32, dbl,
-                             i32, _dp, i32]),
+        "orc_verlet": (i32, [i64, _dp, _dp, _dp, _dp, i32, dbl, dbl, i32, i32, i32, i32, i32,
+                             dbl, i32, _dp, i32]),
         "orc_energy": (None, [i64, _dp, _dp, _dp, _dp, _dp]),
         "orc_cell_eval": (None, [_dp, _dp, dbl, _dp, _dp]),
         "orc_cell_jacobian": (None, [_dp, _dp, dbl, _dp]),
@@ -111,6 +111,7 @@ def direct(x, q, eps):
 
 PAIR_PLUMMER, PAIR_KELBG = 0, 1
 EXP_QUADRUPOLE, EXP_SPECIES = 0, 1
+CURVE_MORTON, CURVE_HILBERT = 0, 1
 
 
 def direct_pair(x, q, eps, pair_law=PAIR_PLUMMER, lambda_ei=0.0):
@@ -157,11 +158,12 @@ def cube(x):
     return lo, e.value
 
 
-def keys(x, lo, e, b):
-    """Morton keys (per-bit interleave, x-major) for key depth b (10 or 21)."""
+def keys(x, lo, e, b, curve=CURVE_MORTON):
+    """Keys for key depth b (10 or 21): Morton (per-bit interleave, x-major) or
+    Hilbert (Skilling's transform, then the same interleave)."""
     x = _f64(x, (-1, 3))
     k = np.zeros(x.shape[0], dtype=np.uint64)
-    _load().orc_keys(x.shape[0], x, _f64(lo), int(e), int(b), k)
+    _load().orc_keys(x.shape[0], x, _f64(lo), int(e), int(b), int(curve), k)
     return k
 
 
@@ -178,17 +180,21 @@ class Tree:
     centres, walk groups and (optionally) frozen interaction lists.
 
     group_mode 0: node groups (a node of at most G particles whose parent holds
-    more); group_mode 1: consecutive runs of G key-sorted particles."""
+    more); group_mode 1: consecutive runs of G key-sorted particles.  curve:
+    the order of the keys (CURVE_MORTON or CURVE_HILBERT); it changes the
+    order of the boxes and of the particles, not the boxes themselves."""
 
     def __init__(self, x, q, theta, eps, b=21, leaf_cap=24, G=64, keep_lists=False, group_mode=1,
-                 pair_law=PAIR_PLUMMER, lambda_ei=0.0, expansion=EXP_QUADRUPOLE):
+                 pair_law=PAIR_PLUMMER, lambda_ei=0.0, expansion=EXP_QUADRUPOLE,
+                 curve=CURVE_MORTON):
         lib = _load()
         self.x = _f64(x, (-1, 3)); self.q = _f64(q)
         self.n = self.x.shape[0]
         self.theta, self.eps, self.b, self.leaf_cap, self.G = theta, eps, b, leaf_cap, G
-        self.group_mode = group_mode
+        self.group_mode, self.curve = group_mode, curve
         h = lib.orc_tree_new(self.n, self.x, self.q, float(theta), float(eps), int(b),
-                             int(leaf_cap), int(G), int(group_mode), int(bool(keep_lists)))
+                             int(leaf_cap), int(G), int(group_mode), int(bool(keep_lists)),
+                             int(curve))
         if not h:
             raise ValueError("oracle tree: invalid parameters or non-finite input")
         self._h = h
@@ -339,10 +345,11 @@ def rebuild(series, cap):
 
 
 def tree_forces(x, q, theta, eps, b=21, leaf_cap=24, G=64, want_phi=True, group_mode=1,
-                pair_law=PAIR_PLUMMER, lambda_ei=0.0, expansion=EXP_QUADRUPOLE):
+                pair_law=PAIR_PLUMMER, lambda_ei=0.0, expansion=EXP_QUADRUPOLE,
+                curve=CURVE_MORTON):
     """Convenience: build the oracle tree and evaluate it."""
     t = Tree(x, q, theta, eps, b, leaf_cap, G, group_mode=group_mode, pair_law=pair_law,
-             lambda_ei=lambda_ei, expansion=expansion)
+             lambda_ei=lambda_ei, expansion=expansion, curve=curve)
     r = t.eval(want_phi=want_phi)
     r["nodes"] = t.nnodes
     r["groups"] = t.ngroups
@@ -353,14 +360,15 @@ def tree_forces(x, q, theta, eps, b=21, leaf_cap=24, G=64, want_phi=True, group_
 # C-3 Verlet and energies.
 # --------------------------------------------------------------------------
 def verlet(x, v, q, m, dt, nsteps, eps, mode="direct", theta=0.5, b=21, leaf_cap=24, G=64,
-           f=None, group_mode=1):
+           f=None, group_mode=1, curve=CURVE_MORTON):
     """KDK velocity Verlet; returns (x, v, f) after nsteps (copies)."""
     x = _f64(x, (-1, 3)).copy(); v = _f64(v, (-1, 3)).copy()
     q = _f64(q); m = _f64(m)
     fv = 1 if f is not None else 0
     f = np.zeros_like(x) if f is None else _f64(f, (-1, 3)).copy()
     rc = _load().orc_verlet(x.shape[0], x, v, q, m, 0 if mode == "direct" else 1, float(theta),
-                            float(eps), int(b), int(leaf_cap), int(G), int(group_mode), float(dt),
+                            float(eps), int(b), int(leaf_cap), int(G), int(group_mode), int(curve),
+                            float(dt),
                             int(nsteps), f, fv)
     if rc != 0:
         raise ValueError("verlet failed")

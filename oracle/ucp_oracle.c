@@ -258,24 +258,49 @@ static uint64_t interleave_bits(uint64_t X, uint64_t Y, uint64_t Z, int b)
     return key;
 }
 
-static void deinterleave_bits(uint64_t key, int b, uint64_t *X, uint64_t *Y, uint64_t *Z)
+/* ------------------------------------------------------------------------- */
+/* C-2.2b  Hilbert keys.  The same cells, with the children of every box     */
+/* visited along a three-dimensional Hilbert curve instead of in octant      */
+/* order, so that consecutive keys are always face-adjacent cells.  The      */
+/* method is Skilling's transform (J. Skilling, "Programming the Hilbert     */
+/* curve", AIP Conf. Proc. 707, 381 (2004)): from the top bit down, each    */
+/* coordinate either flips the lower bits of the first coordinate or swaps   */
+/* them with its own; a Gray code across the coordinates and a final         */
+/* correction follow, and the three results, read bit level by bit level     */
+/* (first coordinate most significant), are the index.  The top 3l bits of  */
+/* the index name the level-l box, as the Morton digits do.                  */
+/* ------------------------------------------------------------------------- */
+static uint64_t hilbert_bits(uint64_t X, uint64_t Y, uint64_t Z, int b)
 {
-    uint64_t a = 0, c = 0, d = 0;
-    for (int t = 0; t < b; ++t) {
-        a |= ((key >> (3 * t + 2)) & 1u) << t;
-        c |= ((key >> (3 * t + 1)) & 1u) << t;
-        d |= ((key >> (3 * t + 0)) & 1u) << t;
+    uint64_t a[3] = {X, Y, Z};
+    for (uint64_t Q = ((uint64_t)1) << (b - 1); Q > 1; Q >>= 1) {
+        uint64_t P = Q - 1;                      /* the bits below Q */
+        for (int i = 0; i < 3; ++i) {
+            if (a[i] & Q) {
+                a[0] ^= P;                       /* flip them in the first coordinate */
+            } else {
+                uint64_t t = (a[0] ^ a[i]) & P;  /* swap them between a[0] and a[i] */
+                a[0] ^= t;
+                a[i] ^= t;
+            }
+        }
     }
-    *X = a; *Y = c; *Z = d;
+    for (int i = 1; i < 3; ++i) a[i] ^= a[i - 1];   /* Gray code */
+    uint64_t t = 0;
+    for (uint64_t Q = ((uint64_t)1) << (b - 1); Q > 1; Q >>= 1)
+        if (a[2] & Q) t ^= Q - 1;
+    for (int i = 0; i < 3; ++i) a[i] ^= t;
+    return interleave_bits(a[0], a[1], a[2], b);
 }
 
-void orc_keys(int64_t n, const double *x, const double *lo, int e, int b, uint64_t *key)
+/* curve 0: Morton order; curve 1: Hilbert order */
+void orc_keys(int64_t n, const double *x, const double *lo, int e, int b, int curve, uint64_t *key)
 {
     for (int64_t i = 0; i < n; ++i) {
         uint64_t X = quantise(x[3 * i + 0], lo[0], e, b);
         uint64_t Y = quantise(x[3 * i + 1], lo[1], e, b);
         uint64_t Z = quantise(x[3 * i + 2], lo[2], e, b);
-        key[i] = interleave_bits(X, Y, Z, b);
+        key[i] = curve == 1 ? hilbert_bits(X, Y, Z, b) : interleave_bits(X, Y, Z, b);
     }
 }
 
@@ -319,7 +344,9 @@ struct orc_tree {
     int b, leaf_cap, G;
     double lo[3];
     int e;
+    int curve;         /* 0: Morton keys, 1: Hilbert keys     */
     uint64_t *skey;    /* keys in sorted order                */
+    uint64_t *icoord;  /* [n][3] quantised coordinates, sorted order */
     int64_t *perm;     /* sorted position -> caller index     */
     /* nodes, preorder */
     int64_t M, Mcap;
@@ -376,13 +403,13 @@ static void build_rec(orc_tree *t, int lvl, int64_t f, int64_t c)
 static int is_leaf(const orc_tree *t, int64_t k) { return t->skip[k] == k + 1; }
 
 /* C-2.4  Box geometry: side s = L 2^-lvl and centre                          */
-/*   c_d = lo_d + (2 k_d + 1) L 2^-(lvl+1),  k_d = X_d >> (b - lvl).          */
+/*   c_d = lo_d + (2 k_d + 1) L 2^-(lvl+1),  k_d = X_d >> (b - lvl),          */
+/* X_d the quantised coordinate of any particle of the box (its first).       */
 static void node_centre(const orc_tree *t, int64_t k, double *c)
 {
-    uint64_t X, Y, Z;
-    deinterleave_bits(t->skey[t->first[k]], t->b, &X, &Y, &Z);
+    const uint64_t *X = t->icoord + 3 * t->first[k];
     int lvl = t->level[k];
-    uint64_t kk[3] = {X >> (t->b - lvl), Y >> (t->b - lvl), Z >> (t->b - lvl)};
+    uint64_t kk[3] = {X[0] >> (t->b - lvl), X[1] >> (t->b - lvl), X[2] >> (t->b - lvl)};
     for (int d = 0; d < 3; ++d)
         c[d] = t->lo[d] + (double)(2 * kk[d] + 1) * ldexp(1.0, t->e - lvl - 1);
 }
@@ -630,11 +657,12 @@ static void sorted_copy(const orc_tree *t, const double *x, const double *q, dou
 void orc_tree_free(orc_tree *t);
 
 orc_tree *orc_tree_new(int64_t n, const double *x, const double *q, double theta, double eps,
-                       int b, int leaf_cap, int G, int group_mode, int keep_lists)
+                       int b, int leaf_cap, int G, int group_mode, int keep_lists, int curve)
 {
     (void)q;
     if (n < 0 || (b != 10 && b != 21) || leaf_cap < 1 || G < 1) return NULL;
     if (group_mode != 0 && group_mode != 1) return NULL;
+    if (curve != 0 && curve != 1) return NULL;
     orc_tree *t = (orc_tree *)calloc(1, sizeof(orc_tree));
     t->n = n;
     t->theta = theta;
@@ -644,14 +672,20 @@ orc_tree *orc_tree_new(int64_t n, const double *x, const double *q, double theta
     t->G = G;
     t->group_mode = group_mode;
     t->keep_lists = keep_lists;
+    t->curve = curve;
     t->skey = (uint64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(uint64_t));
+    t->icoord = (uint64_t *)malloc((size_t)(n > 0 ? n : 1) * 3 * sizeof(uint64_t));
     t->perm = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
     if (n == 0) return t;
     if (orc_cube(n, x, t->lo, &t->e) != 0) { orc_tree_free(t); return NULL; }
     uint64_t *key = (uint64_t *)malloc((size_t)n * sizeof(uint64_t));
-    orc_keys(n, x, t->lo, t->e, b, key);
+    orc_keys(n, x, t->lo, t->e, b, curve, key);
     orc_sort(n, key, t->perm);
-    for (int64_t p = 0; p < n; ++p) t->skey[p] = key[t->perm[p]];
+    for (int64_t p = 0; p < n; ++p) {
+        t->skey[p] = key[t->perm[p]];
+        for (int d = 0; d < 3; ++d)
+            t->icoord[3 * p + d] = quantise(x[3 * t->perm[p] + d], t->lo[d], t->e, b);
+    }
     free(key);
     build_rec(t, 0, 0, n);
     t->centre = (double *)malloc((size_t)t->M * 3 * sizeof(double));
@@ -701,7 +735,7 @@ void orc_tree_free(orc_tree *t)
         free(t->np2p);
         free(t->nsrc);
     }
-    free(t->skey); free(t->perm);
+    free(t->skey); free(t->perm); free(t->icoord);
     free(t->level); free(t->first); free(t->count); free(t->skip); free(t->centre);
     free(t->gfirst); free(t->gcount); free(t->gnode);
     free(t);
@@ -1077,10 +1111,10 @@ int64_t orc_rebuild(int64_t len, const int64_t *series, int64_t cap, int64_t *pa
 /* when f_valid, and F(x_n) on exit.                                         */
 /* ------------------------------------------------------------------------- */
 static int forces_any(int mode, int64_t n, const double *x, const double *q, double theta,
-                      double eps, int b, int leaf_cap, int G, int group_mode, double *f)
+                      double eps, int b, int leaf_cap, int G, int group_mode, int curve, double *f)
 {
     if (mode == 0) { orc_direct(n, x, q, eps, f, NULL); return 0; }
-    orc_tree *t = orc_tree_new(n, x, q, theta, eps, b, leaf_cap, G, group_mode, 0);
+    orc_tree *t = orc_tree_new(n, x, q, theta, eps, b, leaf_cap, G, group_mode, 0, curve);
     if (!t) return -1;
     orc_tree_eval(t, x, q, f, NULL, NULL, NULL, NULL);
     orc_tree_free(t);
@@ -1088,10 +1122,10 @@ static int forces_any(int mode, int64_t n, const double *x, const double *q, dou
 }
 
 int orc_verlet(int64_t n, double *x, double *v, const double *q, const double *m, int mode,
-               double theta, double eps, int b, int leaf_cap, int G, int group_mode, double dt,
-               int nsteps, double *f, int f_valid)
+               double theta, double eps, int b, int leaf_cap, int G, int group_mode, int curve,
+               double dt, int nsteps, double *f, int f_valid)
 {
-    if (!f_valid && forces_any(mode, n, x, q, theta, eps, b, leaf_cap, G, group_mode, f))
+    if (!f_valid && forces_any(mode, n, x, q, theta, eps, b, leaf_cap, G, group_mode, curve, f))
         return -1;
     for (int s = 0; s < nsteps; ++s) {
         for (int64_t i = 0; i < n; ++i)
@@ -1099,7 +1133,7 @@ int orc_verlet(int64_t n, double *x, double *v, const double *q, const double *m
                 v[3 * i + d] += 0.5 * dt * f[3 * i + d] / m[i];
                 x[3 * i + d] += dt * v[3 * i + d];
             }
-        if (forces_any(mode, n, x, q, theta, eps, b, leaf_cap, G, group_mode, f)) return -1;
+        if (forces_any(mode, n, x, q, theta, eps, b, leaf_cap, G, group_mode, curve, f)) return -1;
         for (int64_t i = 0; i < n; ++i)
             for (int d = 0; d < 3; ++d) v[3 * i + d] += 0.5 * dt * f[3 * i + d] / m[i];
     }
