@@ -37,16 +37,21 @@ def walk_source_hash():
     return h.hexdigest()[:16]
 
 
+# order of the keys for every solver and oracle tree of the run (ucp_curve)
+CURVE = 1
+
+
 def traffic_from_profile(precision):
     """HBM bytes per walk launch from the committed rocprofv3 counter summary,
-    or None when the walk kernel changed since the counters were taken."""
+    or None when the walk kernel or the key order changed since the counters
+    were taken."""
     path = os.path.join(ROOT, "profiles", f"walk_{precision}_n524288_traffic.json")
     try:
         with open(path) as fh:
             d = json.load(fh)
     except OSError:
         return None
-    if d.get("walk_source_hash") != walk_source_hash():
+    if d.get("walk_source_hash") != walk_source_hash() or d.get("curve") != CURVE:
         return None
     return d.get("hbm_bytes_per_launch")
 
@@ -74,7 +79,7 @@ def bench_ensemble(args, prec, dev):
                           candidates={"group_size": (32, 64), "list_len": (128,),
                                       "group_mode": (1, 0), "leaf_cap": (8, 16, 24, 32)},
                           reps=2, use_cache=False)
-    ts = TreeSolver(n, clouds, theta=eprm["theta"], eps=eprm["eps"], precision=prec,
+    ts = TreeSolver(n, clouds, curve=CURVE, theta=eprm["theta"], eps=eprm["eps"], precision=prec,
                     group_size=tuned["group_size"], list_len=tuned["list_len"],
                     group_mode=tuned["group_mode"], leaf_cap=tuned["leaf_cap"])
     f = ts.tree_forces(x, q, offs)
@@ -155,7 +160,7 @@ def bench_adjoint(prec, dev):
     out = {"n": n, "eps": prm["eps"], "checkpoint_every": prm["ckpt"], "cases": {}}
     for th, dt, steps, hs, pr in cases:
         if (th, pr) not in solvers:
-            solvers[(th, pr)] = TreeSolver(n, theta=th, eps=prm["eps"], precision=pr)
+            solvers[(th, pr)] = TreeSolver(n, curve=CURVE, theta=th, eps=prm["eps"], precision=pr)
         ts = solvers[(th, pr)]
         print(f"bench: adjoint rollout N={n} theta={th} dt={dt} steps={steps}", file=sys.stderr,
               flush=True)
@@ -205,7 +210,7 @@ def bench_kelbg(args, prec, x, q, cl, plummer_walk_ms):
 
     lam = 0.005
     gm = L.UCP_GROUP_CHUNK if args.group_mode == "chunk" else L.UCP_GROUP_NODE
-    ts = TreeSolver(cl.n, theta=args.theta, eps=0.0, precision=prec, group_size=args.group_size,
+    ts = TreeSolver(cl.n, curve=CURVE, theta=args.theta, eps=0.0, precision=prec, group_size=args.group_size,
                     list_len=args.list_len, group_mode=gm, leaf_cap=args.leaf_cap,
                     walk_waves=args.walk_waves, pair_law=L.UCP_PAIR_KELBG, lambda_ei=lam)
     f = ts.tree_forces(x, q)
@@ -219,7 +224,7 @@ def bench_kelbg(args, prec, x, q, cl, plummer_walk_ms):
     ts.close()
     walk = wm / max(wc, 1)
     xs = x.cpu().numpy()   # the positions after the timed steps
-    t = oracle.Tree(xs, cl.q, args.theta, 0.0, G=args.group_size, group_mode=gm,
+    t = oracle.Tree(xs, cl.q, args.theta, 0.0, curve=CURVE, G=args.group_size, group_mode=gm,
                     leaf_cap=args.leaf_cap, pair_law=oracle.PAIR_KELBG, lambda_ei=lam)
     ref = t.eval_groups(np.arange(0, t.ngroups, 97))["f"]
     mask = ~np.isnan(ref[:, 0])
@@ -255,7 +260,7 @@ def opening_study(dev, dt=1e-6):
     m = torch.from_numpy(cl.m).to(dev)
 
     def run(theta, prec):
-        ts = TreeSolver(cl.n, theta=theta, eps=eps, precision=prec)
+        ts = TreeSolver(cl.n, curve=CURVE, theta=theta, eps=eps, precision=prec)
         x = torch.from_numpy(cl.x).to(dev)
         v = torch.from_numpy(cl.v).to(dev)
         f = ts.tree_forces(x, q)
@@ -333,7 +338,7 @@ def relaxation_study(dev, clouds=16, n_c=10000, steps=10000, every=250, dt=2e-5,
         return te.cpu().numpy(), ti.cpu().numpy()
 
     def run(theta):
-        ts = TreeSolver(n, clouds, theta=theta, eps=eps, precision=L.UCP_SPLIT)
+        ts = TreeSolver(n, clouds, curve=CURVE, theta=theta, eps=eps, precision=L.UCP_SPLIT)
         x = torch.from_numpy(x0.copy()).to(dev)
         v = torch.from_numpy(v0.copy()).to(dev)
         f = ts.tree_forces(x, q, off)
@@ -372,6 +377,8 @@ def main():
     ap.add_argument("--leaf-cap", type=int, default=24)
     ap.add_argument("--walk-waves", type=int, default=0)
     ap.add_argument("--group-mode", choices=["node", "chunk"], default="chunk")
+    ap.add_argument("--curve", choices=["morton", "hilbert"], default="hilbert",
+                    help="order of the keys, and so of the chunk groups")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 comparator run")
     ap.add_argument("--no-theta-sweep", action="store_true",
@@ -392,6 +399,8 @@ def main():
                     help="run a study instead of the benchmark and print its JSON line")
     ap.add_argument("--study-dt", type=float, default=1e-6, help="time step of the study")
     args = ap.parse_args()
+    global CURVE
+    CURVE = 1 if args.curve == "hilbert" else 0
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the method is not "
                           "sharded across GPUs in this build", "n_gpus": args.gpus}), flush=True)
@@ -421,7 +430,7 @@ def main():
     q = torch.from_numpy(cl.q).to(dev)
     m = torch.from_numpy(cl.m).to(dev)
     gm = L.UCP_GROUP_CHUNK if args.group_mode == "chunk" else L.UCP_GROUP_NODE
-    ts = TreeSolver(n, theta=theta, eps=eps, precision=prec, group_size=args.group_size,
+    ts = TreeSolver(n, curve=CURVE, theta=theta, eps=eps, precision=prec, group_size=args.group_size,
                     list_len=args.list_len, group_mode=gm, leaf_cap=args.leaf_cap,
                     walk_waves=args.walk_waves)
     print(f"bench: N={n} theta={theta} precision={args.precision}", file=sys.stderr, flush=True)
@@ -468,9 +477,11 @@ def main():
         "config": {"workload": f"single two-component Gaussian cloud N=524288 (sigma=1, 5% halo "
                                f"shell 2-3 sigma), theta={theta:g}, eps=0.005, G={args.group_size} "
                                f"({args.group_mode} groups), "
-                               f"leaf_cap={args.leaf_cap}, 63-bit keys, one KDK Verlet step dt=5e-5",
+                               f"leaf_cap={args.leaf_cap}, 63-bit {args.curve} keys, one KDK "
+                               f"Verlet step dt=5e-5",
                    "n": n, "theta": theta, "precision": args.precision,
-                   "group_size": args.group_size, "group_mode": args.group_mode},
+                   "group_size": args.group_size, "group_mode": args.group_mode,
+                   "curve": args.curve},
         "interactions_per_s": inter / (walk_avg_ms * 1e-3),
         "interactions_per_particle": inter / n,
         "walk_ms": walk_avg_ms,
@@ -482,7 +493,7 @@ def main():
         # accuracy against the plain FP64 GPU tree at identical parameters and
         # against the FP64 oracle direct sum on sampled targets
         f_split = ts.tree_forces(x, q)
-        ts64 = TreeSolver(n, theta=theta, eps=eps, precision=L.UCP_FP64,
+        ts64 = TreeSolver(n, curve=CURVE, theta=theta, eps=eps, precision=L.UCP_FP64,
                           group_size=args.group_size, list_len=args.list_len, group_mode=gm,
                           leaf_cap=args.leaf_cap, walk_waves=args.walk_waves)
         f64 = ts64.tree_forces(x, q)
@@ -512,7 +523,7 @@ def main():
             # interactions per particle, error against the sampled direct sum
             sweep = {}
             for th in (0.3, 0.5, 0.7):
-                tt = TreeSolver(n, theta=th, eps=eps, precision=prec, group_size=args.group_size,
+                tt = TreeSolver(n, curve=CURVE, theta=th, eps=eps, precision=prec, group_size=args.group_size,
                                 list_len=args.list_len, group_mode=gm, leaf_cap=args.leaf_cap,
                                 walk_waves=args.walk_waves)
                 ft = tt.tree_forces(x, q)
@@ -536,7 +547,7 @@ def main():
             # charge, Eq. (5) with delta) against the quadrupole above
             spc = {}
             for th in (0.3, 0.5, 0.7):
-                tt = TreeSolver(n, theta=th, eps=eps, precision=prec, group_size=args.group_size,
+                tt = TreeSolver(n, curve=CURVE, theta=th, eps=eps, precision=prec, group_size=args.group_size,
                                 list_len=args.list_len, group_mode=gm, leaf_cap=args.leaf_cap,
                                 walk_waves=args.walk_waves, expansion=L.UCP_EXPANSION_SPECIES)
                 ft = tt.tree_forces(x, q)
@@ -557,7 +568,7 @@ def main():
                 tt.close()
             result["species_pseudo_particles"] = spc
         c0 = time.perf_counter()
-        ot = oracle.Tree(xs, qs, theta, eps, G=args.group_size, group_mode=gm,
+        ot = oracle.Tree(xs, qs, theta, eps, curve=CURVE, G=args.group_size, group_mode=gm,
                          leaf_cap=args.leaf_cap)
         ro = ot.eval(want_phi=False)
         c1 = time.perf_counter()

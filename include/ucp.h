@@ -92,6 +92,22 @@ typedef enum {
     UCP_EXPANSION_SPECIES = 1
 } ucp_expansion;
 
+/* Order of the keys, and with it of the sorted particles and of the boxes
+ * (Sec. 3's octasection gives the boxes; the order is free).  Both orders
+ * give the same boxes and the same per-particle interaction lists; they
+ * differ in which particles form a chunk group (UCP_GROUP_CHUNK) and in the
+ * order of the nodes.
+ * UCP_CURVE_MORTON: the octant digits of the recursive subdivision, most
+ *   significant first (octant digit = 4 xbit + 2 ybit + zbit).
+ * UCP_CURVE_HILBERT: the boxes visited along a Hilbert curve (Skilling's
+ *   transform of the quantised coordinates, AIP Conf. Proc. 707, 381
+ *   (2004)): consecutive boxes are face-adjacent, so runs of G consecutive
+ *   particles are more compact and share shorter interaction lists.       */
+typedef enum {
+    UCP_CURVE_MORTON = 0,
+    UCP_CURVE_HILBERT = 1
+} ucp_curve;
+
 /* Method parameters.  The opening test is Eq. (5), s/theta + delta < d, with
  * the pseudo-particle expanded about the box centre (delta = 0), s the box
  * side and d the distance from the target to the box centre; it is evaluated
@@ -113,6 +129,7 @@ typedef struct {
     int32_t pair_law;      /* ucp_pair_law: the pair law of the particle-particle terms  */
     double lambda_ei;      /* Kelbg length lambda_ei of Eq. (4), > 0 (UCP_PAIR_KELBG)     */
     int32_t expansion;     /* ucp_expansion: what an accepted box contributes            */
+    int32_t curve;         /* ucp_curve: the order of the keys                           */
 } ucp_params;
 
 typedef struct ucp_ctx ucp_ctx;   /* opaque */
@@ -138,7 +155,7 @@ typedef struct {
 
 /* Default parameters: theta 0.5, eps 0.005, 63-bit keys, leaf_cap 24, G 64,
  * list_len 128, UCP_SPLIT, walk_waves 0, UCP_GROUP_CHUNK, UCP_PAIR_PLUMMER,
- * lambda_ei 0, UCP_EXPANSION_QUADRUPOLE.                                    */
+ * lambda_ei 0, UCP_EXPANSION_QUADRUPOLE, UCP_CURVE_HILBERT.                 */
 void ucp_default_params(ucp_params *p);
 
 /* Create a context on the current HIP device able to hold n_max particles in
@@ -149,11 +166,12 @@ ucp_status ucp_create(ucp_ctx **out, int64_t n_max, int32_t clouds_max, const uc
 void ucp_destroy(ucp_ctx *c);
 
 /* Replace the parameters (validated as in ucp_create).  A tree built before
- * with other key_bits/leaf_cap/group_size/group_mode must be rebuilt.        */
+ * with other key_bits/leaf_cap/group_size/group_mode/expansion/curve must be
+ * rebuilt.                                                                  */
 ucp_status ucp_set_params(ucp_ctx *c, const ucp_params *p);
 ucp_status ucp_get_params(const ucp_ctx *c, ucp_params *p);
 
-/* Build the tree of one cloud (Sec. 3): enclosing cube, Morton keys, stable
+/* Build the tree of one cloud (Sec. 3): enclosing cube, keys (ucp_curve), stable
  * radix sort, linear octree in preorder, cell moments (net charge, dipole and
  * quadrupole about each box centre, FP64) and walk groups.  x: [n][3], q: [n].
  * The library keeps sorted copies, so x and q may change after the call

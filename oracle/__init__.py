@@ -186,7 +186,7 @@ class Tree:
 
     def __init__(self, x, q, theta, eps, b=21, leaf_cap=24, G=64, keep_lists=False, group_mode=1,
                  pair_law=PAIR_PLUMMER, lambda_ei=0.0, expansion=EXP_QUADRUPOLE,
-                 curve=CURVE_MORTON):
+                 curve=CURVE_HILBERT):
         lib = _load()
         self.x = _f64(x, (-1, 3)); self.q = _f64(q)
         self.n = self.x.shape[0]
@@ -346,7 +346,7 @@ def rebuild(series, cap):
 
 def tree_forces(x, q, theta, eps, b=21, leaf_cap=24, G=64, want_phi=True, group_mode=1,
                 pair_law=PAIR_PLUMMER, lambda_ei=0.0, expansion=EXP_QUADRUPOLE,
-                curve=CURVE_MORTON):
+                curve=CURVE_HILBERT):
     """Convenience: build the oracle tree and evaluate it."""
     t = Tree(x, q, theta, eps, b, leaf_cap, G, group_mode=group_mode, pair_law=pair_law,
              lambda_ei=lambda_ei, expansion=expansion, curve=curve)
@@ -360,7 +360,7 @@ def tree_forces(x, q, theta, eps, b=21, leaf_cap=24, G=64, want_phi=True, group_
 # C-3 Verlet and energies.
 # --------------------------------------------------------------------------
 def verlet(x, v, q, m, dt, nsteps, eps, mode="direct", theta=0.5, b=21, leaf_cap=24, G=64,
-           f=None, group_mode=1, curve=CURVE_MORTON):
+           f=None, group_mode=1, curve=CURVE_HILBERT):
     """KDK velocity Verlet; returns (x, v, f) after nsteps (copies)."""
     x = _f64(x, (-1, 3)).copy(); v = _f64(v, (-1, 3)).copy()
     q = _f64(q); m = _f64(m)

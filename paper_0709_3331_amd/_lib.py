@@ -18,6 +18,7 @@ UCP_FP64, UCP_SPLIT = 0, 1
 UCP_GROUP_NODE, UCP_GROUP_CHUNK = 0, 1
 UCP_PAIR_PLUMMER, UCP_PAIR_KELBG = 0, 1
 UCP_EXPANSION_QUADRUPOLE, UCP_EXPANSION_SPECIES = 0, 1
+UCP_CURVE_MORTON, UCP_CURVE_HILBERT = 0, 1
 UCP_FLAG_NODE_OVERFLOW, UCP_FLAG_NONFINITE, UCP_FLAG_BAD_OFFSETS, UCP_FLAG_BAD_CUBE = 1, 2, 4, 8
 UCP_FLAG_INTERNAL, UCP_FLAG_WALK_STACK = 16, 32
 STATUS_NAMES = {0: "UCP_OK", -1: "UCP_EINVAL", -2: "UCP_ENOMEM", -3: "UCP_EHIP",
@@ -34,7 +35,8 @@ class ucp_params(C.Structure):
     _fields_ = [("theta", C.c_double), ("eps", C.c_double), ("key_bits", C.c_int32),
                 ("leaf_cap", C.c_int32), ("group_size", C.c_int32), ("list_len", C.c_int32),
                 ("precision", C.c_int32), ("walk_waves", C.c_int32), ("group_mode", C.c_int32),
-                ("pair_law", C.c_int32), ("lambda_ei", C.c_double), ("expansion", C.c_int32)]
+                ("pair_law", C.c_int32), ("lambda_ei", C.c_double), ("expansion", C.c_int32),
+                ("curve", C.c_int32)]
 
 
 class ucp_stats(C.Structure):

@@ -40,6 +40,10 @@ bool validate(const ucp_params *p, std::string &why)
         why = "expansion must be UCP_EXPANSION_QUADRUPOLE or UCP_EXPANSION_SPECIES";
         return false;
     }
+    if (p->curve != UCP_CURVE_MORTON && p->curve != UCP_CURVE_HILBERT) {
+        why = "curve must be UCP_CURVE_MORTON or UCP_CURVE_HILBERT";
+        return false;
+    }
     if (p->pair_law != UCP_PAIR_PLUMMER && p->pair_law != UCP_PAIR_KELBG) {
         why = "pair_law must be UCP_PAIR_PLUMMER or UCP_PAIR_KELBG";
         return false;
@@ -185,6 +189,7 @@ void ucp_default_params(ucp_params *p)
     p->pair_law = UCP_PAIR_PLUMMER;
     p->lambda_ei = 0.0;
     p->expansion = UCP_EXPANSION_QUADRUPOLE;
+    p->curve = UCP_CURVE_HILBERT;
 }
 
 const char *ucp_last_error(const ucp_ctx *c)
@@ -283,10 +288,11 @@ ucp_status ucp_set_params(ucp_ctx *c, const ucp_params *p)
     if (!c) return fail(nullptr, UCP_EINVAL, kNoCtx);
     std::string why;
     if (!validate(p, why)) return fail(c, UCP_EINVAL, "ucp_set_params: " + why);
-    // the expansion decides what the build computes, so it needs a new build
+    // the expansion and the curve decide what the build computes, so they need
+    // a new build
     const bool topo = p->key_bits != c->p.key_bits || p->leaf_cap != c->p.leaf_cap ||
                       p->group_size != c->p.group_size || p->group_mode != c->p.group_mode ||
-                      p->expansion != c->p.expansion;
+                      p->expansion != c->p.expansion || p->curve != c->p.curve;
     if (p->expansion == UCP_EXPANSION_SPECIES && !c->d_spec) {
         const hipError_t e = dalloc(&c->d_spec, (size_t)c->node_cap * ucp::kSpecVals);
         if (e != hipSuccess) {

@@ -4,7 +4,8 @@
 // split recursively into eight boxes until each box holds at most leaf_cap
 // particles.  Here the same tree is produced bottom-up and in parallel:
 //   1. enclosing cube per cloud (min/max reduction, side 2^e),
-//   2. Morton keys: the octant digits of the recursive subdivision,
+//   2. keys: the octant digits of the recursive subdivision (Morton order),
+//      or the same boxes numbered along a Hilbert curve,
 //   3. stable LSD radix sort of (key, index), 8-bit digits,
 //   4. per sorted position: the level of the common prefix with the previous
 //      key and the level of the leaf holding it; the nodes that start at a
@@ -13,7 +14,7 @@
 //   5. node records (box centre, side, first particle, level),
 //   6. moments (Q, p, S about the box centre, FP64), one level per launch from
 //      the deepest up: a leaf sums its particles, an internal node sums its
-//      children in octant order with the exact shift of origin; the same pass
+//      children in key order with the exact shift of origin; the same pass
 //      finds each node's particle count, skip link (first node after the
 //      subtree) and its children's parent,
 //   7. walk groups (node groups or consecutive runs of G particles).
@@ -191,8 +192,12 @@ __global__ void k_cube_finish(const unsigned long long *__restrict__ mm,
 }
 
 // ---------------------------------------------------------------------------
-// 2. Morton keys: X_d = min(floor((x_d - lo_d) 2^(b-e)), 2^b - 1), bits of X,
-//    Y, Z interleaved x-major (octant digit = 4 xbit + 2 ybit + zbit).
+// 2. keys from the quantised coordinates X_d = min(floor((x_d - lo_d) 2^(b-e)),
+//    2^b - 1).  Morton: bits of X, Y, Z interleaved x-major (octant digit =
+//    4 xbit + 2 ybit + zbit).  Hilbert: Skilling's transform (AIP Conf. Proc.
+//    707, 381 (2004)) turns (X, Y, Z) into the transposed Hilbert index, which
+//    is then interleaved the same way; the top 3l bits still name the level-l
+//    box, so everything downstream works on either.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint64_t quantise(double v, double lo, double scale, uint64_t top)
 {
@@ -203,9 +208,42 @@ __device__ __forceinline__ uint64_t quantise(double v, double lo, double scale, 
     return (uint64_t)f;
 }
 
+__device__ __forceinline__ uint64_t hilbert_key(uint32_t x, uint32_t y, uint32_t z, int b)
+{
+    // from the top bit down: where a coordinate has the bit set, the lower
+    // bits of x are inverted, otherwise they are exchanged with that
+    // coordinate's lower bits (a no-op for x itself)
+    for (uint32_t Q = 1u << (b - 1); Q > 1; Q >>= 1) {
+        const uint32_t P = Q - 1;
+        x = (x & Q) ? x ^ P : x;
+        uint32_t t = (x ^ y) & P;
+        const bool fy = (y & Q) != 0;
+        x ^= fy ? P : t;
+        y ^= fy ? 0u : t;
+        t = (x ^ z) & P;
+        const bool fz = (z & Q) != 0;
+        x ^= fz ? P : t;
+        z ^= fz ? 0u : t;
+    }
+    // Gray code across the coordinates
+    y ^= x;
+    z ^= y;
+    // then every bit j takes the parity of z's bits above j
+    uint32_t w = z >> 1;
+    w ^= w >> 1;
+    w ^= w >> 2;
+    w ^= w >> 4;
+    w ^= w >> 8;
+    w ^= w >> 16;
+    x ^= w;
+    y ^= w;
+    z ^= w;
+    return (spread3(x) << 2) | (spread3(y) << 1) | spread3(z);
+}
+
 __global__ __launch_bounds__(256) void k_keys(const double *__restrict__ x, int64_t n,
                                              const int64_t *__restrict__ off, int clouds,
-                                             const double4 *__restrict__ cube, int b,
+                                             const double4 *__restrict__ cube, int b, int curve,
                                              uint64_t *key, uint32_t *val,
                                              const int32_t *flags)
 {
@@ -218,7 +256,8 @@ __global__ __launch_bounds__(256) void k_keys(const double *__restrict__ x, int6
     uint64_t X = quantise(x[3 * i + 0], c0.x, c1.x, top);
     uint64_t Y = quantise(x[3 * i + 1], c0.y, c1.x, top);
     uint64_t Z = quantise(x[3 * i + 2], c0.z, c1.x, top);
-    key[i] = (spread3(X) << 2) | (spread3(Y) << 1) | spread3(Z);
+    key[i] = curve == UCP_CURVE_HILBERT ? hilbert_key((uint32_t)X, (uint32_t)Y, (uint32_t)Z, b)
+                                        : (spread3(X) << 2) | (spread3(Y) << 1) | spread3(Z);
     val[i] = (uint32_t)i;
 }
 
@@ -594,12 +633,14 @@ __global__ __launch_bounds__(kLvlTile) void k_levels(const uint64_t *__restrict_
 // 5. node records: the nodes starting at position p are the boxes of levels
 //    L(p)+1 .. leaf(p) holding p, numbered noff[p] + (l - L(p) - 1) in
 //    preorder.  This kernel writes what follows from p and l alone (box
-//    centre, side^2, first particle, level and leaf flag); the particle count,
+//    centre, side^2, first particle, level and leaf flag); the box's integer
+//    coordinates are those of particle p, quantised again exactly as the keys
+//    were, so no key is decoded and either curve works.  The particle count,
 //    the skip link and the parent are found by the moments pass below, which
 //    visits each node's children in order anyway.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_nodes(
-    const uint64_t *__restrict__ key, int64_t n, const int64_t *__restrict__ off, int clouds,
+    const double4 *__restrict__ xq, int64_t n, const int64_t *__restrict__ off, int clouds,
     const double4 *__restrict__ cube, int b, const int8_t *__restrict__ Lv,
     const int8_t *__restrict__ Lf, const int32_t *__restrict__ noff, int64_t node_cap,
     double4 *ngeo, int4 *ninfo, int32_t *npar, uint8_t *nlev, const int32_t *__restrict__ blkmax,
@@ -625,10 +666,12 @@ __global__ __launch_bounds__(256) void k_nodes(
     }
     if (p >= n || lf <= Lp) return;
     const int c = cloud_of(off, clouds, p);
-    const uint64_t kp = key[p];
-    const double4 c0 = cube[2 * c];
-    const int e = (int)cube[2 * c + 1].y;
-    const uint64_t X = compact3(kp >> 2), Y = compact3(kp >> 1), Z = compact3(kp);
+    const double4 xp = xq[p];
+    const double4 c0 = cube[2 * c], c1 = cube[2 * c + 1];
+    const int e = (int)c1.y;
+    const uint64_t top = (1ull << b) - 1;
+    const uint64_t X = quantise(xp.x, c0.x, c1.x, top), Y = quantise(xp.y, c0.y, c1.x, top),
+                   Z = quantise(xp.z, c0.z, c1.x, top);
     const int k0 = noff[p];
     for (int l = Lp + 1; l <= lf; ++l) {
         const int k = k0 + (l - Lp - 1);
@@ -1222,8 +1265,8 @@ void launch_build(Ctx *c, const double *x, const double *q, const int64_t *offse
                        c->d_cube, c->d_flags);
     // 2. keys
     hipLaunchKernelGGL(k_keys, grid_for(n, 256), dim3(256), 0, s, x, n, (const int64_t *)c->d_off,
-                       clouds, (const double4 *)c->d_cube, b, c->d_key[0], c->d_val[0],
-                       (const int32_t *)c->d_flags);
+                       clouds, (const double4 *)c->d_cube, b, c->p.curve, c->d_key[0],
+                       c->d_val[0], (const int32_t *)c->d_flags);
     // 3. sort
     const int ntiles = (int)((n + kSortTile - 1) / kSortTile);
     const int key_passes = (3 * b + 7) / 8;
@@ -1272,7 +1315,7 @@ void launch_build(Ctx *c, const double *x, const double *q, const int64_t *offse
                        (const int32_t *)c->d_flags);
     scan_excl((const int32_t *)c->d_cnt, c->d_noff, n + 1, c->d_scanblk, s);
     // 5. nodes
-    hipLaunchKernelGGL(k_nodes, grid_for(n, 256), dim3(256), 0, s, (const uint64_t *)c->d_skey, n,
+    hipLaunchKernelGGL(k_nodes, grid_for(n, 256), dim3(256), 0, s, (const double4 *)c->d_xq, n,
                        (const int64_t *)c->d_off, clouds, (const double4 *)c->d_cube, b,
                        (const int8_t *)c->d_L, (const int8_t *)c->d_leaf,
                        (const int32_t *)c->d_noff, c->node_cap, c->d_ngeo, c->d_ninfo, c->d_npar,

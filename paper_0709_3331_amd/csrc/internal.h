@@ -174,18 +174,6 @@ __device__ __forceinline__ uint64_t spread3(uint64_t v)
     return v;
 }
 
-// inverse of spread3
-__device__ __forceinline__ uint64_t compact3(uint64_t v)
-{
-    v &= 0x1249249249249249ull;
-    v = (v ^ (v >> 2)) & 0x10c30c30c30c30c3ull;
-    v = (v ^ (v >> 4)) & 0x100f00f00f00f00full;
-    v = (v ^ (v >> 8)) & 0x1f0000ff0000ffull;
-    v = (v ^ (v >> 16)) & 0x1f00000000ffffull;
-    v = (v ^ (v >> 32)) & 0x1fffffull;
-    return v;
-}
-
 // cloud holding particle i: largest c with off[c] <= i (off has clouds+1 entries)
 __device__ __forceinline__ int cloud_of(const int64_t *__restrict__ off, int clouds, int64_t i)
 {

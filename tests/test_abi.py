@@ -40,6 +40,7 @@ def test_default_params_and_version():
     assert p.precision == L.UCP_SPLIT and p.group_mode == L.UCP_GROUP_CHUNK
     assert p.pair_law == L.UCP_PAIR_PLUMMER and p.lambda_ei == 0.0
     assert p.expansion == L.UCP_EXPANSION_QUADRUPOLE
+    assert p.curve == L.UCP_CURVE_HILBERT
     assert L.ucp_version() >= 100
 
 
@@ -50,7 +51,8 @@ def test_default_params_and_version():
                                   dict(pair_law=2), dict(pair_law=1, lambda_ei=0.0),
                                   dict(pair_law=1, lambda_ei=-0.5),
                                   dict(pair_law=1, lambda_ei=0.1, eps=-1.0),
-                                  dict(expansion=2), dict(expansion=-1)])
+                                  dict(expansion=2), dict(expansion=-1),
+                                  dict(curve=2), dict(curve=-1)])
 def test_create_rejects_bad_params_without_gpu(over):
     p = L.default_params(**over)
     with pytest.raises(L.UcpError) as ei:

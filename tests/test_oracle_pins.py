@@ -185,7 +185,8 @@ def test_sort_is_stable_library_order():
 # --------------------------------------------------------------------------
 def test_tiny_tree_golden():
     g = _gold("tiny_tree.json")
-    t = oracle.Tree(g["x"], g["q"], 0.5, 0.01, b=g["b"], leaf_cap=g["leaf_cap"], G=1, group_mode=0)
+    t = oracle.Tree(g["x"], g["q"], 0.5, 0.01, b=g["b"], leaf_cap=g["leaf_cap"], G=1, group_mode=0,
+                    curve=oracle.CURVE_MORTON)   # the fixture is worked in octant order
     lo, e = t.cube()
     assert list(lo) == g["lo"] and e == g["e"]
     assert [int(v) for v in oracle.keys(g["x"], lo, e, g["b"])] == g["keys"]
@@ -247,7 +248,13 @@ def _check_tree_invariants(t, x, leaf_cap, G):
                 o = 4 * (d[0] > 0) + 2 * (d[1] > 0) + (d[2] > 0)
                 octs.append(o)
                 np.testing.assert_allclose(np.abs(d), s / 4, rtol=1e-12)
-            assert octs == sorted(octs) and len(set(octs)) == len(octs)
+            assert len(set(octs)) == len(octs)
+            if t.curve == oracle.CURVE_MORTON:
+                assert octs == sorted(octs)
+            elif len(octs) == 8:
+                # Hilbert: the eight octants in a Gray-code walk, each step to
+                # a face-adjacent box
+                assert all(bin(a ^ b).count("1") == 1 for a, b in zip(octs, octs[1:]))
     # leaves partition [0, n) in order
     pos = 0
     for k in leaves:
@@ -260,10 +267,11 @@ def _check_tree_invariants(t, x, leaf_cap, G):
     assert np.all(gc <= G)
 
 
+@pytest.mark.parametrize("curve", [oracle.CURVE_MORTON, oracle.CURVE_HILBERT])
 @pytest.mark.parametrize("leaf_cap,G,b", [(1, 1, 21), (8, 64, 21), (4, 16, 10), (16, 8, 21)])
-def test_tree_invariants_random(leaf_cap, G, b):
+def test_tree_invariants_random(leaf_cap, G, b, curve):
     cl = _rand_cloud(2000, 11)
-    t = oracle.Tree(cl.x, cl.q, 0.5, 0.01, b=b, leaf_cap=leaf_cap, G=G, group_mode=0)
+    t = oracle.Tree(cl.x, cl.q, 0.5, 0.01, b=b, leaf_cap=leaf_cap, G=G, group_mode=0, curve=curve)
     _check_tree_invariants(t, cl.x, leaf_cap, G)
 
 
