@@ -6,7 +6,8 @@
 //   1. enclosing cube per cloud (min/max reduction, side 2^e),
 //   2. keys: the octant digits of the recursive subdivision (Morton order),
 //      or the same boxes numbered along a Hilbert curve,
-//   3. stable LSD radix sort of (key, index), 8-bit digits,
+//   3. stable LSD radix sort of (key, index), 8-bit digits; the last pass
+//      also gathers x and q into the sorted order,
 //   4. per sorted position: the level of the common prefix with the previous
 //      key and the level of the leaf holding it; the nodes that start at a
 //      position are the levels in between, so a scan numbers all nodes in
@@ -56,38 +57,57 @@ void launch_fill_f64(double *p, double v, int64_t n, hipStream_t s)
     if (n > 0) hipLaunchKernelGGL(k_fill_f64, dim3((n + 255) / 256), dim3(256), 0, s, p, v, n);
 }
 
-// reset of the per-build state: min/max slots, counters, flag word
-// per-build state: cloud extents, counters, flags, the sort's tickets, digit
-// counts and the first pass's look-back status words
-__global__ void k_build_reset(unsigned long long *mm, int clouds, unsigned long long *ctr,
-                              uint32_t *sortctl, uint32_t *ghist, uint32_t *status0,
-                              int64_t nstatus, int32_t *flags)
+__device__ __forceinline__ int block_excl_scan(int v, int *total);
+
+// per-build state: cloud extents, counters, the sort's tickets, digit counts
+// and the first pass's look-back status words (every block); then block 0
+// clears the flag word, sets the cloud offsets ({0, n} for one cloud, or a
+// checked copy of the caller's) and, for chunk groups (G > 0), the first
+// chunk group of each cloud and their total
+__global__ __launch_bounds__(kScanBlock) void k_build_reset(
+    unsigned long long *mm, int clouds, unsigned long long *ctr, uint32_t *sortctl,
+    uint32_t *ghist, uint32_t *status0, int64_t nstatus, const int64_t *__restrict__ src_off,
+    int64_t n, int G, int64_t *off, int32_t *gcl, int32_t *goff_n, int32_t *flags)
 {
+    __shared__ int tot;
     const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (t0 < clouds * 6) mm[t0] = (t0 % 6 < 3) ? ~0ull : 0ull;
     if (t0 < CTR_NCTR) ctr[t0] = 0;
     if (t0 < kSortTickets) sortctl[t0] = 0;
     if (t0 < kSortPassesMax * 256) ghist[t0] = 0;
-    if (t0 == 0) *flags = 0;
     for (int64_t t = t0; t < nstatus; t += (int64_t)gridDim.x * blockDim.x) status0[t] = 0;
-}
-
-// cloud offsets: {0, n} for one cloud, or a checked copy of the caller's
-__global__ void k_offsets_single(int64_t *off, int64_t n)
-{
-    off[0] = 0;
-    off[1] = n;
-}
-
-__global__ void k_offsets_copy(int64_t *dst, const int64_t *__restrict__ src, int clouds,
-                               int64_t n, int32_t *flags)
-{
-    for (int c = threadIdx.x; c <= clouds; c += blockDim.x) {
-        int64_t v = src[c];
-        bool bad = (c == 0 && v != 0) || (c == clouds && v != n) || (c > 0 && v < src[c - 1]) ||
-                   v < 0 || v > n;
-        dst[c] = bad ? (c == 0 ? 0 : n) : v;
-        if (bad) atomicOr(flags, UCP_FLAG_BAD_OFFSETS);
+    if (blockIdx.x != 0) return;
+    if (threadIdx.x == 0) *flags = 0;
+    __syncthreads();
+    if (src_off) {
+        for (int c = threadIdx.x; c <= clouds; c += blockDim.x) {
+            const int64_t v = src_off[c];
+            const bool bad = (c == 0 && v != 0) || (c == clouds && v != n) ||
+                             (c > 0 && v < src_off[c - 1]) || v < 0 || v > n;
+            off[c] = bad ? (c == 0 ? 0 : n) : v;
+            if (bad) atomicOr(flags, UCP_FLAG_BAD_OFFSETS);
+        }
+    } else if (threadIdx.x == 0) {
+        off[0] = 0;
+        off[1] = n;
+    }
+    __syncthreads();
+    if (G <= 0) return;
+    // offsets that failed the check may decrease; their counts are clamped at
+    // 0, and the group emission, which sees the flag, publishes no groups
+    const int per = (clouds + kScanBlock - 1) / kScanBlock;
+    const int c0 = min(clouds, (int)threadIdx.x * per), c1 = min(clouds, c0 + per);
+    int mine = 0;
+    for (int c = c0; c < c1; ++c)
+        mine += (int)max<int64_t>(0, (off[c + 1] - off[c] + G - 1) / G);
+    int run = block_excl_scan(mine, &tot);
+    for (int c = c0; c < c1; ++c) {
+        gcl[c] = run;
+        run += (int)max<int64_t>(0, (off[c + 1] - off[c] + G - 1) / G);
+    }
+    if (threadIdx.x == 0) {
+        gcl[clouds] = tot;
+        *goff_n = tot;
     }
 }
 
@@ -449,7 +469,8 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_pass(
     const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint64_t *kout,
     uint32_t *vout, int64_t n, int shift, const int64_t *__restrict__ off, int clouds,
     const uint32_t *__restrict__ ghist, uint32_t *status, uint32_t *status_next,
-    uint32_t *ticket, int32_t *flags)
+    uint32_t *ticket, const double *__restrict__ gx, const double *__restrict__ gq, double4 *xq,
+    int32_t *flags)
 {
     constexpr int NW = kSortThreads / 64;
     __shared__ uint32_t wh[kSortItems][NW][256];   // per-(round, wave) digit counts, then offsets
@@ -468,6 +489,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_pass(
     uint64_t k[kSortItems];
     uint32_t v[kSortItems], d[kSortItems], lrank[kSortItems];
     bool valid[kSortItems];
+    double4 g[kSortItems];
 #pragma unroll
     for (int it = 0; it < kSortItems; ++it) {
         const int64_t e = base + it * kSortThreads + tid;
@@ -475,6 +497,19 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_pass(
         k[it] = valid[it] ? kin[e] : 0ull;
         v[it] = valid[it] ? vin[e] : 0u;
         d[it] = valid[it] ? sort_digit<CLOUD>(k[it], v[it], shift, off, clouds) : 0u;
+    }
+    // the last pass also gathers each particle's position and charge into the
+    // sorted order; the loads are issued here so that they overlap the ranking
+    // and the look-back
+    if (xq) {
+#pragma unroll
+        for (int it = 0; it < kSortItems; ++it) {
+            const int64_t i = v[it];
+            const bool in = valid[it] && i < n;   // always, unless the records are inconsistent
+            if (valid[it] && !in) atomicOr(flags, UCP_FLAG_INTERNAL);
+            g[it] = in ? make_double4(gx[3 * i], gx[3 * i + 1], gx[3 * i + 2], gq[i])
+                       : make_double4(0.0, 0.0, 0.0, 0.0);
+        }
     }
     // rank equal digits inside each wave and round
 #pragma unroll
@@ -535,6 +570,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_pass(
             }
             kout[dst] = k[it];
             vout[dst] = v[it];
+            if (xq) xq[dst] = g[it];
         }
 }
 
@@ -1148,41 +1184,21 @@ __global__ __launch_bounds__(256) void k_group_count(
 }
 
 // Chunk groups need no scan over positions: cloud c holds ceil(N_c / G)
-// groups, the g-th from its first particle on.  One block finds each cloud's
-// first group (and the total, read by the walk at goff[n]); then every group
-// is written from its index alone.
-__global__ __launch_bounds__(kScanBlock) void k_group_chunk_count(
-    const int64_t *__restrict__ off, int clouds, int G, int32_t *gcl, int32_t *goff_n,
-    const int32_t *flags)
+// groups, the g-th from its first particle on.  The build's first kernel sets
+// each cloud's first group and the total (read by the walk at goff[n]); here
+// every group is written from its index alone.  A build that raised a flag
+// publishes no groups (the walk and the statistics read the total).
+__global__ __launch_bounds__(256) void k_group_chunk_emit(
+    const int64_t *__restrict__ off, int clouds, int G, int32_t *gcl,
+    const int32_t *__restrict__ noff, int4 *groups, int32_t *goff_n, const int32_t *flags)
 {
-    __shared__ int tot;
-    if (*flags) {   // no groups: the walk and the statistics read the total
-        if (threadIdx.x == 0) {
+    if (*flags) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
             gcl[clouds] = 0;
             *goff_n = 0;
         }
         return;
     }
-    const int per = (clouds + kScanBlock - 1) / kScanBlock;
-    const int c0 = min(clouds, (int)threadIdx.x * per), c1 = min(clouds, c0 + per);
-    int mine = 0;
-    for (int c = c0; c < c1; ++c) mine += (int)((off[c + 1] - off[c] + G - 1) / G);
-    int run = block_excl_scan(mine, &tot);
-    for (int c = c0; c < c1; ++c) {
-        gcl[c] = run;
-        run += (int)((off[c + 1] - off[c] + G - 1) / G);
-    }
-    if (threadIdx.x == 0) {
-        gcl[clouds] = tot;
-        *goff_n = tot;
-    }
-}
-
-__global__ __launch_bounds__(256) void k_group_chunk_emit(
-    const int64_t *__restrict__ off, int clouds, int G, const int32_t *__restrict__ gcl,
-    const int32_t *__restrict__ noff, int4 *groups, const int32_t *flags)
-{
-    if (*flags) return;
     const int g = blockIdx.x * 256 + threadIdx.x;
     if (g >= gcl[clouds]) return;
     // the cloud holding group g: the last c with gcl[c] <= g (it has groups)
@@ -1219,19 +1235,6 @@ __global__ __launch_bounds__(256) void k_group_emit(
     }
 }
 
-// gather of the sorted particles (x, y, z, q)
-__global__ __launch_bounds__(256) void k_gather(const double *__restrict__ x,
-                                               const double *__restrict__ q,
-                                               const uint32_t *__restrict__ perm, int64_t n,
-                                               double4 *xq, const int32_t *flags)
-{
-    if (*flags) return;
-    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (p >= n) return;
-    const uint32_t i = perm[p];
-    xq[p] = make_double4(x[3 * (int64_t)i], x[3 * (int64_t)i + 1], x[3 * (int64_t)i + 2], q[i]);
-}
-
 // ---------------------------------------------------------------------------
 // host driver of one build
 // ---------------------------------------------------------------------------
@@ -1245,17 +1248,14 @@ void launch_build(Ctx *c, const double *x, const double *q, const int64_t *offse
     const int G = c->p.group_size;
 
     const int64_t nstatus = 256 * ((n + kSortTile - 1) / kSortTile);
+    const bool chunk = c->p.group_mode == UCP_GROUP_CHUNK;
     hipLaunchKernelGGL(k_build_reset,
                        grid_for(std::max<int64_t>({6 * (int64_t)clouds + CTR_NCTR,
                                                    (int64_t)kSortPassesMax * 256, 1}),
-                                256),
-                       dim3(256), 0, s, c->d_mm, clouds, c->d_ctr, c->d_sortctl, c->d_ghist,
-                       c->d_hist, nstatus, c->d_flags);
-    if (offsets_in)
-        hipLaunchKernelGGL(k_offsets_copy, dim3(1), dim3(256), 0, s, c->d_off, offsets_in, clouds,
-                           n, c->d_flags);
-    else
-        hipLaunchKernelGGL(k_offsets_single, dim3(1), dim3(1), 0, s, c->d_off, n);
+                                kScanBlock),
+                       dim3(kScanBlock), 0, s, c->d_mm, clouds, c->d_ctr, c->d_sortctl,
+                       c->d_ghist, c->d_hist, nstatus, offsets_in, n, chunk ? G : 0, c->d_off,
+                       c->d_gcl, c->d_goff + n, c->d_flags);
 
     // 1. cube
     hipLaunchKernelGGL(k_cube_reduce, grid_for(n, 256 * kCubeItems), dim3(256), 0, s, x, n,
@@ -1282,22 +1282,25 @@ void launch_build(Ctx *c, const double *x, const double *q, const int64_t *offse
                        (const int32_t *)c->d_flags);
     int cur = 0, npass = 0;
     uint32_t *status[2] = {c->d_hist, c->d_histscan};
+    const int total_passes = key_passes + cloud_passes;
     auto pass = [&](bool cloud_pass, int shift) {
         uint32_t *st = status[npass & 1], *st_next = status[(npass + 1) & 1];
         uint32_t *ticket = c->d_sortctl + npass;
         const uint32_t *gh = c->d_ghist + 256 * npass;
+        // the last pass gathers x and q into the sorted order
+        double4 *xq = npass == total_passes - 1 ? c->d_xq : nullptr;
         if (cloud_pass)
             hipLaunchKernelGGL(k_radix_pass<true>, dim3(ntiles), dim3(kSortThreads), 0, s,
                                (const uint64_t *)c->d_key[cur], (const uint32_t *)c->d_val[cur],
                                c->d_key[cur ^ 1], c->d_val[cur ^ 1], n, shift,
-                               (const int64_t *)c->d_off, clouds, gh, st, st_next, ticket,
-                               c->d_flags);
+                               (const int64_t *)c->d_off, clouds, gh, st, st_next, ticket, x, q,
+                               xq, c->d_flags);
         else
             hipLaunchKernelGGL(k_radix_pass<false>, dim3(ntiles), dim3(kSortThreads), 0, s,
                                (const uint64_t *)c->d_key[cur], (const uint32_t *)c->d_val[cur],
                                c->d_key[cur ^ 1], c->d_val[cur ^ 1], n, shift,
-                               (const int64_t *)c->d_off, clouds, gh, st, st_next, ticket,
-                               c->d_flags);
+                               (const int64_t *)c->d_off, clouds, gh, st, st_next, ticket, x, q,
+                               xq, c->d_flags);
         cur ^= 1;
         ++npass;
     };
@@ -1305,9 +1308,6 @@ void launch_build(Ctx *c, const double *x, const double *q, const int64_t *offse
     for (int ps = 0; ps < cloud_passes; ++ps) pass(true, 8 * ps);
     c->d_skey = c->d_key[cur];
     c->d_perm = c->d_val[cur];
-    // gather
-    hipLaunchKernelGGL(k_gather, grid_for(n, 256), dim3(256), 0, s, x, q,
-                       (const uint32_t *)c->d_perm, n, c->d_xq, (const int32_t *)c->d_flags);
     // 4. levels and node numbering
     hipLaunchKernelGGL(k_levels, grid_for(n + 1, kLvlTile), dim3(kLvlTile), 0, s,
                        (const uint64_t *)c->d_skey, n, (const int64_t *)c->d_off, clouds, b, cap,
@@ -1341,14 +1341,12 @@ void launch_build(Ctx *c, const double *x, const double *q, const int64_t *offse
                        (const uint8_t *)c->d_nlev, (const double4 *)c->d_ngeo, c->d_ninfo,
                        c->d_npar, c->d_mom64, c->d_nrec, spec, c->d_ctr, c->d_flags);
     // 7. groups
-    if (c->p.group_mode == UCP_GROUP_CHUNK) {
-        hipLaunchKernelGGL(k_group_chunk_count, dim3(1), dim3(kScanBlock), 0, s,
-                           (const int64_t *)c->d_off, clouds, G, c->d_gcl, c->d_goff + n,
-                           (const int32_t *)c->d_flags);
+    if (chunk) {
         const int64_t gmax = (n + G - 1) / G + clouds;
         hipLaunchKernelGGL(k_group_chunk_emit, grid_for(gmax, 256), dim3(256), 0, s,
-                           (const int64_t *)c->d_off, clouds, G, (const int32_t *)c->d_gcl,
-                           (const int32_t *)c->d_noff, c->d_groups, (const int32_t *)c->d_flags);
+                           (const int64_t *)c->d_off, clouds, G, c->d_gcl,
+                           (const int32_t *)c->d_noff, c->d_groups, c->d_goff + n,
+                           (const int32_t *)c->d_flags);
         return;
     }
     hipLaunchKernelGGL(k_group_count, grid_for(n + 1, 256), dim3(256), 0, s, n,
