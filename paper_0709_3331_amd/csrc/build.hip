@@ -940,7 +940,7 @@ __device__ __forceinline__ bool children_in_window(int k, int level, int nn,
 }
 
 // the internal node k of `level`, first position p: its children's moments
-// shifted to its centre, summed in octant order (preorder).  The children are
+// shifted to its centre, summed in key order (preorder).  The children are
 // read from the level bytes when the subtree is short, else by following the
 // skip links from k + 1.
 template <int BATCH>
@@ -959,7 +959,6 @@ __device__ __forceinline__ void moments_internal(
     int end;
     if (children_in_window(k, level, nn, nlev, &cm, &end)) {
         // BATCH children per round of loads
-        int last = -1, nch = 0;
         bool bad = (cm & 1ull) == 0;   // the first child is k + 1
         while (cm != 0 && !bad) {
             int c[BATCH];
@@ -985,10 +984,8 @@ __device__ __forceinline__ void moments_internal(
                 add_child(m, g, qd, gc[u], rc[u]);
                 if (spec) spec_add_child(sq, spec, c[u], g);
                 npar[c[u]] = k;
-                last = c[u];
                 t = (int64_t)ic[u].x + ic[u].y;
                 skip = ic[u].z;
-                ++nch;
             }
         }
     } else {
