@@ -59,20 +59,23 @@ void launch_fill_f64(double *p, double v, int64_t n, hipStream_t s)
 
 __device__ __forceinline__ int block_excl_scan(int v, int *total);
 
-// per-build state: cloud extents, counters, the sort's tickets, digit counts
-// and the first pass's look-back status words (every block); then block 0
+// per-build state: cloud extents, counters (the walk's included), the walk's
+// queue heads, the sort's tickets, digit counts and the first pass's
+// look-back status words (every block); then block 0
 // clears the flag word, sets the cloud offsets ({0, n} for one cloud, or a
 // checked copy of the caller's) and, for chunk groups (G > 0), the first
 // chunk group of each cloud and their total
 __global__ __launch_bounds__(kScanBlock) void k_build_reset(
     unsigned long long *mm, int clouds, unsigned long long *ctr, uint32_t *sortctl,
     uint32_t *ghist, uint32_t *status0, int64_t nstatus, const int64_t *__restrict__ src_off,
-    int64_t n, int G, int64_t *off, int32_t *gcl, int32_t *goff_n, int32_t *flags)
+    int64_t n, int G, int64_t *off, int32_t *gcl, int32_t *goff_n, unsigned long long *wq,
+    int32_t *flags)
 {
     __shared__ int tot;
     const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (t0 < clouds * 6) mm[t0] = (t0 % 6 < 3) ? ~0ull : 0ull;
     if (t0 < CTR_NCTR) ctr[t0] = 0;
+    if (t0 < kWalkQueues) wq[kQStride * t0] = 0;
     if (t0 < kSortTickets) sortctl[t0] = 0;
     if (t0 < kSortPassesMax * 256) ghist[t0] = 0;
     for (int64_t t = t0; t < nstatus; t += (int64_t)gridDim.x * blockDim.x) status0[t] = 0;
@@ -189,14 +192,14 @@ __global__ __launch_bounds__(256) void k_cube_reduce(const double *__restrict__ 
 
 // lo = minimum corner; side L = 2^e, e the smallest integer with 2^e > extent
 // (frexp gives extent = m 2^e with m in [1/2, 1)); e = 0 for a zero extent.
-__global__ void k_cube_finish(const unsigned long long *__restrict__ mm,
-                              const int64_t *__restrict__ off, int clouds, int b, double4 *cube,
-                              int32_t *flags)
+// the cube of cloud c from its reduced extents: origin lo (the AABB minimum),
+// side 2^e with e the least integer such that 2^e exceeds the largest extent;
+// c1 = (2^(b-e), e).  Returns false when e is out of range.
+__device__ __forceinline__ bool cloud_cube(const unsigned long long *__restrict__ mm,
+                                           const int64_t *__restrict__ off, int c, int b,
+                                           double4 *c0, double4 *c1)
 {
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= clouds) return;
-    if (*flags) return;
-    bool empty = off[c + 1] == off[c];
+    const bool empty = off[c + 1] == off[c];
     double lo[3], ext = 0.0;
     for (int d = 0; d < 3; ++d) {
         lo[d] = empty ? 0.0 : f64_from_ordered(mm[6 * c + d]);
@@ -206,9 +209,9 @@ __global__ void k_cube_finish(const unsigned long long *__restrict__ mm,
     }
     int e = 0;
     if (ext > 0.0) frexp(ext, &e);
-    if (e < -1000 || e > 1000) atomicOr(flags, UCP_FLAG_BAD_CUBE);
-    cube[2 * c] = make_double4(lo[0], lo[1], lo[2], ldexp(1.0, e));
-    cube[2 * c + 1] = make_double4(ldexp(1.0, b - e), (double)e, 0.0, 0.0);
+    *c0 = make_double4(lo[0], lo[1], lo[2], ldexp(1.0, e));
+    *c1 = make_double4(ldexp(1.0, b - e), (double)e, 0.0, 0.0);
+    return e >= -1000 && e <= 1000;
 }
 
 // ---------------------------------------------------------------------------
@@ -261,17 +264,27 @@ __device__ __forceinline__ uint64_t hilbert_key(uint32_t x, uint32_t y, uint32_t
     return (spread3(x) << 2) | (spread3(y) << 1) | spread3(z);
 }
 
+// Each thread derives its cloud's cube from the reduced extents (the same
+// arithmetic for every thread of the cloud); the first threads also store
+// every cloud's cube for the later kernels.
 __global__ __launch_bounds__(256) void k_keys(const double *__restrict__ x, int64_t n,
                                              const int64_t *__restrict__ off, int clouds,
-                                             const double4 *__restrict__ cube, int b, int curve,
-                                             uint64_t *key, uint32_t *val,
-                                             const int32_t *flags)
+                                             const unsigned long long *__restrict__ mm,
+                                             double4 *cube, int b, int curve, uint64_t *key,
+                                             uint32_t *val, int32_t *flags)
 {
     if (*flags) return;
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    for (int64_t cc = i; cc < clouds; cc += (int64_t)gridDim.x * blockDim.x) {
+        double4 a0, a1;
+        if (!cloud_cube(mm, off, (int)cc, b, &a0, &a1)) atomicOr(flags, UCP_FLAG_BAD_CUBE);
+        cube[2 * cc] = a0;
+        cube[2 * cc + 1] = a1;
+    }
     if (i >= n) return;
     int c = cloud_of(off, clouds, i);
-    double4 c0 = cube[2 * c], c1 = cube[2 * c + 1];
+    double4 c0, c1;
+    cloud_cube(mm, off, c, b, &c0, &c1);
     uint64_t top = (1ull << b) - 1;
     uint64_t X = quantise(x[3 * i + 0], c0.x, c1.x, top);
     uint64_t Y = quantise(x[3 * i + 1], c0.y, c1.x, top);
@@ -1252,18 +1265,16 @@ void launch_build(Ctx *c, const double *x, const double *q, const int64_t *offse
                                 kScanBlock),
                        dim3(kScanBlock), 0, s, c->d_mm, clouds, c->d_ctr, c->d_sortctl,
                        c->d_ghist, c->d_hist, nstatus, offsets_in, n, chunk ? G : 0, c->d_off,
-                       c->d_gcl, c->d_goff + n, c->d_flags);
+                       c->d_gcl, c->d_goff + n, c->d_wq, c->d_flags);
+    c->walk_armed = true;
 
     // 1. cube
     hipLaunchKernelGGL(k_cube_reduce, grid_for(n, 256 * kCubeItems), dim3(256), 0, s, x, n,
                        (const int64_t *)c->d_off, clouds, c->d_mm, c->d_flags);
-    hipLaunchKernelGGL(k_cube_finish, grid_for(clouds, 64), dim3(64), 0, s,
-                       (const unsigned long long *)c->d_mm, (const int64_t *)c->d_off, clouds, b,
-                       c->d_cube, c->d_flags);
-    // 2. keys
+    // 2. keys (and each cloud's cube from the reduced extents)
     hipLaunchKernelGGL(k_keys, grid_for(n, 256), dim3(256), 0, s, x, n, (const int64_t *)c->d_off,
-                       clouds, (const double4 *)c->d_cube, b, c->p.curve, c->d_key[0],
-                       c->d_val[0], (const int32_t *)c->d_flags);
+                       clouds, (const unsigned long long *)c->d_mm, c->d_cube, b, c->p.curve,
+                       c->d_key[0], c->d_val[0], c->d_flags);
     // 3. sort
     const int ntiles = (int)((n + kSortTile - 1) / kSortTile);
     const int key_passes = (3 * b + 7) / 8;

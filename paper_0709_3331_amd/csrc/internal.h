@@ -70,6 +70,9 @@ struct Ctx {
 
     // last build
     int built = 0;
+    // the last enqueued build cleared the walk's counters and queue heads and
+    // no walk has run since, so the next force walk needs no reset of its own
+    bool walk_armed = false;
     int64_t n = 0;
     int32_t clouds = 0;
     ucp_params p_built{};

@@ -1153,7 +1153,9 @@ void launch_forces(Ctx *c, double *f, double *phi, hipStream_t s)
 {
     const int64_t n = c->n;
     const WalkArgs wa = walk_args(c);
-    hipLaunchKernelGGL(k_walk_reset, dim3(1), dim3(64), 0, s, c->d_ctr, c->d_wq);
+    // right after a build its reset kernel has cleared the counters and queues
+    if (!c->walk_armed) hipLaunchKernelGGL(k_walk_reset, dim3(1), dim3(64), 0, s, c->d_ctr, c->d_wq);
+    c->walk_armed = false;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (c->timing) {
         if ((int64_t)c->ev.size() < 2 * (c->ev_used + 1)) {
@@ -1197,6 +1199,7 @@ void launch_vjp(Ctx *c, const double *u, double *xbar, hipStream_t s)
                        (const unsigned long long *)c->d_ctr, c->d_w, c->d_xsrc, c->d_cbar,
                        (const int32_t *)c->d_flags);
     hipLaunchKernelGGL(k_walk_reset, dim3(1), dim3(64), 0, s, c->d_ctr, c->d_wq);
+    c->walk_armed = false;
     if (c->p_built.precision == UCP_SPLIT) launch_walk_t<UCP_SPLIT, kWalkVjp>(c, wa, s);
     else launch_walk_t<UCP_FP64, kWalkVjp>(c, wa, s);
     hipLaunchKernelGGL(k_vjp_down, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
