@@ -80,6 +80,8 @@ hipError_t dalloc(T **p, size_t count)
     return hipMalloc((void **)p, count * sizeof(T) + 256);
 }
 
+void drop_graph(Ctx *c);
+
 void free_all(Ctx *c)
 {
     void *ptrs[] = {c->d_off,  c->d_mm,     c->d_cube,  c->d_key[0], c->d_key[1], c->d_val[0],
@@ -91,10 +93,7 @@ void free_all(Ctx *c)
                     c->d_ghist,  c->d_sortctl, c->d_nlev, c->d_spec};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
-    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
-    if (c->graph) (void)hipGraphDestroy(c->graph);
-    c->gexec = nullptr;
-    c->graph = nullptr;
+    drop_graph(c);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     c->ev.clear();
@@ -102,27 +101,48 @@ void free_all(Ctx *c)
 
 void drop_graph(Ctx *c)
 {
-    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
-    if (c->graph) (void)hipGraphDestroy(c->graph);
-    c->gexec = nullptr;
-    c->graph = nullptr;
+    for (hipGraphExec_t *e : {&c->gexec, &c->gexec_last}) {
+        if (*e) (void)hipGraphExecDestroy(*e);
+        *e = nullptr;
+    }
+    for (hipGraph_t *g : {&c->graph, &c->graph_last}) {
+        if (*g) (void)hipGraphDestroy(*g);
+        *g = nullptr;
+    }
     c->gkey.clear();
 }
 
 bool ptr_ok(const void *p, int64_t n) { return n == 0 || p != nullptr; }
 
-// one Verlet step: kick-drift, rebuild, forces, kick
-void enqueue_step(Ctx *c, double *x, double *v, double *f, const double *q, const double *m,
-                  const int64_t *offsets, int clouds, int64_t n, double dt, hipStream_t s)
+// the part of a Verlet step after its opening kick and drift: rebuild,
+// forces, then the closing kick, or (more == true, another step follows in
+// the same call) the closing kick fused with the next step's opening kick
+// and drift
+void enqueue_step_tail(Ctx *c, double *x, double *v, double *f, const double *q,
+                       const double *m, const int64_t *offsets, int clouds, int64_t n, double dt,
+                       bool more, hipStream_t s)
 {
-    ucp::launch_kick_drift(x, v, f, m, n, dt, s);
     ucp::launch_build(c, x, q, offsets, clouds, n, s);
     c->built = 1;
     c->n = n;
     c->clouds = clouds;
     c->p_built = c->p;
     ucp::launch_forces(c, f, nullptr, s);
-    ucp::launch_kick(v, f, m, n, dt, s);
+    if (more) ucp::launch_kick_kick_drift(x, v, f, m, n, dt, s);
+    else ucp::launch_kick(v, f, m, n, dt, s);
+}
+
+hipError_t capture_tail(Ctx *c, double *x, double *v, double *f, const double *q,
+                        const double *m, const int64_t *offsets, int clouds, int64_t n, double dt,
+                        bool more, hipGraph_t *g, hipGraphExec_t *ge)
+{
+    hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) return e;
+    enqueue_step_tail(c, x, v, f, q, m, offsets, clouds, n, dt, more, c->cap_stream);
+    const hipError_t e1 = hipGetLastError();
+    const hipError_t e2 = hipStreamEndCapture(c->cap_stream, g);
+    if (e1 != hipSuccess || e2 != hipSuccess || !*g) return e1 != hipSuccess ? e1 : e2;
+    return hipGraphInstantiate(ge, *g, nullptr, nullptr, 0);
 }
 
 ucp_status run_steps(Ctx *c, double *x, double *v, double *f, const double *q, const double *m,
@@ -131,7 +151,9 @@ ucp_status run_steps(Ctx *c, double *x, double *v, double *f, const double *q, c
 {
     if (nsteps <= 0 || n == 0) return UCP_OK;
     if (c->timing || nsteps < 2) {
-        for (int t = 0; t < nsteps; ++t) enqueue_step(c, x, v, f, q, m, offsets, clouds, n, dt, s);
+        ucp::launch_kick_drift(x, v, f, m, n, dt, s);   // the first step's opening kick and drift
+        for (int t = 0; t < nsteps; ++t)
+            enqueue_step_tail(c, x, v, f, q, m, offsets, clouds, n, dt, t + 1 < nsteps, s);
         HIP_TRY(c, hipGetLastError());
         return UCP_OK;
     }
@@ -146,21 +168,21 @@ ucp_status run_steps(Ctx *c, double *x, double *v, double *f, const double *q, c
     for (uint64_t w : pb) key.push_back((uintptr_t)w);
     if (!c->gexec || key != c->gkey) {
         drop_graph(c);
-        HIP_TRY(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
-        enqueue_step(c, x, v, f, q, m, offsets, clouds, n, dt, c->cap_stream);
-        hipGraph_t g = nullptr;
-        hipError_t e1 = hipGetLastError();
-        hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
-        if (e1 != hipSuccess || e2 != hipSuccess || !g) {
-            if (g) (void)hipGraphDestroy(g);
+        hipError_t e = capture_tail(c, x, v, f, q, m, offsets, clouds, n, dt, true, &c->graph,
+                                    &c->gexec);
+        if (e == hipSuccess)
+            e = capture_tail(c, x, v, f, q, m, offsets, clouds, n, dt, false, &c->graph_last,
+                             &c->gexec_last);
+        if (e != hipSuccess) {
+            drop_graph(c);
             return fail(c, UCP_EHIP, std::string("ucp: step capture failed: ") +
-                                         hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+                                         hipGetErrorString(e));
         }
-        c->graph = g;
-        HIP_TRY(c, hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
         c->gkey = key;
     }
-    for (int t = 0; t < nsteps; ++t) HIP_TRY(c, hipGraphLaunch(c->gexec, s));
+    ucp::launch_kick_drift(x, v, f, m, n, dt, s);   // the first step's opening kick and drift
+    for (int t = 0; t + 1 < nsteps; ++t) HIP_TRY(c, hipGraphLaunch(c->gexec, s));
+    HIP_TRY(c, hipGraphLaunch(c->gexec_last, s));
     c->built = 1;
     c->n = n;
     c->clouds = clouds;

@@ -48,6 +48,9 @@ void launch_vjp(Ctx *c, const double *u, double *xbar, hipStream_t s);
 // integrate.hip
 void launch_kick_drift(double *x, double *v, const double *f, const double *m, int64_t n,
                        double dt, hipStream_t s);
+// the closing kick of one step and the opening kick and drift of the next
+void launch_kick_kick_drift(double *x, double *v, const double *f, const double *m, int64_t n,
+                            double dt, hipStream_t s);
 void launch_kick(double *v, const double *f, const double *m, int64_t n, double dt,
                  hipStream_t s);
 void launch_energy(Ctx *c, const double *v, const double *q, const double *m, int64_t n,
@@ -136,10 +139,11 @@ struct Ctx {
     // energy partials
     double *d_epart = nullptr;              // [256][8]
 
-    // graph of one Verlet step
+    // graphs of a Verlet step: every step but the last (ending in the closing
+    // kick fused with the next step's opening kick and drift) and the last
     hipStream_t cap_stream = nullptr;
-    hipGraphExec_t gexec = nullptr;
-    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr, gexec_last = nullptr;
+    hipGraph_t graph = nullptr, graph_last = nullptr;
     std::vector<uintptr_t> gkey;
 
     // timing

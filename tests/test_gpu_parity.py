@@ -289,6 +289,28 @@ def test_graph_replay_matches_eager_steps():
     ts.close()
 
 
+def test_one_call_of_many_steps_matches_single_step_calls():
+    # inside one call the closing kick of a step and the opening kick and
+    # drift of the next are one kernel; the trajectory must be bitwise that of
+    # one call per step
+    n, dt, steps = 3000, 1e-4, 5
+    say(f"[parity] {steps} steps in one call n={n}")
+    cl = inputs.gaussian_cloud(n, 1.0, 1e-3, 1e-5, 13)
+    ts = TreeSolver(n, theta=0.5, eps=0.01)
+    q, m = dev(cl.q), dev(cl.m)
+    runs = []
+    for per_call in (1, steps):
+        x, v = dev(cl.x), dev(cl.v)
+        f = ts.tree_forces(x, q)
+        for _ in range(steps // per_call):
+            ts.step(x, v, f, q, m, dt, per_call)
+        torch.cuda.synchronize()
+        runs.append((x.clone(), v.clone(), f.clone()))
+    for a, b in zip(runs[0], runs[1]):
+        assert torch.equal(a, b)
+    ts.close()
+
+
 @pytest.mark.parametrize("gm,G", [(NODE, 64), (CHUNK, 64), (CHUNK, 32)])
 def test_full_size_metric_cloud(gm, G):
     c, prm = inputs.metric(0)
