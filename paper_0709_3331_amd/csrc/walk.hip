@@ -54,7 +54,10 @@ struct WalkArgs {
     const int32_t *ngroups;
     const int32_t *nnodes;
     int2 *gstat;
-    double4 *acc;
+    double4 *acc;           // per sorted target (E, phi), when fout and phiout are null
+    double *fout;           // F_i = q_i E_i in the caller's order, or null
+    double *phiout;         // phi_i in the caller's order, or null
+    const uint32_t *perm;   // sorted position -> caller index
     unsigned long long *ctr;
     unsigned long long *wq;     // queue heads (kWalkQueues, kQStride apart)
     const int32_t *flags;
@@ -928,9 +931,25 @@ __global__ __launch_bounds__(256) void k_walk(WalkArgs a)
             s3 += red[4 * src + 3];
         }
         wave_sync();
-        // only lane sub == 0 of an active target owns the result; the others
-        // store to their private spare slot past the particles
-        a.acc[(act && sub == 0) ? (int64_t)i : a.n_spare + lane] = make_double4(s0, s1, s2, s3);
+        // only lane sub == 0 of an active target owns the result.  Forces and
+        // potentials go straight to the caller's order; otherwise (energy,
+        // adjoint) the sorted field is kept, and the other lanes store to
+        // their private spare slot past the particles
+        if (a.fout || a.phiout) {
+            if (act && sub == 0) {
+                const int64_t ci = a.perm[i];
+                if (a.fout) {
+                    const double qq = a.xq[i].w;
+                    a.fout[3 * ci + 0] = qq * s0;
+                    a.fout[3 * ci + 1] = qq * s1;
+                    a.fout[3 * ci + 2] = qq * s2;
+                }
+                if (a.phiout) a.phiout[ci] = s3;
+            }
+        } else {
+            a.acc[(act && sub == 0) ? (int64_t)i : a.n_spare + lane] =
+                make_double4(s0, s1, s2, s3);
+        }
         const int tot_m = wave_isum(my_m), tot_src = wave_isum(my_src);
         a.gstat[g] = make_int2(tot_m, tot_src);   // same value from every lane
         const unsigned long long zero = 0ull;
@@ -948,26 +967,6 @@ __global__ void k_walk_reset(unsigned long long *ctr, unsigned long long *wq)
         ctr[CTR_M2P] = 0;
     }
     if (threadIdx.x < kWalkQueues) wq[kQStride * threadIdx.x] = 0;
-}
-
-// F_i = q_i E_i and phi_i back to the caller's order
-__global__ __launch_bounds__(256) void k_scatter(const double4 *__restrict__ acc,
-                                                const double4 *__restrict__ xq,
-                                                const uint32_t *__restrict__ perm, int64_t n,
-                                                double *f, double *phi, const int32_t *flags)
-{
-    if (*flags) return;
-    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (p >= n) return;
-    const int64_t i = perm[p];
-    const double qq = xq[p].w;
-    const double4 e = acc[p];
-    if (f) {
-        f[3 * i + 0] = qq * e.x;
-        f[3 * i + 1] = qq * e.y;
-        f[3 * i + 2] = qq * e.z;
-    }
-    if (phi) phi[i] = e.w;
 }
 
 // ---------------------------------------------------------------------------
@@ -1125,6 +1124,9 @@ static WalkArgs walk_args(Ctx *c)
     wa.w = nullptr;
     wa.cbar = nullptr;
     wa.xsrc = nullptr;
+    wa.fout = nullptr;
+    wa.phiout = nullptr;
+    wa.perm = c->d_perm;
     wa.nrec = c->d_nrec;
     wa.mom64 = c->d_mom64;
     wa.groups = c->d_groups;
@@ -1151,8 +1153,10 @@ static WalkArgs walk_args(Ctx *c)
 
 void launch_forces(Ctx *c, double *f, double *phi, hipStream_t s)
 {
-    const int64_t n = c->n;
-    const WalkArgs wa = walk_args(c);
+    WalkArgs wa = walk_args(c);
+    // the walk writes F_i = q_i E_i and phi_i in the caller's order itself
+    wa.fout = f;
+    wa.phiout = phi;
     // right after a build its reset kernel has cleared the counters and queues
     if (!c->walk_armed) hipLaunchKernelGGL(k_walk_reset, dim3(1), dim3(64), 0, s, c->d_ctr, c->d_wq);
     c->walk_armed = false;
@@ -1179,9 +1183,6 @@ void launch_forces(Ctx *c, double *f, double *phi, hipStream_t s)
         launch_force_walk<UCP_FP64>(c, wa, want_phi, kelbg, spec, s);
     }
     if (c->timing) (void)hipEventRecord(e1, s);
-    hipLaunchKernelGGL(k_scatter, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
-                       (const double4 *)c->d_acc, (const double4 *)c->d_xq,
-                       (const uint32_t *)c->d_perm, n, f, phi, (const int32_t *)c->d_flags);
 }
 
 void launch_vjp(Ctx *c, const double *u, double *xbar, hipStream_t s)
