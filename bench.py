@@ -194,6 +194,42 @@ def bench_adjoint(prec, dev):
     return out
 
 
+def bench_other_curve(args, prec, cl, prm, dev):
+    """The same workload with the other key order (Morton when the run uses
+    Hilbert keys, and the reverse): the same K timed steps from the same
+    initial state, with the step time, walk time and interactions."""
+    import torch
+
+    from paper_0709_3331_amd import _lib as L
+    from paper_0709_3331_amd.tree import TreeSolver
+
+    other = 1 - CURVE
+    gm = L.UCP_GROUP_CHUNK if args.group_mode == "chunk" else L.UCP_GROUP_NODE
+    x = torch.from_numpy(cl.x).to(dev)
+    v = torch.from_numpy(cl.v).to(dev)
+    q = torch.from_numpy(cl.q).to(dev)
+    m = torch.from_numpy(cl.m).to(dev)
+    ts = TreeSolver(cl.n, curve=other, theta=args.theta, eps=prm["eps"], precision=prec,
+                    group_size=args.group_size, list_len=args.list_len, group_mode=gm,
+                    leaf_cap=args.leaf_cap, walk_waves=args.walk_waves)
+    f = ts.tree_forces(x, q)
+    st0 = ts.stats()
+    for _ in range(args.warmup):
+        ts.step(x, v, f, q, m, prm["dt"], 1)
+    ts.timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ts.step(x, v, f, q, m, prm["dt"], args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wm, wc = ts.timing_read()
+    ts.close()
+    ms = 1e3 * (t1 - t0) / args.steps
+    return {"curve": "hilbert" if other == 1 else "morton", "ms_per_step": ms,
+            "particles_per_s": cl.n * args.steps / (t1 - t0), "walk_ms": wm / max(wc, 1),
+            "interactions_per_particle": (st0["p2p"] + st0["m2p"]) / cl.n}
+
+
 def bench_kelbg(args, prec, x, q, cl, plummer_walk_ms):
     """The same cloud and opening parameter under the Kelbg pair law of
     Eq. (3): electron-ion pairs through q q (1 - exp(-r/lambda)) / r with
@@ -388,6 +424,8 @@ def main():
     ap.add_argument("--ensemble-steps", type=int, default=10)
     ap.add_argument("--no-species", action="store_true",
                     help="skip the per-species pseudo-particle measurement")
+    ap.add_argument("--no-other-curve", action="store_true",
+                    help="skip the same steps with the other key order")
     ap.add_argument("--no-kelbg", action="store_true",
                     help="skip the Kelbg pair-law measurement")
     ap.add_argument("--no-adjoint", action="store_true",
@@ -579,6 +617,9 @@ def main():
             "kind": "oracle",
             "sample": "one full FP64 oracle tree-force evaluation (build + walk, OpenMP over "
                       "groups) of the same N=524288 cloud at the same parameters; %.2f s" % (c1 - c0)}
+    if not args.profile and not args.no_other_curve:
+        key = "morton_keys" if CURVE == 1 else "hilbert_keys"
+        result[key] = bench_other_curve(args, prec, cl, prm, dev)
     if not args.profile and not args.no_kelbg:
         result["kelbg"] = bench_kelbg(args, prec, x, q, cl, walk_avg_ms)
     if not args.profile and not args.no_ensemble:
