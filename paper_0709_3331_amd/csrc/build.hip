@@ -476,6 +476,10 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_counts(
 // lost tile into an internal-error flag rather than a hang.
 constexpr uint32_t kStAgg = 1u << 30, kStIncl = 2u << 30, kStMask = (1u << 30) - 1;
 constexpr int kLookbackSpin = 1 << 18;
+// look-back width: four lanes per digit, each reading kLbSeg consecutive
+// earlier tiles per round, so a round covers 4 * kLbSeg tiles
+constexpr int kLbSeg = 4;
+static_assert(kSortThreads == 4 * 256, "the look-back takes four lanes per digit");
 
 template <bool CLOUD>
 __global__ __launch_bounds__(kSortThreads) void k_radix_pass(
@@ -487,7 +491,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_pass(
 {
     constexpr int NW = kSortThreads / 64;
     __shared__ uint32_t wh[kSortItems][NW][256];   // per-(round, wave) digit counts, then offsets
-    __shared__ uint32_t boff[256];
+    __shared__ uint32_t boff[256], rsh[256], bsh[256];
     __shared__ int btot, tile_sh;
     if (*flags) return;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -545,32 +549,68 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_pass(
                 wh[it][ww][tid] = r;
                 r += c;
             }
-        uint32_t *st = status + (int64_t)tile * 256 + tid;
+        // publish the tile's count at once (tile 0's is already inclusive)
+        __hip_atomic_store(status + (int64_t)tile * 256 + tid, (tile == 0 ? kStIncl : kStAgg) | r,
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        rsh[tid] = r;
+        bsh[tid] = (uint32_t)below;
+        status_next[(int64_t)tile * 256 + tid] = 0u;   // the next pass's status
+    }
+    __syncthreads();
+    // look-back over the earlier tiles' published words, four lanes per digit
+    // (lane q4 of the group takes tiles j - 4 q4 .. j - 4 q4 - 3 of a round): a
+    // round adds the counts up to the first inclusive prefix it meets, or all
+    // 4 kLbSeg of them and moves on; a round that meets an unpublished word
+    // before that prefix is read again.  Before tile 0 the prefix is 0.
+    {
+        const int dg = tid >> 2, q4 = tid & 3;
         uint32_t excl = 0;
-        if (tile == 0) {
-            __hip_atomic_store(st, kStIncl | r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            __hip_atomic_store(st, kStAgg | r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (tile > 0) {
             int j = tile - 1, spins = 0;
             for (;;) {
-                const uint32_t sv = __hip_atomic_load(status + (int64_t)j * 256 + tid,
-                                                      __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if ((sv & ~kStMask) == 0) {
+                uint32_t sv[kLbSeg];
+#pragma unroll
+                for (int m = 0; m < kLbSeg; ++m) {
+                    const int jj = j - q4 * kLbSeg - m;
+                    sv[m] = jj >= 0 ? __hip_atomic_load(status + (int64_t)jj * 256 + dg,
+                                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                    : kStIncl;
+                }
+                bool ok = true, found = false;
+                uint32_t sum = 0;
+#pragma unroll
+                for (int m = 0; m < kLbSeg; ++m)
+                    if (!found) {
+                        ok = ok && (sv[m] & ~kStMask) != 0;
+                        sum += sv[m] & kStMask;
+                        found = (sv[m] & kStIncl) != 0;
+                    }
+                const int sh = lane & ~3;
+                const uint32_t gf = (uint32_t)(__ballot(found) >> sh) & 0xFu;
+                const uint32_t go = (uint32_t)(__ballot(ok) >> sh) & 0xFu;
+                const int f = gf ? __builtin_ctz(gf) : 4;   // first lane that met a prefix
+                const uint32_t need = f == 4 ? 0xFu : ((2u << f) - 1u);
+                if ((go & need) != need) {
                     if (++spins > kLookbackSpin) {
-                        atomicOr(flags, UCP_FLAG_INTERNAL);
+                        atomicOr(flags, q4 == 0 ? UCP_FLAG_INTERNAL : 0);
                         break;
                     }
                     continue;
                 }
-                excl += sv & kStMask;
-                if ((sv & kStIncl) || j == 0) break;
-                --j;
+                uint32_t add = q4 <= f ? sum : 0u;
+                add += __shfl_xor(add, 1);
+                add += __shfl_xor(add, 2);
+                excl += add;
+                if (f < 4) break;
+                j -= 4 * kLbSeg;
             }
-            __hip_atomic_store(st, kStIncl | (excl + r), __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
         }
-        boff[tid] = (uint32_t)below + excl;
-        status_next[(int64_t)tile * 256 + tid] = 0u;   // the next pass's status
+        if (q4 == 0) {
+            if (tile > 0)
+                __hip_atomic_store(status + (int64_t)tile * 256 + dg, kStIncl | (excl + rsh[dg]),
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            boff[dg] = bsh[dg] + excl;
+        }
     }
     __syncthreads();
 #pragma unroll
