@@ -2,8 +2,10 @@
 
 A step is one velocity-Verlet (kick-drift-kick) step of the whole hot path on
 the N = 524,288 cloud (theta = 0.5, eps = 0.005, dt = 5e-5): enclosing cube,
-Morton keys, radix sort, octree build, moments, groups, group walk (M2P + P2P),
-scatter and the two kicks.  Inputs are resident in HBM before the timed region.
+keys (Hilbert order by default, --curve morton for Morton order), radix sort,
+octree build, moments, groups, group walk (M2P + P2P) writing the forces in
+the caller's order, and the two kicks.  Inputs are resident in HBM before the
+timed region.
 
 Prints ONE JSON line.  value = particles/s = N * steps / elapsed.
 """
