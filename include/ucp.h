@@ -190,15 +190,21 @@ ucp_status ucp_build_tree_batched(ucp_ctx *c, const double *x, const double *q,
 /* Tree forces of the last build: the group walk of Sec. 3 with the opening
  * test of Eq. (5); accepted boxes contribute their expansion, opened leaves
  * their particles (Eq. (1)-(2), softened).  f: [n][3] out (caller order).
- * phi: [n] out or NULL; the potential excludes the self pair.
+ * phi: [n] out or NULL; the potential excludes the self pair.  The walk
+ * writes each target's F and phi as it finishes the target's group, so when
+ * the walk raises a device flag (reported by the next ucp_get_stats) the
+ * outputs may be partly written.
  * Errors: UCP_ENOTBUILT.                                                    */
 ucp_status ucp_compute_forces(ucp_ctx *c, double *f, double *phi, void *stream);
 
 /* nsteps velocity-Verlet (kick-drift-kick) steps, Sec. 2:
  *   v += dt/2 F/m;  x += dt v;  rebuild tree, F = F(x);  v += dt/2 F/m.
  * On entry f must hold F(x) (e.g. from ucp_build_tree + ucp_compute_forces);
- * on exit x, v, f hold the state after nsteps.  The step is captured once in
- * a hipGraph and replayed (re-captured when pointers or sizes change).
+ * on exit x, v, f hold the state after nsteps.  Within one call the closing
+ * kick of a step and the opening kick and drift of the next run as one pass
+ * (the same arithmetic, so the trajectory is bitwise that of nsteps calls of
+ * one step).  Steps are captured once in hipGraphs and replayed (re-captured
+ * when pointers, sizes or parameters change).
  * Errors: UCP_EINVAL.                                                       */
 ucp_status ucp_step(ucp_ctx *c, double *x, double *v, double *f, const double *q,
                     const double *m, int64_t n, double dt, int32_t nsteps, void *stream);

@@ -8,7 +8,9 @@
 //     accept  iff  s^2 < theta^2 d^2,   d^2 = fma(dz,dz, fma(dy,dy, dx*dx)),
 // and the node is opened iff any target fails.  Accepted boxes go to an LDS
 // M2P list, opened leaves to an LDS P2P list; a full list is evaluated
-// (flushed) at once.
+// (flushed) at once.  At the end of a group the lane that owns a target
+// writes F_i = q_i E_i and phi_i at the caller's index (or, for the energy
+// and the adjoint, the sorted field).
 //
 // Node record (two 64-byte lines per node, written by the build): line 1
 // holds the FP64 centre, side^2, skip, first, count and level|leaf flag and
