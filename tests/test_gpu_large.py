@@ -90,3 +90,22 @@ def test_rollout_workload_checkpointing_and_finiteness():
     assert out[0][0] == out[1][0]
     assert out[0][1] == pytest.approx(out[1][1], rel=1e-9)
     ts.close()
+
+
+def test_sort_at_look_back_window_boundaries():
+    # the radix passes' look-back reads 16 earlier tiles (of 2048 keys) per
+    # round; tile counts on and around multiples of 16, ragged last tiles
+    sizes = [2048 * 16, 2048 * 17 - 2, 2048 * 33, 2048 * 48 - 6, 2048 * 257 + 2, 2048 * 300 - 2]
+    ts = TreeSolver(max(sizes), theta=0.5, eps=0.005)
+    for k, n in enumerate(sizes):
+        cl = inputs.gaussian_cloud(n, 1.0, 1e-3, 1e-5, 500 + k)
+        say(f"[large] sort n={n} tiles={-(-n // 2048)}")
+        x = torch.from_numpy(cl.x).cuda()
+        q = torch.from_numpy(cl.q).cuda()
+        ts.build(x, q)
+        st = ts.stats()
+        t = oracle.Tree(cl.x, cl.q, 0.5, 0.005)
+        np.testing.assert_array_equal(ts.debug("keys"), t.sorted_keys())
+        np.testing.assert_array_equal(ts.debug("perm").astype(np.int64), t.perm())
+        assert st["nodes"] == t.nnodes
+    ts.close()
