@@ -58,9 +58,9 @@ def _load():
         "orc_tree_centres": (None, [vp, _dp]),
         "orc_tree_groups": (None, [vp, _i64p, _i64p, _i64p]),
         "orc_tree_moments": (None, [vp, _dp, _dp, _dp]),
-        "orc_tree_eval": (None, [vp, _dp, _dp, _dp, vp, vp, vp, vp]),
-        "orc_tree_vjp": (i32, [vp, _dp, _dp, _dp, _dp]),
-        "orc_tree_eval_groups": (i32, [vp, _dp, _dp, i64, _i64p, _dp, vp, vp, vp]),
+        "orc_tree_eval": (None, [vp, _dp, _dp, _dp, vp, vp, vp, vp, vp]),
+        "orc_tree_vjp": (i32, [vp, _dp, _dp, _dp, _dp, vp, vp]),
+        "orc_tree_eval_groups": (i32, [vp, _dp, _dp, i64, _i64p, _dp, vp, vp, vp, vp]),
         "orc_tree_arch_series": (i64, [vp, _i64p]),
         "orc_rebuild": (i64, [i64, _i64p, i64, _i64p, _i64p]),
         "orc_verlet": (i32, [i64, _dp, _dp, _dp, _dp, i32, dbl, dbl, i32, i32, i32, i32, i32,
@@ -262,8 +262,11 @@ class Tree:
         _lib.orc_tree_moments(self._h, x, self.q, m)
         return m
 
-    def eval(self, x=None, want_phi=True, group_counts=False):
-        """Tree forces (C-2.8).  Returns dict f, phi, p2p, m2p[, gm2p, gp2p]."""
+    def eval(self, x=None, want_phi=True, group_counts=False, cond=False):
+        """Tree forces (C-2.8).  Returns dict f, phi, p2p, m2p[, gm2p, gp2p]
+        [, cond].  cond: per particle the size A_i of the terms its field is
+        summed from, so that an evaluation in a precision of unit roundoff u_w
+        errs by a small multiple of u_w A_i in E_i (and |q_i| u_w A_i in F_i)."""
         x = self.x if x is None else _f64(x, (-1, 3))
         f = np.zeros((self.n, 3))
         phi = np.zeros(self.n) if want_phi else None
@@ -272,35 +275,47 @@ class Tree:
         if group_counts:
             gm = np.zeros(self.ngroups, dtype=np.int64)
             gp = np.zeros(self.ngroups, dtype=np.int64)
-        _lib.orc_tree_eval(self._h, x, self.q, f, _ptr(phi), _ptr(st), _ptr(gm), _ptr(gp))
+        cd = np.zeros(self.n) if cond else None
+        _lib.orc_tree_eval(self._h, x, self.q, f, _ptr(phi), _ptr(st), _ptr(gm), _ptr(gp), _ptr(cd))
         out = {"f": f, "phi": phi, "p2p": int(st[0]), "m2p": int(st[1])}
         if group_counts:
             out["gm2p"], out["gp2p"] = gm, gp
+        if cond:
+            out["cond"] = cd
         return out
 
-    def eval_groups(self, gsel, x=None, want_phi=False):
+    def eval_groups(self, gsel, x=None, want_phi=False, cond=False):
         """Tree forces of the members of the selected groups only.  Returns
         dict f, phi (caller order; rows of other particles are NaN) and the
-        per-selected-group list lengths gm2p, gp2p."""
+        per-selected-group list lengths gm2p, gp2p [, cond as in eval]."""
         x = self.x if x is None else _f64(x, (-1, 3))
         gsel = np.ascontiguousarray(gsel, dtype=np.int64)
         f = np.full((self.n, 3), np.nan)
         phi = np.full(self.n, np.nan) if want_phi else None
         gm = np.zeros(gsel.size, dtype=np.int64)
         gp = np.zeros(gsel.size, dtype=np.int64)
+        cd = np.full(self.n, np.nan) if cond else None
         if _lib.orc_tree_eval_groups(self._h, x, self.q, gsel.size, gsel, f, _ptr(phi), _ptr(gm),
-                                     _ptr(gp)) != 0:
+                                     _ptr(gp), _ptr(cd)) != 0:
             raise ValueError("group index out of range")
-        return {"f": f, "phi": phi, "gm2p": gm, "gp2p": gp}
+        out = {"f": f, "phi": phi, "gm2p": gm, "gp2p": gp}
+        if cond:
+            out["cond"] = cd
+        return out
 
-    def vjp(self, u, x=None):
-        """Frozen-list (dF/dx)^T u; needs keep_lists=True."""
+    def vjp(self, u, x=None, extras=False):
+        """(dF/dx)^T u with the lists of the build held fixed and the cube
+        origin's dependence on the minimum particles included; needs
+        keep_lists=True.  extras=True returns (xbar, cond, lobar): cond the
+        per-particle term sizes B_j, lobar the cube-origin cotangent."""
         x = self.x if x is None else _f64(x, (-1, 3))
         u = _f64(u, (-1, 3))
         xb = np.zeros_like(x)
-        if _lib.orc_tree_vjp(self._h, x, self.q, u, xb) != 0:
+        cd = np.zeros(self.n) if extras else None
+        lob = np.zeros(3)
+        if _lib.orc_tree_vjp(self._h, x, self.q, u, xb, _ptr(lob), _ptr(cd)) != 0:
             raise ValueError("tree vjp needs keep_lists=True and the Plummer pair law")
-        return xb
+        return (xb, cd, lob) if extras else xb
 
     def lists(self, g):
         """Frozen lists of group g: (accepted cells, opened leaves); keep_lists only."""

@@ -815,11 +815,69 @@ void orc_tree_moments(const orc_tree *t, const double *x, const double *q, doubl
 /* stats[1] = M2P interactions.  gm2p/gp2p (optional, length ng) receive the  */
 /* per-group number of accepted cells and of P2P source particles.           */
 /* ------------------------------------------------------------------------- */
+/* ------------------------------------------------------------------------- */
+/* Size of the terms a target's field is summed from.  An evaluation that     */
+/* forms every term in a working precision with unit roundoff u_w (FP32 or   */
+/* FP64) and takes the offsets r from a point inside the bounding box of the */
+/* target's walk group errs, per target, by at most a small multiple of      */
+/*   u_w * A_i,   A_i = sum over the target's terms of                        */
+/*                      |term|_+  +  ||d term / d r|| (2 |r| + D_g),          */
+/* where |term|_+ is the term with every sum taken over magnitudes (no        */
+/* cancellation inside a term), ||d term/d r|| a bound of its Jacobian, and   */
+/* D_g the diagonal of the group's bounding box (offsets rounded relative to  */
+/* a point of that box move r by at most u_w (2 |r| + D_g)).  This is the   */
+/* first-order error analysis of a sum of rounded terms; it bounds each      */
+/* particle's error separately instead of the norm over the cloud.           */
+/* ------------------------------------------------------------------------- */
+static double frob3(const double S[3][3])
+{
+    double s = 0.0;
+    for (int a = 0; a < 3; ++a)
+        for (int c = 0; c < 3; ++c) s += S[a][c] * S[a][c];
+    return sqrt(s);
+}
+
+static void cell_jacobian(const double *mom, const double *r, double eps2, double J[3][3]);
+
+/* |term|_+ and the Jacobian term of one accepted box (C-2.7) */
+static double cell_cond(const double *mom, const double *r, double eps2, double rho)
+{
+    const double S[3][3] = {{mom[4], mom[7], mom[8]}, {mom[7], mom[5], mom[9]},
+                            {mom[8], mom[9], mom[6]}};
+    const double Qa = fabs(mom[0]);
+    const double pa = sqrt(mom[1] * mom[1] + mom[2] * mom[2] + mom[3] * mom[3]);
+    const double Sa = frob3(S), trSa = fabs(mom[4]) + fabs(mom[5]) + fabs(mom[6]);
+    const double rn = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+    const double ih = 1.0 / sqrt(rn * rn + eps2);
+    const double ih3 = ih * ih * ih, ih5 = ih3 * ih * ih, ih7 = ih5 * ih * ih;
+    const double mag = (Qa * ih3 + 3.0 * pa * rn * ih5 + 7.5 * Sa * rn * rn * ih7 +
+                        1.5 * trSa * ih5) * rn + pa * ih3 + 3.0 * Sa * rn * ih5;
+    double J[3][3];
+    cell_jacobian(mom, r, eps2, J);
+    return mag + frob3(J) * rho;
+}
+
+/* the same for one particle pair: the field q_j a r has the Jacobian         */
+/* q_j (a I + (da/dr) r r^T / r), of norm at most 2 |q_j| a for the softened  */
+/* law and |q_j| (2 a + 1/(e lambda r^2)) for the Kelbg pair (its bracket's   */
+/* derivative u e^-u is at most 1/e)                                          */
+static double pair_cond(const orc_pair *pl, double qi, double qj, double r2, double a,
+                        double rho)
+{
+    const double rn = sqrt(r2);
+    double jac = 2.0 * fabs(a);
+    if (pl->law == ORC_PAIR_KELBG && qi * qj < 0.0 && r2 > 0.0)
+        jac += 1.0 / (exp(1.0) * pl->lambda * r2);
+    return fabs(qj) * (fabs(a) * rn + jac * rho);
+}
+
 /* Forces and potentials of the members of group g (C-2.8), written in the   */
 /* caller's order; returns the group's list lengths (cells, P2P sources).    */
+/* cond (optional, caller order) receives A_i.                               */
 static void eval_group(const orc_tree *t, const double *xs, const double *qs, const double *mom,
                        const double *ps, double eps2, const orc_pair *pl, int64_t g, ivec *M,
-                       ivec *P, double *f, double *phi, int64_t *mn_out, int64_t *nsrc_out)
+                       ivec *P, double *f, double *phi, double *cond, int64_t *mn_out,
+                       int64_t *nsrc_out)
 {
     const int64_t *mv, *pv;
     int64_t mn, pn;
@@ -835,10 +893,21 @@ static void eval_group(const orc_tree *t, const double *xs, const double *qs, co
     for (int64_t a = 0; a < pn; ++a) nsrc += t->count[pv[a]];
     *mn_out = mn;
     *nsrc_out = nsrc;
+    /* diagonal of the members' bounding box */
+    double bl[3] = {INFINITY, INFINITY, INFINITY}, bh[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t a = 0; a < t->gcount[g]; ++a)
+        for (int d = 0; d < 3; ++d) {
+            const double v = xs[3 * (t->gfirst[g] + a) + d];
+            bl[d] = v < bl[d] ? v : bl[d];
+            bh[d] = v > bh[d] ? v : bh[d];
+        }
+    const double Dg = sqrt((bh[0] - bl[0]) * (bh[0] - bl[0]) + (bh[1] - bl[1]) * (bh[1] - bl[1]) +
+                           (bh[2] - bl[2]) * (bh[2] - bl[2]));
     for (int64_t a = 0; a < t->gcount[g]; ++a) {
         int64_t i = t->gfirst[g] + a;
         const double *xi = xs + 3 * i;
         nsum E[3] = {{0, 0}, {0, 0}, {0, 0}}, ph = {0, 0};
+        double A = 0.0;
         for (int64_t m = 0; m < mn; ++m) {
             int64_t k = mv[m];
             const double *c = t->centre + 3 * k;
@@ -848,6 +917,20 @@ static void eval_group(const orc_tree *t, const double *xs, const double *qs, co
             else cell_field(mom + 10 * k, r, eps2, Ec, &pc);
             for (int d = 0; d < 3; ++d) nadd(&E[d], Ec[d]);
             nadd(&ph, pc);
+            if (cond && !ps) {
+                const double rn = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+                A += cell_cond(mom + 10 * k, r, eps2, 2.0 * rn + Dg);
+            } else if (cond) {
+                /* two softened monopoles at the centres of charge */
+                for (int sp = 0; sp < 2; ++sp) {
+                    const double *v = ps + 10 * k + 4 * sp;
+                    double rs[3] = {xi[0] - v[1], xi[1] - v[2], xi[2] - v[3]};
+                    const double r2 = rs[0] * rs[0] + rs[1] * rs[1] + rs[2] * rs[2];
+                    const double ih = 1.0 / sqrt(r2 + eps2);
+                    const orc_pair pp = {ORC_PAIR_PLUMMER, eps2, 0.0};
+                    A += pair_cond(&pp, 1.0, v[0], r2, ih * ih * ih, 2.0 * sqrt(r2) + Dg);
+                }
+            }
         }
         for (int64_t m = 0; m < pn; ++m) {
             int64_t k = pv[m];
@@ -855,15 +938,18 @@ static void eval_group(const orc_tree *t, const double *xs, const double *qs, co
                 double r[3] = {xi[0] - xs[3 * j], xi[1] - xs[3 * j + 1], xi[2] - xs[3 * j + 2]};
                 if (j == i) continue;   /* the self pair: r = 0, no field, no potential */
                 double a, b;
-                pair_factors(pl, qs[i], qs[j], r[0] * r[0] + r[1] * r[1] + r[2] * r[2], &a, &b);
+                const double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+                pair_factors(pl, qs[i], qs[j], r2, &a, &b);
                 double w = qs[j] * a;
                 for (int d = 0; d < 3; ++d) nadd(&E[d], w * r[d]);
                 nadd(&ph, qs[j] * b);
+                if (cond) A += pair_cond(pl, qs[i], qs[j], r2, a, 2.0 * sqrt(r2) + Dg);
             }
         }
         int64_t ci = t->perm[i];
         for (int d = 0; d < 3; ++d) f[3 * ci + d] = qs[i] * nval(E[d]);
         if (phi) phi[ci] = nval(ph);
+        if (cond) cond[ci] = A;
     }
 }
 
@@ -872,8 +958,8 @@ static void eval_group(const orc_tree *t, const double *xs, const double *qs, co
 /* gp2p, when given, receive the list lengths per evaluated group, in the    */
 /* order evaluated.                                                          */
 static void eval_groups(const orc_tree *t, const double *x, const double *q, int64_t ngs,
-                        const int64_t *gsel, double *f, double *phi, int64_t *stats, int64_t *gm2p,
-                        int64_t *gp2p)
+                        const int64_t *gsel, double *f, double *phi, double *cond, int64_t *stats,
+                        int64_t *gm2p, int64_t *gp2p)
 {
     int64_t n = t->n;
     if (stats) { stats[0] = 0; stats[1] = 0; }
@@ -901,7 +987,7 @@ static void eval_groups(const orc_tree *t, const double *x, const double *q, int
         for (int64_t e = 0; e < ngs; ++e) {
             const int64_t g = gsel ? gsel[e] : e;
             int64_t mn, nsrc;
-            eval_group(t, xs, qs, mom, ps, eps2, &pl, g, &M, &P, f, phi, &mn, &nsrc);
+            eval_group(t, xs, qs, mom, ps, eps2, &pl, g, &M, &P, f, phi, cond, &mn, &nsrc);
             if (gm2p) gm2p[e] = mn;
             if (gp2p) gp2p[e] = nsrc;
             sp2p += nsrc * t->gcount[g];
@@ -917,26 +1003,33 @@ static void eval_groups(const orc_tree *t, const double *x, const double *q, int
     free(ps);
 }
 
+/* cond (optional, [n], caller order) receives the term sizes A_i above.     */
 void orc_tree_eval(const orc_tree *t, const double *x, const double *q, double *f, double *phi,
-                   int64_t *stats, int64_t *gm2p, int64_t *gp2p)
+                   int64_t *stats, int64_t *gm2p, int64_t *gp2p, double *cond)
 {
-    eval_groups(t, x, q, t->ng, NULL, f, phi, stats, gm2p, gp2p);
+    eval_groups(t, x, q, t->ng, NULL, f, phi, cond, stats, gm2p, gp2p);
 }
 
 /* Tree forces of selected groups only (for checks of large clouds).  Returns */
 /* -1 if a selected index is out of range.                                   */
 int orc_tree_eval_groups(const orc_tree *t, const double *x, const double *q, int64_t ngs,
-                         const int64_t *gsel, double *f, double *phi, int64_t *gm2p, int64_t *gp2p)
+                         const int64_t *gsel, double *f, double *phi, int64_t *gm2p, int64_t *gp2p,
+                         double *cond)
 {
     for (int64_t e = 0; e < ngs; ++e)
         if (gsel[e] < 0 || gsel[e] >= t->ng) return -1;
-    eval_groups(t, x, q, ngs, gsel, f, phi, NULL, gm2p, gp2p);
+    eval_groups(t, x, q, ngs, gsel, f, phi, cond, NULL, gm2p, gp2p);
     return 0;
 }
 
 /* ------------------------------------------------------------------------- */
-/* Frozen-list tree VJP: xbar = (dF/dx)^T u with the cube, topology, centres  */
-/* and interaction lists of the build held fixed.  Three contributions:       */
+/* Tree VJP: xbar = (dF/dx)^T u, the derivative of the forces of this build   */
+/* with respect to the positions.  The topology, the interaction lists and    */
+/* the cube's side are piecewise constant in x and held fixed (their jumps    */
+/* are not differentiated).  The cube's origin lo is not: it is the per-axis  */
+/* minimum of the positions (C-2.1), and every box centre is lo plus a fixed  */
+/* offset (C-2.4), so the centres move with the particle that attains the     */
+/* minimum.  Four contributions:                                             */
 /*  (a) target side, J_C = dE_C/dr (symmetric, minus the Hessian of phi_C):   */
 /*        xbar_i += q_i J_C(r) u_i                                            */
 /*  (b) P2P source side: xbar_j -= q_i q_j K(r_ij) u_i                         */
@@ -944,7 +1037,18 @@ int orc_tree_eval_groups(const orc_tree *t, const double *x, const double *q, in
 /*        pbar_C += q_i (dE_C/dp)^T u_i,  Sbar_C += q_i (dE_C/dS)^T u_i        */
 /*      pushed to every particle j of C:                                     */
 /*        xbar_j += q_j [pbar_C + (Sbar_C + Sbar_C^T)(x_j - c_C)]             */
+/*  (d) the cube origin, by the chain rule through every accepted box's      */
+/*      centre c_C (r = x_i - c_C, p = sum q_j (x_j - c_C) and S likewise):   */
+/*        cbar_C = - sum_i q_i J_C u_i - Q_C pbar_C - (Sbar_C + Sbar_C^T) p_C, */
+/*        lobar  = sum_C cbar_C,                                              */
+/*      added on each axis d to the particle holding the minimum of that     */
+/*      axis (the lowest caller index among equal minima).                   */
 /* Requires keep_lists.  Returns 0, or -1 without lists.                     */
+/* lobar (optional, [3]) receives the cube-origin cotangent.  cond (optional, */
+/* [n], caller order) receives B_j, the sum of the sizes of every term added  */
+/* to xbar_j, each taken with its sums over magnitudes: an evaluation that   */
+/* forms each term in a working precision with unit roundoff u_w from        */
+/* offsets rounded once errs by at most a small multiple of u_w B_j.         */
 /* ------------------------------------------------------------------------- */
 static void cell_jacobian(const double *mom, const double *r, double eps2, double J[3][3])
 {
@@ -972,9 +1076,11 @@ static void cell_jacobian(const double *mom, const double *r, double eps2, doubl
                       3.0 * S[a][c] * ih5 + 15.0 * Sr[a] * r[c] * ih7;
 }
 
-int orc_tree_vjp(const orc_tree *t, const double *x, const double *q, const double *u, double *xbar)
+int orc_tree_vjp(const orc_tree *t, const double *x, const double *q, const double *u, double *xbar,
+                 double *lobar, double *cond)
 {
     int64_t n = t->n;
+    if (lobar) lobar[0] = lobar[1] = lobar[2] = 0.0;
     if (n == 0) return 0;
     if (!t->keep_lists || t->pair_law != ORC_PAIR_PLUMMER) return -1;
     double *xs = (double *)malloc((size_t)n * 3 * sizeof(double));
@@ -985,41 +1091,75 @@ int orc_tree_vjp(const orc_tree *t, const double *x, const double *q, const doub
     sorted_copy(t, u, NULL, us, NULL);
     for (int64_t k = 0; k < t->M; ++k) node_moments(t, k, xs, qs, t->centre + 3 * k, mom + 10 * k);
     const double eps2 = t->eps * t->eps;
-    /* per-cell cotangents pbar (3) and full-matrix Sbar (9), per-particle xbar */
-    double *cot = (double *)calloc((size_t)t->M * 12, sizeof(double));
+    /* per cell: pbar (3), full-matrix Sbar (9), target-side sum rbar (3); per
+       particle xbar; and the term sizes (per cell: of pbar and of Sbar + Sbar^T;
+       per particle: of xbar; of lobar) */
+    double *cot = (double *)calloc((size_t)t->M * 15, sizeof(double));
+    double *cab = (double *)calloc((size_t)t->M * 2, sizeof(double));
     double *xb = (double *)calloc((size_t)n * 3, sizeof(double));
+    double *xa = (double *)calloc((size_t)n, sizeof(double));
+    double loa = 0.0;
     /* serial accumulation: deterministic and plainly correct */
     for (int64_t g = 0; g < t->ng; ++g) {
         for (int64_t a = 0; a < t->gcount[g]; ++a) {
             int64_t i = t->gfirst[g] + a;
             const double *xi = xs + 3 * i, *ui = us + 3 * i;
             double qi = qs[i];
+            const double wa = fabs(qi) * sqrt(ui[0] * ui[0] + ui[1] * ui[1] + ui[2] * ui[2]);
             for (int64_t m = 0; m < t->nm2p[g]; ++m) {
                 int64_t k = t->m2p[g][m];
                 const double *c = t->centre + 3 * k;
                 double r[3] = {xi[0] - c[0], xi[1] - c[1], xi[2] - c[2]};
                 double J[3][3];
                 cell_jacobian(mom + 10 * k, r, eps2, J);
-                for (int d = 0; d < 3; ++d)
-                    xb[3 * i + d] += qi * (J[d][0] * ui[0] + J[d][1] * ui[1] + J[d][2] * ui[2]);
+                double *pb = cot + 15 * k, *Sb = cot + 15 * k + 3, *rb = cot + 15 * k + 12;
+                for (int d = 0; d < 3; ++d) {
+                    const double Ju = qi * (J[d][0] * ui[0] + J[d][1] * ui[1] + J[d][2] * ui[2]);
+                    xb[3 * i + d] += Ju;
+                    rb[d] += Ju;
+                }
                 double h2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2] + eps2;
                 double ih = 1.0 / sqrt(h2);
-                double ih2 = ih * ih, ih3 = ih2 * ih, ih5 = ih3 * ih2, ih7 = ih5 * ih2;
+                double ih2 = ih * ih, ih3 = ih2 * ih, ih5 = ih3 * ih2, ih7 = ih5 * ih2, ih9 = ih7 * ih2;
                 double ur = ui[0] * r[0] + ui[1] * r[1] + ui[2] * r[2];
-                double *pb = cot + 12 * k, *Sb = cot + 12 * k + 3;
                 for (int d = 0; d < 3; ++d) pb[d] += qi * (3.0 * r[d] * ur * ih5 - ui[d] * ih3);
                 for (int b2 = 0; b2 < 3; ++b2)
                     for (int c2 = 0; c2 < 3; ++c2)
                         Sb[3 * b2 + c2] += qi * (7.5 * ur * r[b2] * r[c2] * ih7 -
                                                  (b2 == c2 ? 1.5 * ur * ih5 : 0.0) -
                                                  3.0 * ui[b2] * r[c2] * ih5);
+                if (cond) {
+                    const double *mm = mom + 10 * k;
+                    const double S[3][3] = {{mm[4], mm[7], mm[8]}, {mm[7], mm[5], mm[9]},
+                                            {mm[8], mm[9], mm[6]}};
+                    const double Qa = fabs(mm[0]);
+                    const double pa = sqrt(mm[1] * mm[1] + mm[2] * mm[2] + mm[3] * mm[3]);
+                    const double Sa = frob3(S), tra = fabs(mm[4]) + fabs(mm[5]) + fabs(mm[6]);
+                    const double rn = sqrt(h2 - eps2 > 0.0 ? h2 - eps2 : 0.0);
+                    /* J u with every sum over magnitudes */
+                    const double al = Qa * ih3 + 3.0 * pa * rn * ih5 + 7.5 * Sa * rn * rn * ih7 +
+                                      1.5 * tra * ih5;
+                    const double ga = 3.0 * Qa * rn * ih5 + 3.0 * pa * ih5 +
+                                      15.0 * pa * rn * rn * ih7 + 15.0 * Sa * rn * ih7 +
+                                      52.5 * Sa * rn * rn * rn * ih9 + 7.5 * tra * rn * ih7;
+                    xa[i] += wa * (al + rn * ga + 3.0 * pa * rn * ih5 + 3.0 * Sa * ih5 +
+                                   15.0 * Sa * rn * rn * ih7);
+                    cab[2 * k] += wa * (3.0 * rn * rn * ih5 + ih3);
+                    cab[2 * k + 1] += wa * (15.0 * rn * rn * rn * ih7 + 12.0 * rn * ih5);
+                    /* the box's share of lobar, the part of J u through S */
+                    loa += wa * ((52.5 * Sa * rn * rn * ih9 + 15.0 * Sa * ih7 + 7.5 * tra * ih7) *
+                                     rn * rn +
+                                 7.5 * Sa * rn * rn * ih7 + 1.5 * tra * ih5 +
+                                 15.0 * Sa * rn * rn * ih7 + 3.0 * Sa * ih5);
+                }
             }
             for (int64_t m = 0; m < t->np2p[g]; ++m) {
                 int64_t k = t->p2p[g][m];
                 for (int64_t j = t->first[k]; j < t->first[k] + t->count[k]; ++j) {
                     if (j == i) continue;
                     double r[3] = {xi[0] - xs[3 * j], xi[1] - xs[3 * j + 1], xi[2] - xs[3 * j + 2]};
-                    double h2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2] + eps2;
+                    double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+                    double h2 = r2 + eps2;
                     double ih = 1.0 / sqrt(h2);
                     double ih3 = ih * ih * ih, ih5 = ih3 * ih * ih;
                     double ur = ui[0] * r[0] + ui[1] * r[1] + ui[2] * r[2];
@@ -1028,13 +1168,18 @@ int orc_tree_vjp(const orc_tree *t, const double *x, const double *q, const doub
                         xb[3 * i + d] += qi * qs[j] * Ku;
                         xb[3 * j + d] -= qi * qs[j] * Ku;
                     }
+                    if (cond) {
+                        const double ka = wa * fabs(qs[j]) * (ih3 + 3.0 * r2 * ih5);
+                        xa[i] += ka;
+                        xa[j] += ka;
+                    }
                 }
             }
         }
     }
     /* push cell cotangents to the particles of each cell */
     for (int64_t k = 0; k < t->M; ++k) {
-        const double *pb = cot + 12 * k, *Sb = cot + 12 * k + 3;
+        const double *pb = cot + 15 * k, *Sb = cot + 15 * k + 3;
         const double *c = t->centre + 3 * k;
         for (int64_t j = t->first[k]; j < t->first[k] + t->count[k]; ++j) {
             double rp[3] = {xs[3 * j] - c[0], xs[3 * j + 1] - c[1], xs[3 * j + 2] - c[2]};
@@ -1043,11 +1188,36 @@ int orc_tree_vjp(const orc_tree *t, const double *x, const double *q, const doub
                 for (int e2 = 0; e2 < 3; ++e2) s += (Sb[3 * d + e2] + Sb[3 * e2 + d]) * rp[e2];
                 xb[3 * j + d] += qs[j] * s;
             }
+            if (cond)
+                xa[j] += fabs(qs[j]) *
+                         (cab[2 * k] + cab[2 * k + 1] *
+                                           sqrt(rp[0] * rp[0] + rp[1] * rp[1] + rp[2] * rp[2]));
+        }
+    }
+    /* (d) the cube origin: chain rule through every box centre */
+    double lob[3] = {0.0, 0.0, 0.0};
+    for (int64_t k = 0; k < t->M; ++k) {
+        const double *pb = cot + 15 * k, *Sb = cot + 15 * k + 3, *rb = cot + 15 * k + 12;
+        const double Q = mom[10 * k], *pm = mom + 10 * k + 1;
+        for (int d = 0; d < 3; ++d) {
+            double s = -rb[d] - Q * pb[d];
+            for (int e2 = 0; e2 < 3; ++e2) s -= (Sb[3 * d + e2] + Sb[3 * e2 + d]) * pm[e2];
+            lob[d] += s;
         }
     }
     for (int64_t p = 0; p < n; ++p)
         for (int d = 0; d < 3; ++d) xbar[3 * t->perm[p] + d] = xb[3 * p + d];
-    free(xs); free(qs); free(us); free(mom); free(cot); free(xb);
+    if (cond)
+        for (int64_t p = 0; p < n; ++p) cond[t->perm[p]] = xa[p];
+    for (int d = 0; d < 3; ++d) {
+        int64_t jm = 0;
+        for (int64_t i = 1; i < n; ++i)
+            if (x[3 * i + d] < x[3 * jm + d]) jm = i;
+        xbar[3 * jm + d] += lob[d];
+        if (cond) cond[jm] += loa;
+        if (lobar) lobar[d] = lob[d];
+    }
+    free(xs); free(qs); free(us); free(mom); free(cot); free(cab); free(xb); free(xa);
     return 0;
 }
 
@@ -1116,7 +1286,7 @@ static int forces_any(int mode, int64_t n, const double *x, const double *q, dou
     if (mode == 0) { orc_direct(n, x, q, eps, f, NULL); return 0; }
     orc_tree *t = orc_tree_new(n, x, q, theta, eps, b, leaf_cap, G, group_mode, 0, curve);
     if (!t) return -1;
-    orc_tree_eval(t, x, q, f, NULL, NULL, NULL, NULL);
+    orc_tree_eval(t, x, q, f, NULL, NULL, NULL, NULL, NULL);
     orc_tree_free(t);
     return 0;
 }

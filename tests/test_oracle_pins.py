@@ -632,19 +632,131 @@ def test_tree_vjp_theta0_equals_direct_vjp():
                                atol=1e-10 * np.abs(oracle.direct_vjp(cl.x, cl.q, 0.02, u)).max())
 
 
+def _argmins(x):
+    return [int(np.argmin(x[:, d])) for d in range(3)]
+
+
 def test_tree_vjp_matches_frozen_list_finite_differences():
+    # With the lists and the box centres frozen (eval at a displaced x reuses
+    # the build's centres), the derivative is the VJP without its cube-origin
+    # term, which sits on the minimum particle of each axis.
     cl = _rand_cloud(800, 25)
     eps = 0.02
     t = oracle.Tree(cl.x, cl.q, 0.6, eps, leaf_cap=4, G=16, keep_lists=True)
     rng = np.random.default_rng(26)
     for _ in range(3):
         u = rng.normal(size=(cl.n, 3)); w = rng.normal(size=(cl.n, 3))
-        xb = t.vjp(u)
+        xb, _, lob = t.vjp(u, extras=True)
+        for d, j in enumerate(_argmins(cl.x)):
+            xb[j, d] -= lob[d]
         h = 1e-6    # central differences converge as h^2 here; 1e-6 leaves ~1e-8
         fp = t.eval(cl.x + h * w, want_phi=False)["f"]
         fm = t.eval(cl.x - h * w, want_phi=False)["f"]
         fd = (u * (fp - fm) / (2 * h)).sum()
         assert abs(fd - (xb * w).sum()) < 1e-6 * abs(fd)
+
+
+@pytest.mark.parametrize("theta,group_mode,curve", [(0.5, 1, oracle.CURVE_HILBERT),
+                                                    (0.7, 0, oracle.CURVE_MORTON),
+                                                    (0.3, 1, oracle.CURVE_MORTON)])
+def test_tree_vjp_is_translation_invariant(theta, group_mode, curve):
+    # Moving every particle by the same vector moves the cube origin and every
+    # box centre with it and leaves every force unchanged, so the full
+    # derivative sums to zero over the particles.  The frozen part alone does
+    # not (its sum is minus the cube-origin cotangent, 1e-5 of its scale here).
+    cl = _rand_cloud(2000, 31)
+    t = oracle.Tree(cl.x, cl.q, theta, 0.01, leaf_cap=8, G=16, keep_lists=True,
+                    group_mode=group_mode, curve=curve)
+    u = np.random.default_rng(32).normal(size=(cl.n, 3))
+    xb, cond, lob = t.vjp(u, extras=True)
+    scale = np.abs(xb).sum(axis=0)
+    assert np.all(np.abs(xb.sum(axis=0)) < 1e-13 * scale)
+    assert np.all(np.abs(lob) > 1e-7 * scale)     # the term is really there
+    # the term sizes bound every value they are summed into
+    assert np.all(cond >= np.linalg.norm(xb, axis=1))
+
+
+def test_tree_vjp_cube_term_vanishes_without_accepted_boxes():
+    cl = _rand_cloud(300, 33)
+    t = oracle.Tree(cl.x, cl.q, 0.0, 0.02, leaf_cap=4, G=16, keep_lists=True)
+    _, _, lob = t.vjp(np.random.default_rng(34).normal(size=(cl.n, 3)), extras=True)
+    assert np.all(lob == 0.0)
+
+
+def _same_lists(t0, t1):
+    if t0.nnodes != t1.nnodes or t0.ngroups != t1.ngroups:
+        return False
+    for g in range(t0.ngroups):
+        m0, p0 = t0.lists(g)
+        m1, p1 = t1.lists(g)
+        if not (np.array_equal(m0, m1) and np.array_equal(p0, p1)):
+            return False
+    return True
+
+
+def test_tree_vjp_matches_full_rebuild_finite_differences():
+    # Central differences of L = sum u.F(x) with the whole tree rebuilt at each
+    # displaced x (cube, keys, topology, lists), for displacements small
+    # enough that no list changes (checked): the minimum particle of each
+    # axis, whose move shifts the cube origin and every box centre, and
+    # interior particles.
+    cl = _rand_cloud(1500, 35)
+    th, eps, kw = 0.5, 0.01, dict(leaf_cap=8, G=16)
+    t = oracle.Tree(cl.x, cl.q, th, eps, keep_lists=True, **kw)
+    rng = np.random.default_rng(36)
+    u = rng.normal(size=(cl.n, 3))
+    xb = t.vjp(u)
+
+    def loss(xx):
+        tt = oracle.Tree(xx, cl.q, th, eps, keep_lists=True, **kw)
+        assert _same_lists(t, tt)
+        return float((u * tt.eval(xx, want_phi=False)["f"]).sum())
+
+    h = 1e-7
+    picks = [(j, d) for d, j in enumerate(_argmins(cl.x))]
+    picks += [(int(j), int(d)) for j, d in zip(rng.integers(0, cl.n, 6), rng.integers(0, 3, 6))]
+    for j, d in picks:
+        xp = cl.x.copy(); xp[j, d] += h
+        xm = cl.x.copy(); xm[j, d] -= h
+        fd = (loss(xp) - loss(xm)) / (2 * h)
+        assert abs(fd - xb[j, d]) < 1e-5 * abs(xb[j, d]) + 1e-6 * np.abs(xb).max(), (j, d)
+    # and along a random direction over all particles
+    w = rng.normal(size=(cl.n, 3))
+    fd = (loss(cl.x + h * w) - loss(cl.x - h * w)) / (2 * h)
+    assert abs(fd - (xb * w).sum()) < 1e-6 * abs(fd)
+
+
+def test_term_sizes_bound_an_fp32_direct_sum():
+    # At theta = 0 the tree is the direct sum, and A_i is sum_j |q_j| h^-3
+    # (|r| + 2 (2|r| + D_g)).  Forming each pair term in FP32 from offsets
+    # rounded relative to the group's box centre (numpy float32) stays within
+    # a few u_32 A_i of the FP64 field, particle by particle.
+    cl = _rand_cloud(512, 37)
+    eps = 0.01
+    t = oracle.Tree(cl.x, cl.q, 0.0, eps, leaf_cap=8, G=64, keep_lists=True)
+    r = t.eval(cond=True)
+    gf, gc, _ = t.groups()
+    perm = t.perm()
+    xs = cl.x[perm]; qs = cl.q[perm]
+    A = np.zeros(cl.n); E32 = np.zeros((cl.n, 3))
+    for g in range(t.ngroups):
+        mem = np.arange(gf[g], gf[g] + gc[g])
+        lo_, hi_ = xs[mem].min(0), xs[mem].max(0)
+        cg = 0.5 * (lo_ + hi_); Dg = np.linalg.norm(hi_ - lo_)
+        off = (xs - cg).astype(np.float32)
+        for i in mem:
+            rr = xs[i] - xs; rn = np.linalg.norm(rr, axis=1)
+            ih3 = (rn ** 2 + eps ** 2) ** -1.5
+            keep = np.arange(cl.n) != i
+            A[perm[i]] = np.sum((np.abs(qs) * ih3 * (rn + 2 * (2 * rn + Dg)))[keep])
+            r32 = off[i] - off
+            h2 = (r32 * r32).sum(1, dtype=np.float32) + np.float32(eps * eps)
+            w32 = qs.astype(np.float32) / (h2 * np.sqrt(h2))
+            E32[perm[i]] = (w32[keep, None] * r32[keep]).sum(0, dtype=np.float64)
+    np.testing.assert_allclose(r["cond"], A, rtol=1e-12)
+    E = r["f"] / cl.q[:, None]
+    ratio = np.linalg.norm(E32 - E, axis=1) / (2.0 ** -24 * A)
+    assert ratio.max() < 4.0
 
 
 def test_eval_of_selected_groups_equals_full_eval():
