@@ -86,21 +86,31 @@ def bench_ensemble(args, prec, dev):
                     group_mode=tuned["group_mode"], leaf_cap=tuned["leaf_cap"])
     f = ts.tree_forces(x, q, offs)
     st = ts.stats()
+    # one untimed call captures the step graphs; the timed call replays them
     ts.step(x, v, f, q, m, eprm["dt"], 2, offsets=offs)
-    torch.cuda.synchronize()
-    ts.timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ts.step(x, v, f, q, m, eprm["dt"], args.ensemble_steps, offsets=offs)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    ts.stats()
+    # the walk time: the same steps enqueued directly with HIP events around
+    # every walk launch (timing on bypasses the graphs)
+    ts.timing(True)
+    torch.cuda.synchronize()
+    e0 = time.perf_counter()
+    ts.step(x, v, f, q, m, eprm["dt"], args.ensemble_steps, offsets=offs)
+    torch.cuda.synchronize()
+    e1 = time.perf_counter()
     wms, wc = ts.timing_read()
     ts.stats()
     ts.close()
     el = t1 - t0
     return {"clouds": clouds, "n_total": n, "steps": args.ensemble_steps,
+            "path": "hipGraph replay of the batched step",
             "particles_per_s": n * args.ensemble_steps / el,
             "ms_per_step": 1e3 * el / args.ensemble_steps,
+            "direct_enqueue_ms_per_step": 1e3 * (e1 - e0) / args.ensemble_steps,
             "walk_ms": wms / max(wc, 1),
             "interactions_per_particle": (st["p2p"] + st["m2p"]) / n,
             "tuned": {"group_size": tuned["group_size"], "list_len": tuned["list_len"],
@@ -116,6 +126,191 @@ def bench_ensemble(args, prec, dev):
 def _finite(v):
     """JSON has no NaN or infinity: report those as null."""
     return v if isinstance(v, float) and math.isfinite(v) else None
+
+
+def per_particle_rel(f, ref):
+    """Per-particle relative force error |F_i - ref_i| / |ref_i|: median, 99th
+    percentile and maximum (rows of ref that are NaN are skipped)."""
+    import numpy as np
+    m = ~np.isnan(ref[:, 0])
+    r = np.linalg.norm(f[m] - ref[m], axis=1) / np.maximum(np.linalg.norm(ref[m], axis=1), 1e-300)
+    return {"median": float(np.median(r)), "p99": float(np.quantile(r, 0.99)),
+            "max": float(r.max()), "particles": int(m.sum())}
+
+
+def cpu_info():
+    """Model name of the host CPU and the cores this process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": usable, "logical_cpus": os.cpu_count()}
+
+
+def bench_accuracy_target(args, prec, x, v, q, m, n, eps, dt, tg, fd, target=1e-3):
+    """The cheapest setting of (theta, leaf_cap) at G = 64 chunk groups whose
+    relative RMS force error against the FP64 direct sum on the sampled
+    targets meets `target`: every candidate is evaluated once for its error,
+    and those that meet it are timed over whole Verlet steps (particles/s as
+    in the headline, directly enqueued); the fastest is reported with its
+    error."""
+    import numpy as np
+    import torch
+
+    from paper_0709_3331_amd import _lib as L
+    from paper_0709_3331_amd.tree import TreeSolver
+
+    gm = L.UCP_GROUP_CHUNK if args.group_mode == "chunk" else L.UCP_GROUP_NODE
+    rows = []
+    for th in (0.3, 0.35, 0.4, 0.45, 0.5):
+        for cap in (16, 24, 32, 48, 64):
+            tt = TreeSolver(n, curve=CURVE, theta=th, eps=eps, precision=prec,
+                            group_size=args.group_size, list_len=args.list_len, group_mode=gm,
+                            leaf_cap=cap, walk_waves=args.walk_waves)
+            fa = tt.tree_forces(x, q).cpu().numpy()
+            err = float(np.linalg.norm(fa[tg] - fd) / np.linalg.norm(fd))
+            row = {"theta": th, "leaf_cap": cap, "group_size": args.group_size,
+                   "rel_force_err_vs_direct_sampled": err}
+            if err <= target:
+                xx, vv = x.clone(), v.clone()
+                ff = tt.tree_forces(xx, q)
+                tt.step(xx, vv, ff, q, m, dt, 1)
+                tt.timing(True)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                tt.step(xx, vv, ff, q, m, dt, 5)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                wm, wc = tt.timing_read()
+                row["ms_per_step"] = 1e3 * (t1 - t0) / 5
+                row["particles_per_s"] = n * 5 / (t1 - t0)
+                row["walk_ms"] = wm / max(wc, 1)
+            tt.stats()
+            tt.close()
+            rows.append(row)
+    ok = [r for r in rows if "ms_per_step" in r]
+    best = min(ok, key=lambda r: r["ms_per_step"]) if ok else None
+    return {"target_rel_rms_vs_direct": target, "cheapest": best,
+            "candidates": [{k: (round(v, 6) if isinstance(v, float) else v) for k, v in r.items()}
+                           for r in rows]}
+
+
+def bench_seeds(args, prec, dev, seeds=(1, 2)):
+    """The headline steps on the same workload drawn with other seeds (run to
+    run variance of the input): ms per step and particles/s."""
+    import torch
+
+    from paper_0709_3331_amd import _lib as L
+    from paper_0709_3331_amd import inputs
+    from paper_0709_3331_amd.tree import TreeSolver
+
+    gm = L.UCP_GROUP_CHUNK if args.group_mode == "chunk" else L.UCP_GROUP_NODE
+    out = {}
+    for sd in seeds:
+        cl, prm = inputs.metric(sd)
+        x = torch.from_numpy(cl.x).to(dev)
+        v = torch.from_numpy(cl.v).to(dev)
+        q = torch.from_numpy(cl.q).to(dev)
+        m = torch.from_numpy(cl.m).to(dev)
+        ts = TreeSolver(cl.n, curve=CURVE, theta=args.theta, eps=prm["eps"], precision=prec,
+                        group_size=args.group_size, list_len=args.list_len, group_mode=gm,
+                        leaf_cap=args.leaf_cap, walk_waves=args.walk_waves)
+        f = ts.tree_forces(x, q)
+        st = ts.stats()
+        for _ in range(args.warmup):
+            ts.step(x, v, f, q, m, prm["dt"], 1)
+        ts.timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ts.step(x, v, f, q, m, prm["dt"], args.steps)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        wm, wc = ts.timing_read()
+        ts.stats()
+        ts.close()
+        out[str(sd)] = {"ms_per_step": 1e3 * (t1 - t0) / args.steps,
+                        "particles_per_s": cl.n * args.steps / (t1 - t0),
+                        "walk_ms": wm / max(wc, 1),
+                        "interactions_per_particle": (st["p2p"] + st["m2p"]) / cl.n}
+    return out
+
+
+def bench_large(args, prec, dev):
+    """The N = 4,194,304 cloud (10% of the electrons hot, eps = 0.002,
+    theta = 0.5): one force evaluation (build + walk) timed on its own, its
+    particles/s, then 50 Verlet steps (dt = 5e-5), and the error of the
+    forces against the FP64 oracle tree on every 997th walk group and against
+    the FP64 direct sum on 1024 sampled targets."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_0709_3331_amd import _lib as L
+    from paper_0709_3331_amd import inputs
+    from paper_0709_3331_amd.tree import TreeSolver
+
+    cl, prm = inputs.large(0)
+    n = cl.n
+    print(f"bench: large cloud N={n}", file=sys.stderr, flush=True)
+    gm = L.UCP_GROUP_CHUNK if args.group_mode == "chunk" else L.UCP_GROUP_NODE
+    x = torch.from_numpy(cl.x).to(dev)
+    v = torch.from_numpy(cl.v).to(dev)
+    q = torch.from_numpy(cl.q).to(dev)
+    m = torch.from_numpy(cl.m).to(dev)
+    ts = TreeSolver(n, curve=CURVE, theta=prm["theta"], eps=prm["eps"], precision=prec,
+                    group_size=args.group_size, list_len=args.list_len, group_mode=gm,
+                    leaf_cap=args.leaf_cap, walk_waves=args.walk_waves)
+    f = ts.tree_forces(x, q)
+    st = ts.stats()
+    f0 = f.cpu().numpy()
+    reps = 5
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ts.build(x, q)
+        L.ucp_compute_forces(ts.h, f.data_ptr(), None, torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ts.stats()
+    eval_s = (t1 - t0) / reps
+    ts.step(x, v, f, q, m, prm["dt"], 1)
+    ts.timing(True)
+    torch.cuda.synchronize()
+    s0 = time.perf_counter()
+    ts.step(x, v, f, q, m, prm["dt"], prm["steps"])
+    torch.cuda.synchronize()
+    s1 = time.perf_counter()
+    wm, wc = ts.timing_read()
+    ts.stats()
+    ts.close()
+    t = oracle.Tree(cl.x, cl.q, prm["theta"], prm["eps"], curve=CURVE, G=args.group_size,
+                    group_mode=gm, leaf_cap=args.leaf_cap)
+    ref = t.eval_groups(np.arange(0, t.ngroups, 997))["f"]
+    mk = ~np.isnan(ref[:, 0])
+    tg = np.sort(np.random.default_rng(0).choice(n, 1024, replace=False))
+    fd, _ = oracle.direct_targets(cl.x, cl.q, prm["eps"], tg)
+    return {"n": n, "eps": prm["eps"], "theta": prm["theta"],
+            "force_eval_ms": 1e3 * eval_s, "force_eval_particles_per_s": n / eval_s,
+            "steps": prm["steps"], "dt": prm["dt"],
+            "ms_per_step": 1e3 * (s1 - s0) / prm["steps"],
+            "particles_per_s": n * prm["steps"] / (s1 - s0),
+            "walk_ms": wm / max(wc, 1),
+            "interactions_per_particle": (st["p2p"] + st["m2p"]) / n,
+            "rel_force_err_vs_oracle_tree_sampled": float(
+                np.linalg.norm(f0[mk] - ref[mk]) / np.linalg.norm(ref[mk])),
+            "per_particle_err_vs_oracle_tree_sampled": per_particle_rel(f0, ref),
+            "rel_force_err_vs_direct_sampled": float(
+                np.linalg.norm(f0[tg] - fd) / np.linalg.norm(fd)),
+            "sampled_groups": int(len(range(0, t.ngroups, 997))), "sampled_targets": 1024}
 
 
 def bench_adjoint(prec, dev):
@@ -432,6 +627,12 @@ def main():
                     help="skip the Kelbg pair-law measurement")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the differentiable 200-step rollout measurement")
+    ap.add_argument("--no-accuracy-target", action="store_true",
+                    help="skip the search for the cheapest setting that meets 1e-3 vs direct")
+    ap.add_argument("--no-seeds", action="store_true",
+                    help="skip the headline steps on the inputs of seeds 1 and 2")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the N = 4,194,304 cloud")
     ap.add_argument("--profile", action="store_true", help="short run for rocprofv3 (no extras)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 256 MiB device-to-device copy (counter calibration)")
@@ -571,6 +772,13 @@ def main():
         fd, _ = oracle.direct_targets(xs, qs, eps, tg)
         result["rel_force_err_vs_direct_sampled"] = float(
             np.linalg.norm(fs[tg] - fd) / np.linalg.norm(fd))
+        result["meets_1e-3_vs_direct"] = result["rel_force_err_vs_direct_sampled"] <= 1e-3
+        fdn = np.full_like(fs, np.nan)
+        fdn[tg] = fd
+        result["per_particle_err_vs_direct_sampled"] = per_particle_rel(fs, fdn)
+        if not args.no_accuracy_target:
+            result["accuracy_target"] = bench_accuracy_target(args, prec, x, v, q, m, n, eps, dt,
+                                                              tg, fd)
         if not args.no_theta_sweep:
             # the other opening parameters of the same workload: walk time,
             # interactions per particle, error against the sampled direct sum
@@ -627,18 +835,24 @@ def main():
         c1 = time.perf_counter()
         result["rel_force_err_vs_oracle_tree"] = float(
             np.linalg.norm(fs - ro["f"]) / np.linalg.norm(ro["f"]))
+        result["per_particle_err_vs_oracle_tree"] = per_particle_rel(fs, ro["f"])
         result["cpu_baseline"] = {
             "value": n / (c1 - c0), "unit": "particles/s", "cores": oracle.max_threads(),
             "kind": "oracle",
             "sample": "one full FP64 oracle tree-force evaluation (build + walk, OpenMP over "
-                      "groups) of the same N=524288 cloud at the same parameters; %.2f s" % (c1 - c0)}
+                      "groups) of the same N=524288 cloud at the same parameters; %.2f s" % (c1 - c0),
+            **cpu_info()}
     if not args.profile and not args.no_other_curve:
         key = "morton_keys" if CURVE == 1 else "hilbert_keys"
         result[key] = bench_other_curve(args, prec, cl, prm, dev)
     if not args.profile and not args.no_kelbg:
         result["kelbg"] = bench_kelbg(args, prec, x, q, cl, walk_avg_ms)
+    if not args.profile and not args.no_seeds:
+        result["seed_repeats"] = bench_seeds(args, prec, dev)
     if not args.profile and not args.no_ensemble:
         result["ensemble"] = bench_ensemble(args, prec, dev)
+    if not args.profile and not args.no_large:
+        result["large"] = bench_large(args, prec, dev)
     if not args.profile and not args.no_adjoint:
         result["adjoint"] = bench_adjoint(prec, dev)
     if args.calib_copy:

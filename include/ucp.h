@@ -23,7 +23,10 @@
  *    failure on that context.  Device-detected problems (node capacity
  *    exceeded, non-finite coordinates, inconsistent offsets) are raised as
  *    flags on the device and reported by the next synchronising call
- *    (ucp_get_stats); kernels launched after a flag is raised do no work.
+ *    (ucp_get_stats); kernels launched after a flag is raised do no work
+ *    until the next build.  A build starts with clear flags, but keeps every
+ *    flag raised since the last ucp_get_stats in a sticky word, so a flag
+ *    raised in any step of a multi-step call (or graph replay) is reported.
  *  - A context is not thread-safe; calls that overlap on one context race.
  */
 #ifndef UCP_H
@@ -224,20 +227,25 @@ ucp_status ucp_energy(ucp_ctx *c, const double *x, const double *v, const double
                       const double *m, int64_t n, double *out, void *stream);
 
 /* Vector-Jacobian product of the tree forces of the last build with respect
- * to positions, xbar = (dF/dx)^T u, with the cube, topology, box centres and
- * interaction lists of that build held fixed (they are piecewise constant in
- * x; the forces are those of Sec. 3 under the expansion of ucp_compute_forces).
- * The walk of the last build is repeated, giving the same lists; each
- * accepted box contributes through the target position and through its
- * dipole and quadrupole (their derivatives with respect to the box's
- * particles), each particle pair through both positions.
+ * to positions, xbar = (dF/dx)^T u (the forces are those of Sec. 3 under the
+ * expansion of ucp_compute_forces).  The topology, the interaction lists and
+ * the cube's side are piecewise constant in x and held fixed (their jumps are
+ * not differentiated).  The cube's origin is the per-axis minimum of each
+ * cloud's positions and every box centre is that origin plus a fixed offset,
+ * so the centres move with the minimum particles: the derivative through
+ * them goes, per cloud and axis, to the particle holding the minimum (the
+ * lowest caller index among equal minima).  The walk of the last build is
+ * repeated, giving the same lists; each accepted box contributes through the
+ * target position, through its dipole and quadrupole (their derivatives with
+ * respect to the box's particles) and through its centre, each particle pair
+ * through both positions.
  * u, xbar: device [n][3] FP64 (caller order), owned by the caller; u may not
  * alias xbar.  The positions given to the last build must be unchanged.
  * Precision as for the forces (UCP_SPLIT: FP32 arithmetic on offsets formed
  * in FP64, FP64 accumulation).  Contributions of different walk groups to one
  * box or particle are added with FP64 atomics, so xbar is reproducible to
  * rounding, not bitwise.  The first call allocates the adjoint scratch
- * (48 bytes per particle, 80 per node slot).
+ * (48 bytes per particle, 80 per node slot, 44 per cloud).
  * Errors: UCP_EINVAL (NULL argument, or a pair law other than
  * UCP_PAIR_PLUMMER or an expansion other than UCP_EXPANSION_QUADRUPOLE: only
  * those have an adjoint), UCP_ENOTBUILT, UCP_ENOMEM, UCP_EHIP; device flags
@@ -245,8 +253,10 @@ ucp_status ucp_energy(ucp_ctx *c, const double *x, const double *v, const double
 ucp_status ucp_force_vjp(ucp_ctx *c, const double *u, double *xbar, void *stream);
 
 /* Synchronise `stream`, read the device counters and flags.  Returns
- * UCP_ECAPACITY / UCP_ENONFINITE / UCP_EINVAL when a flag is raised (the
- * stats are still filled in), else UCP_OK.                                 */
+ * UCP_ECAPACITY / UCP_ENONFINITE / UCP_EINVAL when a flag is raised by the
+ * last build or any build since the previous ucp_get_stats (the stats are
+ * still filled in; out->flags is their union), else UCP_OK.  Clears the
+ * sticky flags; the last build's own flags stay until the next build.     */
 ucp_status ucp_get_stats(ucp_ctx *c, ucp_stats *out, void *stream);
 
 /* Introspection of the last build, for tests and tools: copies one internal

@@ -307,12 +307,14 @@ class Tree:
         """(dF/dx)^T u with the lists of the build held fixed and the cube
         origin's dependence on the minimum particles included; needs
         keep_lists=True.  extras=True returns (xbar, cond, lobar): cond the
-        per-particle term sizes B_j, lobar the cube-origin cotangent."""
+        per-particle term sizes B_j, lobar the cube-origin cotangent (xyz),
+        the size of its terms and the size of the chain-rule terms this oracle
+        sums to get it (its own rounding scales with the latter)."""
         x = self.x if x is None else _f64(x, (-1, 3))
         u = _f64(u, (-1, 3))
         xb = np.zeros_like(x)
         cd = np.zeros(self.n) if extras else None
-        lob = np.zeros(3)
+        lob = np.zeros(5)
         if _lib.orc_tree_vjp(self._h, x, self.q, u, xb, _ptr(lob), _ptr(cd)) != 0:
             raise ValueError("tree vjp needs keep_lists=True and the Plummer pair law")
         return (xb, cd, lob) if extras else xb

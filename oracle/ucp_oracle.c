@@ -1044,11 +1044,15 @@ int orc_tree_eval_groups(const orc_tree *t, const double *x, const double *q, in
 /*      added on each axis d to the particle holding the minimum of that     */
 /*      axis (the lowest caller index among equal minima).                   */
 /* Requires keep_lists.  Returns 0, or -1 without lists.                     */
-/* lobar (optional, [3]) receives the cube-origin cotangent.  cond (optional, */
-/* [n], caller order) receives B_j, the sum of the sizes of every term added  */
-/* to xbar_j, each taken with its sums over magnitudes: an evaluation that   */
-/* forms each term in a working precision with unit roundoff u_w from        */
-/* offsets rounded once errs by at most a small multiple of u_w B_j.         */
+/* lobar (optional, [5]) receives the cube-origin cotangent (xyz), the size  */
+/* of its terms (the part of each J u through S, which is what the centre's  */
+/* derivative reduces to) and the size of the chain-rule terms summed above  */
+/* (they cancel to the former, so this oracle's own rounding of lobar is a   */
+/* small multiple of 2^-53 times that size).  cond (optional, [n], caller    */
+/* order) receives B_j, the sum of the sizes of every term added to xbar_j,  */
+/* each taken with its sums over magnitudes: an evaluation that forms each   */
+/* term in a working precision with unit roundoff u_w from offsets rounded   */
+/* once errs by at most a small multiple of u_w B_j.                         */
 /* ------------------------------------------------------------------------- */
 static void cell_jacobian(const double *mom, const double *r, double eps2, double J[3][3])
 {
@@ -1080,7 +1084,7 @@ int orc_tree_vjp(const orc_tree *t, const double *x, const double *q, const doub
                  double *lobar, double *cond)
 {
     int64_t n = t->n;
-    if (lobar) lobar[0] = lobar[1] = lobar[2] = 0.0;
+    if (lobar) lobar[0] = lobar[1] = lobar[2] = lobar[3] = lobar[4] = 0.0;
     if (n == 0) return 0;
     if (!t->keep_lists || t->pair_law != ORC_PAIR_PLUMMER) return -1;
     double *xs = (double *)malloc((size_t)n * 3 * sizeof(double));
@@ -1098,7 +1102,7 @@ int orc_tree_vjp(const orc_tree *t, const double *x, const double *q, const doub
     double *cab = (double *)calloc((size_t)t->M * 2, sizeof(double));
     double *xb = (double *)calloc((size_t)n * 3, sizeof(double));
     double *xa = (double *)calloc((size_t)n, sizeof(double));
-    double loa = 0.0;
+    double loa = 0.0, lch = 0.0;
     /* serial accumulation: deterministic and plainly correct */
     for (int64_t g = 0; g < t->ng; ++g) {
         for (int64_t a = 0; a < t->gcount[g]; ++a) {
@@ -1142,8 +1146,10 @@ int orc_tree_vjp(const orc_tree *t, const double *x, const double *q, const doub
                     const double ga = 3.0 * Qa * rn * ih5 + 3.0 * pa * ih5 +
                                       15.0 * pa * rn * rn * ih7 + 15.0 * Sa * rn * ih7 +
                                       52.5 * Sa * rn * rn * rn * ih9 + 7.5 * tra * rn * ih7;
-                    xa[i] += wa * (al + rn * ga + 3.0 * pa * rn * ih5 + 3.0 * Sa * ih5 +
-                                   15.0 * Sa * rn * rn * ih7);
+                    const double jua = wa * (al + rn * ga + 3.0 * pa * rn * ih5 + 3.0 * Sa * ih5 +
+                                             15.0 * Sa * rn * rn * ih7);
+                    xa[i] += jua;
+                    lch += jua;
                     cab[2 * k] += wa * (3.0 * rn * rn * ih5 + ih3);
                     cab[2 * k + 1] += wa * (15.0 * rn * rn * rn * ih7 + 12.0 * rn * ih5);
                     /* the box's share of lobar, the part of J u through S */
@@ -1199,6 +1205,9 @@ int orc_tree_vjp(const orc_tree *t, const double *x, const double *q, const doub
     for (int64_t k = 0; k < t->M; ++k) {
         const double *pb = cot + 15 * k, *Sb = cot + 15 * k + 3, *rb = cot + 15 * k + 12;
         const double Q = mom[10 * k], *pm = mom + 10 * k + 1;
+        if (cond)
+            lch += fabs(Q) * cab[2 * k] + cab[2 * k + 1] * sqrt(pm[0] * pm[0] + pm[1] * pm[1] +
+                                                                   pm[2] * pm[2]);
         for (int d = 0; d < 3; ++d) {
             double s = -rb[d] - Q * pb[d];
             for (int e2 = 0; e2 < 3; ++e2) s -= (Sb[3 * d + e2] + Sb[3 * e2 + d]) * pm[e2];
@@ -1216,6 +1225,10 @@ int orc_tree_vjp(const orc_tree *t, const double *x, const double *q, const doub
         xbar[3 * jm + d] += lob[d];
         if (cond) cond[jm] += loa;
         if (lobar) lobar[d] = lob[d];
+    }
+    if (lobar && cond) {
+        lobar[3] = loa;
+        lobar[4] = lch;
     }
     free(xs); free(qs); free(us); free(mom); free(cot); free(cab); free(xb); free(xa);
     return 0;

@@ -2,11 +2,14 @@
 
 `TreeForce` is the force map F(x) of the TREE method (Sec. 3) as a
 torch.autograd.Function.  Its backward is the library's adjoint walk
-(ucp_force_vjp): the vector-Jacobian product (dF/dx)^T u with the cube,
-topology, box centres and interaction lists of the build at x held fixed
-(they are piecewise constant in x).  The backward rebuilds the tree at the
-saved positions first, because later builds (the next Verlet steps) replace
-the context's tree.
+(ucp_force_vjp): the vector-Jacobian product (dF/dx)^T u with the topology,
+the interaction lists and the cube's side of the build at x held fixed (they
+are piecewise constant in x).  The box centres are not: they are the cube
+origin, the per-axis minimum of the positions, plus fixed offsets, and the
+adjoint carries their derivative to the minimum particles.  The backward
+rebuilds the tree at the saved positions first, because later builds (the
+next Verlet steps) replace the context's tree, and checks the library's
+device flags (a raised flag raises UcpError).
 
 `rollout` integrates velocity Verlet (kick-drift-kick, Sec. 2) with TreeForce
 and recomputes each segment of `checkpoint_every` steps during the backward
@@ -14,8 +17,10 @@ pass instead of storing it (torch.utils.checkpoint).  Gradients reach the
 initial positions and velocities, and through them any parameter they were
 made from (e.g. the cloud width sigma with x0 = sigma z).
 
-The solver object needs `tree_forces(x, q)`, `build(x, q)` and `vjp(u)`, as
-`tree.TreeSolver` provides.
+The solver object needs `tree_forces(x, q)`, `build(x, q)`, `vjp(u)` and
+`check()` (raises if the device flagged a problem since the last check), as
+`tree.TreeSolver` provides.  The forward of a rollout checks once at its end:
+the library keeps every flag raised since the last check.
 """
 from __future__ import annotations
 
@@ -40,6 +45,7 @@ class TreeForce(torch.autograd.Function):
         solver = ctx.solver
         solver.build(x, q)   # the lists of this x
         xbar = solver.vjp(fbar.contiguous())
+        solver.check()
         return xbar, None, None
 
 
@@ -70,6 +76,7 @@ def rollout(solver, x0, v0, q, m, dt, nsteps, checkpoint_every=20):
         else:
             x, v, f = kdk_segment(solver, x, v, f, q, inv_m, dt, k)
         done += k
+    solver.check()
     return x, v
 
 

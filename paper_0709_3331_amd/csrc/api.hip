@@ -89,7 +89,7 @@ void free_all(Ctx *c)
                     c->d_leaf, c->d_cnt,    c->d_lend, c->d_lvlmax, c->d_noff,  c->d_goff,   c->d_gnode,  c->d_gcl, c->d_scanblk,
                     c->d_ngeo, c->d_ninfo,  c->d_npar,  c->d_mom64,  c->d_nrec,
                     c->d_groups, c->d_gstat, c->d_acc,  c->d_ctr,    c->d_flags,  c->d_epart,
-                    c->d_leafof, c->d_w,    c->d_xsrc,  c->d_cbar,  c->d_wq,
+                    c->d_leafof, c->d_w,    c->d_xsrc,  c->d_cbar,  c->d_lobar, c->d_lomin, c->d_wq,
                     c->d_ghist,  c->d_sortctl, c->d_nlev, c->d_spec};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -448,13 +448,17 @@ ucp_status ucp_force_vjp(ucp_ctx *c, const double *u, double *xbar, void *stream
         hipError_t e = hipMalloc((void **)&c->d_w, (size_t)c->n_max * sizeof(double4) + 256);
         if (e == hipSuccess) e = hipMalloc((void **)&c->d_xsrc, (size_t)c->n_max * 4 * sizeof(double) + 256);
         if (e == hipSuccess) e = hipMalloc((void **)&c->d_cbar, (size_t)c->node_cap * 10 * sizeof(double) + 256);
+        if (e == hipSuccess) e = hipMalloc((void **)&c->d_lobar, (size_t)c->clouds_max * 4 * sizeof(double) + 256);
+        if (e == hipSuccess) e = hipMalloc((void **)&c->d_lomin, (size_t)c->clouds_max * 3 * sizeof(uint32_t) + 256);
         if (e != hipSuccess) {
-            (void)hipFree(c->d_w);
-            (void)hipFree(c->d_xsrc);
-            (void)hipFree(c->d_cbar);
+            for (void *q : {(void *)c->d_w, (void *)c->d_xsrc, (void *)c->d_cbar, (void *)c->d_lobar,
+                            (void *)c->d_lomin})
+                (void)hipFree(q);
             c->d_w = nullptr;
             c->d_xsrc = nullptr;
             c->d_cbar = nullptr;
+            c->d_lobar = nullptr;
+            c->d_lomin = nullptr;
             return fail(c, e == hipErrorOutOfMemory ? UCP_ENOMEM : UCP_EHIP,
                         std::string("ucp_force_vjp: ") + hipGetErrorString(e));
         }
@@ -473,9 +477,16 @@ ucp_status ucp_get_stats(ucp_ctx *c, ucp_stats *out, void *stream)
     out->clouds = c->clouds;
     if (!c->built || c->n == 0) return UCP_OK;
     unsigned long long ctr[ucp::CTR_NCTR];
-    int32_t flags = 0, nodes = 0, groups = 0;
+    int32_t fl[2] = {0, 0}, nodes = 0, groups = 0;
     HIP_TRY(c, hipMemcpy(ctr, c->d_ctr, sizeof ctr, hipMemcpyDeviceToHost));
-    HIP_TRY(c, hipMemcpy(&flags, c->d_flags, sizeof flags, hipMemcpyDeviceToHost));
+    // the current build's flags and those of every build since the last call;
+    // the sticky word is cleared and the current build's flags are marked as
+    // reported (they stay set, and stop its kernels, until the next build)
+    HIP_TRY(c, hipMemcpy(fl, c->d_flags, sizeof fl, hipMemcpyDeviceToHost));
+    const int32_t clear_and_mark[2] = {0, fl[0]};
+    HIP_TRY(c, hipMemcpy(c->d_flags + 1, clear_and_mark, sizeof clear_and_mark,
+                         hipMemcpyHostToDevice));
+    const int32_t flags = fl[0] | fl[1];
     HIP_TRY(c, hipMemcpy(&nodes, c->d_noff + c->n, sizeof nodes, hipMemcpyDeviceToHost));
     HIP_TRY(c, hipMemcpy(&groups, c->d_goff + c->n, sizeof groups, hipMemcpyDeviceToHost));
     out->nodes = nodes;

@@ -62,7 +62,9 @@ __device__ __forceinline__ int block_excl_scan(int v, int *total);
 // per-build state: cloud extents, counters (the walk's included), the walk's
 // queue heads, the sort's tickets, digit counts and the first pass's
 // look-back status words (every block); then block 0
-// clears the flag word, sets the cloud offsets ({0, n} for one cloud, or a
+// moves the last build's flags that ucp_get_stats has not yet reported
+// (flags[2] holds the reported ones) into the sticky word (flags[1], cleared
+// only by ucp_get_stats) and clears the flag word, sets the cloud offsets ({0, n} for one cloud, or a
 // checked copy of the caller's) and, for chunk groups (G > 0), the first
 // chunk group of each cloud and their total
 __global__ __launch_bounds__(kScanBlock) void k_build_reset(
@@ -80,7 +82,11 @@ __global__ __launch_bounds__(kScanBlock) void k_build_reset(
     if (t0 < kSortPassesMax * 256) ghist[t0] = 0;
     for (int64_t t = t0; t < nstatus; t += (int64_t)gridDim.x * blockDim.x) status0[t] = 0;
     if (blockIdx.x != 0) return;
-    if (threadIdx.x == 0) *flags = 0;
+    if (threadIdx.x == 0) {
+        flags[1] |= flags[0] & ~flags[2];
+        flags[0] = 0;
+        flags[2] = 0;
+    }
     __syncthreads();
     if (src_off) {
         for (int c = threadIdx.x; c <= clouds; c += blockDim.x) {

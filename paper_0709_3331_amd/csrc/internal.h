@@ -132,6 +132,8 @@ struct Ctx {
     double4 *d_w = nullptr;                 // [n_max] q_i u_i, sorted
     double *d_xsrc = nullptr;               // [n_max][4] source-side P2P cotangent
     double *d_cbar = nullptr;               // [node_cap][10] cell cotangents
+    double *d_lobar = nullptr;              // [clouds_max][4] cube-origin cotangent per cloud
+    uint32_t *d_lomin = nullptr;            // [clouds_max][3] caller index of each axis' minimum
     // counters, flags
     unsigned long long *d_ctr = nullptr;    // [CTR_NCTR]
     unsigned long long *d_wq = nullptr;     // [kWalkQueues * kQStride] walk queue heads

@@ -50,6 +50,9 @@ struct WalkArgs {
     const double4 *w;       // adjoint: sorted target cotangents q_i u_i
     double *cbar;           // adjoint: per node pbar[3], (Sbar + Sbar^T)[6], pad (10 doubles)
     double *xsrc;           // adjoint: per particle source-side P2P cotangent (4 doubles)
+    double *lobar;          // adjoint: per cloud cotangent of the cube origin (4 doubles)
+    const int64_t *off;     // cloud offsets [clouds + 1]
+    int clouds;
     const float4 *nrec;
     const double *mom64;
     const int4 *groups;
@@ -236,22 +239,31 @@ __device__ __forceinline__ void m2p_entry(const T *r, T tx, T ty, T tz, T eps2, 
 }
 
 // ---------------------------------------------------------------------------
-// adjoint of one accepted box (frozen lists).  With w the target's cotangent
-// (q_i times the cotangent of F_i), r = target - centre and h^2 = |r|^2 + eps^2:
-//   target side  g = d(w.E)/dr = alpha r + beta w + 3 (w.r) h^-5 p
-//                    + 15 (w.r) h^-7 S r - 3 h^-5 S w,
-//     alpha = (w.r)(-3 Q h^-5 - 15 (p.r) h^-7 - 52.5 (r.S.r) h^-9 + 7.5 trS h^-7)
-//             + 3 (w.p) h^-5 + 15 (w.S.r) h^-7,
-//     beta  = Q h^-3 + 3 (p.r) h^-5 + 7.5 (r.S.r) h^-7 - 1.5 trS h^-5;
+// adjoint of one accepted box.  With w the target's cotangent (q_i times the
+// cotangent of F_i), r = target - centre and h^2 = |r|^2 + eps^2:
+//   target side  g = d(w.E)/dr = g_QP + g_S,
+//     g_QP = [(w.r)(-3 Q h^-5 - 15 (p.r) h^-7) + 3 (w.p) h^-5] r
+//            + (Q h^-3 + 3 (p.r) h^-5) w + 3 (w.r) h^-5 p,
+//     g_S  = [(w.r)(-52.5 (r.S.r) h^-9 + 7.5 trS h^-7) + 15 (w.S.r) h^-7] r
+//            + (7.5 (r.S.r) h^-7 - 1.5 trS h^-5) w + 15 (w.r) h^-7 S r - 3 h^-5 S w;
 //   source side  pbar += 3 (w.r) h^-5 r - h^-3 w,
 //                sym  += 15 (w.r) h^-7 r r^T - 3 (w.r) h^-5 I - 3 h^-5 (w r^T + r w^T),
 // sym being Sbar + Sbar^T; a particle j of the box then receives
 // q_j (pbar + sym (x_j - c)).
+//   Box centre.  Every centre is the cube origin plus a fixed offset, and the
+// origin is the minimum particle of each axis.  The derivative of a Taylor
+// expansion to order n with respect to its expansion point, the moments
+// moving with it, telescopes to the order-n terms alone (the lower orders
+// cancel): here d(w.E)/dc = (1/2) w_d S_ab d^4 G/dr_a dr_b dr_c dr_d with
+// G = 1/h, which is -g_S.  So the centre's cotangent is -g_S, formed without
+// the cancellation of the Q and p terms, and its sum over the boxes of a
+// cloud goes to the cloud's minimum particles.
 // ---------------------------------------------------------------------------
 template <typename T>
 __device__ __forceinline__ void m2p_adj_target(T rx, T ry, T rz, T Q, T px, T py, T pz, T Sxx,
                                                T Syy, T Szz, T Sxy, T Sxz, T Syz, T trS15, T wx,
-                                               T wy, T wz, T eps2, T &gx, T &gy, T &gz)
+                                               T wy, T wz, T eps2, T &gx, T &gy, T &gz, T &lx,
+                                               T &ly, T &lz)
 {
     const T h2 = fma(rx, rx, fma(ry, ry, fma(rz, rz, eps2)));
     T ih;
@@ -269,14 +281,20 @@ __device__ __forceinline__ void m2p_adj_target(T rx, T ry, T rz, T Q, T px, T py
     const T up = fma(wx, px, fma(wy, py, wz * pz));
     const T rSr = fma(rx, Srx, fma(ry, Sry, rz * Srz));
     const T uSr = fma(wx, Srx, fma(wy, Sry, wz * Srz));
-    const T alpha = ur * (-(T)3 * Q * ih5 - (T)15 * pr * ih7 - (T)52.5 * rSr * ih9 +
-                          (T)5 * trS15 * ih7) +
-                    (T)3 * up * ih5 + (T)15 * uSr * ih7;
-    const T beta = Q * ih3 + (T)3 * pr * ih5 + (T)7.5 * rSr * ih7 - trS15 * ih5;
+    const T aS = ur * ((T)5 * trS15 * ih7 - (T)52.5 * rSr * ih9) + (T)15 * uSr * ih7;
+    const T aQP = ur * (-(T)3 * Q * ih5 - (T)15 * pr * ih7) + (T)3 * up * ih5;
+    const T bS = (T)7.5 * rSr * ih7 - trS15 * ih5;
+    const T bQP = Q * ih3 + (T)3 * pr * ih5;
     const T cp = (T)3 * ur * ih5, cs = (T)15 * ur * ih7, cw = (T)3 * ih5;
-    gx += alpha * rx + beta * wx + cp * px + cs * Srx - cw * Swx;
-    gy += alpha * ry + beta * wy + cp * py + cs * Sry - cw * Swy;
-    gz += alpha * rz + beta * wz + cp * pz + cs * Srz - cw * Swz;
+    const T sx = aS * rx + bS * wx + cs * Srx - cw * Swx;
+    const T sy = aS * ry + bS * wy + cs * Sry - cw * Swy;
+    const T sz = aS * rz + bS * wz + cs * Srz - cw * Swz;
+    gx += aQP * rx + bQP * wx + cp * px + sx;
+    gy += aQP * ry + bQP * wy + cp * py + sy;
+    gz += aQP * rz + bQP * wz + cp * pz + sz;
+    lx -= sx;
+    ly -= sy;
+    lz -= sz;
 }
 
 template <typename T>
@@ -454,6 +472,7 @@ struct Target {
     double px, py, pz;           // FP64 position (adjoint P2P differences)
     int i;                       // sorted index of the lane's target
     double E0, E1, E2, PH;       // field and potential, or the target-side adjoint
+    double C0, C1, C2;           // adjoint: the lane's share of the cube-origin cotangent
 };
 
 // Evaluate the M2P and P2P index lists of a group.  Entries are staged into
@@ -553,18 +572,21 @@ __device__ __forceinline__ void flush_lists(const WalkArgs &a, const int4 *ml, i
             tg.E2 += (double)(ez + fz);
             tg.PH += (double)(ph + fp);
         } else {
-            T gx = 0, gy = 0, gz = 0;
+            T gx = 0, gy = 0, gz = 0, lx = 0, ly = 0, lz = 0;
             for (int e = sub; e < cnt; e += lpt) {
                 CellRec<T> r;
                 double cx, cy, cz;
                 load_adj_rec<PREC>(stage + kRec * e, r, cx, cy, cz);
                 m2p_adj_target<T>((T)(tg.px - cx), (T)(tg.py - cy), (T)(tg.pz - cz), r.Q, r.px,
                                   r.py, r.pz, r.Sxx, r.Syy, r.Szz, r.Sxy, r.Sxz, r.Syz, r.trS15,
-                                  tg.wx, tg.wy, tg.wz, eps2, gx, gy, gz);
+                                  tg.wx, tg.wy, tg.wz, eps2, gx, gy, gz, lx, ly, lz);
             }
             tg.E0 += (double)gx;
             tg.E1 += (double)gy;
             tg.E2 += (double)gz;
+            tg.C0 += (double)lx;
+            tg.C1 += (double)ly;
+            tg.C2 += (double)lz;
             // source side: lane e owns staged record e
             CellRec<T> r;
             double cx, cy, cz;
@@ -785,6 +807,7 @@ __global__ __launch_bounds__(256) void k_walk(WalkArgs a)
         tg.qt = (T)xi.w;
         tg.i = i;
         tg.E0 = tg.E1 = tg.E2 = tg.PH = 0.0;
+        tg.C0 = tg.C1 = tg.C2 = 0.0;
         stk[0] = make_int2(root, min(((const int *)(a.nrec + 8 * (int64_t)root + 2))[0], nn));
         int sp = 1;
         wave_sync();
@@ -952,6 +975,19 @@ __global__ __launch_bounds__(256) void k_walk(WalkArgs a)
             a.acc[(act && sub == 0) ? (int64_t)i : a.n_spare + lane] =
                 make_double4(s0, s1, s2, s3);
         }
+        if constexpr (MODE == kWalkVjp) {
+            // the group's share of its cloud's cube-origin cotangent (lanes
+            // without a target carry w = 0 and add nothing)
+            double c0 = tg.C0, c1 = tg.C1, c2 = tg.C2;
+            for (int o = 32; o > 0; o >>= 1) {
+                c0 += __shfl_xor(c0, o);
+                c1 += __shfl_xor(c1, o);
+                c2 += __shfl_xor(c2, o);
+            }
+            const int cl = cloud_of(a.off, a.clouds, gfirst);
+            const double v = lane == 0 ? c0 : lane == 1 ? c1 : c2;
+            if (lane < 3) atomicAdd(a.lobar + 4 * (int64_t)cl + lane, v);
+        }
         const int tot_m = wave_isum(my_m), tot_src = wave_isum(my_src);
         a.gstat[g] = make_int2(tot_m, tot_src);   // same value from every lane
         const unsigned long long zero = 0ull;
@@ -1010,22 +1046,30 @@ __device__ __forceinline__ double vjp_scale(const unsigned long long *ctr)
     return ldexp(1.0, e);   // power of two > mx
 }
 
-__global__ void k_vjp_reset(unsigned long long *ctr)
+// clears the scale and the per-cloud cube-origin cotangents, and marks every
+// cloud's minimum particles as not yet found
+__global__ void k_vjp_reset(unsigned long long *ctr, double *lobar, uint32_t *lomin, int clouds)
 {
     if (threadIdx.x == 0) ctr[CTR_VJPMAX] = 0ull;
+    for (int k = threadIdx.x; k < 4 * clouds; k += blockDim.x) lobar[k] = 0.0;
+    for (int k = threadIdx.x; k < 3 * clouds; k += blockDim.x) lomin[k] = 0xffffffffu;
 }
 
 // ---------------------------------------------------------------------------
 // adjoint: prepare the sorted cotangents and clear the accumulators
 //   w_p = q_p u_{perm[p]} / s,  xsrc = 0,  cbar = 0 (nodes read from the device)
 // ---------------------------------------------------------------------------
+//   and, per cloud and axis, the lowest caller index among the particles on
+//   the cube origin (the minimum of that axis)
 __global__ __launch_bounds__(256) void k_vjp_prep(const double *__restrict__ u,
                                                  const double4 *__restrict__ xq,
                                                  const uint32_t *__restrict__ perm, int64_t n,
                                                  const int32_t *__restrict__ nnodes,
                                                  const unsigned long long *__restrict__ ctr,
+                                                 const int64_t *__restrict__ off, int clouds,
+                                                 const double4 *__restrict__ cube,
                                                  double4 *w, double *xsrc, double *cbar,
-                                                 const int32_t *flags)
+                                                 uint32_t *lomin, const int32_t *flags)
 {
     if (*flags) return;
     const double inv = 1.0 / vjp_scale(ctr);
@@ -1033,9 +1077,15 @@ __global__ __launch_bounds__(256) void k_vjp_prep(const double *__restrict__ u,
     const int64_t t0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     for (int64_t p = t0; p < n; p += stride) {
         const int64_t i = perm[p];
-        const double qq = xq[p].w * inv;
+        const double4 x = xq[p];
+        const double qq = x.w * inv;
         w[p] = make_double4(qq * u[3 * i], qq * u[3 * i + 1], qq * u[3 * i + 2], 0.0);
         *(double4 *)(xsrc + 4 * p) = make_double4(0.0, 0.0, 0.0, 0.0);
+        const int cl = cloud_of(off, clouds, p);
+        const double4 lo = cube[2 * cl];
+        if (x.x == lo.x) atomicMin(lomin + 3 * cl + 0, (uint32_t)i);
+        if (x.y == lo.y) atomicMin(lomin + 3 * cl + 1, (uint32_t)i);
+        if (x.z == lo.z) atomicMin(lomin + 3 * cl + 2, (uint32_t)i);
     }
     const int64_t nc = 10 * (int64_t)*nnodes;
     for (int64_t e = t0; e < nc; e += stride) cbar[e] = 0.0;
@@ -1045,7 +1095,8 @@ __global__ __launch_bounds__(256) void k_vjp_prep(const double *__restrict__ u,
 // adjoint: per particle j (sorted), the target side (walk accumulators), the
 // P2P source side, and the cell cotangents of every box holding j:
 //   xbar_j = g_j + xsrc_j + q_j sum_{C holding j} (pbar_C + sym_C (x_j - c_C)),
-// then back to the caller's order.
+// plus, on each axis where j is its cloud's marked minimum particle, the
+// cloud's cube-origin cotangent; then back to the caller's order.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_vjp_down(const double4 *__restrict__ acc,
                                                  const double *__restrict__ xsrc,
@@ -1057,6 +1108,9 @@ __global__ __launch_bounds__(256) void k_vjp_down(const double4 *__restrict__ ac
                                                  const int32_t *__restrict__ nnodes,
                                                  const uint32_t *__restrict__ perm, int64_t n,
                                                  const unsigned long long *__restrict__ ctr,
+                                                 const int64_t *__restrict__ off, int clouds,
+                                                 const uint32_t *__restrict__ lomin,
+                                                 const double *__restrict__ lobar,
                                                  double *xbar, int32_t *flags)
 {
     if (*flags) return;
@@ -1082,9 +1136,12 @@ __global__ __launch_bounds__(256) void k_vjp_down(const double4 *__restrict__ ac
         k = npar[k];
     }
     const int64_t i = perm[p];
-    xbar[3 * i + 0] = sc * (g.x + xsrc[4 * p + 0] + x.w * bx);
-    xbar[3 * i + 1] = sc * (g.y + xsrc[4 * p + 1] + x.w * by);
-    xbar[3 * i + 2] = sc * (g.z + xsrc[4 * p + 2] + x.w * bz);
+    const int cl = cloud_of(off, clouds, p);
+    const uint32_t *lm = lomin + 3 * cl;
+    const double *lb = lobar + 4 * (int64_t)cl;
+    xbar[3 * i + 0] = sc * (g.x + xsrc[4 * p + 0] + x.w * bx + (lm[0] == (uint32_t)i ? lb[0] : 0.0));
+    xbar[3 * i + 1] = sc * (g.y + xsrc[4 * p + 1] + x.w * by + (lm[1] == (uint32_t)i ? lb[1] : 0.0));
+    xbar[3 * i + 2] = sc * (g.z + xsrc[4 * p + 2] + x.w * bz + (lm[2] == (uint32_t)i ? lb[2] : 0.0));
 }
 
 template <int PREC, int MODE, bool KELBG = false, bool SPEC = false>
@@ -1126,6 +1183,9 @@ static WalkArgs walk_args(Ctx *c)
     wa.w = nullptr;
     wa.cbar = nullptr;
     wa.xsrc = nullptr;
+    wa.lobar = nullptr;
+    wa.off = c->d_off;
+    wa.clouds = c->clouds;
     wa.fout = nullptr;
     wa.phiout = nullptr;
     wa.perm = c->d_perm;
@@ -1194,12 +1254,15 @@ void launch_vjp(Ctx *c, const double *u, double *xbar, hipStream_t s)
     wa.w = c->d_w;
     wa.cbar = c->d_cbar;
     wa.xsrc = c->d_xsrc;
-    hipLaunchKernelGGL(k_vjp_reset, dim3(1), dim3(64), 0, s, c->d_ctr);
+    wa.lobar = c->d_lobar;
+    hipLaunchKernelGGL(k_vjp_reset, dim3(1), dim3(256), 0, s, c->d_ctr, c->d_lobar, c->d_lomin,
+                       c->clouds);
     hipLaunchKernelGGL(k_vjp_max, dim3(256), dim3(256), 0, s, u, (const double4 *)c->d_xq,
                        (const uint32_t *)c->d_perm, n, c->d_ctr, (const int32_t *)c->d_flags);
     hipLaunchKernelGGL(k_vjp_prep, dim3(1024), dim3(256), 0, s, u, (const double4 *)c->d_xq,
                        (const uint32_t *)c->d_perm, n, (const int32_t *)(c->d_noff + n),
-                       (const unsigned long long *)c->d_ctr, c->d_w, c->d_xsrc, c->d_cbar,
+                       (const unsigned long long *)c->d_ctr, (const int64_t *)c->d_off, c->clouds,
+                       (const double4 *)c->d_cube, c->d_w, c->d_xsrc, c->d_cbar, c->d_lomin,
                        (const int32_t *)c->d_flags);
     hipLaunchKernelGGL(k_walk_reset, dim3(1), dim3(64), 0, s, c->d_ctr, c->d_wq);
     c->walk_armed = false;
@@ -1210,8 +1273,9 @@ void launch_vjp(Ctx *c, const double *u, double *xbar, hipStream_t s)
                        (const double *)c->d_cbar, (const double4 *)c->d_xq,
                        (const double4 *)c->d_ngeo, (const int32_t *)c->d_npar,
                        (const int32_t *)c->d_leafof, (const int32_t *)(c->d_noff + n),
-                       (const uint32_t *)c->d_perm, n, (const unsigned long long *)c->d_ctr, xbar,
-                       c->d_flags);
+                       (const uint32_t *)c->d_perm, n, (const unsigned long long *)c->d_ctr,
+                       (const int64_t *)c->d_off, c->clouds, (const uint32_t *)c->d_lomin,
+                       (const double *)c->d_lobar, xbar, c->d_flags);
 }
 
 }  // namespace ucp

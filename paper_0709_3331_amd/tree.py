@@ -95,6 +95,11 @@ class TreeSolver:
         st, rc = L.ucp_get_stats(self.h, _stream(), raise_on_flag)
         return {k: getattr(st, k) for k, _ in L.ucp_stats._fields_} | {"status": rc}
 
+    def check(self):
+        """Raise UcpError if the device flagged a problem in any build, walk
+        or adjoint since the last check (synchronises the stream)."""
+        self.stats(raise_on_flag=True)
+
     def timing(self, on=True):
         L.ucp_set_timing(self.h, on)
 

@@ -32,6 +32,22 @@ class DirectSolver:
     def vjp(self, u):
         return torch.from_numpy(oracle.direct_vjp(self.x, self.q, self.eps, u.numpy()))
 
+    def check(self):
+        pass
+
+
+class FlaggingSolver(DirectSolver):
+    """Reports a device flag (as the library's sticky word would) once a
+    given number of force evaluations has happened."""
+
+    def __init__(self, eps, flag_after):
+        super().__init__(eps)
+        self.flag_after = flag_after
+
+    def check(self):
+        if self.calls >= self.flag_after:
+            raise RuntimeError("device flag raised")
+
 
 def _setup(n=64, seed=3):
     cl = inputs.gaussian_cloud(n, 1.0, 1e-3, 1e-5, seed)
@@ -97,3 +113,18 @@ def test_tree_force_backward_rebuilds_at_saved_positions():
     (f1 * u).sum().backward()
     want = oracle.direct_vjp(z.numpy(), q.numpy(), 0.05, u.numpy())
     np.testing.assert_allclose(x1.grad.numpy(), want, rtol=1e-13, atol=1e-13)
+
+
+def test_rollout_forward_and_backward_check_the_device_flags():
+    # a flag raised by any step of the forward is seen once the forward ends
+    z, v0, q, m = _setup()
+    with pytest.raises(RuntimeError):
+        _loss(FlaggingSolver(0.05, 3), torch.tensor(1.0, dtype=torch.float64), z, v0, q, m,
+              1e-3, 5, 0)
+    # and a flag raised while the backward recomputes a segment is seen there
+    solver = FlaggingSolver(0.05, 10 ** 9)
+    sigma = torch.tensor(1.0, dtype=torch.float64, requires_grad=True)
+    loss = _loss(solver, sigma, z, v0, q, m, 1e-3, 5, 2)
+    solver.flag_after = 0
+    with pytest.raises(RuntimeError):
+        loss.backward()

@@ -1,10 +1,11 @@
 """GPU parity of the adjoint walk (ucp_force_vjp) and the differentiable rollout.
 
-The VJP (dF/dx)^T u with the lists of the build held fixed is compared with
-the FP64 oracle's frozen-list tree VJP at the same parameters (same lists, so
-the same function), with the oracle's analytic direct-sum VJP at theta = 0,
+The VJP (dF/dx)^T u with the lists of the build held fixed, the cube origin's
+dependence on each axis' minimum particle included, is compared with the FP64
+oracle's tree VJP at the same parameters (same lists, so the same function),
+particle by particle, with the oracle's analytic direct-sum VJP at theta = 0,
 and per cloud for a batched build.  The rollout gradient is checked against
-central finite differences at theta = 0, where the force map is smooth.
+central finite differences at theta = 0 and at theta = 0.5.
 """
 import numpy as np
 import pytest
@@ -22,12 +23,17 @@ from paper_0709_3331_amd import _lib as L  # noqa: E402
 from paper_0709_3331_amd import adjoint  # noqa: E402
 from paper_0709_3331_amd.tree import TreeSolver  # noqa: E402
 
-TOL_FP64 = 1e-10   # FP64 atomics add the per-group source terms in any order
-# UCP_SPLIT: each pair or cell term is FP32 (relative error ~1e-6 after the
-# reciprocal square root and products), and the adjoint's sums cancel: over
-# the test clouds sum|terms| / |xbar| is 10-20 (the pair terms q_i q_j K(r)
-# (u_i - u_j) of the direct sum already show it), so the bound is 5e-5
-TOL_SPLIT = 5e-5
+TOL_FP64 = 1e-10   # relative RMS: FP64 atomics add the per-group source terms in any order
+# Per-particle bound.  The oracle returns B_j, the sum of the sizes of the
+# terms added into xbar_j (each with its sums over magnitudes).  Each term is
+# formed from offsets rounded once to the working precision (unit roundoff
+# u_w) by at most 32 roundings in sequence, powers up to h^-9 included, and
+# the walk sums at most 64 terms in the working precision before an FP64
+# accumulator, so |xbar_j(GPU) - xbar_j(oracle)| <= K u_w B_j with K = 128,
+# plus the oracle's own FP64 rounding (K 2^-53 B_j, and on the minimum
+# particles K 2^-53 times the size of the chain-rule terms it sums).
+K_BOUND = 128.0
+U32, U64 = 2.0 ** -24, 2.0 ** -53
 
 
 def say(*a):
@@ -40,6 +46,20 @@ def relrms(a, b):
 
 def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def argmins(x):
+    return [int(np.argmin(x[:, d])) for d in range(3)]
+
+
+def vjp_bound_ratio(xb, ref, cond, lob, x, prec):
+    """max_j |xbar_j - ref_j| / (per-particle bound); <= 1 passes."""
+    uw = U32 if prec == L.UCP_SPLIT else U64
+    tol = K_BOUND * (uw + U64) * cond
+    for j in argmins(x):
+        tol[j] += K_BOUND * U64 * lob[4]
+    err = np.linalg.norm(xb - ref, axis=1)
+    return float(np.max(err / np.maximum(tol, 1e-300)))
 
 
 CASES = [
@@ -57,16 +77,23 @@ def test_vjp_matches_oracle_frozen_list_vjp(case):
     cl = inputs.gaussian_cloud(n, 1.0, 1e-3, 1e-5, seed)
     u = np.random.default_rng(seed).normal(size=(n, 3))
     t = oracle.Tree(cl.x, cl.q, theta, eps, leaf_cap=cap, G=G, group_mode=gm, keep_lists=True)
-    ref = t.vjp(u)
-    for prec, tol in ((L.UCP_FP64, TOL_FP64), (L.UCP_SPLIT, TOL_SPLIT)):
+    ref, cond, lob = t.vjp(u, extras=True)
+    for prec in (L.UCP_FP64, L.UCP_SPLIT):
         ts = TreeSolver(n, theta=theta, eps=eps, leaf_cap=cap, group_size=G, group_mode=gm,
                         precision=prec, list_len=64)
         ts.build(dev(cl.x), dev(cl.q))
         xb = ts.vjp(dev(u)).cpu().numpy()
         ts.stats()
         e = relrms(xb, ref)
-        say(f"[adjoint]   prec={prec} rel RMS vs oracle tree VJP {e:.3e}")
-        assert e < tol
+        ratio = vjp_bound_ratio(xb, ref, cond, lob, cl.x, prec)
+        am = argmins(cl.x)
+        lo_err = max(abs(xb[j, d] - ref[j, d]) / abs(lob[d]) for d, j in enumerate(am))
+        say(f"[adjoint]   prec={prec} rel RMS vs oracle tree VJP {e:.3e}; max error / "
+            f"per-particle bound {ratio:.3e}; minimum particles' error / cube cotangent "
+            f"{lo_err:.3e}")
+        if prec == L.UCP_FP64:
+            assert e < TOL_FP64
+        assert ratio <= 1.0
         ts.close()
 
 
@@ -102,7 +129,30 @@ def test_vjp_batched_clouds():
             continue
         a, b = off[k], off[k + 1]
         t = oracle.Tree(p.x, p.q, 0.5, 0.01, G=32, keep_lists=True)
-        assert relrms(xb[a:b], t.vjp(u[a:b])) < TOL_FP64, k
+        ref, cond, lob = t.vjp(u[a:b], extras=True)
+        assert relrms(xb[a:b], ref) < TOL_FP64, k
+        assert vjp_bound_ratio(xb[a:b], ref, cond, lob, p.x, L.UCP_FP64) <= 1.0, k
+    ts.close()
+
+
+@pytest.mark.parametrize("prec", [L.UCP_FP64, L.UCP_SPLIT], ids=["fp64", "split"])
+def test_vjp_translation_invariance_full_adjoint_cloud(prec):
+    # N = 65,536 cloud of the differentiation workload: moving every particle
+    # by one vector leaves the forces unchanged, so the VJP sums to zero over
+    # the particles (without the cube-origin term it does not: its sum is
+    # then minus that term).  Bounds: FP64 1e-12 and FP32 terms 1e-6 of
+    # sum |xbar|.
+    cl, prm = inputs.adjoint(0)
+    n = cl.n
+    say(f"[adjoint] translation invariance n={n} prec={prec}")
+    u = np.random.default_rng(7).normal(size=(n, 3))
+    ts = TreeSolver(n, theta=prm["theta"], eps=prm["eps"], precision=prec)
+    ts.build(dev(cl.x), dev(cl.q))
+    xb = ts.vjp(dev(u)).cpu().numpy()
+    ts.stats()
+    rel = np.abs(xb.sum(axis=0)) / np.abs(xb).sum(axis=0)
+    say(f"[adjoint]   |sum xbar| / sum |xbar| = {rel}")
+    assert np.all(rel < (1e-12 if prec == L.UCP_FP64 else 1e-6))
     ts.close()
 
 
@@ -137,6 +187,37 @@ def test_rollout_gradient_theta0_matches_finite_differences():
     fd = (lp - lm).item() / (2 * h)
     say(f"[adjoint]   dL/dsigma {sigma.grad.item():.10e} FD {fd:.10e}")
     assert sigma.grad.item() == pytest.approx(fd, rel=1e-5)
+    ts.close()
+
+
+def test_rollout_gradient_theta05_matches_finite_differences():
+    # The small cloud (N = 4096, eps = 0.01) at theta = 0.5 in FP64, 5 steps
+    # of dt = 1e-5, which the bound electrons resolve (omega dt = 0.43).  The
+    # finite differences rebuild the tree at every step of both perturbed
+    # runs; at h = 3e-7 and 1e-7 they agree to 1e-8 (no list changes on the
+    # way, converged; at h = 1e-6 a walk list changes along the way, on the
+    # FP64 oracle's Verlet run too), and the adjoint, cube-origin term
+    # included, must agree with them to 1e-6.
+    cl, prm = inputs.small(0)
+    n, dt, steps = cl.n, 1e-5, 5
+    say(f"[adjoint] rollout FD theta=0.5 n={n} steps={steps} dt={dt}")
+    z, v0, q, m = dev(cl.x), dev(cl.v), dev(cl.q), dev(cl.m)
+    ts = TreeSolver(n, theta=0.5, eps=prm["eps"], precision=L.UCP_FP64)
+    sigma = torch.tensor(1.0, dtype=torch.float64, device="cuda", requires_grad=True)
+    loss = _rollout_loss(ts, sigma, z, v0, q, m, dt, steps, 0)
+    loss.backward()
+    fds = []
+    with torch.no_grad():
+        for h in (3e-7, 1e-7):
+            lp = _rollout_loss(ts, torch.tensor(1.0 + h, dtype=torch.float64, device="cuda"), z,
+                               v0, q, m, dt, steps, 0)
+            lm = _rollout_loss(ts, torch.tensor(1.0 - h, dtype=torch.float64, device="cuda"), z,
+                               v0, q, m, dt, steps, 0)
+            fds.append((lp - lm).item() / (2 * h))
+    g = sigma.grad.item()
+    say(f"[adjoint]   dL/dsigma {g:.12e} FD {fds[0]:.12e} (h=3e-7) {fds[1]:.12e} (h=1e-7)")
+    assert fds[0] == pytest.approx(fds[1], rel=1e-8)
+    assert g == pytest.approx(fds[0], rel=1e-6)
     ts.close()
 
 

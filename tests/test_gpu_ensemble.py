@@ -52,6 +52,57 @@ def test_full_ensemble_sampled_clouds_match_oracle():
         ts.close()
 
 
+def test_batched_graph_step_matches_oracle_and_eager_steps():
+    # ucp_step_batched on ragged clouds (one empty, one of 3 particles): calls
+    # of 3 steps replay the captured graphs (a first call captures them);
+    # positions and velocities against the oracle's Verlet run of each cloud
+    # alone (FP64), and the graph path bitwise against the directly enqueued
+    # steps (timing on) of the same calls.
+    sizes = [900, 0, 2400, 64, 3]
+    dt, theta, eps, steps, calls = 1e-4, 0.5, 0.01, 3, 2
+    say(f"[ensemble] batched graph step sizes={sizes} calls={calls}x{steps}")
+    parts = [inputs.gaussian_cloud(s, 0.7 + 0.2 * k, 1e-3, 1e-5, 60 + k) if s % 2 == 0 and s else None
+             for k, s in enumerate(sizes)]
+    tiny = np.random.default_rng(9).normal(size=(3, 3))
+    xs = [p.x if p is not None else (tiny if s == 3 else np.zeros((0, 3)))
+          for p, s in zip(parts, sizes)]
+    vs = [p.v if p is not None else np.zeros((s, 3)) for p, s in zip(parts, sizes)]
+    qs = [p.q if p is not None else np.array([1.0, -1.0, 1.0])[:s] for p, s in zip(parts, sizes)]
+    ms = [p.m if p is not None else np.ones(s) for p, s in zip(parts, sizes)]
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    n = int(off[-1])
+    cat = lambda a: torch.from_numpy(np.ascontiguousarray(np.concatenate(a))).cuda()  # noqa: E731
+    q, m, offs = cat(qs), cat(ms), torch.from_numpy(off).cuda()
+    ts = TreeSolver(n, len(sizes), theta=theta, eps=eps, precision=L.UCP_FP64, group_size=32)
+    runs = []
+    for mode in ("graph", "eager"):
+        x, v = cat(xs), cat(vs)
+        f = ts.tree_forces(x, q, offs)
+        ts.timing(mode == "eager")
+        for c in range(calls):
+            ts.step(x, v, f, q, m, dt, steps, offsets=offs)
+            torch.cuda.synchronize()
+            _ = (x * 1.0).sum().item()          # eager work between the calls
+        ts.timing(False)
+        ts.timing_read()
+        ts.stats()
+        runs.append((x.clone(), v.clone(), f.clone()))
+    for a, b in zip(runs[0], runs[1]):
+        assert torch.equal(a, b)
+    xg, vg = runs[0][0].cpu().numpy(), runs[0][1].cpu().numpy()
+    for k in range(len(sizes)):
+        a, b = off[k], off[k + 1]
+        if b - a == 0:
+            continue
+        xr, vr, _ = oracle.verlet(xs[k], vs[k], qs[k], ms[k], dt, calls * steps, eps, mode="tree",
+                                  theta=theta, G=32)
+        dx = np.abs(xg[a:b] - xr).max()
+        dv = np.linalg.norm(vg[a:b] - vr) / max(np.linalg.norm(vr), 1e-300)
+        say(f"[ensemble]   cloud {k} (N={b - a}): max |dx| {dx:.2e}, v rel RMS {dv:.2e}")
+        assert dx < 1e-12 and dv < 1e-12, k
+    ts.close()
+
+
 def test_autotune_picks_fastest_candidate_and_caches(tmp_path):
     sizes = [6000, 10000]
     parts = [inputs.gaussian_cloud(s, 1.0, 1e-3, 1e-5, 40 + k) for k, s in enumerate(sizes)]

@@ -3,7 +3,9 @@
 Every comparison is made through the C-ABI on the same seeded inputs:
 keys, permutation, topology, box centres, groups and per-group interaction
 counts bit-exact; moments to 1e-13 of their natural scale; forces to 1e-12
-relative RMS on the FP64 path and 1e-5 on the FP32/FP64 split path.
+relative RMS on the FP64 path and 1e-5 on the FP32/FP64 split path, and
+particle by particle within the rounding bound of the terms each force is
+summed from.
 """
 import numpy as np
 import pytest
@@ -22,6 +24,16 @@ from paper_0709_3331_amd.tree import TreeSolver  # noqa: E402
 
 TOL_FP64 = 1e-12
 TOL_SPLIT = 1e-5
+# Per-particle bound.  The oracle returns A_i, the sum over the terms of E_i
+# of each term's size (its sums over magnitudes) and of its Jacobian times
+# the largest move of its offset when the offsets are rounded relative to a
+# point of the group's bounding box.  Each term takes at most 32 roundings in
+# sequence and the walk sums at most 64 terms in the working precision
+# (unit roundoff u_w) before an FP64 accumulator, so
+#     |F_i(GPU) - F_i(oracle)| <= K (u_w + 2^-53) |q_i| A_i,  K = 128,
+# the 2^-53 term covering the oracle's own FP64 rounding.
+K_BOUND = 128.0
+U32, U64 = 2.0 ** -24, 2.0 ** -53
 
 
 def say(*a):
@@ -35,6 +47,22 @@ def relrms(a, b):
 
 def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def force_bound_ratio(f, ref, cond, q, prec):
+    """max_i |F_i - ref_i| / (per-particle bound); <= 1 passes."""
+    uw = U32 if prec == L.UCP_SPLIT else U64
+    m = ~np.isnan(ref[:, 0])
+    tol = K_BOUND * (uw + U64) * np.abs(q[m]) * cond[m]
+    err = np.linalg.norm(f[m] - ref[m], axis=1)
+    return float(np.max(err / np.maximum(tol, 1e-300))) if err.size else 0.0
+
+
+def per_particle_rel(f, ref):
+    """median, 99th percentile and maximum of |F_i - ref_i| / |ref_i|."""
+    m = ~np.isnan(ref[:, 0])
+    r = np.linalg.norm(f[m] - ref[m], axis=1) / np.maximum(np.linalg.norm(ref[m], axis=1), 1e-300)
+    return float(np.median(r)), float(np.quantile(r, 0.99)), float(r.max())
 
 
 def check_topology(ts, t):
@@ -95,7 +123,7 @@ def test_tree_parity(case):
     cl = inputs.gaussian_cloud(n, 1.0, 1e-3, 1e-5, seed, halo_frac=halo)
     b = 21 if kb == 63 else 10
     t = oracle.Tree(cl.x, cl.q, theta, eps, b=b, leaf_cap=cap, G=G, group_mode=gm)
-    ref = t.eval(group_counts=True)
+    ref = t.eval(group_counts=True, cond=True)
     x, q = dev(cl.x), dev(cl.q)
     for prec, tol in ((L.UCP_FP64, TOL_FP64), (L.UCP_SPLIT, TOL_SPLIT)):
         ts = TreeSolver(n, 1, theta=theta, eps=eps, leaf_cap=cap, group_size=G, key_bits=kb,
@@ -110,10 +138,15 @@ def test_tree_parity(case):
         np.testing.assert_array_equal(gs[:, 0], ref["gm2p"])
         np.testing.assert_array_equal(gs[:, 1], ref["gp2p"])
         assert st["p2p"] == ref["p2p"] and st["m2p"] == ref["m2p"]
-        ef = relrms(f.cpu().numpy(), ref["f"])
+        fa = f.cpu().numpy()
+        ef = relrms(fa, ref["f"])
         ep = relrms(phi.cpu().numpy(), ref["phi"])
-        say(f"[parity]   force rel RMS vs oracle tree {ef:.3e}, phi {ep:.3e}")
+        ratio = force_bound_ratio(fa, ref["f"], ref["cond"], cl.q, prec)
+        med, p99, mx = per_particle_rel(fa, ref["f"])
+        say(f"[parity]   force rel RMS vs oracle tree {ef:.3e}, phi {ep:.3e}; per particle: "
+            f"median {med:.2e} p99 {p99:.2e} max {mx:.2e}; max error / bound {ratio:.3e}")
         assert ef < tol and ep < tol
+        assert ratio <= 1.0
         ts.close()
 
 
@@ -172,6 +205,23 @@ def test_nonfinite_input_is_flagged():
     f = ts.tree_forces(dev(xx), dev(np.ones(64)))
     ts.stats()
     assert torch.isfinite(f).all()
+    ts.close()
+
+
+def test_flags_survive_later_builds_until_read():
+    # a flag raised by one build stays visible after a later clean build
+    # (as between the steps of one multi-step call) until ucp_get_stats reads it
+    say("[parity] sticky flags")
+    ts = TreeSolver(64, theta=0.5, eps=0.01)
+    good = np.random.default_rng(2).normal(size=(64, 3))
+    bad = good.copy(); bad[7, 2] = np.inf
+    ts.build(dev(bad), dev(np.ones(64)))
+    f = ts.tree_forces(dev(good), dev(np.ones(64)))
+    with pytest.raises(L.UcpError) as ei:
+        ts.stats()
+    assert ei.value.status == L.UCP_ENONFINITE
+    st = ts.stats()                      # read: the sticky word is clear
+    assert st["flags"] == 0 and torch.isfinite(f).all()
     ts.close()
 
 
@@ -324,11 +374,16 @@ def test_full_size_metric_cloud(gm, G):
     say(f"[parity]   nodes={st['nodes']} groups={st['groups']} p2p/N={st['p2p'] / n:.1f} "
         f"m2p/N={st['m2p'] / n:.1f}")
     check_topology(ts, t)
-    ref = t.eval(group_counts=True)
+    ref = t.eval(group_counts=True, cond=True)
     gs = ts.debug("gstat")
     np.testing.assert_array_equal(gs[:, 0], ref["gm2p"])
     np.testing.assert_array_equal(gs[:, 1], ref["gp2p"])
-    ef = relrms(f.cpu().numpy(), ref["f"])
-    say(f"[parity]   split force rel RMS vs oracle tree {ef:.3e}")
+    fa = f.cpu().numpy()
+    ef = relrms(fa, ref["f"])
+    ratio = force_bound_ratio(fa, ref["f"], ref["cond"], c.q, L.UCP_SPLIT)
+    med, p99, mx = per_particle_rel(fa, ref["f"])
+    say(f"[parity]   split force rel RMS vs oracle tree {ef:.3e}; per particle: median "
+        f"{med:.2e} p99 {p99:.2e} max {mx:.2e}; max error / bound {ratio:.3e}")
     assert ef < TOL_SPLIT
+    assert ratio <= 1.0
     ts.close()

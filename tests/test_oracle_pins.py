@@ -671,7 +671,7 @@ def test_tree_vjp_is_translation_invariant(theta, group_mode, curve):
     xb, cond, lob = t.vjp(u, extras=True)
     scale = np.abs(xb).sum(axis=0)
     assert np.all(np.abs(xb.sum(axis=0)) < 1e-13 * scale)
-    assert np.all(np.abs(lob) > 1e-7 * scale)     # the term is really there
+    assert np.all(np.abs(lob[:3]) > 1e-7 * scale)     # the term is really there
     # the term sizes bound every value they are summed into
     assert np.all(cond >= np.linalg.norm(xb, axis=1))
 
@@ -680,7 +680,7 @@ def test_tree_vjp_cube_term_vanishes_without_accepted_boxes():
     cl = _rand_cloud(300, 33)
     t = oracle.Tree(cl.x, cl.q, 0.0, 0.02, leaf_cap=4, G=16, keep_lists=True)
     _, _, lob = t.vjp(np.random.default_rng(34).normal(size=(cl.n, 3)), extras=True)
-    assert np.all(lob == 0.0)
+    assert np.all(lob[:3] == 0.0)
 
 
 def _same_lists(t0, t1):
