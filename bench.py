@@ -639,6 +639,10 @@ def main():
     ap.add_argument("--study", choices=["opening", "relaxation"],
                     help="run a study instead of the benchmark and print its JSON line")
     ap.add_argument("--study-dt", type=float, default=1e-6, help="time step of the study")
+    ap.add_argument("--workload", choices=["metric", "large"], default="metric",
+                    help="metric: the N=524,288 cloud (the benchmark); large: the N=4,194,304 "
+                         "cloud (eps=0.002, 10%% hot electrons) under the same step protocol, "
+                         "for profiling its build")
     args = ap.parse_args()
     global CURVE
     CURVE = 1 if args.curve == "hilbert" else 0
@@ -662,7 +666,7 @@ def main():
     if args.study == "relaxation":
         print(json.dumps(relaxation_study(dev)), flush=True)
         return
-    cl, prm = inputs.metric(0)
+    cl, prm = inputs.metric(0) if args.workload == "metric" else inputs.large(0)
     n = cl.n
     theta, eps, dt = args.theta, prm["eps"], prm["dt"]
     prec = L.UCP_SPLIT if args.precision == "split" else L.UCP_FP64
@@ -727,11 +731,13 @@ def main():
         "vs_baseline": None,
         "dtype": "f32-interactions/f64-accumulate" if prec == L.UCP_SPLIT else "f64",
         "data": "synthetic",
-        "config": {"workload": f"single two-component Gaussian cloud N=524288 (sigma=1, 5% halo "
-                               f"shell 2-3 sigma), theta={theta:g}, eps=0.005, G={args.group_size} "
+        "config": {"workload": (f"single two-component Gaussian cloud N=524288 (sigma=1, 5% halo "
+                                f"shell 2-3 sigma)" if args.workload == "metric" else
+                                f"single two-component Gaussian cloud N=4194304 (sigma=1, 10% of "
+                                f"electrons hot)") + f", theta={theta:g}, eps={eps:g}, G={args.group_size} "
                                f"({args.group_mode} groups), "
                                f"leaf_cap={args.leaf_cap}, 63-bit {args.curve} keys, one KDK "
-                               f"Verlet step dt=5e-5",
+                               f"Verlet step dt={dt:g}",
                    "n": n, "theta": theta, "precision": args.precision,
                    "group_size": args.group_size, "group_mode": args.group_mode,
                    "curve": args.curve},
