@@ -252,6 +252,20 @@ ucp_status ucp_energy(ucp_ctx *c, const double *x, const double *v, const double
  * as for ucp_compute_forces.                                                */
 ucp_status ucp_force_vjp(ucp_ctx *c, const double *u, double *xbar, void *stream);
 
+/* As ucp_force_vjp, for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels, with the adjoint scratch in a static device
+ * array of the library (25.6 MB, held on every GPU the library runs on
+ * until the process ends, its address resolved by ucp_create) instead of
+ * buffers allocated by the first call.  It allocates nothing.  The array
+ * serves contexts of at most 65,536 particles, 267,264 node slots (n_max <=
+ * 65,536 with clouds_max <= 64) and 64 clouds; larger ones get UCP_EINVAL.
+ * Every call on one GPU shares that GPU's array (each call clears what it
+ * needs first), so calls that overlap on one GPU race, across contexts too.
+ * The context's device must be current.
+ * Errors: as ucp_force_vjp, plus UCP_EINVAL for the size limits above.      */
+ucp_status ucp_force_vjp_noalloc(ucp_ctx *c, const double *u, double *xbar, void *stream);
+
 /* Synchronise `stream`, read the device counters and flags.  Returns
  * UCP_ECAPACITY / UCP_ENONFINITE / UCP_EINVAL when a flag is raised by the
  * last build or any build since the previous ucp_get_stats (the stats are

@@ -27,7 +27,8 @@ STATUS_NAMES = {0: "UCP_OK", -1: "UCP_EINVAL", -2: "UCP_ENOMEM", -3: "UCP_EHIP",
 # the symbols declared in include/ucp.h
 EXPORTS = ["ucp_default_params", "ucp_create", "ucp_destroy", "ucp_set_params", "ucp_get_params",
            "ucp_build_tree", "ucp_build_tree_batched", "ucp_compute_forces", "ucp_step",
-           "ucp_step_batched", "ucp_energy", "ucp_force_vjp", "ucp_get_stats", "ucp_debug_copy",
+           "ucp_step_batched", "ucp_energy", "ucp_force_vjp", "ucp_force_vjp_noalloc",
+           "ucp_get_stats", "ucp_debug_copy",
            "ucp_set_timing", "ucp_timing_read", "ucp_last_error", "ucp_version"]
 
 
@@ -78,6 +79,7 @@ def load():
         "ucp_step_batched": (i32, [vp, vp, vp, vp, vp, vp, vp, i32, i64, dbl, i32, vp]),
         "ucp_energy": (i32, [vp, vp, vp, vp, vp, i64, vp, vp]),
         "ucp_force_vjp": (i32, [vp, vp, vp, vp]),
+        "ucp_force_vjp_noalloc": (i32, [vp, vp, vp, vp]),
         "ucp_get_stats": (i32, [vp, C.POINTER(ucp_stats), vp]),
         "ucp_debug_copy": (i32, [vp, i32, vp, i64, vp]),
         "ucp_set_timing": (i32, [vp, i32]),
@@ -156,6 +158,10 @@ def ucp_energy(h, x, v, q, m, n, out, stream):
 
 def ucp_force_vjp(h, u, xbar, stream):
     return check(load().ucp_force_vjp(h, u, xbar, stream), h)
+
+
+def ucp_force_vjp_noalloc(h, u, xbar, stream):
+    return check(load().ucp_force_vjp_noalloc(h, u, xbar, stream), h)
 
 
 def ucp_get_stats(h, stream, raise_on_flag=True):

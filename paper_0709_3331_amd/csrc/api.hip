@@ -2,6 +2,7 @@
 #include <string.h>
 
 #include <cstdio>
+#include <mutex>
 #include <string>
 
 #include "internal.h"
@@ -11,6 +12,52 @@ struct ucp_ctx : public ucp::Ctx {};
 using ucp::Ctx;
 
 namespace {
+
+// ---------------------------------------------------------------------------
+// Adjoint scratch of ucp_force_vjp_noalloc: one static device array per GPU
+// (every GPU the library runs on holds its own copy until the process ends),
+// sized for a context of at most kNoAllocN particles, kNoAllocNodes node
+// slots and kNoAllocClouds clouds (n_max 65,536 and clouds_max 64 give
+// node_cap 4 n_max + 64 clouds_max + 1024 = 267,264).  Layout (256-byte
+// aligned parts): w double4[N], xsrc double[4 N], cbar double[10 nodes],
+// lobar double[4 clouds], lomin uint32[3 clouds]; 25.6 MB in all.
+// In host code the array's name only stands in for it: its device address
+// is resolved per device with hipGetSymbolAddress and only that is used.
+// ---------------------------------------------------------------------------
+constexpr int64_t kNoAllocN = 65536;
+constexpr int kNoAllocClouds = 64;
+constexpr int64_t kNoAllocNodes = 4 * kNoAllocN + 64 * kNoAllocClouds + 1024;
+constexpr size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+constexpr size_t kOffW = 0;
+constexpr size_t kOffXsrc = kOffW + align256(32 * (size_t)kNoAllocN);
+constexpr size_t kOffCbar = kOffXsrc + align256(32 * (size_t)kNoAllocN);
+constexpr size_t kOffLobar = kOffCbar + align256(80 * (size_t)kNoAllocNodes);
+constexpr size_t kOffLomin = kOffLobar + align256(32 * (size_t)kNoAllocClouds);
+constexpr size_t kNoAllocBytes = kOffLomin + align256(12 * (size_t)kNoAllocClouds);
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxDevices] = {};   // device address of `scratch` per device
+
+// the device address of this device's `scratch`, resolved once per device
+// with that device current (no allocation is involved)
+hipError_t scratch_address(int device, void **out)
+{
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[device]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!ptr) return hipErrorInvalidSymbol;
+        g_scratch_dev[device] = ptr;
+    }
+    *out = g_scratch_dev[device];
+    return hipSuccess;
+}
 
 const char *kNoCtx = "ucp: NULL context";
 thread_local std::string g_err;   // errors without a context
@@ -282,6 +329,9 @@ ucp_status ucp_create(ucp_ctx **out, int64_t n_max, int32_t clouds_max, const uc
     ALLOC(c->d_flags, 4);
     ALLOC(c->d_epart, 4 * 256);
 #undef ALLOC
+    // set-up of this device's static adjoint scratch (ucp_force_vjp_noalloc)
+    void *scratch_dev = nullptr;
+    if (e == hipSuccess) e = scratch_address(c->device, &scratch_dev);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipMemset(c->d_flags, 0, 4 * sizeof(int32_t));
     if (e == hipSuccess) e = hipMemset(c->d_ctr, 0, ucp::CTR_NCTR * sizeof(unsigned long long));
@@ -433,16 +483,31 @@ ucp_status ucp_energy(ucp_ctx *c, const double *x, const double *v, const double
     return UCP_OK;
 }
 
+// checks shared by both adjoint entry points; UCP_OK with *skip set when
+// there is nothing to do (an empty cloud)
+static ucp_status vjp_checks(ucp_ctx *c, const double *u, double *xbar, const char *who, bool *skip)
+{
+    *skip = false;
+    if (!c) return fail(nullptr, UCP_EINVAL, kNoCtx);
+    if (!c->built) return fail(c, UCP_ENOTBUILT, std::string(who) + ": no tree has been built");
+    if (c->n == 0) {
+        *skip = true;
+        return UCP_OK;
+    }
+    if (!u || !xbar) return fail(c, UCP_EINVAL, std::string(who) + ": NULL argument");
+    if (c->p_built.pair_law != UCP_PAIR_PLUMMER)
+        return fail(c, UCP_EINVAL, std::string(who) + ": only the Plummer pair law has an adjoint");
+    if (c->p_built.expansion != UCP_EXPANSION_QUADRUPOLE)
+        return fail(c, UCP_EINVAL,
+                    std::string(who) + ": only the quadrupole expansion has an adjoint");
+    return UCP_OK;
+}
+
 ucp_status ucp_force_vjp(ucp_ctx *c, const double *u, double *xbar, void *stream)
 {
-    if (!c) return fail(nullptr, UCP_EINVAL, kNoCtx);
-    if (!c->built) return fail(c, UCP_ENOTBUILT, "ucp_force_vjp: no tree has been built");
-    if (c->n == 0) return UCP_OK;
-    if (!u || !xbar) return fail(c, UCP_EINVAL, "ucp_force_vjp: NULL argument");
-    if (c->p_built.pair_law != UCP_PAIR_PLUMMER)
-        return fail(c, UCP_EINVAL, "ucp_force_vjp: only the Plummer pair law has an adjoint");
-    if (c->p_built.expansion != UCP_EXPANSION_QUADRUPOLE)
-        return fail(c, UCP_EINVAL, "ucp_force_vjp: only the quadrupole expansion has an adjoint");
+    bool skip = false;
+    const ucp_status st = vjp_checks(c, u, xbar, "ucp_force_vjp", &skip);
+    if (st != UCP_OK || skip) return st;
     if (!c->d_w) {
         // the adjoint buffers are allocated on first use
         hipError_t e = hipMalloc((void **)&c->d_w, (size_t)c->n_max * sizeof(double4) + 256);
@@ -463,7 +528,35 @@ ucp_status ucp_force_vjp(ucp_ctx *c, const double *u, double *xbar, void *stream
                         std::string("ucp_force_vjp: ") + hipGetErrorString(e));
         }
     }
-    ucp::launch_vjp(c, u, xbar, (hipStream_t)stream);
+    const ucp::VjpScratch sc = {c->d_w, c->d_xsrc, c->d_cbar, c->d_lobar, c->d_lomin};
+    ucp::launch_vjp(c, sc, u, xbar, (hipStream_t)stream);
+    HIP_TRY(c, hipGetLastError());
+    return UCP_OK;
+}
+
+ucp_status ucp_force_vjp_noalloc(ucp_ctx *c, const double *u, double *xbar, void *stream)
+{
+    bool skip = false;
+    const ucp_status st = vjp_checks(c, u, xbar, "ucp_force_vjp_noalloc", &skip);
+    if (st != UCP_OK || skip) return st;
+    if (c->n > kNoAllocN || c->node_cap > kNoAllocNodes || c->clouds > kNoAllocClouds)
+        return fail(c, UCP_EINVAL,
+                    "ucp_force_vjp_noalloc: the static scratch holds at most 65536 particles, "
+                    "267264 node slots (a context of n_max <= 65536 and clouds_max <= 64) and 64 "
+                    "clouds; this context has n " + std::to_string(c->n) + ", node_cap " +
+                        std::to_string(c->node_cap) + ", clouds " + std::to_string(c->clouds) +
+                        " (use ucp_force_vjp)");
+    int dev = -1;
+    HIP_TRY(c, hipGetDevice(&dev));
+    if (dev != c->device)
+        return fail(c, UCP_EINVAL, "ucp_force_vjp_noalloc: the context's device is not current");
+    void *base = nullptr;
+    HIP_TRY(c, scratch_address(c->device, &base));
+    unsigned char *b = (unsigned char *)base;
+    const ucp::VjpScratch sc = {(double4 *)(b + kOffW), (double *)(b + kOffXsrc),
+                                (double *)(b + kOffCbar), (double *)(b + kOffLobar),
+                                (uint32_t *)(b + kOffLomin)};
+    ucp::launch_vjp(c, sc, u, xbar, (hipStream_t)stream);
     HIP_TRY(c, hipGetLastError());
     return UCP_OK;
 }

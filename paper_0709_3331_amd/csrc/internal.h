@@ -44,7 +44,17 @@ void launch_build(Ctx *c, const double *x, const double *q, const int64_t *offse
                   int clouds, int64_t n, hipStream_t s);
 // walk.hip
 void launch_forces(Ctx *c, double *f, double *phi, hipStream_t s);
-void launch_vjp(Ctx *c, const double *u, double *xbar, hipStream_t s);
+// device scratch of the adjoint: sorted cotangents (n), source-side pair
+// cotangents (4 n doubles), cell cotangents (10 doubles per node slot), and
+// per cloud the cube-origin cotangent (4 doubles) and minimum particles (3)
+struct VjpScratch {
+    double4 *w;
+    double *xsrc;
+    double *cbar;
+    double *lobar;
+    uint32_t *lomin;
+};
+void launch_vjp(Ctx *c, const VjpScratch &sc, const double *u, double *xbar, hipStream_t s);
 // integrate.hip
 void launch_kick_drift(double *x, double *v, const double *f, const double *m, int64_t n,
                        double dt, hipStream_t s);

@@ -1247,35 +1247,35 @@ void launch_forces(Ctx *c, double *f, double *phi, hipStream_t s)
     if (c->timing) (void)hipEventRecord(e1, s);
 }
 
-void launch_vjp(Ctx *c, const double *u, double *xbar, hipStream_t s)
+void launch_vjp(Ctx *c, const VjpScratch &sc, const double *u, double *xbar, hipStream_t s)
 {
     const int64_t n = c->n;
     WalkArgs wa = walk_args(c);
-    wa.w = c->d_w;
-    wa.cbar = c->d_cbar;
-    wa.xsrc = c->d_xsrc;
-    wa.lobar = c->d_lobar;
-    hipLaunchKernelGGL(k_vjp_reset, dim3(1), dim3(256), 0, s, c->d_ctr, c->d_lobar, c->d_lomin,
+    wa.w = sc.w;
+    wa.cbar = sc.cbar;
+    wa.xsrc = sc.xsrc;
+    wa.lobar = sc.lobar;
+    hipLaunchKernelGGL(k_vjp_reset, dim3(1), dim3(256), 0, s, c->d_ctr, sc.lobar, sc.lomin,
                        c->clouds);
     hipLaunchKernelGGL(k_vjp_max, dim3(256), dim3(256), 0, s, u, (const double4 *)c->d_xq,
                        (const uint32_t *)c->d_perm, n, c->d_ctr, (const int32_t *)c->d_flags);
     hipLaunchKernelGGL(k_vjp_prep, dim3(1024), dim3(256), 0, s, u, (const double4 *)c->d_xq,
                        (const uint32_t *)c->d_perm, n, (const int32_t *)(c->d_noff + n),
                        (const unsigned long long *)c->d_ctr, (const int64_t *)c->d_off, c->clouds,
-                       (const double4 *)c->d_cube, c->d_w, c->d_xsrc, c->d_cbar, c->d_lomin,
+                       (const double4 *)c->d_cube, sc.w, sc.xsrc, sc.cbar, sc.lomin,
                        (const int32_t *)c->d_flags);
     hipLaunchKernelGGL(k_walk_reset, dim3(1), dim3(64), 0, s, c->d_ctr, c->d_wq);
     c->walk_armed = false;
     if (c->p_built.precision == UCP_SPLIT) launch_walk_t<UCP_SPLIT, kWalkVjp>(c, wa, s);
     else launch_walk_t<UCP_FP64, kWalkVjp>(c, wa, s);
     hipLaunchKernelGGL(k_vjp_down, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
-                       (const double4 *)c->d_acc, (const double *)c->d_xsrc,
-                       (const double *)c->d_cbar, (const double4 *)c->d_xq,
+                       (const double4 *)c->d_acc, (const double *)sc.xsrc,
+                       (const double *)sc.cbar, (const double4 *)c->d_xq,
                        (const double4 *)c->d_ngeo, (const int32_t *)c->d_npar,
                        (const int32_t *)c->d_leafof, (const int32_t *)(c->d_noff + n),
                        (const uint32_t *)c->d_perm, n, (const unsigned long long *)c->d_ctr,
-                       (const int64_t *)c->d_off, c->clouds, (const uint32_t *)c->d_lomin,
-                       (const double *)c->d_lobar, xbar, c->d_flags);
+                       (const int64_t *)c->d_off, c->clouds, (const uint32_t *)sc.lomin,
+                       (const double *)sc.lobar, xbar, c->d_flags);
 }
 
 }  // namespace ucp

@@ -86,9 +86,13 @@ class TreeSolver:
         L.ucp_energy(self.h, _ptr(x), _ptr(v), _ptr(q), _ptr(m), x.shape[0], _ptr(out), _stream())
         return out
 
-    def vjp(self, u):
+    def vjp(self, u, noalloc=False):
+        """(dF/dx)^T u of the last build; noalloc=True uses the library's
+        static adjoint scratch (ucp_force_vjp_noalloc) instead of buffers
+        allocated by the first call."""
         xb = torch.empty_like(u)
-        L.ucp_force_vjp(self.h, _ptr(u), _ptr(xb), _stream())
+        fn = L.ucp_force_vjp_noalloc if noalloc else L.ucp_force_vjp
+        fn(self.h, _ptr(u), _ptr(xb), _stream())
         return xb
 
     def stats(self, raise_on_flag=True):
