@@ -876,14 +876,39 @@ __global__ __launch_bounds__(256) void k_walk(WalkArgs a)
             }
             const bool band = have && !sure_acc && !sure_open;
             bool acc = sure_acc;
-            // nodes in the band one at a time: the node is broadcast from its
-            // lane and every lane tests its own member
+            // nodes in the band one at a time, every lane testing its own
+            // member against the node
             unsigned long long bandm = __ballot(band);
-            while (bandm != 0ull) {
+            if constexpr (!SPEC) {
+                // the popped nodes' centres and side^2 go through LDS (the
+                // staging area is free during traversal), so a band node is
+                // read by every lane with one broadcast load; the nodes that
+                // every member accepts collect in a scalar mask
+                double4 *bnode = (double4 *)stage;
+                bnode[lane] = geo;
+                wave_sync();
+                unsigned long long okm = 0ull;
+                while (bandm != 0ull) {
+                    const int bl = __builtin_ctzll(bandm);
+                    bandm &= bandm - 1ull;
+                    const double4 nd = bnode[bl];
+                    const double dx = xi.x - nd.x;
+                    const double dy = xi.y - nd.y;
+                    const double dz = xi.z - nd.z;
+                    const double d2 = fma(dz, dz, fma(dy, dy, dx * dx));
+                    // lanes without a target hold the group's first member
+                    // (xi of i = gfirst), so they only repeat its test
+                    const bool fail = !(nd.w < th2 * d2);
+                    okm |= __builtin_amdgcn_ballot_w64(fail) == 0ull ? (1ull << bl) : 0ull;
+                }
+                acc = sure_acc || ((okm >> lane) & 1ull) != 0ull;
+            }
+            // the per-sign test of the species pseudo-particles broadcasts
+            // each band node's centres of charge from its lane
+            while (SPEC && bandm != 0ull) {
                 const int bl = __builtin_ctzll(bandm);
                 bandm &= bandm - 1ull;
-                bool fail;
-                if constexpr (SPEC) {
+                {
                     const double qp = readlane_d(sp_p.w, bl), qm = readlane_d(sp_m.w, bl);
                     const double px = xi.x - readlane_d(sp_p.x, bl);
                     const double py = xi.y - readlane_d(sp_p.y, bl);
@@ -894,17 +919,10 @@ __global__ __launch_bounds__(256) void k_walk(WalkArgs a)
                     const double rp = readlane_d(R2p, bl), rm = readlane_d(R2m, bl);
                     const double dp = fma(pz, pz, fma(py, py, px * px));
                     const double dm = fma(mz, mz, fma(my, my, mx * mx));
-                    fail = act && ((qp != 0.0 && !(rp < dp)) || (qm != 0.0 && !(rm < dm)));
-                } else {
-                    const double dx = xi.x - readlane_d(geo.x, bl);
-                    const double dy = xi.y - readlane_d(geo.y, bl);
-                    const double dz = xi.z - readlane_d(geo.z, bl);
-                    const double s2 = readlane_d(geo.w, bl);
-                    const double d2 = fma(dz, dz, fma(dy, dy, dx * dx));
-                    fail = act && !(s2 < th2 * d2);
+                    const bool fail = act && ((qp != 0.0 && !(rp < dp)) || (qm != 0.0 && !(rm < dm)));
+                    const bool ok = __ballot(fail) == 0ull;
+                    acc = lane == bl ? ok : acc;
                 }
-                const bool ok = __ballot(fail) == 0ull;
-                acc = lane == bl ? ok : acc;
             }
             const bool isleaf = (inf.w & 256) != 0;
             const bool leaf_ok = inf.y >= 0 && inf.z >= 0 && (int64_t)inf.y + inf.z <= a.n;
