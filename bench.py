@@ -78,7 +78,7 @@ def bench_ensemble(args, prec, dev):
     offs = torch.from_numpy(off).to(dev)
     print(f"bench: ensemble of {clouds} clouds, N={n}: tuning", file=sys.stderr, flush=True)
     tuned = autotune.tune(x, q, offs, theta=eprm["theta"], eps=eprm["eps"], precision=prec,
-                          candidates={"group_size": (32, 64), "list_len": (128,),
+                          candidates={"group_size": (32, 64), "list_len": (64, 128, 256),
                                       "group_mode": (1, 0), "leaf_cap": (8, 16, 24, 32)},
                           reps=2, use_cache=False)
     ts = TreeSolver(n, clouds, curve=CURVE, theta=eprm["theta"], eps=eprm["eps"], precision=prec,
@@ -116,11 +116,17 @@ def bench_ensemble(args, prec, dev):
             "tuned": {"group_size": tuned["group_size"], "list_len": tuned["list_len"],
                       "leaf_cap": tuned["leaf_cap"],
                       "group_mode": "chunk" if tuned["group_mode"] == 1 else "node",
+                      "rel_force_err_vs_direct": tuned["rel_force_err_vs_direct"],
+                      "per_particle_walk_err_vs_direct": tuned["per_particle_walk_err_vs_direct"],
+                      "err_bound": tuned["err_bound"],
                       "rel_force_diff_vs_per_particle_fp64":
                           tuned.get("rel_force_diff_vs_per_particle_fp64"),
-                      "candidates_walk_ms": {f"{r['group_mode']}/{r['group_size']}/{r['list_len']}/"
-                                             f"{r['leaf_cap']}":
-                                             round(r["walk_ms"], 4) for r in tuned["candidates"]}}}
+                      "candidates": {f"{'chunk' if r['group_mode'] == 1 else 'node'}/G{r['group_size']}/"
+                                     f"L{r['list_len']}/cap{r['leaf_cap']}":
+                                     {"walk_ms": round(r["walk_ms"], 4),
+                                      "err_vs_direct": float("%.4g" % r["rel_force_err_vs_direct"]),
+                                      "admitted": r["admitted"]}
+                                     for r in tuned["candidates"]}}}
 
 
 def _finite(v):

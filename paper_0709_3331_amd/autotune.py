@@ -4,11 +4,14 @@ capacity.
 G, the group rule and the leaf capacity decide which targets share one
 traversal and where the near field starts, so they change the accepted sets
 (and the force error at truncation level), not only the speed; L changes only
-the FP64 summation order.  The tuner therefore times the
-walk for every candidate on the caller's own workload, keeps the fastest, and
-reports that setting's force difference from the FP64 per-particle walk over
-a tree of single-particle leaves (G = 1, leaf capacity 1: the tree and walk of
-Sec. 3) on the same input, so the choice can be judged on accuracy as well.
+the FP64 summation order.  The tuner therefore times the walk for every
+candidate on the caller's own workload and measures every candidate's force
+error against the direct sum of Eq. (1)-(2) on the same input (the
+library's FP64 evaluation at theta = 0, where no box is accepted).  A
+candidate is admitted only if its error does not exceed the error of the
+per-particle walk over a tree of single-particle leaves (G = 1, leaf capacity
+1: the tree and walk of Sec. 3) at the same theta, times `err_factor`; the
+fastest admitted candidate is chosen.
 
 Timing uses the library's own HIP events around each walk launch
 (ucp_set_timing / ucp_timing_read).  Results are cached in a JSON file keyed by
@@ -50,12 +53,17 @@ def _load(path):
         return {}
 
 
+def _rel(a, b):
+    return float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+
+
 def _time_walk(x, q, offsets, reps, **params):
+    """Walk time per launch, interactions per particle and the forces."""
     n = x.shape[0]
     clouds = 1 if offsets is None else offsets.numel() - 1
     ts = TreeSolver(n, clouds, **params)
     try:
-        ts.tree_forces(x, q, offsets)          # warm-up (and graph-free first build)
+        f = ts.tree_forces(x, q, offsets)      # warm-up (and graph-free first build)
         ts.stats()
         ts.timing(True)
         torch.cuda.synchronize()
@@ -67,17 +75,32 @@ def _time_walk(x, q, offsets, reps, **params):
         ts.timing(False)
     finally:
         ts.close()
-    return ms / max(cnt, 1), (st["p2p"] + st["m2p"]) / max(n, 1)
+    return ms / max(cnt, 1), (st["p2p"] + st["m2p"]) / max(n, 1), f
+
+
+def _forces(x, q, offsets, **params):
+    n = x.shape[0]
+    clouds = 1 if offsets is None else offsets.numel() - 1
+    ts = TreeSolver(n, clouds, **params)
+    try:
+        f = ts.tree_forces(x, q, offsets)
+        ts.stats()
+    finally:
+        ts.close()
+    return f
 
 
 def tune(x, q, offsets=None, *, theta, eps, precision=L.UCP_SPLIT, candidates=None, reps=3,
-         cache_path=None, use_cache=True, reference=True):
+         cache_path=None, use_cache=True, err_factor=1.0):
     """Pick (group_size, list_len, group_mode, leaf_cap) for this workload.
 
     x, q: float64 GPU tensors ((N, 3), (N,)); offsets: int64 GPU tensor of
-    cloud offsets or None.  Returns a dict with the chosen parameters, the
-    timing of every candidate, and (reference=True) the relative RMS force
-    difference of the chosen setting from the FP64 per-particle walk."""
+    cloud offsets or None.  Every candidate is timed and its relative RMS
+    force error against the FP64 direct sum is measured; candidates whose
+    error exceeds err_factor times that of the FP64 per-particle walk (G = 1,
+    leaf capacity 1) are rejected, and the fastest of the others is chosen.
+    Returns the chosen parameters, its walk time and error, the reference
+    errors and bound, and every candidate's row."""
     n = x.shape[0]
     clouds = 1 if offsets is None else offsets.numel() - 1
     path = cache_path or default_cache_path()
@@ -87,38 +110,40 @@ def tune(x, q, offsets=None, *, theta, eps, precision=L.UCP_SPLIT, candidates=No
         return dict(cache[key], cached=True)
     cand = dict(DEFAULT_CANDIDATES)
     cand.update(candidates or {})
+    # references: the direct sum (theta = 0 accepts no box) and the paper's
+    # per-particle walk at this theta, both FP64
+    fd = _forces(x, q, offsets, theta=0.0, eps=eps, precision=L.UCP_FP64)
+    fpp = _forces(x, q, offsets, theta=theta, eps=eps, precision=L.UCP_FP64, group_size=1,
+                  group_mode=L.UCP_GROUP_CHUNK, leaf_cap=1)
+    err_pp = _rel(fpp, fd)
+    bound = err_factor * err_pp
     rows = []
     for lc in cand["leaf_cap"]:
         for gm in cand["group_mode"]:
             for G in cand["group_size"]:
                 for Lq in cand["list_len"]:
-                    ms, ipp = _time_walk(x, q, offsets, reps, theta=theta, eps=eps,
-                                         precision=precision, group_size=G, list_len=Lq,
-                                         group_mode=gm, leaf_cap=lc)
+                    ms, ipp, f = _time_walk(x, q, offsets, reps, theta=theta, eps=eps,
+                                            precision=precision, group_size=G, list_len=Lq,
+                                            group_mode=gm, leaf_cap=lc)
+                    err = _rel(f, fd)
                     rows.append({"group_size": G, "list_len": Lq, "group_mode": gm,
                                  "leaf_cap": lc, "walk_ms": ms,
-                                 "interactions_per_particle": ipp})
-    best = min(rows, key=lambda r: r["walk_ms"])
+                                 "interactions_per_particle": ipp,
+                                 "rel_force_err_vs_direct": err,
+                                 "rel_force_diff_vs_per_particle_fp64": _rel(f, fpp),
+                                 "admitted": err <= bound})
+                    del f
+    ok = [r for r in rows if r["admitted"]]
+    if not ok:
+        raise RuntimeError(f"autotune: no candidate within {bound:.3e} of the direct sum")
+    best = min(ok, key=lambda r: r["walk_ms"])
     out = {"group_size": best["group_size"], "list_len": best["list_len"],
            "group_mode": best["group_mode"], "leaf_cap": best["leaf_cap"],
-           "walk_ms": best["walk_ms"], "candidates": rows}
-    if reference:
-        clouds_max = max(clouds, 1)
-        tb = TreeSolver(n, clouds_max, theta=theta, eps=eps, precision=precision,
-                        group_size=best["group_size"], list_len=best["list_len"],
-                        group_mode=best["group_mode"], leaf_cap=best["leaf_cap"])
-        tr = TreeSolver(n, clouds_max, theta=theta, eps=eps, precision=L.UCP_FP64, group_size=1,
-                        group_mode=L.UCP_GROUP_CHUNK, leaf_cap=1)
-        try:
-            fb = tb.tree_forces(x, q, offsets)
-            fr = tr.tree_forces(x, q, offsets)
-            tb.stats()
-            tr.stats()
-            out["rel_force_diff_vs_per_particle_fp64"] = float(
-                torch.linalg.norm(fb - fr) / torch.linalg.norm(fr))
-        finally:
-            tb.close()
-            tr.close()
+           "walk_ms": best["walk_ms"],
+           "rel_force_err_vs_direct": best["rel_force_err_vs_direct"],
+           "rel_force_diff_vs_per_particle_fp64": best["rel_force_diff_vs_per_particle_fp64"],
+           "per_particle_walk_err_vs_direct": err_pp, "err_bound": bound,
+           "candidates": rows}
     if use_cache:
         cache = _load(path)
         cache[key] = out

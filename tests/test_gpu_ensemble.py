@@ -103,22 +103,38 @@ def test_batched_graph_step_matches_oracle_and_eager_steps():
     ts.close()
 
 
-def test_autotune_picks_fastest_candidate_and_caches(tmp_path):
+def test_autotune_picks_fastest_admitted_candidate_and_caches(tmp_path):
     sizes = [6000, 10000]
     parts = [inputs.gaussian_cloud(s, 1.0, 1e-3, 1e-5, 40 + k) for k, s in enumerate(sizes)]
-    x = torch.from_numpy(np.concatenate([p.x for p in parts])).cuda()
-    q = torch.from_numpy(np.concatenate([p.q for p in parts])).cuda()
+    xn = np.concatenate([p.x for p in parts])
+    qn = np.concatenate([p.q for p in parts])
+    x = torch.from_numpy(xn).cuda()
+    q = torch.from_numpy(qn).cuda()
     offs = torch.tensor([0, sizes[0], sum(sizes)], dtype=torch.int64, device="cuda")
     cache = str(tmp_path / "tune.json")
     cand = {"group_size": (32, 64), "list_len": (64, 128), "group_mode": (L.UCP_GROUP_CHUNK,),
             "leaf_cap": (24,)}
     r = autotune.tune(x, q, offs, theta=0.5, eps=0.01, candidates=cand, reps=2, cache_path=cache)
-    say(f"[autotune] chose G={r['group_size']} L={r['list_len']} "
-        f"diff vs per-particle FP64 {r['rel_force_diff_vs_per_particle_fp64']:.3e}")
+    say(f"[autotune] chose G={r['group_size']} L={r['list_len']} error vs direct "
+        f"{r['rel_force_err_vs_direct']:.3e} (bound {r['err_bound']:.3e}, per-particle walk "
+        f"{r['per_particle_walk_err_vs_direct']:.3e})")
     assert not r["cached"]
     assert len(r["candidates"]) == 4
-    assert r["walk_ms"] == min(c["walk_ms"] for c in r["candidates"])
+    ok = [c for c in r["candidates"] if c["admitted"]]
+    assert ok and r["walk_ms"] == min(c["walk_ms"] for c in ok)
+    assert all(c["admitted"] == (c["rel_force_err_vs_direct"] <= r["err_bound"])
+               for c in r["candidates"])
     assert (r["group_size"], r["list_len"]) in [(G, Lq) for G in (32, 64) for Lq in (64, 128)]
-    assert 0.0 < r["rel_force_diff_vs_per_particle_fp64"] < 1e-2
+    # the tuner's direct-sum reference is the direct sum: check the errors it
+    # reports against the oracle's direct sum of each cloud
+    ref = np.concatenate([oracle.direct(p.x, p.q, 0.01)[0] for p in parts])
+    ts = TreeSolver(sum(sizes), 2, theta=0.5, eps=0.01, group_size=r["group_size"],
+                    list_len=r["list_len"], group_mode=r["group_mode"], leaf_cap=r["leaf_cap"])
+    f = ts.tree_forces(x, q, offs).cpu().numpy()
+    ts.stats()
+    ts.close()
+    e = relrms(f, ref)
+    assert abs(e - r["rel_force_err_vs_direct"]) <= 1e-6 * e + 1e-9
+    assert 0.0 < r["per_particle_walk_err_vs_direct"] < 1e-2
     r2 = autotune.tune(x, q, offs, theta=0.5, eps=0.01, candidates=cand, cache_path=cache)
     assert r2["cached"] and r2["group_size"] == r["group_size"] and r2["list_len"] == r["list_len"]
