@@ -727,7 +727,7 @@ __device__ __forceinline__ void flush_lists(const WalkArgs &a, const int4 *ml, i
 }
 
 template <int PREC, int MODE, bool KELBG, bool SPEC>
-__global__ __launch_bounds__(256) void k_walk(WalkArgs a)
+__device__ __forceinline__ void walk_body(const WalkArgs &a)
 {
     using T = typename std::conditional<PREC == UCP_SPLIT, float, double>::type;
     HIP_DYNAMIC_SHARED(char, lds_raw)
@@ -1016,6 +1016,22 @@ __global__ __launch_bounds__(256) void k_walk(WalkArgs a)
     }
 }
 
+template <int PREC, int MODE, bool KELBG, bool SPEC>
+__global__ __launch_bounds__(256) void k_walk(WalkArgs a)
+{
+    walk_body<PREC, MODE, KELBG, SPEC>(a);
+}
+
+// The split-precision force walks under the Plummer law with the quadrupole
+// expansion fit in 128 VGPRs without spilling, so they can keep four waves
+// per SIMD, as many as their LDS allows (the other variants would spill).
+template <int MODE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_walk_w4(
+    WalkArgs a)
+{
+    walk_body<UCP_SPLIT, MODE, false, false>(a);
+}
+
 __global__ void k_walk_reset(unsigned long long *ctr, unsigned long long *wq)
 {
     if (threadIdx.x == 0) {
@@ -1168,7 +1184,10 @@ static void launch_walk_t(Ctx *c, const WalkArgs &wa, hipStream_t s)
     const int waves_per_cu = c->p_built.walk_waves > 0 ? c->p_built.walk_waves : 32;
     const int blocks = (c->num_cu * waves_per_cu + 3) / 4;
     const size_t lds = (size_t)4 * walk_wave_bytes<PREC>(wa.L);
-    hipLaunchKernelGGL((k_walk<PREC, MODE, KELBG, SPEC>), dim3(blocks), dim3(256), lds, s, wa);
+    if constexpr (PREC == UCP_SPLIT && MODE != kWalkVjp && !KELBG && !SPEC)
+        hipLaunchKernelGGL((k_walk_w4<MODE>), dim3(blocks), dim3(256), lds, s, wa);
+    else
+        hipLaunchKernelGGL((k_walk<PREC, MODE, KELBG, SPEC>), dim3(blocks), dim3(256), lds, s, wa);
 }
 
 // the force walks: precision x (forces | forces and potentials) x pair law x
