@@ -131,13 +131,13 @@ void drop_graph(Ctx *c);
 
 void free_all(Ctx *c)
 {
-    void *ptrs[] = {c->d_off,  c->d_mm,     c->d_cube,  c->d_key[0], c->d_key[1], c->d_val[0],
-                    c->d_val[1], c->d_hist, c->d_histscan, c->d_xq, c->d_L,
+    void *ptrs[] = {c->d_off,  c->d_mm,     c->d_cube,  c->d_key[0], c->d_key[1], c->d_key[2],
+                    c->d_val[0], c->d_val[1], c->d_val[2], c->d_hist, c->d_histscan, c->d_xin, c->d_xq, c->d_L,
                     c->d_leaf, c->d_cnt,    c->d_lend, c->d_lvlmax, c->d_noff,  c->d_goff,   c->d_gnode,  c->d_gcl, c->d_scanblk,
                     c->d_ngeo, c->d_ninfo,  c->d_npar,  c->d_mom64,  c->d_nrec,
                     c->d_groups, c->d_gstat, c->d_acc,  c->d_ctr,    c->d_flags,  c->d_epart,
                     c->d_leafof, c->d_w,    c->d_xsrc,  c->d_cbar,  c->d_lobar, c->d_lomin, c->d_wq,
-                    c->d_ghist,  c->d_sortctl, c->d_nlev, c->d_spec};
+                    c->d_ghist,  c->d_sortctl, c->d_nlev, c->d_uplist, c->d_spec};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     drop_graph(c);
@@ -297,12 +297,15 @@ ucp_status ucp_create(ucp_ctx **out, int64_t n_max, int32_t clouds_max, const uc
     ALLOC(c->d_cube, 2 * (size_t)clouds_max);
     ALLOC(c->d_key[0], N);
     ALLOC(c->d_key[1], N);
+    ALLOC(c->d_key[2], N);
     ALLOC(c->d_val[0], N);
     ALLOC(c->d_val[1], N);
+    ALLOC(c->d_val[2], N);
     ALLOC(c->d_hist, c->hist_cap);
     ALLOC(c->d_histscan, c->hist_cap);
     ALLOC(c->d_ghist, ucp::kSortPassesMax * 256);
     ALLOC(c->d_sortctl, ucp::kSortTickets);
+    ALLOC(c->d_xin, N);
     ALLOC(c->d_xq, N);
     ALLOC(c->d_L, N + 1);
     ALLOC(c->d_leaf, N + 1);
@@ -317,6 +320,7 @@ ucp_status ucp_create(ucp_ctx **out, int64_t n_max, int32_t clouds_max, const uc
     ALLOC(c->d_ninfo, NC);
     ALLOC(c->d_npar, NC);
     ALLOC(c->d_nlev, NC + 128);
+    ALLOC(c->d_uplist, NC);
     if (p->expansion == UCP_EXPANSION_SPECIES) ALLOC(c->d_spec, ucp::kSpecVals * NC);
     ALLOC(c->d_mom64, 16 * NC);
     ALLOC(c->d_nrec, 8 * NC);

@@ -273,11 +273,12 @@ __device__ __forceinline__ uint64_t hilbert_key(uint32_t x, uint32_t y, uint32_t
 // Each thread derives its cloud's cube from the reduced extents (the same
 // arithmetic for every thread of the cloud); the first threads also store
 // every cloud's cube for the later kernels.
-__global__ __launch_bounds__(256) void k_keys(const double *__restrict__ x, int64_t n,
+__global__ __launch_bounds__(256) void k_keys(const double *__restrict__ x,
+                                             const double *__restrict__ q, int64_t n,
                                              const int64_t *__restrict__ off, int clouds,
                                              const unsigned long long *__restrict__ mm,
                                              double4 *cube, int b, int curve, uint64_t *key,
-                                             uint32_t *val, int32_t *flags)
+                                             uint32_t *val, double4 *xin, int32_t *flags)
 {
     if (*flags) return;
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -292,12 +293,16 @@ __global__ __launch_bounds__(256) void k_keys(const double *__restrict__ x, int6
     double4 c0, c1;
     cloud_cube(mm, off, c, b, &c0, &c1);
     uint64_t top = (1ull << b) - 1;
-    uint64_t X = quantise(x[3 * i + 0], c0.x, c1.x, top);
-    uint64_t Y = quantise(x[3 * i + 1], c0.y, c1.x, top);
-    uint64_t Z = quantise(x[3 * i + 2], c0.z, c1.x, top);
+    const double x0 = x[3 * i + 0], x1 = x[3 * i + 1], x2 = x[3 * i + 2];
+    uint64_t X = quantise(x0, c0.x, c1.x, top);
+    uint64_t Y = quantise(x1, c0.y, c1.x, top);
+    uint64_t Z = quantise(x2, c0.z, c1.x, top);
     key[i] = curve == UCP_CURVE_HILBERT ? hilbert_key((uint32_t)X, (uint32_t)Y, (uint32_t)Z, b)
                                         : (spread3(X) << 2) | (spread3(Y) << 1) | spread3(Z);
     val[i] = (uint32_t)i;
+    // position and charge packed in one 32-byte record, so that gathering
+    // them into the sorted order reads one record per particle
+    xin[i] = make_double4(x0, x1, x2, q[i]);
 }
 
 // ---------------------------------------------------------------------------
@@ -428,15 +433,25 @@ static void scan_excl(const int32_t *in, int32_t *out, int64_t n, int32_t *blk, 
 }
 
 // ---------------------------------------------------------------------------
-// 3. stable LSD radix sort of (key, index), 8-bit digits.  The digit counts
-//    of every pass are found first, in one kernel (they do not depend on the
-//    order).  Then each pass is one kernel: a tile of kSortTile elements is
-//    ranked (inside a round of kSortThreads each wave ranks equal digits with
-//    ballots, and the waves and rounds are ordered through LDS), its digit
-//    counts are published, its digit prefixes over the earlier tiles are found
-//    by a decoupled look-back, and the tile is scattered.  The last pass(es)
-//    of a multi-cloud build sort by cloud, restoring the clouds' contiguity
-//    while keeping key order inside each cloud.
+// 3. stable sort of (key, index): ordered by key, equal keys by index.
+//    Stable LSD radix passes with 8-bit digits run over the top three (four
+//    above 2^20 particles) digits of the key only, and then over the cloud
+//    digits of a multi-cloud build, which restores the clouds' contiguity
+//    while keeping the order inside each cloud.  After them, the elements of
+//    a run of equal top digits lie together in index order, and one kernel
+//    finishes the order inside every run by ranking (k_sort_finish, which
+//    also gathers x and q).  The top three digits name boxes of level 7-8, so
+//    runs are short for the clouds this library is for; a run longer than
+//    kFinishMax raises a word that
+//    turns on the full sort queued behind (all digits, least significant
+//    first, from the keys in input order), whose passes otherwise return at
+//    once.
+//    The digit counts of every pass are found first, in one kernel (they do
+//    not depend on the order).  Each pass is one kernel: a tile of kSortTile
+//    elements is ranked (inside a round of kSortThreads each wave ranks equal
+//    digits with ballots, and the waves and rounds are ordered through LDS),
+//    its digit counts are published, its digit prefixes over the earlier
+//    tiles are found by a decoupled look-back, and the tile is scattered.
 // ---------------------------------------------------------------------------
 template <bool CLOUD>
 __device__ __forceinline__ uint32_t sort_digit(uint64_t k, uint32_t v, int shift,
@@ -492,14 +507,15 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_pass(
     const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint64_t *kout,
     uint32_t *vout, int64_t n, int shift, const int64_t *__restrict__ off, int clouds,
     const uint32_t *__restrict__ ghist, uint32_t *status, uint32_t *status_next,
-    uint32_t *ticket, const double *__restrict__ gx, const double *__restrict__ gq, double4 *xq,
-    int32_t *flags)
+    uint32_t *ticket, const double4 *__restrict__ xin, double4 *xq,
+    const unsigned long long *__restrict__ gate, int32_t *flags)
 {
     constexpr int NW = kSortThreads / 64;
     __shared__ uint32_t wh[kSortItems][NW][256];   // per-(round, wave) digit counts, then offsets
     __shared__ uint32_t boff[256], rsh[256], bsh[256];
     __shared__ int btot, tile_sh;
     if (*flags) return;
+    if (gate && *gate == 0ull) return;   // a pass of the full sort, not needed
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     if (tid == 0) tile_sh = (int)atomicAdd(ticket, 1u);
     for (int j = tid; j < kSortItems * NW * 256; j += kSortThreads) (&wh[0][0][0])[j] = 0;
@@ -530,8 +546,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_pass(
             const int64_t i = v[it];
             const bool in = valid[it] && i < n;   // always, unless the records are inconsistent
             if (valid[it] && !in) atomicOr(flags, UCP_FLAG_INTERNAL);
-            g[it] = in ? make_double4(gx[3 * i], gx[3 * i + 1], gx[3 * i + 2], gq[i])
-                       : make_double4(0.0, 0.0, 0.0, 0.0);
+            g[it] = in ? xin[i] : make_double4(0.0, 0.0, 0.0, 0.0);
         }
     }
     // rank equal digits inside each wave and round
@@ -631,6 +646,71 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_pass(
             vout[dst] = v[it];
             if (xq) xq[dst] = g[it];
         }
+}
+
+// The runs of equal top digits (bits from `shift` up, inside one cloud) after
+// the passes over those digits: an element's place in its run is the number
+// of elements of the run with a smaller key, or with an equal key and an
+// earlier position (an earlier index: the passes were stable).  The run is
+// scanned outwards from the element, four keys per round of loads, counting
+// as it goes; a run longer than kFinishMax is not ranked but raises `full`,
+// the word that gates the full sort.  The kernel writes the sorted keys and
+// indices and gathers x and q.
+constexpr int kFinishMax = 2048;
+constexpr int kFinishThreads = 256, kFinishHalo = 64;   // keys staged in LDS on either side
+__global__ __launch_bounds__(kFinishThreads) void k_sort_finish(
+    const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint64_t *kout,
+    uint32_t *vout, int64_t n, int shift, const int64_t *__restrict__ off, int clouds,
+    const double4 *__restrict__ xin, double4 *xq, unsigned long long *full, int32_t *flags)
+{
+    __shared__ uint64_t sk[kFinishThreads + 2 * kFinishHalo];
+    if (*flags) return;
+    const int64_t base = blockIdx.x * (int64_t)kFinishThreads;
+    const int64_t wlo = base - kFinishHalo, whi = base + kFinishThreads + kFinishHalo;
+    for (int t = threadIdx.x; t < kFinishThreads + 2 * kFinishHalo; t += kFinishThreads) {
+        const int64_t q = wlo + t;
+        sk[t] = q >= 0 && q < n ? kin[q] : 0ull;
+    }
+    __syncthreads();
+    const int64_t p = base + threadIdx.x;
+    if (p >= n) return;
+    // key at position q (q inside the cloud): from LDS inside the window
+    auto key = [&](int64_t q) -> uint64_t { return q >= wlo && q < whi ? sk[q - wlo] : kin[q]; };
+    const int c = cloud_of(off, clouds, p);
+    const int64_t c0 = off[c], c1 = off[c + 1];
+    const uint64_t k = sk[p - wlo];
+    const uint64_t top = k >> shift;
+    // the top digits do not decrease inside a cloud, so equal tops at p and
+    // p -+ kFinishMax mean a run longer than kFinishMax
+    if ((p - kFinishMax >= c0 && (kin[p - kFinishMax] >> shift) == top) ||
+        (p + kFinishMax < c1 && (kin[p + kFinishMax] >> shift) == top)) {
+        *full = 1ull;
+        return;
+    }
+    // earlier members (m of them): ranked before p when their key is not
+    // larger; later members: when their key is smaller
+    int64_t r = 0, m = 0;
+    for (int64_t q = p - 1; q >= c0; --q) {
+        const uint64_t kq = key(q);
+        if ((kq >> shift) != top) break;
+        r += kq <= k ? 1 : 0;
+        ++m;
+    }
+    for (int64_t q = p + 1; q < c1; ++q) {
+        const uint64_t kq = key(q);
+        if ((kq >> shift) != top) break;
+        r += kq < k ? 1 : 0;
+    }
+    const int64_t d = p - m + r;   // the run starts m positions before p
+    const uint32_t v = vin[p];
+    kout[d] = k;
+    vout[d] = v;
+    const int64_t i = v;
+    if (i >= n) {   // only inconsistent records lead here
+        atomicOr(flags, UCP_FLAG_INTERNAL);
+        return;
+    }
+    xq[d] = xin[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -1097,21 +1177,43 @@ __device__ __forceinline__ void internal_node(
 // Internal level maxl - 1 - j, with maxl the deepest leaf level: the
 // deepest internal levels hold most internal nodes, and each node reads its
 // children's records with loads that no two lanes share, so each of them
-// takes a launch over the whole chip, one node per thread.
+// takes a launch over the whole chip, one node per thread.  The first of
+// these passes (j = 0) also lists the internal nodes of the levels above
+// them (in any order; each is computed alone), so that the pass over those
+// levels reads only them.
 constexpr int kDeepThreads = 256, kDeepLevels = 4;
 __global__ __launch_bounds__(kDeepThreads) void k_moments_level(
     int j, int64_t n, const int32_t *__restrict__ noff, const uint8_t *__restrict__ nlev,
     const double4 *__restrict__ ngeo, int4 *ninfo, int32_t *npar, double *mom64, float4 *nrec,
-    double *spec, const unsigned long long *__restrict__ ctr, int32_t *flags)
+    double *spec, unsigned long long *ctr, int32_t *uplist, int32_t *flags)
 {
     if (*flags) return;
     const int l = (int)ctr[CTR_MAXLEVEL] - 1 - j;
     if (l < 0) return;
     const int nn = noff[n];
+    const int lup = l - kDeepLevels;   // the upper levels are 0 .. lup (j = 0)
+    const int lane = threadIdx.x & 63;
     for (int64_t k = blockIdx.x * (int64_t)kDeepThreads + threadIdx.x; k < nn;
-         k += (int64_t)gridDim.x * kDeepThreads)
-        if ((int)nlev[k] == l)
+         k += (int64_t)gridDim.x * kDeepThreads) {
+        const int lv = (int)nlev[k];
+        if (j == 0) {
+            // lv < kLeafBit: internal; one atomic per wave reserves the slots
+            const bool up = lv <= lup;
+            const unsigned long long bm = __ballot(up);
+            if (bm != 0ull) {
+                const int leader = __builtin_ctzll(bm);
+                unsigned long long base = 0;
+                if (lane == leader) base = atomicAdd(&ctr[CTR_UPCOUNT], (unsigned long long)__popcll(bm));
+                base = __shfl(base, leader);
+                if (up) {
+                    const unsigned long long below = bm & (lane == 0 ? 0ull : (~0ull >> (64 - lane)));
+                    uplist[base + __popcll(below)] = (int)k;
+                }
+            }
+        }
+        if (lv == l)
             internal_node<4>((int)k, l, n, nn, nlev, ngeo, ninfo, npar, mom64, nrec, spec, flags);
+    }
 }
 
 // Grid-wide barrier of a launch whose blocks are all resident at once (one
@@ -1145,19 +1247,17 @@ __device__ __forceinline__ bool grid_barrier(unsigned long long *bar, unsigned l
 // count of arrivals stays exact; a block whose wait times out flags the build
 // and stops waiting.  Few blocks keep the barrier cheap: each block's release
 // writes back its L2.
-constexpr int kUpThreads = 512, kUpBlocks = 16, kUpScan = 16;   // level bytes per thread
-constexpr int kUpChunk = kUpThreads * kUpScan;
+constexpr int kUpThreads = 512, kUpBlocks = 16;
 __global__ __launch_bounds__(kUpThreads) void k_moments_up(
     int64_t n, const int32_t *__restrict__ noff, const uint8_t *__restrict__ nlev,
     const double4 *__restrict__ ngeo, int4 *ninfo, int32_t *npar, double *mom64, float4 *nrec,
-    double *spec, unsigned long long *ctr, int32_t *flags)
+    double *spec, unsigned long long *ctr, const int32_t *__restrict__ uplist, int32_t *flags)
 {
-    // the matching nodes of one chunk of the preorder, gathered so that the
-    // block's threads share them evenly
-    __shared__ int match[kUpChunk];
-    __shared__ int nmatch, go_s;
+    __shared__ int go_s;
     const int maxl = (int)ctr[CTR_MAXLEVEL];   // deepest leaf; internal nodes lie above it
     const int nn = noff[n];
+    // the internal nodes of these levels, listed by the first deep-level pass
+    const int nup = (int)min((unsigned long long)nn, ctr[CTR_UPCOUNT]);
     unsigned long long target = 0;
     bool wait = true;
     for (int l = maxl - 1 - kDeepLevels; l >= 0; --l) {
@@ -1168,26 +1268,15 @@ __global__ __launch_bounds__(kUpThreads) void k_moments_up(
         __syncthreads();
         const bool go = go_s != 0;
         __syncthreads();
-        for (int64_t cb = (int64_t)blockIdx.x * kUpChunk; go && cb < nn;
-             cb += (int64_t)gridDim.x * kUpChunk) {
-            if (threadIdx.x == 0) nmatch = 0;
-            __syncthreads();
-            const int64_t k0 = cb + (int64_t)threadIdx.x * kUpScan;
-            if (k0 < nn) {
-                const uint4 v = *(const uint4 *)(nlev + k0);
-                const uint32_t d[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-                for (int b = 0; b < kUpScan; ++b) {
-                    const int64_t k = k0 + b;
-                    if (k < nn && (int)((d[b >> 2] >> (8 * (b & 3))) & 255u) == l)
-                        match[atomicAdd(&nmatch, 1)] = (int)k;
-                }
+        for (int i = blockIdx.x * kUpThreads + threadIdx.x; go && i < nup;
+             i += gridDim.x * kUpThreads) {
+            const int k = uplist[i];
+            if (k < 0 || k >= nn) {
+                atomicOr(flags, UCP_FLAG_INTERNAL);
+                continue;
             }
-            __syncthreads();
-            for (int i = threadIdx.x; i < nmatch; i += kUpThreads)
-                internal_node<2>(match[i], l, n, nn, nlev, ngeo, ninfo, npar, mom64, nrec, spec,
-                                 flags);
-            __syncthreads();
+            if ((int)nlev[k] == l)
+                internal_node<2>(k, l, n, nn, nlev, ngeo, ninfo, npar, mom64, nrec, spec, flags);
         }
         if (l == 0 || !wait) continue;
         target += gridDim.x;
@@ -1318,12 +1407,15 @@ void launch_build(Ctx *c, const double *x, const double *q, const int64_t *offse
     hipLaunchKernelGGL(k_cube_reduce, grid_for(n, 256 * kCubeItems), dim3(256), 0, s, x, n,
                        (const int64_t *)c->d_off, clouds, c->d_mm, c->d_flags);
     // 2. keys (and each cloud's cube from the reduced extents)
-    hipLaunchKernelGGL(k_keys, grid_for(n, 256), dim3(256), 0, s, x, n, (const int64_t *)c->d_off,
-                       clouds, (const unsigned long long *)c->d_mm, c->d_cube, b, c->p.curve,
-                       c->d_key[0], c->d_val[0], c->d_flags);
+    hipLaunchKernelGGL(k_keys, grid_for(n, 256), dim3(256), 0, s, x, q, n,
+                       (const int64_t *)c->d_off, clouds, (const unsigned long long *)c->d_mm,
+                       c->d_cube, b, c->p.curve, c->d_key[0], c->d_val[0], c->d_xin, c->d_flags);
     // 3. sort
     const int ntiles = (int)((n + kSortTile - 1) / kSortTile);
     const int key_passes = (3 * b + 7) / 8;
+    // three top digits (boxes of level 7-8) leave runs of a few particles up
+    // to about 2^20 particles; above that a fourth keeps ranking cheap
+    const int top_passes = std::min(n > (int64_t(1) << 20) ? 4 : 3, key_passes);
     int cloud_passes = 0;
     if (clouds > 1) {
         int cbits = 0;
@@ -1334,34 +1426,61 @@ void launch_build(Ctx *c, const double *x, const double *q, const int64_t *offse
                        dim3(kSortThreads), 0, s, (const uint64_t *)c->d_key[0], n, key_passes,
                        cloud_passes, (const int64_t *)c->d_off, clouds, c->d_ghist,
                        (const int32_t *)c->d_flags);
-    int cur = 0, npass = 0;
+    int npass = 0;
     uint32_t *status[2] = {c->d_hist, c->d_histscan};
-    const int total_passes = key_passes + cloud_passes;
-    auto pass = [&](bool cloud_pass, int shift) {
+    // one pass from buffer `from` to `to` over key digit `digit` (or cloud
+    // digit `digit` - key_passes); the counts of digit j are ghist[256 j]
+    auto pass = [&](int from, int to, int digit, double4 *xq, const unsigned long long *gate) {
         uint32_t *st = status[npass & 1], *st_next = status[(npass + 1) & 1];
         uint32_t *ticket = c->d_sortctl + npass;
-        const uint32_t *gh = c->d_ghist + 256 * npass;
-        // the last pass gathers x and q into the sorted order
-        double4 *xq = npass == total_passes - 1 ? c->d_xq : nullptr;
+        const uint32_t *gh = c->d_ghist + 256 * digit;
+        const bool cloud_pass = digit >= key_passes;
+        const int shift = 8 * (cloud_pass ? digit - key_passes : digit);
         if (cloud_pass)
             hipLaunchKernelGGL(k_radix_pass<true>, dim3(ntiles), dim3(kSortThreads), 0, s,
-                               (const uint64_t *)c->d_key[cur], (const uint32_t *)c->d_val[cur],
-                               c->d_key[cur ^ 1], c->d_val[cur ^ 1], n, shift,
-                               (const int64_t *)c->d_off, clouds, gh, st, st_next, ticket, x, q,
-                               xq, c->d_flags);
+                               (const uint64_t *)c->d_key[from], (const uint32_t *)c->d_val[from],
+                               c->d_key[to], c->d_val[to], n, shift, (const int64_t *)c->d_off,
+                               clouds, gh, st, st_next, ticket, (const double4 *)c->d_xin, xq, gate,
+                               c->d_flags);
         else
             hipLaunchKernelGGL(k_radix_pass<false>, dim3(ntiles), dim3(kSortThreads), 0, s,
-                               (const uint64_t *)c->d_key[cur], (const uint32_t *)c->d_val[cur],
-                               c->d_key[cur ^ 1], c->d_val[cur ^ 1], n, shift,
-                               (const int64_t *)c->d_off, clouds, gh, st, st_next, ticket, x, q,
-                               xq, c->d_flags);
-        cur ^= 1;
+                               (const uint64_t *)c->d_key[from], (const uint32_t *)c->d_val[from],
+                               c->d_key[to], c->d_val[to], n, shift, (const int64_t *)c->d_off,
+                               clouds, gh, st, st_next, ticket, (const double4 *)c->d_xin, xq, gate,
+                               c->d_flags);
         ++npass;
     };
-    for (int ps = 0; ps < key_passes; ++ps) pass(false, 8 * ps);
-    for (int ps = 0; ps < cloud_passes; ++ps) pass(true, 8 * ps);
-    c->d_skey = c->d_key[cur];
-    c->d_perm = c->d_val[cur];
+    // the digits of a sequence of passes, least significant first
+    std::vector<int> digits;
+    // passes over the top digits and the cloud digits, from buffer 0 to buffer 1
+    for (int d = key_passes - top_passes; d < key_passes; ++d) digits.push_back(d);
+    for (int d = 0; d < cloud_passes; ++d) digits.push_back(key_passes + d);
+    int cur = 0;
+    for (size_t i = 0; i < digits.size(); ++i) {
+        // the first pass goes to the buffer that makes the last one land in 1
+        const int to = i == 0 ? ((digits.size() - 1) % 2 == 0 ? 1 : 2) : (cur == 1 ? 2 : 1);
+        pass(cur, to, digits[i], nullptr, nullptr);
+        cur = to;
+    }
+    // each run of equal top digits ordered by ranking, into buffer 2
+    const int fin_shift = 8 * (key_passes - top_passes);
+    hipLaunchKernelGGL(k_sort_finish, grid_for(n, kFinishThreads), dim3(kFinishThreads), 0, s,
+                       (const uint64_t *)c->d_key[1], (const uint32_t *)c->d_val[1], c->d_key[2],
+                       c->d_val[2], n, fin_shift, (const int64_t *)c->d_off, clouds,
+                       (const double4 *)c->d_xin, c->d_xq, c->d_ctr + CTR_SORTFULL, c->d_flags);
+    // the full sort, gated by the finish's word: every digit from buffer 0,
+    // ending in buffer 2; its last pass gathers x and q
+    digits.clear();
+    for (int d = 0; d < key_passes + cloud_passes; ++d) digits.push_back(d);
+    cur = 0;
+    for (size_t i = 0; i < digits.size(); ++i) {
+        const int to = i == 0 ? ((digits.size() - 1) % 2 == 0 ? 2 : 1) : (cur == 1 ? 2 : 1);
+        pass(cur, to, digits[i], i + 1 == digits.size() ? c->d_xq : nullptr,
+             c->d_ctr + CTR_SORTFULL);
+        cur = to;
+    }
+    c->d_skey = c->d_key[2];
+    c->d_perm = c->d_val[2];
     // 4. levels and node numbering
     hipLaunchKernelGGL(k_levels, grid_for(n + 1, kLvlTile), dim3(kLvlTile), 0, s,
                        (const uint64_t *)c->d_skey, n, (const int64_t *)c->d_off, clouds, b, cap,
@@ -1383,17 +1502,19 @@ void launch_build(Ctx *c, const double *x, const double *q, const int64_t *offse
                        (const int8_t *)c->d_leaf, (const int32_t *)c->d_lend,
                        (const int32_t *)c->d_noff, (const double4 *)c->d_ngeo, c->d_ninfo,
                        c->d_mom64, c->d_nrec, c->d_leafof, spec, (const int32_t *)c->d_flags);
+    // a grid over the whole chip, striding over the node records
     const int deep_blocks = (int)std::min<int64_t>((c->node_cap + kDeepThreads - 1) / kDeepThreads,
-                                                   16384);
+                                                   8 * (int64_t)std::max(c->num_cu, 1));
     for (int j = 0; j < kDeepLevels; ++j)
         hipLaunchKernelGGL(k_moments_level, dim3(deep_blocks), dim3(kDeepThreads), 0, s, j, n,
                            (const int32_t *)c->d_noff, (const uint8_t *)c->d_nlev,
                            (const double4 *)c->d_ngeo, c->d_ninfo, c->d_npar, c->d_mom64,
-                           c->d_nrec, spec, (const unsigned long long *)c->d_ctr, c->d_flags);
+                           c->d_nrec, spec, c->d_ctr, c->d_uplist, c->d_flags);
     hipLaunchKernelGGL(k_moments_up, dim3(std::min(kUpBlocks, std::max(c->num_cu, 1))),
                        dim3(kUpThreads), 0, s, n, (const int32_t *)c->d_noff,
                        (const uint8_t *)c->d_nlev, (const double4 *)c->d_ngeo, c->d_ninfo,
-                       c->d_npar, c->d_mom64, c->d_nrec, spec, c->d_ctr, c->d_flags);
+                       c->d_npar, c->d_mom64, c->d_nrec, spec, c->d_ctr,
+                       (const int32_t *)c->d_uplist, c->d_flags);
     // 7. groups
     if (chunk) {
         const int64_t gmax = (n + G - 1) / G + clouds;

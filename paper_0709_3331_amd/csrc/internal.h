@@ -30,7 +30,8 @@ constexpr uint8_t kLeafBit = 0x80;             // leaf flag of the per-node leve
 constexpr int kSpecVals = 12;                   // doubles per node of the species pseudo-particles
 
 // device counter slots (unsigned long long)
-enum { CTR_P2P = 0, CTR_M2P = 1, CTR_MAXLEVEL = 2, CTR_BARRIER = 3, CTR_VJPMAX = 4, CTR_NCTR = 8 };
+enum { CTR_P2P = 0, CTR_M2P = 1, CTR_MAXLEVEL = 2, CTR_BARRIER = 3, CTR_VJPMAX = 4,
+       CTR_UPCOUNT = 5, CTR_SORTFULL = 6, CTR_NCTR = 8 };
 // walk work queues: one per XCD, each on its own 128-byte line
 constexpr int kWalkQueues = 8, kQStride = 16;
 
@@ -95,8 +96,9 @@ struct Ctx {
     unsigned long long *d_mm = nullptr;     // [clouds_max][6] ordered min xyz, max xyz
     double4 *d_cube = nullptr;              // [clouds_max][2]: {lo xyz, L}, {scale, e, -, -}
     // sort
-    uint64_t *d_key[2] = {nullptr, nullptr};
-    uint32_t *d_val[2] = {nullptr, nullptr};
+    // buffer 0: keys in input order; 1 and 2: the passes; the sorted keys end in 2
+    uint64_t *d_key[3] = {nullptr, nullptr, nullptr};
+    uint32_t *d_val[3] = {nullptr, nullptr, nullptr};
     // radix sort: per-(tile, digit) status words of the decoupled look-back
     // (two arrays, alternating by pass), the digit counts of every pass, and
     // one ticket counter per pass
@@ -106,7 +108,8 @@ struct Ctx {
     uint32_t *d_sortctl = nullptr;          // [kSortTickets]
     uint64_t *d_skey = nullptr;             // sorted keys (points into d_key[])
     uint32_t *d_perm = nullptr;             // sorted position -> caller index
-    // sorted particles
+    // particles: packed in input order by the key kernel, then sorted
+    double4 *d_xin = nullptr;               // [n_max] x, y, z, q  (input order)
     double4 *d_xq = nullptr;                // [n_max] x, y, z, q  (sorted order)
     // per position
     int8_t *d_L = nullptr;                  // [n_max + 1] common-prefix level with predecessor
@@ -124,6 +127,7 @@ struct Ctx {
     int4 *d_ninfo = nullptr;                // [node_cap] first, count, skip, level | 256*leaf
     int32_t *d_npar = nullptr;              // [node_cap] parent (-1 for a root)
     uint8_t *d_nlev = nullptr;              // [node_cap + 128] level of each node, | kLeafBit for a leaf
+    int32_t *d_uplist = nullptr;            // [node_cap] internal nodes above the deep levels
     // per-species pseudo-particles (UCP_EXPANSION_SPECIES), allocated when that
     // expansion is first set: c+[3] Q+ c-[3] Q- delta+ delta- 0 0
     double *d_spec = nullptr;               // [node_cap][kSpecVals]

@@ -161,3 +161,57 @@ def test_metric_cloud_late_states_match_oracle(dt):
         assert ratio <= 1.0
         tl.close()
     ts.close()
+
+
+def _clustered(n_tight, n_wide, seed):
+    # n_tight particles within 1e-6 of one point (one box down to level 8 and
+    # beyond), the rest Gaussian: the run of equal top key digits is longer
+    # than the sort's finishing kernel ranks, so the full sort runs
+    rng = np.random.default_rng(seed)
+    x = np.concatenate([0.3 + 1e-6 * rng.standard_normal((n_tight, 3)),
+                        rng.standard_normal((n_wide, 3))])
+    q = np.where(np.arange(n_tight + n_wide) % 2 == 0, 1.0, -1.0)
+    return x, q
+
+
+def _top_run(x, bits=23):
+    lo, e = oracle.cube(x)
+    k = oracle.keys(x, lo, e, 21, oracle.CURVE_HILBERT)
+    _, cnt = np.unique(k >> np.uint64(63 - bits), return_counts=True)
+    return int(cnt.max())
+
+
+@pytest.mark.parametrize("batched", [False, True], ids=["one-cloud", "batched"])
+def test_sort_falls_back_to_the_full_sort_for_long_runs(batched):
+    x1, q1 = _clustered(3000, 5000, 80)
+    x2, q2 = _clustered(10, 2500, 81)
+    assert _top_run(x1) > 2048 and _top_run(x2) <= 2048
+    say(f"[sort] long run of {_top_run(x1)} equal top digits, batched={batched}")
+    parts = [(x1, q1), (x2, q2)] if batched else [(x1, q1)]
+    x = np.concatenate([p[0] for p in parts]); q = np.concatenate([p[1] for p in parts])
+    off = np.concatenate([[0], np.cumsum([p[0].shape[0] for p in parts])]).astype(np.int64)
+    n = x.shape[0]
+    for prec, tol in ((L.UCP_FP64, 1e-12), (L.UCP_SPLIT, 1e-5)):
+        ts = TreeSolver(n, len(parts), theta=0.5, eps=0.01, precision=prec)
+        f = ts.tree_forces(torch.from_numpy(x).cuda(), torch.from_numpy(q).cuda(),
+                           torch.from_numpy(off).cuda() if batched else None).cpu().numpy()
+        ts.stats()
+        keys, perm = ts.debug("keys"), ts.debug("perm").astype(np.int64)
+        for k, (xp, qp) in enumerate(parts):
+            a, b = off[k], off[k + 1]
+            t = oracle.Tree(xp, qp, 0.5, 0.01)
+            np.testing.assert_array_equal(keys[a:b], t.sorted_keys())
+            np.testing.assert_array_equal(perm[a:b] - a, t.perm())
+            ref = t.eval(cond=True)
+            # the 3000 particles of the cluster lie inside each other's
+            # softening core and cancel there, so FP32 forces are checked
+            # against the per-particle rounding bound rather than the RMS
+            uw = U32 if prec == L.UCP_SPLIT else U64
+            err = np.linalg.norm(f[a:b] - ref["f"], axis=1)
+            ratio = float(np.max(err / (K_BOUND * (uw + U64) * np.abs(qp) * ref["cond"])))
+            say(f"[sort]   cloud {k} prec={prec} rel RMS {relrms(f[a:b], ref['f']):.3e}, "
+                f"max error / bound {ratio:.3e}")
+            assert ratio <= 1.0, (k, prec)
+            if prec == L.UCP_FP64:
+                assert relrms(f[a:b], ref["f"]) < tol, k
+        ts.close()
