@@ -58,6 +58,7 @@ void launch_fill_f64(double *p, double v, int64_t n, hipStream_t s)
 }
 
 __device__ __forceinline__ int block_excl_scan(int v, int *total);
+__device__ __forceinline__ bool grid_barrier(unsigned long long *bar, unsigned long long target);
 
 // per-build state: cloud extents, counters (the walk's included), the walk's
 // queue heads, the sort's tickets, digit counts and the first pass's
@@ -502,27 +503,25 @@ constexpr int kLookbackSpin = 1 << 18;
 constexpr int kLbSeg = 4;
 static_assert(kSortThreads == 4 * 256, "the look-back takes four lanes per digit");
 
+// LDS of one tile of a pass
+struct SortLds {
+    uint32_t wh[kSortItems][kSortThreads / 64][256];   // per-(round, wave) digit counts, then offsets
+    uint32_t boff[256], rsh[256], bsh[256];
+    int btot, tile_sh;
+};
+
+// One tile of a pass: ranked, its counts published, its prefixes found by the
+// look-back, scattered.  `below` is, on thread tid < 256, the exclusive prefix
+// of digit tid over the pass's digit totals; L.wh is zero on entry.
 template <bool CLOUD>
-__global__ __launch_bounds__(kSortThreads) void k_radix_pass(
-    const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint64_t *kout,
-    uint32_t *vout, int64_t n, int shift, const int64_t *__restrict__ off, int clouds,
-    const uint32_t *__restrict__ ghist, uint32_t *status, uint32_t *status_next,
-    uint32_t *ticket, const double4 *__restrict__ xin, double4 *xq,
-    const unsigned long long *__restrict__ gate, int32_t *flags)
+__device__ __forceinline__ void radix_tile(
+    SortLds &L, int tile, int below, const uint64_t *__restrict__ kin,
+    const uint32_t *__restrict__ vin, uint64_t *kout, uint32_t *vout, int64_t n, int shift,
+    const int64_t *__restrict__ off, int clouds, uint32_t *status, uint32_t *status_next,
+    const double4 *__restrict__ xin, double4 *xq, int32_t *flags)
 {
     constexpr int NW = kSortThreads / 64;
-    __shared__ uint32_t wh[kSortItems][NW][256];   // per-(round, wave) digit counts, then offsets
-    __shared__ uint32_t boff[256], rsh[256], bsh[256];
-    __shared__ int btot, tile_sh;
-    if (*flags) return;
-    if (gate && *gate == 0ull) return;   // a pass of the full sort, not needed
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    if (tid == 0) tile_sh = (int)atomicAdd(ticket, 1u);
-    for (int j = tid; j < kSortItems * NW * 256; j += kSortThreads) (&wh[0][0][0])[j] = 0;
-    // digit totals of this pass and their exclusive prefix over the digits
-    const uint32_t tot = tid < 256 ? ghist[tid] : 0u;
-    const int below = block_excl_scan((int)tot, &btot);   // synchronises the block
-    const int tile = tile_sh;
     const int64_t base = (int64_t)tile * kSortTile;
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     uint64_t k[kSortItems];
@@ -558,7 +557,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_pass(
             peers &= ((d[it] >> bit) & 1u) ? bb : ~bb;
         }
         lrank[it] = (uint32_t)__popcll(peers & lt);
-        if (valid[it] && lrank[it] == 0) wh[it][w][d[it]] = (uint32_t)__popcll(peers);
+        if (valid[it] && lrank[it] == 0) L.wh[it][w][d[it]] = (uint32_t)__popcll(peers);
     }
     __syncthreads();
     if (tid < 256) {
@@ -566,15 +565,15 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_pass(
         uint32_t r = 0;
         for (int it = 0; it < kSortItems; ++it)
             for (int ww = 0; ww < NW; ++ww) {
-                const uint32_t c = wh[it][ww][tid];
-                wh[it][ww][tid] = r;
+                const uint32_t c = L.wh[it][ww][tid];
+                L.wh[it][ww][tid] = r;
                 r += c;
             }
         // publish the tile's count at once (tile 0's is already inclusive)
         __hip_atomic_store(status + (int64_t)tile * 256 + tid, (tile == 0 ? kStIncl : kStAgg) | r,
                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        rsh[tid] = r;
-        bsh[tid] = (uint32_t)below;
+        L.rsh[tid] = r;
+        L.bsh[tid] = (uint32_t)below;
         status_next[(int64_t)tile * 256 + tid] = 0u;   // the next pass's status
     }
     __syncthreads();
@@ -628,16 +627,16 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_pass(
         }
         if (q4 == 0) {
             if (tile > 0)
-                __hip_atomic_store(status + (int64_t)tile * 256 + dg, kStIncl | (excl + rsh[dg]),
+                __hip_atomic_store(status + (int64_t)tile * 256 + dg, kStIncl | (excl + L.rsh[dg]),
                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            boff[dg] = bsh[dg] + excl;
+            L.boff[dg] = L.bsh[dg] + excl;
         }
     }
     __syncthreads();
 #pragma unroll
     for (int it = 0; it < kSortItems; ++it)
         if (valid[it]) {
-            const uint32_t dst = boff[d[it]] + wh[it][w][d[it]] + lrank[it];
+            const uint32_t dst = L.boff[d[it]] + L.wh[it][w][d[it]] + lrank[it];
             if ((int64_t)dst >= n) {   // only inconsistent prefixes lead here
                 atomicOr(flags, UCP_FLAG_INTERNAL);
                 continue;
@@ -648,6 +647,91 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_pass(
         }
 }
 
+// one pass, one tile per block
+template <bool CLOUD>
+__global__ __launch_bounds__(kSortThreads) void k_radix_pass(
+    const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint64_t *kout,
+    uint32_t *vout, int64_t n, int shift, const int64_t *__restrict__ off, int clouds,
+    const uint32_t *__restrict__ ghist, uint32_t *status, uint32_t *status_next,
+    uint32_t *ticket, const double4 *__restrict__ xin, double4 *xq, int32_t *flags)
+{
+    __shared__ SortLds L;
+    if (*flags) return;
+    const int tid = threadIdx.x;
+    if (tid == 0) L.tile_sh = (int)atomicAdd(ticket, 1u);
+    for (int j = tid; j < kSortItems * (kSortThreads / 64) * 256; j += kSortThreads)
+        (&L.wh[0][0][0])[j] = 0;
+    // digit totals of this pass and their exclusive prefix over the digits
+    const uint32_t tot = tid < 256 ? ghist[tid] : 0u;
+    const int below = block_excl_scan((int)tot, &L.btot);   // synchronises the block
+    radix_tile<CLOUD>(L, L.tile_sh, below, kin, vin, kout, vout, n, shift, off, clouds, status,
+                      status_next, xin, xq, flags);
+}
+
+// The passes of the full sort behind the finish, in one launch whose blocks
+// are all resident at once: every block takes tiles by ticket, pass after
+// pass, with a grid barrier between passes (a tile's look-back then only
+// waits for tiles of running blocks).  The whole launch returns at once unless
+// the finish raised the gate, so the common build pays one empty launch.
+struct SortPassArgs {
+    const uint64_t *kin;
+    const uint32_t *vin;
+    uint64_t *kout;
+    uint32_t *vout;
+    const uint32_t *ghist;
+    uint32_t *status, *status_next, *ticket;
+    double4 *xq;   // the last pass gathers x and q
+    int shift, cloud;
+};
+struct SortPlan {
+    SortPassArgs p[kSortPassesMax];
+    int npass;
+};
+
+__global__ __launch_bounds__(kSortThreads) void k_sort_full(
+    const SortPlan plan, int64_t n, const int64_t *__restrict__ off, int clouds,
+    const double4 *__restrict__ xin, const unsigned long long *__restrict__ gate,
+    unsigned long long *bar, int32_t *flags)
+{
+    __shared__ SortLds L;
+    __shared__ int go_s;
+    const int tid = threadIdx.x;
+    if (tid == 0) go_s = *gate != 0ull && *flags == 0;
+    __syncthreads();
+    if (!go_s) return;
+    const int ntiles = (int)((n + kSortTile - 1) / kSortTile);
+    unsigned long long target = 0;
+    bool wait = true;
+    for (int ip = 0; ip < plan.npass; ++ip) {
+        const SortPassArgs &P = plan.p[ip];
+        const uint32_t tot = tid < 256 ? P.ghist[tid] : 0u;
+        const int below = block_excl_scan((int)tot, &L.btot);
+        for (;;) {
+            if (tid == 0) L.tile_sh = (int)atomicAdd(P.ticket, 1u);
+            for (int j = tid; j < kSortItems * (kSortThreads / 64) * 256; j += kSortThreads)
+                (&L.wh[0][0][0])[j] = 0;
+            __syncthreads();
+            const int tile = L.tile_sh;
+            if (tile >= ntiles) break;   // the same on every thread of the block
+            if (P.cloud)
+                radix_tile<true>(L, tile, below, P.kin, P.vin, P.kout, P.vout, n, P.shift, off,
+                                 clouds, P.status, P.status_next, xin, P.xq, flags);
+            else
+                radix_tile<false>(L, tile, below, P.kin, P.vin, P.kout, P.vout, n, P.shift, off,
+                                  clouds, P.status, P.status_next, xin, P.xq, flags);
+            __syncthreads();
+        }
+        // every block passes every barrier, so that the count of arrivals
+        // stays exact; a wait that times out flags the build and stops waiting
+        if (ip + 1 < plan.npass && wait) {
+            target += gridDim.x;
+            if (!grid_barrier(bar, target)) {
+                if (tid == 0) atomicOr(flags, UCP_FLAG_INTERNAL);
+                wait = false;
+            }
+        }
+    }
+}
 // The runs of equal top digits (bits from `shift` up, inside one cloud) after
 // the passes over those digits: an element's place in its run is the number
 // of elements of the run with a smaller key, or with an equal key and an
@@ -1428,27 +1512,23 @@ void launch_build(Ctx *c, const double *x, const double *q, const int64_t *offse
                        (const int32_t *)c->d_flags);
     int npass = 0;
     uint32_t *status[2] = {c->d_hist, c->d_histscan};
-    // one pass from buffer `from` to `to` over key digit `digit` (or cloud
-    // digit `digit` - key_passes); the counts of digit j are ghist[256 j]
-    auto pass = [&](int from, int to, int digit, double4 *xq, const unsigned long long *gate) {
-        uint32_t *st = status[npass & 1], *st_next = status[(npass + 1) & 1];
-        uint32_t *ticket = c->d_sortctl + npass;
-        const uint32_t *gh = c->d_ghist + 256 * digit;
-        const bool cloud_pass = digit >= key_passes;
-        const int shift = 8 * (cloud_pass ? digit - key_passes : digit);
-        if (cloud_pass)
-            hipLaunchKernelGGL(k_radix_pass<true>, dim3(ntiles), dim3(kSortThreads), 0, s,
-                               (const uint64_t *)c->d_key[from], (const uint32_t *)c->d_val[from],
-                               c->d_key[to], c->d_val[to], n, shift, (const int64_t *)c->d_off,
-                               clouds, gh, st, st_next, ticket, (const double4 *)c->d_xin, xq, gate,
-                               c->d_flags);
-        else
-            hipLaunchKernelGGL(k_radix_pass<false>, dim3(ntiles), dim3(kSortThreads), 0, s,
-                               (const uint64_t *)c->d_key[from], (const uint32_t *)c->d_val[from],
-                               c->d_key[to], c->d_val[to], n, shift, (const int64_t *)c->d_off,
-                               clouds, gh, st, st_next, ticket, (const double4 *)c->d_xin, xq, gate,
-                               c->d_flags);
+    // pass number npass from buffer `from` to `to` over key digit `digit` (or
+    // cloud digit `digit` - key_passes); the counts of digit j are ghist[256 j]
+    auto pass_args = [&](int from, int to, int digit, double4 *xq) {
+        SortPassArgs a;
+        a.kin = (const uint64_t *)c->d_key[from];
+        a.vin = (const uint32_t *)c->d_val[from];
+        a.kout = c->d_key[to];
+        a.vout = c->d_val[to];
+        a.ghist = c->d_ghist + 256 * digit;
+        a.status = status[npass & 1];
+        a.status_next = status[(npass + 1) & 1];
+        a.ticket = c->d_sortctl + npass;
+        a.xq = xq;
+        a.cloud = digit >= key_passes;
+        a.shift = 8 * (a.cloud ? digit - key_passes : digit);
         ++npass;
+        return a;
     };
     // the digits of a sequence of passes, least significant first
     std::vector<int> digits;
@@ -1459,7 +1539,17 @@ void launch_build(Ctx *c, const double *x, const double *q, const int64_t *offse
     for (size_t i = 0; i < digits.size(); ++i) {
         // the first pass goes to the buffer that makes the last one land in 1
         const int to = i == 0 ? ((digits.size() - 1) % 2 == 0 ? 1 : 2) : (cur == 1 ? 2 : 1);
-        pass(cur, to, digits[i], nullptr, nullptr);
+        const SortPassArgs a = pass_args(cur, to, digits[i], nullptr);
+        if (a.cloud)
+            hipLaunchKernelGGL(k_radix_pass<true>, dim3(ntiles), dim3(kSortThreads), 0, s, a.kin,
+                               a.vin, a.kout, a.vout, n, a.shift, (const int64_t *)c->d_off,
+                               clouds, a.ghist, a.status, a.status_next, a.ticket,
+                               (const double4 *)c->d_xin, a.xq, c->d_flags);
+        else
+            hipLaunchKernelGGL(k_radix_pass<false>, dim3(ntiles), dim3(kSortThreads), 0, s, a.kin,
+                               a.vin, a.kout, a.vout, n, a.shift, (const int64_t *)c->d_off,
+                               clouds, a.ghist, a.status, a.status_next, a.ticket,
+                               (const double4 *)c->d_xin, a.xq, c->d_flags);
         cur = to;
     }
     // each run of equal top digits ordered by ranking, into buffer 2
@@ -1470,15 +1560,18 @@ void launch_build(Ctx *c, const double *x, const double *q, const int64_t *offse
                        (const double4 *)c->d_xin, c->d_xq, c->d_ctr + CTR_SORTFULL, c->d_flags);
     // the full sort, gated by the finish's word: every digit from buffer 0,
     // ending in buffer 2; its last pass gathers x and q
-    digits.clear();
-    for (int d = 0; d < key_passes + cloud_passes; ++d) digits.push_back(d);
+    SortPlan plan;
+    plan.npass = key_passes + cloud_passes;
     cur = 0;
-    for (size_t i = 0; i < digits.size(); ++i) {
-        const int to = i == 0 ? ((digits.size() - 1) % 2 == 0 ? 2 : 1) : (cur == 1 ? 2 : 1);
-        pass(cur, to, digits[i], i + 1 == digits.size() ? c->d_xq : nullptr,
-             c->d_ctr + CTR_SORTFULL);
+    for (int i = 0; i < plan.npass; ++i) {
+        const int to = i == 0 ? ((plan.npass - 1) % 2 == 0 ? 2 : 1) : (cur == 1 ? 2 : 1);
+        plan.p[i] = pass_args(cur, to, i, i + 1 == plan.npass ? c->d_xq : nullptr);
         cur = to;
     }
+    hipLaunchKernelGGL(k_sort_full, dim3(std::max(1, std::min(ntiles, c->num_cu / 2))),
+                       dim3(kSortThreads), 0, s, plan, n, (const int64_t *)c->d_off, clouds,
+                       (const double4 *)c->d_xin, (const unsigned long long *)(c->d_ctr + CTR_SORTFULL),
+                       c->d_ctr + CTR_SORTBAR, c->d_flags);
     c->d_skey = c->d_key[2];
     c->d_perm = c->d_val[2];
     // 4. levels and node numbering

@@ -31,7 +31,7 @@ constexpr int kSpecVals = 12;                   // doubles per node of the speci
 
 // device counter slots (unsigned long long)
 enum { CTR_P2P = 0, CTR_M2P = 1, CTR_MAXLEVEL = 2, CTR_BARRIER = 3, CTR_VJPMAX = 4,
-       CTR_UPCOUNT = 5, CTR_SORTFULL = 6, CTR_NCTR = 8 };
+       CTR_UPCOUNT = 5, CTR_SORTFULL = 6, CTR_SORTBAR = 7, CTR_NCTR = 8 };
 // walk work queues: one per XCD, each on its own 128-byte line
 constexpr int kWalkQueues = 8, kQStride = 16;
 

@@ -215,3 +215,20 @@ def test_sort_falls_back_to_the_full_sort_for_long_runs(batched):
             if prec == L.UCP_FP64:
                 assert relrms(f[a:b], ref["f"]) < tol, k
         ts.close()
+
+
+def test_full_sort_with_several_tiles_per_block():
+    # 295 tiles of 2048 keys: more than the full sort's resident blocks, so
+    # each block takes several tiles per pass
+    x, q = _clustered(3000, 600000, 82)
+    assert _top_run(x) > 2048
+    n = x.shape[0]
+    say(f"[sort] full sort over {(n + 2047) // 2048} tiles")
+    ts = TreeSolver(n, 1, theta=0.5, eps=0.01)
+    ts.build(torch.from_numpy(x).cuda(), torch.from_numpy(q).cuda())
+    ts.stats()
+    keys, perm = ts.debug("keys"), ts.debug("perm").astype(np.int64)
+    ts.close()
+    t = oracle.Tree(x, q, 0.5, 0.01)
+    np.testing.assert_array_equal(keys, t.sorted_keys())
+    np.testing.assert_array_equal(perm, t.perm())
