@@ -31,6 +31,11 @@ PEAK_FP64_TFLOPS = 78.6
 WALK_SOURCES = ["paper_0709_3331_amd/csrc/walk.hip", "paper_0709_3331_amd/csrc/internal.h"]
 
 
+def note(msg):
+    """A progress line on stderr (the JSON line alone goes to stdout)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def walk_source_hash():
     h = hashlib.sha256()
     for p in WALK_SOURCES:
@@ -86,8 +91,16 @@ def bench_ensemble(args, prec, dev):
                     group_mode=tuned["group_mode"], leaf_cap=tuned["leaf_cap"])
     f = ts.tree_forces(x, q, offs)
     st = ts.stats()
+    x0, v0, f0 = x.clone(), v.clone(), f.clone()
+
+    def restore():
+        for dst, src in ((x, x0), (v, v0), (f, f0)):
+            dst.copy_(src)
+
     # one untimed call captures the step graphs; the timed call replays them
+    # from the state the directly enqueued steps below start from too
     ts.step(x, v, f, q, m, eprm["dt"], 2, offsets=offs)
+    restore()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ts.step(x, v, f, q, m, eprm["dt"], args.ensemble_steps, offsets=offs)
@@ -96,6 +109,7 @@ def bench_ensemble(args, prec, dev):
     ts.stats()
     # the walk time: the same steps enqueued directly with HIP events around
     # every walk launch (timing on bypasses the graphs)
+    restore()
     ts.timing(True)
     torch.cuda.synchronize()
     e0 = time.perf_counter()
@@ -326,7 +340,13 @@ def bench_adjoint(prec, dev):
     differences in sigma.  Cases:
       - the stated workload (theta = 0.5, dt = 1e-4) at 5, 20 and 200 steps;
       - theta = 0 (direct sum: no lists to change) at 5 steps, several h;
-      - a resolved control, dt = 1e-6, theta = 0.5, 200 steps, several h.
+      - a resolved control, dt = 1e-6, 200 steps, at theta = 0.5 and at
+        theta = 0, several h (h = 1e-4 is the workload's own).
+    At theta > 0 the loss of a long rollout is only piecewise smooth in
+    sigma: a perturbed run changes some interaction lists (an opening
+    decision flips), and central differences over an h that spans such jumps
+    do not converge to the derivative the adjoint returns; at theta = 0 there
+    are no lists.
     The stated dt does not resolve electrons bound in the softened ion wells
     (omega dt ~ 4), so perturbations grow ~18x per step there and the finite
     differences stop being linear within a few steps unless h is tiny; in the
@@ -359,7 +379,8 @@ def bench_adjoint(prec, dev):
              (prm["theta"], prm["dt"], 5, (1e-7, 1e-9, 1e-11), fp64),
              (prm["theta"], prm["dt"], 20, (1e-9, 1e-11), fp64),
              (0.0, prm["dt"], 5, (1e-7, 1e-9, 1e-11), fp64),
-             (prm["theta"], 1e-6, prm["steps"], (1e-7, 1e-9), fp64)]
+             (prm["theta"], 1e-6, prm["steps"], (1e-4, 1e-5, 1e-7, 1e-9), fp64),
+             (0.0, 1e-6, prm["steps"], (1e-4, 1e-7, 1e-9), fp64)]
     out = {"n": n, "eps": prm["eps"], "checkpoint_every": prm["ckpt"], "cases": {}}
     for th, dt, steps, hs, pr in cases:
         if (th, pr) not in solvers:
@@ -694,6 +715,10 @@ def main():
     torch.cuda.synchronize()
     print("bench: warmup done", file=sys.stderr, flush=True)
 
+    # the state the timed steps start from, so that the graph replays below
+    # advance the same state (the cloud evolves from step to step, and so
+    # does the walk's work)
+    x0, v0, f0 = x.clone(), v.clone(), f.clone()
     # timed region: exactly K steps, walk kernels bracketed by HIP events on
     # the stream they are launched on
     ts.timing(True)
@@ -707,16 +732,25 @@ def main():
     st = ts.stats()
     graph = None
     if not args.profile:
-        # the same steps replayed from the library's captured graphs, which
-        # carry no timing events: one untimed call captures them
+        # the same K steps from the same state, replayed from the library's
+        # captured graphs (which carry no timing events): one untimed call
+        # captures them
+        for dst, src in ((x, x0), (v, v0), (f, f0)):
+            dst.copy_(src)
         ts.step(x, v, f, q, m, dt, 2)
+        for dst, src in ((x, x0), (v, v0), (f, f0)):
+            dst.copy_(src)
         torch.cuda.synchronize()
         g0 = time.perf_counter()
         ts.step(x, v, f, q, m, dt, args.steps)
         torch.cuda.synchronize()
         g1 = time.perf_counter()
         graph = {"ms_per_step": 1e3 * (g1 - g0) / args.steps,
-                 "particles_per_s": n * args.steps / (g1 - g0)}
+                 "particles_per_s": n * args.steps / (g1 - g0),
+                 "same_steps_as_timed": True}
+    # the accuracy figures below refer to the state the timed steps start from
+    for dst, src in ((x, x0), (v, v0), (f, f0)):
+        dst.copy_(src)
     elapsed = t1 - t0
     ms_per_step = 1e3 * elapsed / args.steps
     walk_avg_ms = walk_ms / max(walk_launches, 1)
@@ -755,7 +789,9 @@ def main():
                      "frac": achieved / peak,
                      "traffic": traffic_from_profile(args.precision)},
     }
+    note(f"timed steps done, {ms_per_step:.4f} ms per step")
     if not args.profile and not args.no_compare:
+        note("SPLIT against the FP64 GPU tree")
         # accuracy against the plain FP64 GPU tree at identical parameters and
         # against the FP64 oracle direct sum on sampled targets
         f_split = ts.tree_forces(x, q)
@@ -776,6 +812,7 @@ def main():
         ts64.close()
     if not args.profile and not args.no_cpu_baseline:
         import oracle
+        note("accuracy against the oracle direct sum")
         xs = x.cpu().numpy()
         qs = cl.q
         fs = ts.tree_forces(x, q).cpu().numpy()
@@ -789,9 +826,11 @@ def main():
         fdn[tg] = fd
         result["per_particle_err_vs_direct_sampled"] = per_particle_rel(fs, fdn)
         if not args.no_accuracy_target:
+            note("cheapest setting that meets 1e-3 against the direct sum")
             result["accuracy_target"] = bench_accuracy_target(args, prec, x, v, q, m, n, eps, dt,
                                                               tg, fd)
         if not args.no_theta_sweep:
+            note("theta sweep")
             # the other opening parameters of the same workload: walk time,
             # interactions per particle, error against the sampled direct sum
             sweep = {}
@@ -816,6 +855,7 @@ def main():
                 tt.close()
             result["theta_sweep"] = sweep
         if not args.no_species:
+            note("per-sign pseudo-particles")
             # the paper's pseudo-particles (one per sign at its centre of
             # charge, Eq. (5) with delta) against the quadrupole above
             spc = {}
@@ -840,6 +880,7 @@ def main():
                         float(np.linalg.norm(fa[tg] - fd) / np.linalg.norm(fd))}
                 tt.close()
             result["species_pseudo_particles"] = spc
+        note("oracle tree on the host (cpu_baseline)")
         c0 = time.perf_counter()
         ot = oracle.Tree(xs, qs, theta, eps, curve=CURVE, G=args.group_size, group_mode=gm,
                          leaf_cap=args.leaf_cap)
@@ -856,10 +897,13 @@ def main():
             **cpu_info()}
     if not args.profile and not args.no_other_curve:
         key = "morton_keys" if CURVE == 1 else "hilbert_keys"
+        note("the other key order")
         result[key] = bench_other_curve(args, prec, cl, prm, dev)
     if not args.profile and not args.no_kelbg:
+        note("Kelbg pair law")
         result["kelbg"] = bench_kelbg(args, prec, x, q, cl, walk_avg_ms)
     if not args.profile and not args.no_seeds:
+        note("seed repeats")
         result["seed_repeats"] = bench_seeds(args, prec, dev)
     if not args.profile and not args.no_ensemble:
         result["ensemble"] = bench_ensemble(args, prec, dev)
