@@ -17,7 +17,10 @@
  *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *    Work is enqueued on it; no entry point synchronises the stream unless
  *    it says so.  The context owns every scratch buffer, sized at create
- *    time; no entry point other than ucp_create allocates device memory.
+ *    time.  Device memory is allocated by ucp_create, and besides only by the
+ *    first ucp_force_vjp on a context (the adjoint's scratch) and by
+ *    ucp_set_params when it first selects UCP_EXPANSION_SPECIES (the
+ *    pseudo-particle records); ucp_force_vjp_noalloc never allocates.
  *  - Every entry point returns a ucp_status.  No C++ exception crosses the
  *    ABI.  ucp_last_error() returns a human-readable message for the last
  *    failure on that context.  Device-detected problems (node capacity
@@ -41,7 +44,7 @@ extern "C" {
 typedef enum {
     UCP_OK = 0,
     UCP_EINVAL = -1,       /* invalid argument or parameter                    */
-    UCP_ENOMEM = -2,       /* device allocation failed in ucp_create           */
+    UCP_ENOMEM = -2,       /* a device allocation failed (see the conventions) */
     UCP_EHIP = -3,         /* a HIP runtime call failed                        */
     UCP_ECAPACITY = -4,    /* a device capacity (nodes, particles) was exceeded */
     UCP_ENOTBUILT = -5,    /* forces/VJP requested before a tree was built     */
