@@ -210,7 +210,8 @@ ucp_status ucp_compute_forces(ucp_ctx *c, double *f, double *phi, void *stream);
  * kick of a step and the opening kick and drift of the next run as one pass
  * (the same arithmetic, so the trajectory is bitwise that of nsteps calls of
  * one step).  Steps are captured once in hipGraphs and replayed (re-captured
- * when pointers, sizes or parameters change).
+ * when pointers, sizes or parameters change); a call of one step, and every
+ * call while ucp_set_timing is on, enqueues the kernels directly instead.
  * Errors: UCP_EINVAL.                                                       */
 ucp_status ucp_step(ucp_ctx *c, double *x, double *v, double *f, const double *q,
                     const double *m, int64_t n, double dt, int32_t nsteps, void *stream);
