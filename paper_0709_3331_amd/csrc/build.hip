@@ -1168,7 +1168,7 @@ __device__ __forceinline__ bool children_in_window(int k, int level, int nn,
 // skip links from k + 1.
 template <int BATCH>
 __device__ __forceinline__ void moments_internal(
-    int k, int64_t p, int level, int nn, const uint8_t *__restrict__ nlev,
+    int k, int64_t p, int64_t n, int level, int nn, const uint8_t *__restrict__ nlev,
     const double4 *__restrict__ ngeo, int4 *ninfo, int32_t *npar, double *mom64, float4 *nrec,
     double *spec, int32_t *flags)
 {
@@ -1233,6 +1233,12 @@ __device__ __forceinline__ void moments_internal(
             ci = si;
         }
     }
+    // the first particle is checked only here, so that its record, the
+    // node's centre and the level bytes are loaded in one round
+    if (p < 0 || p >= n) {
+        atomicOr(flags, UCP_FLAG_INTERNAL);
+        return;
+    }
     if (spec) spec_store(spec, k, g, sq);
     const int cnt = (int)(t - p), info = level;
     ninfo[k] = make_int4((int)p, cnt, skip, info);
@@ -1250,12 +1256,8 @@ __device__ __forceinline__ void internal_node(
     const double4 *__restrict__ ngeo, int4 *ninfo, int32_t *npar, double *mom64, float4 *nrec,
     double *spec, int32_t *flags)
 {
-    const int p = ninfo[k].x;
-    if (p < 0 || (int64_t)p >= n) {
-        atomicOr(flags, UCP_FLAG_INTERNAL);
-        return;
-    }
-    moments_internal<BATCH>(k, p, level, nn, nlev, ngeo, ninfo, npar, mom64, nrec, spec, flags);
+    moments_internal<BATCH>(k, ninfo[k].x, n, level, nn, nlev, ngeo, ninfo, npar, mom64, nrec,
+                            spec, flags);
 }
 
 // Internal level maxl - 1 - j, with maxl the deepest leaf level: the
