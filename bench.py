@@ -70,6 +70,7 @@ def bench_ensemble(args, prec, dev):
     autotuner, run on this input."""
     import torch
 
+    from paper_0709_3331_amd import _lib as L
     from paper_0709_3331_amd import autotune, inputs
     from paper_0709_3331_amd.tree import TreeSolver
 
@@ -117,8 +118,23 @@ def bench_ensemble(args, prec, dev):
     torch.cuda.synchronize()
     e1 = time.perf_counter()
     wms, wc = ts.timing_read()
+    balance = wave_balance(ts)
     ts.stats()
     ts.close()
+    # the plain FP64 walk of the same batched build at the same setting
+    t64 = TreeSolver(n, clouds, curve=CURVE, theta=eprm["theta"], eps=eprm["eps"],
+                     precision=L.UCP_FP64, group_size=tuned["group_size"],
+                     list_len=tuned["list_len"], group_mode=tuned["group_mode"],
+                     leaf_cap=tuned["leaf_cap"])
+    t64.tree_forces(x, q, offs)
+    t64.timing(True)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        t64.tree_forces(x, q, offs)
+    torch.cuda.synchronize()
+    w64, c64 = t64.timing_read()
+    t64.stats()
+    t64.close()
     el = t1 - t0
     return {"clouds": clouds, "n_total": n, "steps": args.ensemble_steps,
             "path": "hipGraph replay of the batched step",
@@ -126,6 +142,9 @@ def bench_ensemble(args, prec, dev):
             "ms_per_step": 1e3 * el / args.ensemble_steps,
             "direct_enqueue_ms_per_step": 1e3 * (e1 - e0) / args.ensemble_steps,
             "walk_ms": wms / max(wc, 1),
+            "walk_wave_balance": balance,
+            "fp64_walk_ms": w64 / max(c64, 1),
+            "split_speedup_walk": (w64 / max(c64, 1)) / (wms / max(wc, 1)),
             "interactions_per_particle": (st["p2p"] + st["m2p"]) / n,
             "tuned": {"group_size": tuned["group_size"], "list_len": tuned["list_len"],
                       "leaf_cap": tuned["leaf_cap"],
@@ -146,6 +165,20 @@ def bench_ensemble(args, prec, dev):
 def _finite(v):
     """JSON has no NaN or infinity: report those as null."""
     return v if isinstance(v, float) and math.isfinite(v) else None
+
+
+def wave_balance(ts):
+    """Balance of the persistent walk's waves in the last timed walk: each
+    wave's busy span (start to end), their mean and maximum, and how long
+    the last wave runs past the mean end, against the walk's span."""
+    import numpy as np
+    t = ts.wave_clock()
+    busy = t[:, 1] - t[:, 0]
+    span = float(t[:, 1].max() - t[:, 0].min())
+    return {"waves": int(t.shape[0]), "busy_mean_us": float(busy.mean()),
+            "busy_max_us": float(busy.max()), "busy_max_over_mean": float(busy.max() / busy.mean()),
+            "span_us": span, "last_end_past_mean_end_us": float(t[:, 1].max() - t[:, 1].mean()),
+            "start_spread_us": float(np.ptp(t[:, 0]))}
 
 
 def per_particle_rel(f, ref):
@@ -219,7 +252,30 @@ def bench_accuracy_target(args, prec, x, v, q, m, n, eps, dt, tg, fd, target=1e-
             rows.append(row)
     ok = [r for r in rows if "ms_per_step" in r]
     best = min(ok, key=lambda r: r["ms_per_step"]) if ok else None
-    return {"target_rel_rms_vs_direct": target, "cheapest": best,
+    # the same with a margin: an error at most 3/4 of the target, which other
+    # samples and states of the cloud keep below it
+    okm = [r for r in ok if r["rel_force_err_vs_direct_sampled"] <= 0.75 * target]
+    robust = min(okm, key=lambda r: r["ms_per_step"]) if okm else None
+    # the plain FP64 walk at those settings: the split's speedup at equal
+    # force accuracy (the two differ by ~1e-6, far below the tree's error)
+    for r in (best, robust):
+        if r is None or "fp64_walk_ms" in r:
+            continue
+        tt = TreeSolver(n, curve=CURVE, theta=r["theta"], eps=eps, precision=L.UCP_FP64,
+                        group_size=args.group_size, list_len=args.list_len, group_mode=gm,
+                        leaf_cap=r["leaf_cap"], walk_waves=args.walk_waves)
+        tt.tree_forces(x, q)
+        tt.timing(True)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            tt.tree_forces(x, q)
+        torch.cuda.synchronize()
+        wm, wc = tt.timing_read()
+        tt.stats()
+        tt.close()
+        r["fp64_walk_ms"] = wm / max(wc, 1)
+        r["split_speedup_walk"] = r["fp64_walk_ms"] / r["walk_ms"]
+    return {"target_rel_rms_vs_direct": target, "cheapest": best, "cheapest_with_margin": robust,
             "candidates": [{k: (round(v, 6) if isinstance(v, float) else v) for k, v in r.items()}
                            for r in rows]}
 
@@ -743,6 +799,7 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     walk_ms, walk_launches = ts.timing_read()
+    balance = wave_balance(ts)
     ts.timing(False)
     st = ts.stats()
     graph = None
@@ -806,6 +863,7 @@ def main():
         "interactions_per_s": inter / (walk_avg_ms * 1e-3),
         "interactions_per_particle": inter / n,
         "walk_ms": walk_avg_ms,
+        "walk_wave_balance": balance,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak,
                      "traffic": traffic_from_profile(args.precision)},

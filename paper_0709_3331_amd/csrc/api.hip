@@ -137,7 +137,7 @@ void free_all(Ctx *c)
                     c->d_ngeo, c->d_ninfo,  c->d_npar,  c->d_mom64,  c->d_nrec,
                     c->d_groups, c->d_gstat, c->d_acc,  c->d_ctr,    c->d_flags,  c->d_epart,
                     c->d_leafof, c->d_w,    c->d_xsrc,  c->d_cbar,  c->d_lobar, c->d_lomin, c->d_wq,
-                    c->d_ghist,  c->d_sortctl, c->d_nlev, c->d_uplist, c->d_spec};
+                    c->d_ghist,  c->d_sortctl, c->d_nlev, c->d_uplist, c->d_spec, c->d_wclock};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     drop_graph(c);
@@ -332,6 +332,7 @@ ucp_status ucp_create(ucp_ctx **out, int64_t n_max, int32_t clouds_max, const uc
     ALLOC(c->d_wq, ucp::kWalkQueues * ucp::kQStride);
     ALLOC(c->d_flags, 4);
     ALLOC(c->d_epart, 4 * 256);
+    ALLOC(c->d_wclock, 2 * ((size_t)std::max(c->num_cu, 1) * 64 + 4));
 #undef ALLOC
     // set-up of this device's static adjoint scratch (ucp_force_vjp_noalloc)
     void *scratch_dev = nullptr;
@@ -626,6 +627,7 @@ ucp_status ucp_debug_copy(ucp_ctx *c, int32_t which, void *dst, int64_t bytes, v
     case 5: src = c->d_groups; need = 16 * (int64_t)groups; break;
     case 6: src = c->d_gstat; need = 8 * (int64_t)groups; break;
     case 7: src = c->d_cube; need = 32 * (int64_t)c->clouds; break;
+    case 8: src = c->d_wclock; need = 16 * c->wclock_waves; break;
     default: return fail(c, UCP_EINVAL, "ucp_debug_copy: unknown array");
     }
     if (bytes < need) return fail(c, UCP_EINVAL, "ucp_debug_copy: buffer too small, need " + std::to_string(need));

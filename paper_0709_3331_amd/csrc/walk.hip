@@ -77,6 +77,7 @@ struct WalkArgs {
     const double *spec;     // per-species pseudo-particles (UCP_EXPANSION_SPECIES)
     double theta;
     int L;
+    unsigned long long *wclock;   // or null: each wave's start and end (real-time counter)
 };
 
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -753,6 +754,9 @@ __device__ __forceinline__ void walk_body(const WalkArgs &a)
     // atomic, only lane 0 adds 1, so lane 0 receives the value before its own
     // increment.  Queue heads only grow, so each wave passes each exhausted
     // queue once and the loop ends.
+    // the wave's own busy span, for the balance of the persistent waves
+    const int64_t wid = 4 * (int64_t)blockIdx.x + wave;
+    if (a.wclock && lane == 0) a.wclock[2 * wid] = __builtin_amdgcn_s_memrealtime();
     int qx = (int)(blockIdx.x % kWalkQueues), exhausted = 0;
     for (;;) {
         const unsigned long long old =
@@ -1014,6 +1018,7 @@ __device__ __forceinline__ void walk_body(const WalkArgs &a)
         atomicAdd(&a.ctr[CTR_M2P],
                   lane == 0 ? (unsigned long long)c * (unsigned long long)tot_m : zero);
     }
+    if (a.wclock && lane == 0) a.wclock[2 * wid + 1] = __builtin_amdgcn_s_memrealtime();
 }
 
 template <int PREC, int MODE, bool KELBG, bool SPEC>
@@ -1247,6 +1252,7 @@ static WalkArgs walk_args(Ctx *c)
     wa.spec = c->d_spec;
     wa.theta = c->p_built.theta;
     wa.L = c->p_built.list_len;
+    wa.wclock = nullptr;
     return wa;
 }
 
@@ -1272,6 +1278,10 @@ void launch_forces(Ctx *c, double *f, double *phi, hipStream_t s)
         e1 = c->ev[2 * c->ev_used + 1];
         c->ev_used++;
         (void)hipEventRecord(e0, s);
+        // every wave stamps its start and end (the launch shape of launch_walk_t)
+        const int wpc = c->p_built.walk_waves > 0 ? c->p_built.walk_waves : 32;
+        wa.wclock = c->d_wclock;
+        c->wclock_waves = 4 * (int64_t)((c->num_cu * wpc + 3) / 4);
     }
     const bool want_phi = phi != nullptr || f == nullptr;
     const bool kelbg = c->p_built.pair_law == UCP_PAIR_KELBG;

@@ -110,6 +110,17 @@ class TreeSolver:
     def timing_read(self):
         return L.ucp_timing_read(self.h)
 
+    def wave_clock(self):
+        """Start and end (microseconds, from the first start) of every wave of
+        the last force walk launched with timing on: array [waves, 2]."""
+        cu = torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count
+        w = self.params.walk_waves if self.params.walk_waves > 0 else 32
+        waves = 4 * ((cu * w + 3) // 4)
+        out = np.zeros((waves, 2), dtype=np.uint64)
+        L.ucp_debug_copy(self.h, 8, out.ctypes.data_as(C.c_void_p), out.nbytes, _stream())
+        t = out.astype(np.float64) / 100.0   # 100 MHz real-time counter
+        return t - t[:, 0].min()
+
     # -- introspection (host numpy arrays)
     def debug(self, which):
         st = self.stats(raise_on_flag=False)

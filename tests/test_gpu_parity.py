@@ -387,3 +387,23 @@ def test_full_size_metric_cloud(gm, G):
     assert ef < TOL_SPLIT
     assert ratio <= 1.0
     ts.close()
+
+
+def test_wave_clocks_of_a_timed_walk():
+    # with timing on, every wave of the persistent walk stamps its start and
+    # end; they lie inside the walk's own HIP-event span
+    cl = inputs.gaussian_cloud(20000, 1.0, 1e-3, 1e-5, 31)
+    x, q = torch.from_numpy(cl.x).cuda(), torch.from_numpy(cl.q).cuda()
+    ts = TreeSolver(cl.n, theta=0.5, eps=0.01)
+    ts.build(x, q)
+    ts.timing(True)
+    ts.forces(cl.n)
+    ms, launches = ts.timing_read()
+    t = ts.wave_clock()
+    ts.timing(False)
+    ts.stats()
+    ts.close()
+    say(f"[clock] waves={t.shape[0]} span {t[:, 1].max():.1f} us, event {1e3 * ms:.1f} us")
+    assert launches == 1
+    assert t.shape[0] % 4 == 0 and np.all(t[:, 1] >= t[:, 0]) and t[:, 0].min() == 0.0
+    assert t[:, 1].max() <= 1e3 * ms + 20.0
