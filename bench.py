@@ -168,17 +168,22 @@ def _finite(v):
 
 
 def wave_balance(ts):
-    """Balance of the persistent walk's waves in the last timed walk: each
-    wave's busy span (start to end), their mean and maximum, and how long
-    the last wave runs past the mean end, against the walk's span."""
+    """Balance of the persistent walk in the last timed walk, from every
+    wave's start and end.  More waves are launched than can be resident, so
+    the waves that start with the launch take the groups and the rest start
+    as those end, find the queues empty and stop.  Reported: the span of the
+    walk, how many waves started with the launch, the spread of their end
+    times, and the share of their wave-time spent idle after their own end
+    (the tail of the walk)."""
     import numpy as np
     t = ts.wave_clock()
-    busy = t[:, 1] - t[:, 0]
-    span = float(t[:, 1].max() - t[:, 0].min())
-    return {"waves": int(t.shape[0]), "busy_mean_us": float(busy.mean()),
-            "busy_max_us": float(busy.max()), "busy_max_over_mean": float(busy.max() / busy.mean()),
-            "span_us": span, "last_end_past_mean_end_us": float(t[:, 1].max() - t[:, 1].mean()),
-            "start_spread_us": float(np.ptp(t[:, 0]))}
+    span = float(t[:, 1].max())
+    first = t[:, 0] <= 0.02 * span
+    ends = t[first, 1]
+    return {"waves": int(t.shape[0]), "waves_at_launch": int(first.sum()), "span_us": span,
+            "launch_wave_end_us": {"min": float(ends.min()), "p10": float(np.quantile(ends, 0.1)),
+                                   "median": float(np.median(ends)), "max": float(ends.max())},
+            "launch_wave_idle_share": float(np.mean(span - ends) / span)}
 
 
 def per_particle_rel(f, ref):
