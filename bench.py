@@ -763,11 +763,12 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     dev = torch.device("cuda:0")
+    command = "python bench.py " + " ".join(sys.argv[1:])
     if args.study == "opening":
-        print(json.dumps(opening_study(dev, args.study_dt)), flush=True)
+        print(json.dumps({"command": command, **opening_study(dev, args.study_dt)}), flush=True)
         return
     if args.study == "relaxation":
-        print(json.dumps(relaxation_study(dev)), flush=True)
+        print(json.dumps({"command": command, **relaxation_study(dev)}), flush=True)
         return
     cl, prm = inputs.metric(0) if args.workload == "metric" else inputs.large(0)
     n = cl.n
