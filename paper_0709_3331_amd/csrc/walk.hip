@@ -754,9 +754,6 @@ __device__ __forceinline__ void walk_body(const WalkArgs &a)
     // atomic, only lane 0 adds 1, so lane 0 receives the value before its own
     // increment.  Queue heads only grow, so each wave passes each exhausted
     // queue once and the loop ends.
-    // the wave's own busy span, for the balance of the persistent waves
-    const int64_t wid = 4 * (int64_t)blockIdx.x + wave;
-    if (a.wclock && lane == 0) a.wclock[2 * wid] = __builtin_amdgcn_s_memrealtime();
     int qx = (int)(blockIdx.x % kWalkQueues), exhausted = 0;
     for (;;) {
         const unsigned long long old =
@@ -1018,13 +1015,23 @@ __device__ __forceinline__ void walk_body(const WalkArgs &a)
         atomicAdd(&a.ctr[CTR_M2P],
                   lane == 0 ? (unsigned long long)c * (unsigned long long)tot_m : zero);
     }
-    if (a.wclock && lane == 0) a.wclock[2 * wid + 1] = __builtin_amdgcn_s_memrealtime();
+}
+
+// each wave's own busy span (start, end), for the balance of the persistent
+// waves, when the launch asks for it
+__device__ __forceinline__ void wave_stamp(unsigned long long *wclock, int end)
+{
+    if (wclock && (threadIdx.x & 63) == 0)
+        wclock[2 * (4 * (int64_t)blockIdx.x + (threadIdx.x >> 6)) + end] =
+            __builtin_amdgcn_s_memrealtime();
 }
 
 template <int PREC, int MODE, bool KELBG, bool SPEC>
 __global__ __launch_bounds__(256) void k_walk(WalkArgs a)
 {
+    wave_stamp(a.wclock, 0);
     walk_body<PREC, MODE, KELBG, SPEC>(a);
+    wave_stamp(a.wclock, 1);
 }
 
 // The split-precision force walks under the Plummer law with the quadrupole
@@ -1034,7 +1041,9 @@ template <int MODE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_walk_w4(
     WalkArgs a)
 {
+    wave_stamp(a.wclock, 0);
     walk_body<UCP_SPLIT, MODE, false, false>(a);
+    wave_stamp(a.wclock, 1);
 }
 
 __global__ void k_walk_reset(unsigned long long *ctr, unsigned long long *wq)
