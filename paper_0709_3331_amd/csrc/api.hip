@@ -137,7 +137,7 @@ void free_all(Ctx *c)
                     c->d_ngeo, c->d_ninfo,  c->d_npar,  c->d_mom64,  c->d_nrec,
                     c->d_groups, c->d_gstat, c->d_acc,  c->d_ctr,    c->d_flags,  c->d_epart,
                     c->d_leafof, c->d_w,    c->d_xsrc,  c->d_cbar,  c->d_lobar, c->d_lomin, c->d_wq,
-                    c->d_ghist,  c->d_sortctl, c->d_nlev, c->d_uplist, c->d_spec, c->d_wclock};
+                    c->d_ghist,  c->d_sortctl, c->d_nlev, c->d_uplist, c->d_ctab, c->d_spec, c->d_wclock};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     drop_graph(c);
@@ -321,6 +321,7 @@ ucp_status ucp_create(ucp_ctx **out, int64_t n_max, int32_t clouds_max, const uc
     ALLOC(c->d_npar, NC);
     ALLOC(c->d_nlev, NC + 128);
     ALLOC(c->d_uplist, NC);
+    ALLOC(c->d_ctab, 8 * NC);
     if (p->expansion == UCP_EXPANSION_SPECIES) ALLOC(c->d_spec, ucp::kSpecVals * NC);
     ALLOC(c->d_mom64, 16 * NC);
     ALLOC(c->d_nrec, 8 * NC);

@@ -895,8 +895,8 @@ __global__ __launch_bounds__(kLvlTile) void k_levels(const uint64_t *__restrict_
 //    centre, side^2, first particle, level and leaf flag); the box's integer
 //    coordinates are those of particle p, quantised again exactly as the keys
 //    were, so no key is decoded and either curve works.  The particle count,
-//    the skip link and the parent are found by the moments pass below, which
-//    visits each node's children in order anyway.
+//    the skip link and the parent of an internal node are found by the
+//    moments pass below.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_nodes(
     const double4 *__restrict__ xq, int64_t n, const int64_t *__restrict__ off, int clouds,
@@ -950,11 +950,12 @@ __global__ __launch_bounds__(256) void k_nodes(
 // 6. moments about the box centre: the node (p, l) exists iff
 //    L(p) < l <= leaf(p).  A leaf holds the positions p .. t-1 with t the
 //    first later position whose L(t) < l (L is -1 at every cloud edge and at
-//    n); it sums its particles.  An internal node sums its children's moments
-//    with the exact shift of origin, so the internal levels are done from the
-//    deepest up.  Each node records its count and its skip link (noff[t] for a
-//    leaf, that of its last child otherwise); internal nodes also record each
-//    child's parent.
+//    n); it sums its particles (6a).  The range and children of an internal
+//    node follow from the levels alone; a node of up to direct_max particles
+//    sums its particles too (6b), a larger one sums its children's moments
+//    with the exact shift of origin, from the deepest up (6c).
+//    Every node records its count and its skip link noff[t]; every node but
+//    a root records its parent.
 //    Record per node, FP64 (16 doubles): cx cy cz Q px py pz trS Sxx Syy Szz
 //    Sxy Sxz Syz 0 0; FP32 copy in the second line of the walk record:
 //    Q px py pz, 1.5 trS 3Sxx 3Syy 3Szz, 3Sxy 3Sxz 3Syz 0.
@@ -1008,17 +1009,7 @@ __device__ __forceinline__ void spec_store(double *spec, int k, const double4 &g
     r[11] = 0.0;
 }
 
-// a child's pseudo-particles added to its parent's accumulators
-__device__ __forceinline__ void spec_add_child(double *sq, const double *spec, int ch,
-                                               const double4 &g)
-{
-    const double *r = spec + kSpecVals * (int64_t)ch;
-    const double4 a = *(const double4 *)r, b = *(const double4 *)(r + 4);
-    spec_add(sq, a.w, a.x - g.x, a.y - g.y, a.z - g.z);
-    spec_add(sq, b.w, b.x - g.x, b.y - g.y, b.z - g.z);
-}
-
-// The leaf starting at position p, if there is one (every level at once: a
+// 6a. The leaf starting at position p, if there is one (every level at once: a
 // leaf depends on nothing but its particles).  Its end was found by the level
 // pass, or is -1 for a max-depth leaf wider than that pass's window.
 constexpr int kLeafThreads = 256, kP2MBatch = 4;
@@ -1073,36 +1064,6 @@ __global__ __launch_bounds__(kLeafThreads) void k_leaf_moments(
     store_moments(mom64, nrec, k, g, m);
 }
 
-// one child's moments shifted from its centre to the parent's centre g and
-// added: p' = p + Q d, S' = S + p d^T + d p^T + Q d d^T with d = c_child - g
-// (each component +-qd)
-__device__ __forceinline__ void add_child(double *m, const double4 &g, double qd,
-                                          const double4 &cg, const double *c)
-{
-    const double d0 = cg.x > g.x ? qd : -qd;
-    const double d1 = cg.y > g.y ? qd : -qd;
-    const double d2 = cg.z > g.z ? qd : -qd;
-    const double Q = c[0], p0 = c[1], p1 = c[2], p2 = c[3];
-    m[0] += Q;
-    m[1] += p0 + Q * d0;
-    m[2] += p1 + Q * d1;
-    m[3] += p2 + Q * d2;
-    m[4] += c[5] + 2.0 * p0 * d0 + Q * d0 * d0;
-    m[5] += c[6] + 2.0 * p1 * d1 + Q * d1 * d1;
-    m[6] += c[7] + 2.0 * p2 * d2 + Q * d2 * d2;
-    m[7] += c[8] + p0 * d1 + d0 * p1 + Q * d0 * d1;
-    m[8] += c[9] + p0 * d2 + d0 * p2 + Q * d0 * d2;
-    m[9] += c[10] + p1 * d2 + d1 * p2 + Q * d1 * d2;
-}
-
-// Q p S of node ch (the FP64 record holds cx cy cz Q px py pz trS S[6])
-__device__ __forceinline__ void load_child(const double *mom64, int ch, double *c)
-{
-    const double *r = mom64 + 16 * (int64_t)ch + 3;
-#pragma unroll
-    for (int i = 0; i < 11; ++i) c[i] = r[i];
-}
-
 // High bit of each byte of x set where that byte (taken mod 128) is < v,
 // for 0 < v <= 127; the bias 0x80 per byte keeps borrows inside each byte.
 __device__ __forceinline__ uint32_t bytes_below(uint32_t x, uint32_t v)
@@ -1115,190 +1076,292 @@ __device__ __forceinline__ uint32_t gather4(uint32_t m)
     return ((m >> 7) & 1u) | ((m >> 14) & 2u) | ((m >> 21) & 4u) | ((m >> 28) & 8u);
 }
 
-// Direct children of internal node k (level l) from the level bytes of the
-// kWin nodes after it: in preorder they are the nodes of level l + 1 before
-// the first node of level <= l (or nn).  On return bit i of *cm marks node
-// k + 1 + i as a child and *end is the offset of that first node; false if
-// the subtree runs past the window.
-constexpr int kWin = 64;
-__device__ __forceinline__ bool children_in_window(int k, int level, int nn,
-                                                   const uint8_t *__restrict__ nlev,
-                                                   uint64_t *cm, int *end)
+// ---------------------------------------------------------------------------
+// 6b. internal nodes, each by one wave.  The node (p, l) holds the positions
+//     p .. t-1, t the first later position with L(t) < l (L is -1 at every
+//     cloud edge and at n).  Its children are the nodes of level l + 1 that
+//     start at p (node k + 1) and at each position s in (p, t) with L(s) = l
+//     (node noff[s], the first node there).  The wave reads the level bytes
+//     of the next 1024 positions, 16 per lane; for a node that runs past
+//     them, eight 8-ary searches over the sorted keys, eight lanes each, find
+//     its end (the first key whose level-l prefix exceeds the node's prefix
+//     P) and the start of each child octant o (the first key whose
+//     level-(l + 1) prefix is at least 8 P + o).  It writes the count, the
+//     skip link noff[t] (the node after the subtree in preorder), the walk
+//     record's header, the children in order (-1 after the last) and each
+//     child's parent.  A node of at most direct_max particles then sums its
+//     particles' moments about its centre, lane j taking particles p + j,
+//     p + j + 64, ..., and the lanes' sums are added in a fixed order; a
+//     larger node is listed for 6c.
+// ---------------------------------------------------------------------------
+constexpr int kNodeThreads = 256, kNodeSpan = 16, kRangeWin = 16 * kWave;
+// the largest node summed from its particles, for trees below and from
+// kUpperWide particles on (measured from 256 to 2048 on 524,288 and
+// 4,194,304 particles: 1024 and 2048 within a microsecond on the first,
+// 1024 the faster on the second)
+constexpr int kDirectMax = 1024, kDirectMaxWide = 1024;
+constexpr int kDirectFirst = 4;   // particles per lane read with the level window
+
+// v moved across lanes by the DPP control `ctrl` (rows outside row_mask read
+// 0), each 32-bit half alike
+template <int ctrl, int row_mask>
+__device__ __forceinline__ double dpp_d(double v)
 {
-    const int base = (k + 1) & ~15, off = k + 1 - base;
-    const uint4 *w4 = (const uint4 *)(nlev + base);
-    // 80 bytes from base: flags of "level == l + 1" and "level <= l", one bit
-    // per byte
-    uint64_t clo = 0, slo = 0;
-    uint32_t chi = 0, shi = 0;
-#pragma unroll
-    for (int i = 0; i < 5; ++i) {
-        const uint4 v = w4[i];
-        const uint32_t d[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const uint32_t le = bytes_below(d[q], (uint32_t)level + 1);
-            const uint32_t eq = bytes_below(d[q], (uint32_t)level + 2) & ~le;
-            const int sh = 4 * (4 * i + q);   // bit position of this dword's first byte
-            if (sh < 64) {
-                clo |= (uint64_t)gather4(eq) << sh;
-                slo |= (uint64_t)gather4(le) << sh;
-            } else {
-                chi |= gather4(eq) << (sh - 64);
-                shi |= gather4(le) << (sh - 64);
-            }
-        }
-    }
-    // shift to offsets 0 .. 63 after k
-    uint64_t child = (clo >> off) | (off ? (uint64_t)chi << (64 - off) : 0ull);
-    uint64_t stop = (slo >> off) | (off ? (uint64_t)shi << (64 - off) : 0ull);
-    // nodes past nn end the subtree
-    const int room = nn - (k + 1);   // >= 0
-    if (room < kWin) stop |= ~0ull << room;
-    if (stop == 0) return false;
-    const int e = __builtin_ctzll(stop);
-    *end = e;
-    *cm = child & ((1ull << e) - 1);
-    return true;
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, ctrl, row_mask, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), ctrl, row_mask, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// the internal node k of `level`, first position p: its children's moments
-// shifted to its centre, summed in key order (preorder).  The children are
-// read from the level bytes when the subtree is short, else by following the
-// skip links from k + 1.
-template <int BATCH>
-__device__ __forceinline__ void moments_internal(
-    int k, int64_t p, int64_t n, int level, int nn, const uint8_t *__restrict__ nlev,
-    const double4 *__restrict__ ngeo, int4 *ninfo, int32_t *npar, double *mom64, float4 *nrec,
-    double *spec, int32_t *flags)
+// the sum of v over the wave, in lane 63, added in a fixed order: within
+// each row of 16 lanes by swaps of lane pairs and quads and rotations by 4
+// and 8 (every lane then holds its row's sum), then row 0 into row 1 and
+// row 2 into row 3 (lane 15 and 47 broadcast), then rows 0-1 into rows 2-3
+// (lane 31 broadcast).  All lanes must be active.
+__device__ __forceinline__ double wave_dsum(double v)
 {
-    const double4 g = ngeo[k];
-    double m[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    double sq[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    const double qd = 0.25 * sqrt(g.w);   // |child centre - parent centre| per axis
-    int64_t t;
-    int skip;
-    uint64_t cm;
-    int end;
-    if (children_in_window(k, level, nn, nlev, &cm, &end)) {
-        // BATCH children per round of loads
-        bool bad = (cm & 1ull) == 0;   // the first child is k + 1
-        while (cm != 0 && !bad) {
-            int c[BATCH];
-#pragma unroll
-            for (int u = 0; u < BATCH; ++u) {
-                c[u] = cm != 0 ? k + 1 + __builtin_ctzll(cm) : -1;
-                if (cm != 0) cm &= cm - 1;
-            }
-            int4 ic[BATCH];
-            double4 gc[BATCH];
-            double rc[BATCH][11];
-#pragma unroll
-            for (int u = 0; u < BATCH; ++u) {
-                const int cu = c[u] >= 0 ? c[u] : c[0];
-                ic[u] = ninfo[cu];
-                gc[u] = ngeo[cu];
-                load_child(mom64, cu, rc[u]);
-            }
-#pragma unroll
-            for (int u = 0; u < BATCH; ++u) {
-                if (c[u] < 0) break;
-                bad = bad || ic[u].y < 1;
-                add_child(m, g, qd, gc[u], rc[u]);
-                if (spec) spec_add_child(sq, spec, c[u], g);
-                npar[c[u]] = k;
-                t = (int64_t)ic[u].x + ic[u].y;
-                skip = ic[u].z;
-            }
-        }
-    } else {
-        int ch = k + 1;
-        int4 ci = ch < nn ? ninfo[ch] : make_int4(0, 0, 0, 0);
-        for (int j = 0;; ++j) {
-            if (j == 8 || ci.y < 1 || ci.z <= ch || (ci.w & 255) != level + 1) {
-                atomicOr(flags, UCP_FLAG_INTERNAL);   // inconsistent records: stop
-                return;
-            }
-            npar[ch] = k;
-            t = (int64_t)ci.x + ci.y;
-            skip = ci.z;
-            // the next candidate sibling's record, loaded with this child's
-            const int4 si = skip < nn ? ninfo[skip] : make_int4(0, 0, 0, 0);
-            double r[11];
-            load_child(mom64, ch, r);
-            add_child(m, g, qd, ngeo[ch], r);
-            if (spec) spec_add_child(sq, spec, ch, g);
-            if (skip >= nn || (si.w & 255) != level + 1) break;   // no further sibling
-            ch = skip;
-            ci = si;
-        }
-    }
-    // the first particle is checked only here, so that its record, the
-    // node's centre and the level bytes are loaded in one round
-    if (p < 0 || p >= n) {
-        atomicOr(flags, UCP_FLAG_INTERNAL);
-        return;
-    }
-    if (spec) spec_store(spec, k, g, sq);
-    const int cnt = (int)(t - p), info = level;
-    ninfo[k] = make_int4((int)p, cnt, skip, info);
-    *(double4 *)(nrec + 8 * (int64_t)k) = g;
-    *(int4 *)(nrec + 8 * (int64_t)k + 2) = make_int4(skip, (int)p, cnt, info);
-    store_moments(mom64, nrec, k, g, m);
+    v += dpp_d<0xB1, 0xf>(v);    // quad_perm [1, 0, 3, 2]
+    v += dpp_d<0x4E, 0xf>(v);    // quad_perm [2, 3, 0, 1]
+    v += dpp_d<0x124, 0xf>(v);   // row_ror 4
+    v += dpp_d<0x128, 0xf>(v);   // row_ror 8
+    v += dpp_d<0x142, 0xa>(v);   // row_bcast 15 into rows 1 and 3
+    v += dpp_d<0x143, 0xc>(v);   // row_bcast 31 into rows 2 and 3
+    return v;
 }
 
-// Internal nodes by level.  nlev[k] is the level of node k, with kLeafBit
-// set for a leaf; a pass over level l takes the nodes whose byte equals l.
-// The nodes of one level are spread over the whole preorder.
-template <int BATCH>
-__device__ __forceinline__ void internal_node(
-    int k, int level, int64_t n, int nn, const uint8_t *__restrict__ nlev,
-    const double4 *__restrict__ ngeo, int4 *ninfo, int32_t *npar, double *mom64, float4 *nrec,
-    double *spec, int32_t *flags)
+// one particle's terms about the centre g: Q, p, S (m) and, by sign, Q and
+// the first moment (sq)
+__device__ __forceinline__ void moment_terms(const double4 &a, const double4 &g, double *m,
+                                             double *sq, bool with_spec)
 {
-    moments_internal<BATCH>(k, ninfo[k].x, n, level, nn, nlev, ngeo, ninfo, npar, mom64, nrec,
-                            spec, flags);
+    const double r0 = a.x - g.x, r1 = a.y - g.y, r2 = a.z - g.z, qq = a.w;
+    m[0] += qq;
+    m[1] += qq * r0;
+    m[2] += qq * r1;
+    m[3] += qq * r2;
+    m[4] += qq * r0 * r0;
+    m[5] += qq * r1 * r1;
+    m[6] += qq * r2 * r2;
+    m[7] += qq * r0 * r1;
+    m[8] += qq * r0 * r2;
+    m[9] += qq * r1 * r2;
+    if (with_spec) {
+        const double qp = qq > 0.0 ? qq : 0.0, qm = qq < 0.0 ? qq : 0.0;
+        sq[0] += qp;
+        sq[1] += qp * r0;
+        sq[2] += qp * r1;
+        sq[3] += qp * r2;
+        sq[4] += qm;
+        sq[5] += qm * r0;
+        sq[6] += qm * r1;
+        sq[7] += qm * r2;
+    }
 }
 
-// Internal level maxl - 1 - j, with maxl the deepest leaf level: the
-// deepest internal levels hold most internal nodes, and each node reads its
-// children's records with loads that no two lanes share, so each of them
-// takes a launch over the whole chip, one node per thread.  The first of
-// these passes (j = 0) also lists the internal nodes of the levels above
-// them (in any order; each is computed alone), so that the pass over those
-// levels reads only them.
-constexpr int kDeepThreads = 256, kDeepLevels = 4;
-__global__ __launch_bounds__(kDeepThreads) void k_moments_level(
-    int j, int64_t n, const int32_t *__restrict__ noff, const uint8_t *__restrict__ nlev,
-    const double4 *__restrict__ ngeo, int4 *ninfo, int32_t *npar, double *mom64, float4 *nrec,
-    double *spec, unsigned long long *ctr, int32_t *uplist, int32_t *flags)
+template <bool SPEC>
+__global__ __launch_bounds__(kNodeThreads) void k_node_moments(
+    const uint64_t *__restrict__ key, const int8_t *__restrict__ Lv,
+    const double4 *__restrict__ xq, int64_t n, const int64_t *__restrict__ off, int clouds, int b,
+    const int32_t *__restrict__ noff, const uint8_t *__restrict__ nlev,
+    const double4 *__restrict__ ngeo, int4 *ninfo, float4 *nrec, double *mom64, int32_t *npar,
+    int32_t *ctab, int32_t *uplist, double *spec, unsigned long long *ctr, int direct_max,
+    int32_t *flags)
 {
     if (*flags) return;
-    const int l = (int)ctr[CTR_MAXLEVEL] - 1 - j;
-    if (l < 0) return;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t wave = (blockIdx.x * (int64_t)kNodeThreads + threadIdx.x) / kWave;
+    const int64_t nwaves = (int64_t)gridDim.x * (kNodeThreads / kWave);
     const int nn = noff[n];
-    const int lup = l - kDeepLevels;   // the upper levels are 0 .. lup (j = 0)
-    const int lane = threadIdx.x & 63;
-    for (int64_t k = blockIdx.x * (int64_t)kDeepThreads + threadIdx.x; k < nn;
-         k += (int64_t)gridDim.x * kDeepThreads) {
-        const int lv = (int)nlev[k];
-        if (j == 0) {
-            // lv < kLeafBit: internal; one atomic per wave reserves the slots
-            const bool up = lv <= lup;
-            const unsigned long long bm = __ballot(up);
-            if (bm != 0ull) {
-                const int leader = __builtin_ctzll(bm);
-                unsigned long long base = 0;
-                if (lane == leader) base = atomicAdd(&ctr[CTR_UPCOUNT], (unsigned long long)__popcll(bm));
-                base = __shfl(base, leader);
-                if (up) {
-                    const unsigned long long below = bm & (lane == 0 ? 0ull : (~0ull >> (64 - lane)));
-                    uplist[base + __popcll(below)] = (int)k;
+    constexpr bool with_spec = SPEC;
+    // wave w takes kNodeSpan consecutive node slots at a time (the nodes of a
+    // chain that start at one position, a node and its first child, read the
+    // same particles); each lane reads its slot's first position, level and
+    // centre
+    for (int64_t s0 = wave * kNodeSpan; s0 < nn; s0 += kNodeSpan * nwaves) {
+        const int64_t kl = lane < kNodeSpan ? s0 + lane : nn;
+        // the three reads are issued together (a leaf's record is not used)
+        const int64_t kr = kl < nn ? kl : 0;
+        const uint8_t lv = nlev[kr];
+        const int4 infl = ninfo[kr];
+        const double4 gl = ngeo[kr];
+        const bool inner = kl < nn && !(lv & kLeafBit);
+        unsigned long long im = __ballot(inner);
+        while (im != 0ull) {
+            const int src = __builtin_ctzll(im);
+            im &= im - 1ull;
+            const int k = (int)(s0 + src);
+            const int64_t p = __shfl(infl.x, src);
+            const int iw = __shfl(infl.w, src);
+            const int l = iw & 255;
+            const double4 g = make_double4(__shfl(gl.x, src), __shfl(gl.y, src),
+                                           __shfl(gl.z, src), __shfl(gl.w, src));
+            if (p < 0 || p >= n || (iw & 256) || l >= b || k + 1 >= nn) {
+                if (lane == 0) atomicOr(flags, UCP_FLAG_INTERNAL);
+                continue;
+            }
+            // the node's first particles, read with the level window
+            double4 xa[kDirectFirst];
+#pragma unroll
+            for (int u = 0; u < kDirectFirst; ++u) {
+                const int64_t q = p + lane + u * kWave;
+                xa[u] = xq[q < n ? q : p];
+            }
+            // level bytes of positions base .. base + 1023 (base: p + 1
+            // rounded down to 16), flagged where the node ends (L < l, or a
+            // cloud edge) or a child starts (L == l), over p + 1 .. n only
+            const int64_t base = (p + 1) & ~(int64_t)15;
+            const int64_t q0 = base + 16 * lane;
+            uint32_t endm = 0, eqm = 0;
+            if (q0 <= n) {
+                const uint4 v = *(const uint4 *)(Lv + q0);
+                const uint32_t d[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int w = 0; w < 4; ++w) {
+                    const uint32_t lt = bytes_below(d[w], (uint32_t)l) | (d[w] & 0x80808080u);
+                    const uint32_t eq = bytes_below(d[w], (uint32_t)l + 1) & ~lt;
+                    endm |= gather4(lt) << (4 * w);
+                    eqm |= gather4(eq) << (4 * w);
+                }
+                const int lo = (int)max<int64_t>(0, p + 1 - q0);
+                const int hi = (int)min<int64_t>(16, n + 1 - q0);
+                const uint32_t valid = ((1u << hi) - 1u) & ~((1u << lo) - 1u);
+                endm &= valid;
+                eqm &= valid;
+            }
+            const unsigned long long hasend = __ballot(endm != 0);
+            int64_t t = -1;
+            if (hasend != 0ull) {
+                const int f = __builtin_ctzll(hasend);
+                t = base + 16 * f + __builtin_ctz((uint32_t)__shfl((int)endm, f));
+            }
+            int nch;
+            if (t >= 0) {
+                // the child starts are the flagged positions before t
+                uint32_t cm = eqm;
+                const int64_t lim = t - q0;
+                if (lim <= 0) cm = 0;
+                else if (lim < 16) cm &= (1u << lim) - 1u;
+                const int c = __popc(cm);
+                const int incl = wave_incl_scan(c);
+                nch = 1 + __shfl(incl, kWave - 1);
+                int j = 1 + incl - c;
+                while (cm != 0u) {
+                    const int s = noff[q0 + __builtin_ctz(cm)];
+                    cm &= cm - 1u;
+                    if (j < 8) ctab[8 * (int64_t)k + j] = s;
+                    npar[s] = k;
+                    ++j;
+                }
+                if (lane == 0) {
+                    ctab[8 * (int64_t)k] = k + 1;
+                    npar[k + 1] = k;
+                }
+            } else {
+                // group g of eight lanes finds, over [p + 1, ce), the first
+                // key past the node (g = 0) or the start of octant g (g >= 1);
+                // the predicate is false then true along the sorted keys.
+                // Each round probes 7 points splitting [a, e) into 8 parts, or
+                // every point of a part of at most 8.
+                const int64_t ce = off[cloud_of(off, clouds, p) + 1];
+                const int g8 = lane >> 3, jj = lane & 7;
+                const int sh = 3 * (b - l), sh1 = sh - 3;
+                const uint64_t kp = key[p];
+                const uint64_t P = kp >> sh, Po = (P << 3) | (uint64_t)g8;
+                int64_t a = p + 1, e = ce;
+                bool done = false;
+                for (int it = 0; it < 64; ++it) {
+                    const int64_t m = e - a;
+                    const bool small = m <= 8;
+                    const bool probe = !done && (small ? jj < m : jj < 7);
+                    const int64_t q = small ? a + jj : a + ((m * (jj + 1)) >> 3);
+                    bool pr = false;
+                    if (probe) {
+                        const uint64_t kq = key[q];
+                        pr = g8 == 0 ? (kq >> sh) > P : (kq >> sh1) >= Po;
+                    }
+                    const unsigned long long fb = __ballot(probe && !pr);
+                    const int nf = __popcll((fb >> (8 * g8)) & 0xFFull);
+                    if (!done) {
+                        if (small) {
+                            a += nf;
+                            e = a;
+                            done = true;
+                        } else {
+                            const int64_t qlo = nf > 0 ? a + ((m * nf) >> 3) : a - 1;
+                            const int64_t qhi = nf < 7 ? a + ((m * (nf + 1)) >> 3) : e;
+                            a = qlo + 1;
+                            e = qhi;
+                        }
+                    }
+                    if (__ballot(!done) == 0ull) break;
+                }
+                if (__ballot(!done) != 0ull) {
+                    if (lane == 0) atomicOr(flags, UCP_FLAG_INTERNAL);
+                    continue;
+                }
+                const int ai = (int)a;
+                t = __shfl(ai, 0);
+                // lanes 0..7: S_o, the first position of octant o (p for the
+                // octants up to that of particle p), and S_8 = t
+                const int dig0 = (int)((kp >> sh1) & 7);
+                int so = __shfl(ai, 8 * (lane & 7));
+                if (lane <= dig0) so = (int)p;
+                int snext = __shfl(so, (lane + 1) & (kWave - 1));
+                if (lane == 7) snext = (int)t;
+                const bool has = lane < 8 && so < snext;
+                const unsigned long long hm = __ballot(has);
+                nch = __popcll(hm);
+                if (has) {
+                    const int ch = so == (int)p ? k + 1 : noff[so];
+                    ctab[8 * (int64_t)k + __popcll(hm & ((1ull << lane) - 1ull))] = ch;
+                    npar[ch] = k;
                 }
             }
+            if (lane >= nch && lane < 8) ctab[8 * (int64_t)k + lane] = -1;
+            const int cntp = (int)(t - p);
+            if (lane == 0) {
+                if (t < p + 2 || nch < 1 || nch > 8) atomicOr(flags, UCP_FLAG_INTERNAL);
+                const int skip = noff[t];
+                ninfo[k] = make_int4((int)p, cntp, skip, iw);
+                *(double4 *)(nrec + 8 * (int64_t)k) = g;
+                *(int4 *)(nrec + 8 * (int64_t)k + 2) = make_int4(skip, (int)p, cntp, iw);
+            }
+            if (cntp > direct_max) {
+                // summed from its children (6c)
+                if (lane == 0) {
+                    const unsigned long long slot = atomicAdd(&ctr[CTR_UPCOUNT], 1ull);
+                    if (slot < (unsigned long long)nn) uplist[slot] = k;
+                    else atomicOr(flags, UCP_FLAG_INTERNAL);
+                }
+                continue;
+            }
+            // the moments of the particles p .. t-1 about the centre g
+            double m[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+            double sq[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+            for (int u = 0; u < kDirectFirst; ++u)
+                if (p + lane + u * kWave < t) moment_terms(xa[u], g, m, sq, with_spec);
+            for (int64_t q = p + lane + kDirectFirst * kWave; q < t; q += kDirectFirst * kWave) {
+#pragma unroll
+                for (int u = 0; u < kDirectFirst; ++u) {
+                    const int64_t qq = q + u * kWave;
+                    xa[u] = xq[qq < t ? qq : p];
+                }
+#pragma unroll
+                for (int u = 0; u < kDirectFirst; ++u)
+                    if (q + u * kWave < t) moment_terms(xa[u], g, m, sq, with_spec);
+            }
+#pragma unroll
+            for (int i = 0; i < 10; ++i) m[i] = wave_dsum(m[i]);
+            if (with_spec) {
+#pragma unroll
+                for (int i = 0; i < 8; ++i) sq[i] = wave_dsum(sq[i]);
+            }
+            if (lane == kWave - 1) {
+                if (with_spec) spec_store(spec, k, g, sq);
+                store_moments(mom64, nrec, k, g, m);
+            }
         }
-        if (lv == l)
-            internal_node<4>((int)k, l, n, nn, nlev, ngeo, ninfo, npar, mom64, nrec, spec, flags);
     }
 }
 
@@ -1327,26 +1390,133 @@ __device__ __forceinline__ bool grid_barrier(unsigned long long *bar, unsigned l
     return ok != 0;
 }
 
-// The internal levels above those, from the deepest up, in one launch of
-// kUpBlocks blocks with a grid barrier between levels (these levels hold few
-// nodes, so a kernel launch per level would cost more than its work).  Every block passes every barrier, whatever it finds, so that the
-// count of arrivals stays exact; a block whose wait times out flags the build
-// and stops waiting.  Few blocks keep the barrier cheap: each block's release
-// writes back its L2.
-constexpr int kUpThreads = 512, kUpBlocks = 16;
-__global__ __launch_bounds__(kUpThreads) void k_moments_up(
+// ---------------------------------------------------------------------------
+// 6c. the internal nodes of more than direct_max particles (few, and near the
+//     root), from the deepest up: a node sums its children's moments (read
+//     through its child table) shifted to its centre, in order.  A small
+//     tree takes one block, with a block barrier between levels; from
+//     kUpperWide particles on, kUpperBlocks blocks (all resident at once)
+//     with a grid barrier between levels.  Every block passes every barrier,
+//     whatever it finds; few blocks keep the barrier cheap, since each
+//     block's release writes back its L2.
+// ---------------------------------------------------------------------------
+constexpr int kUpperThreads = 512, kUpperBlocks = 16;
+constexpr int64_t kUpperWide = int64_t(1) << 21;
+
+struct UpperNode {
+    int k, l;
+    double4 g;
+    int4 c0, c1;
+};
+
+// one child's moments shifted from its centre to the parent's centre g and
+// added: p' = p + Q d, S' = S + p d^T + d p^T + Q d d^T with d = c_child - g
+// (each component +-qd); c holds the child's FP64 record from cx on
+__device__ __forceinline__ void add_child(double *m, const double4 &g, double qd, const double *c)
+{
+    const double d0 = c[0] > g.x ? qd : -qd;
+    const double d1 = c[1] > g.y ? qd : -qd;
+    const double d2 = c[2] > g.z ? qd : -qd;
+    const double Q = c[3], p0 = c[4], p1 = c[5], p2 = c[6];
+    m[0] += Q;
+    m[1] += p0 + Q * d0;
+    m[2] += p1 + Q * d1;
+    m[3] += p2 + Q * d2;
+    m[4] += c[8] + 2.0 * p0 * d0 + Q * d0 * d0;
+    m[5] += c[9] + 2.0 * p1 * d1 + Q * d1 * d1;
+    m[6] += c[10] + 2.0 * p2 * d2 + Q * d2 * d2;
+    m[7] += c[11] + p0 * d1 + d0 * p1 + Q * d0 * d1;
+    m[8] += c[12] + p0 * d2 + d0 * p2 + Q * d0 * d2;
+    m[9] += c[13] + p1 * d2 + d1 * p2 + Q * d1 * d2;
+}
+
+// a child's pseudo-particles added to its parent's accumulators
+__device__ __forceinline__ void spec_add_child(double *sq, const double *spec, int ch,
+                                               const double4 &g)
+{
+    const double *r = spec + kSpecVals * (int64_t)ch;
+    const double4 a = *(const double4 *)r, b = *(const double4 *)(r + 4);
+    spec_add(sq, a.w, a.x - g.x, a.y - g.y, a.z - g.z);
+    spec_add(sq, b.w, b.x - g.x, b.y - g.y, b.z - g.z);
+}
+
+__device__ __forceinline__ void moments_from_children(const UpperNode &nd, int nn, double *mom64,
+                                                      float4 *nrec, double *spec, int32_t *flags)
+{
+    const int ch[8] = {nd.c0.x, nd.c0.y, nd.c0.z, nd.c0.w, nd.c1.x, nd.c1.y, nd.c1.z, nd.c1.w};
+    bool bad = ch[0] < 0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) bad = bad || ch[u] >= nn;
+    if (bad) {
+        atomicOr(flags, UCP_FLAG_INTERNAL);
+        return;
+    }
+    const double4 g = nd.g;
+    double m[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    double sq[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const double qd = 0.25 * sqrt(g.w);   // |child centre - parent centre| per axis
+    // four children's records (cx cy cz Q px py pz trS S[6]) per round of loads
+#pragma unroll
+    for (int r0 = 0; r0 < 8; r0 += 4) {
+        if (ch[r0] < 0) break;
+        double rc[4][14];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int cu = ch[r0 + u] >= 0 ? ch[r0 + u] : ch[r0];
+            const double2 *r = (const double2 *)(mom64 + 16 * (int64_t)cu);
+#pragma unroll
+            for (int i = 0; i < 7; ++i) {
+                const double2 v = r[i];
+                rc[u][2 * i] = v.x;
+                rc[u][2 * i + 1] = v.y;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (ch[r0 + u] < 0) break;
+            add_child(m, g, qd, rc[u]);
+            if (spec) spec_add_child(sq, spec, ch[r0 + u], g);
+        }
+    }
+    if (spec) spec_store(spec, nd.k, g, sq);
+    store_moments(mom64, nrec, nd.k, g, m);
+}
+
+__global__ __launch_bounds__(kUpperThreads) void k_moments_upper(
     int64_t n, const int32_t *__restrict__ noff, const uint8_t *__restrict__ nlev,
-    const double4 *__restrict__ ngeo, int4 *ninfo, int32_t *npar, double *mom64, float4 *nrec,
-    double *spec, unsigned long long *ctr, const int32_t *__restrict__ uplist, int32_t *flags)
+    const double4 *__restrict__ ngeo, const int32_t *__restrict__ ctab,
+    const int32_t *__restrict__ uplist, unsigned long long *ctr, double *mom64, float4 *nrec,
+    double *spec, int32_t *flags)
 {
     __shared__ int go_s;
     const int maxl = (int)ctr[CTR_MAXLEVEL];   // deepest leaf; internal nodes lie above it
     const int nn = noff[n];
-    // the internal nodes of these levels, listed by the first deep-level pass
-    const int nup = (int)min((unsigned long long)nn, ctr[CTR_UPCOUNT]);
+    const int cnt = (int)min(ctr[CTR_UPCOUNT], (unsigned long long)nn);
+    const int t0 = blockIdx.x * kUpperThreads + threadIdx.x;
+    auto node_at = [&](int i) -> UpperNode {
+        UpperNode t;
+        t.k = uplist[i];
+        t.l = -1;
+        if (t.k < 0 || t.k >= nn) {
+            atomicOr(flags, UCP_FLAG_INTERNAL);
+            t.k = -1;
+            return t;
+        }
+        t.l = nlev[t.k];
+        t.g = ngeo[t.k];
+        t.c0 = *(const int4 *)(ctab + 8 * (int64_t)t.k);
+        t.c1 = *(const int4 *)(ctab + 8 * (int64_t)t.k + 4);
+        return t;
+    };
+    const int stride = gridDim.x * kUpperThreads;
+    // this thread's first node, read once
+    UpperNode held;
+    held.k = -1;
+    held.l = -1;
+    if (t0 < cnt) held = node_at(t0);
     unsigned long long target = 0;
     bool wait = true;
-    for (int l = maxl - 1 - kDeepLevels; l >= 0; --l) {
+    for (int l = maxl - 1; l >= 0; --l) {
         // one reading of the flags for the whole block, so that its threads
         // agree on every loop bound below
         if (threadIdx.x == 0)
@@ -1354,21 +1524,20 @@ __global__ __launch_bounds__(kUpThreads) void k_moments_up(
         __syncthreads();
         const bool go = go_s != 0;
         __syncthreads();
-        for (int i = blockIdx.x * kUpThreads + threadIdx.x; go && i < nup;
-             i += gridDim.x * kUpThreads) {
-            const int k = uplist[i];
-            if (k < 0 || k >= nn) {
-                atomicOr(flags, UCP_FLAG_INTERNAL);
-                continue;
-            }
-            if ((int)nlev[k] == l)
-                internal_node<2>(k, l, n, nn, nlev, ngeo, ninfo, npar, mom64, nrec, spec, flags);
+        for (int i = t0; go && i < cnt; i += stride) {
+            const UpperNode nd = i == t0 ? held : node_at(i);
+            if (nd.k >= 0 && nd.l == l) moments_from_children(nd, nn, mom64, nrec, spec, flags);
         }
-        if (l == 0 || !wait) continue;
-        target += gridDim.x;
-        if (!grid_barrier(&ctr[CTR_BARRIER], target)) {
-            if (threadIdx.x == 0) atomicOr(flags, UCP_FLAG_INTERNAL);
-            wait = false;
+        if (gridDim.x == 1) {
+            __syncthreads();
+        } else if (l > 0 && wait) {
+            // every block passes every barrier, so that the count of
+            // arrivals stays exact; a wait that times out flags the build
+            target += gridDim.x;
+            if (!grid_barrier(&ctr[CTR_BARRIER], target)) {
+                if (threadIdx.x == 0) atomicOr(flags, UCP_FLAG_INTERNAL);
+                wait = false;
+            }
         }
     }
 }
@@ -1597,19 +1766,23 @@ void launch_build(Ctx *c, const double *x, const double *q, const int64_t *offse
                        (const int8_t *)c->d_leaf, (const int32_t *)c->d_lend,
                        (const int32_t *)c->d_noff, (const double4 *)c->d_ngeo, c->d_ninfo,
                        c->d_mom64, c->d_nrec, c->d_leafof, spec, (const int32_t *)c->d_flags);
-    // a grid over the whole chip, striding over the node records
-    const int deep_blocks = (int)std::min<int64_t>((c->node_cap + kDeepThreads - 1) / kDeepThreads,
-                                                   8 * (int64_t)std::max(c->num_cu, 1));
-    for (int j = 0; j < kDeepLevels; ++j)
-        hipLaunchKernelGGL(k_moments_level, dim3(deep_blocks), dim3(kDeepThreads), 0, s, j, n,
-                           (const int32_t *)c->d_noff, (const uint8_t *)c->d_nlev,
-                           (const double4 *)c->d_ngeo, c->d_ninfo, c->d_npar, c->d_mom64,
-                           c->d_nrec, spec, c->d_ctr, c->d_uplist, c->d_flags);
-    hipLaunchKernelGGL(k_moments_up, dim3(std::min(kUpBlocks, std::max(c->num_cu, 1))),
-                       dim3(kUpThreads), 0, s, n, (const int32_t *)c->d_noff,
-                       (const uint8_t *)c->d_nlev, (const double4 *)c->d_ngeo, c->d_ninfo,
-                       c->d_npar, c->d_mom64, c->d_nrec, spec, c->d_ctr,
-                       (const int32_t *)c->d_uplist, c->d_flags);
+    // the internal nodes, one wave per node over a grid that fills the chip;
+    // then the large ones from their children
+    const int nwblocks = 8 * std::max(c->num_cu, 1);
+    auto node_kernel = spec ? k_node_moments<true> : k_node_moments<false>;
+    hipLaunchKernelGGL(node_kernel, dim3(nwblocks), dim3(kNodeThreads), 0, s,
+                       (const uint64_t *)c->d_skey, (const int8_t *)c->d_L,
+                       (const double4 *)c->d_xq, n, (const int64_t *)c->d_off, clouds, b,
+                       (const int32_t *)c->d_noff, (const uint8_t *)c->d_nlev,
+                       (const double4 *)c->d_ngeo, c->d_ninfo, c->d_nrec, c->d_mom64, c->d_npar,
+                       c->d_ctab, c->d_uplist, spec, c->d_ctr,
+                       n >= kUpperWide ? kDirectMaxWide : kDirectMax, c->d_flags);
+    const int upper_blocks = n >= kUpperWide ? std::min(kUpperBlocks, std::max(c->num_cu, 1)) : 1;
+    hipLaunchKernelGGL(k_moments_upper, dim3(upper_blocks), dim3(kUpperThreads), 0, s, n,
+                       (const int32_t *)c->d_noff, (const uint8_t *)c->d_nlev,
+                       (const double4 *)c->d_ngeo, (const int32_t *)c->d_ctab,
+                       (const int32_t *)c->d_uplist, c->d_ctr, c->d_mom64, c->d_nrec, spec,
+                       c->d_flags);
     // 7. groups
     if (chunk) {
         const int64_t gmax = (n + G - 1) / G + clouds;

@@ -127,7 +127,8 @@ struct Ctx {
     int4 *d_ninfo = nullptr;                // [node_cap] first, count, skip, level | 256*leaf
     int32_t *d_npar = nullptr;              // [node_cap] parent (-1 for a root)
     uint8_t *d_nlev = nullptr;              // [node_cap + 128] level of each node, | kLeafBit for a leaf
-    int32_t *d_uplist = nullptr;            // [node_cap] internal nodes above the deep levels
+    int32_t *d_uplist = nullptr;            // [node_cap] the internal nodes summed from their children
+    int32_t *d_ctab = nullptr;              // [8 node_cap] an internal node's children in order, -1 after the last
     // per-species pseudo-particles (UCP_EXPANSION_SPECIES), allocated when that
     // expansion is first set: c+[3] Q+ c-[3] Q- delta+ delta- 0 0
     double *d_spec = nullptr;               // [node_cap][kSpecVals]
