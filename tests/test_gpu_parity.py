@@ -192,6 +192,32 @@ def test_degenerate_inputs():
     ts.close()
 
 
+def test_large_coincident_cluster():
+    # 3000 coincident particles beside a cloud: a chain of internal nodes of
+    # more than 1024 particles down to the maximum depth, each with one child,
+    # whose ends and children come from the searches over the sorted keys and
+    # whose moments come from their children, level by level
+    say("[parity] 3000 coincident particles beside a cloud of 3000")
+    cl = inputs.gaussian_cloud(6000, 1.0, 1e-3, 1e-5, 11)
+    x = cl.x.copy()
+    x[:3000] = [0.37, -0.41, 0.29]
+    for cap in (8, 24):
+        t = oracle.Tree(x, cl.q, 0.5, 0.01, leaf_cap=cap, G=64, group_mode=CHUNK)
+        ref = t.eval(want_phi=True)
+        lv, fi, co, sk = t.nodes()
+        assert int(lv.max()) == 21 and int(co[sk != np.arange(len(lv)) + 1].max()) > 1024
+        ts = TreeSolver(6000, theta=0.5, eps=0.01, leaf_cap=cap, group_size=64,
+                        precision=L.UCP_FP64, group_mode=CHUNK)
+        f, phi = ts.tree_forces(dev(x), dev(cl.q), want_phi=True)
+        st = ts.stats()
+        say(f"[parity]   leaf_cap={cap} nodes={st['nodes']} max level={int(lv.max())}")
+        check_topology(ts, t)
+        check_moments(ts, t, x, cl.q)
+        assert relrms(f.cpu().numpy(), ref["f"]) < TOL_FP64
+        assert relrms(phi.cpu().numpy(), ref["phi"]) < TOL_FP64
+        ts.close()
+
+
 def test_nonfinite_input_is_flagged():
     say("[parity] non-finite input")
     ts = TreeSolver(64, theta=0.5, eps=0.01)
