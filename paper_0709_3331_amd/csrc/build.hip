@@ -1009,99 +1009,6 @@ __device__ __forceinline__ void spec_store(double *spec, int k, const double4 &g
     r[11] = 0.0;
 }
 
-// 6a. The leaf starting at position p, if there is one (every level at once: a
-// leaf depends on nothing but its particles).  Its end was found by the level
-// pass, or is -1 for a max-depth leaf wider than that pass's window.
-constexpr int kLeafThreads = 256, kP2MBatch = 4;
-__global__ __launch_bounds__(kLeafThreads) void k_leaf_moments(
-    const double4 *__restrict__ xq, int64_t n, const int8_t *__restrict__ Lv,
-    const int8_t *__restrict__ Lf, const int32_t *__restrict__ lend,
-    const int32_t *__restrict__ noff, const double4 *__restrict__ ngeo, int4 *ninfo,
-    double *mom64, float4 *nrec, int32_t *leafof, double *spec, const int32_t *flags)
-{
-    if (*flags) return;
-    const int64_t p = blockIdx.x * (int64_t)kLeafThreads + threadIdx.x;
-    if (p >= n) return;
-    const int Lp = Lv[p], lf = Lf[p];
-    if (lf <= Lp) return;
-    const int k = noff[p] + (lf - Lp - 1);
-    const double4 g = ngeo[k];
-    int64_t t = lend[p];
-    if (t < 0) {
-        t = p + 1;
-        while ((int)Lv[t] >= lf) ++t;   // Lv[n] = -1 ends the scan
-    }
-    double m[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    double sq[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    // particles in order; the loads of a batch are issued together
-    for (int64_t j0 = p; j0 < t; j0 += kP2MBatch) {
-        double4 a[kP2MBatch];
-#pragma unroll
-        for (int u = 0; u < kP2MBatch; ++u) a[u] = xq[j0 + u < t ? j0 + u : t - 1];
-#pragma unroll
-        for (int u = 0; u < kP2MBatch; ++u) {
-            if (j0 + u >= t) break;
-            leafof[j0 + u] = k;
-            const double r0 = a[u].x - g.x, r1 = a[u].y - g.y, r2 = a[u].z - g.z, qq = a[u].w;
-            m[0] += qq;
-            m[1] += qq * r0;
-            m[2] += qq * r1;
-            m[3] += qq * r2;
-            m[4] += qq * r0 * r0;
-            m[5] += qq * r1 * r1;
-            m[6] += qq * r2 * r2;
-            m[7] += qq * r0 * r1;
-            m[8] += qq * r0 * r2;
-            m[9] += qq * r1 * r2;
-            if (spec) spec_add(sq, qq, r0, r1, r2);
-        }
-    }
-    if (spec) spec_store(spec, k, g, sq);
-    const int cnt = (int)(t - p), skip = noff[t], info = lf | 256;
-    ninfo[k] = make_int4((int)p, cnt, skip, info);
-    *(double4 *)(nrec + 8 * (int64_t)k) = g;
-    *(int4 *)(nrec + 8 * (int64_t)k + 2) = make_int4(skip, (int)p, cnt, info);
-    store_moments(mom64, nrec, k, g, m);
-}
-
-// High bit of each byte of x set where that byte (taken mod 128) is < v,
-// for 0 < v <= 127; the bias 0x80 per byte keeps borrows inside each byte.
-__device__ __forceinline__ uint32_t bytes_below(uint32_t x, uint32_t v)
-{
-    return ~((x & 0x7F7F7F7Fu) + 0x80808080u - v * 0x01010101u) & 0x80808080u;
-}
-// the four byte flags (bits 7, 15, 23, 31) gathered into bits 0..3
-__device__ __forceinline__ uint32_t gather4(uint32_t m)
-{
-    return ((m >> 7) & 1u) | ((m >> 14) & 2u) | ((m >> 21) & 4u) | ((m >> 28) & 8u);
-}
-
-// ---------------------------------------------------------------------------
-// 6b. internal nodes, each by one wave.  The node (p, l) holds the positions
-//     p .. t-1, t the first later position with L(t) < l (L is -1 at every
-//     cloud edge and at n).  Its children are the nodes of level l + 1 that
-//     start at p (node k + 1) and at each position s in (p, t) with L(s) = l
-//     (node noff[s], the first node there).  The wave reads the level bytes
-//     of the next 1024 positions, 16 per lane; for a node that runs past
-//     them, eight 8-ary searches over the sorted keys, eight lanes each, find
-//     its end (the first key whose level-l prefix exceeds the node's prefix
-//     P) and the start of each child octant o (the first key whose
-//     level-(l + 1) prefix is at least 8 P + o).  It writes the count, the
-//     skip link noff[t] (the node after the subtree in preorder), the walk
-//     record's header, the children in order (-1 after the last) and each
-//     child's parent.  A node of at most direct_max particles then sums its
-//     particles' moments about its centre, lane j taking particles p + j,
-//     p + j + 64, ..., and the lanes' sums are added in a fixed order; a
-//     larger node is listed for 6c.
-// ---------------------------------------------------------------------------
-constexpr int kNodeThreads = 256, kNodeSpan = 16, kRangeWin = 16 * kWave;
-// the largest node summed from its particles, for trees below and from
-// kUpperWide particles on (measured from 256 to 2048 on 524,288 and
-// 4,194,304 particles: 1024 and 2048 within a microsecond on the first,
-// 1024 the faster on the second)
-constexpr int kDirectMax = 1024, kDirectMaxWide = 1024;
-constexpr int kDirectFirst = 4;   // particles per lane read with the level window
-
 // v moved across lanes by the DPP control `ctrl` (rows outside row_mask read
 // 0), each 32-bit half alike
 template <int ctrl, int row_mask>
@@ -1157,6 +1064,128 @@ __device__ __forceinline__ void moment_terms(const double4 &a, const double4 &g,
         sq[7] += qm * r2;
     }
 }
+
+// 6a. The leaves, every level at once (a leaf depends on nothing but its
+// particles).  A wave takes 64 positions; the leaves starting there are handed
+// out through LDS to groups of four lanes, 16 at a time, and lane s of a group
+// takes the particles p + s, p + s + 4, ... of its leaf; the four sums are
+// added by DPP in a fixed order.  A leaf's end was found by the level pass,
+// or is -1 for a max-depth leaf wider than that pass's window (its starting
+// lane then scans for it).
+constexpr int kLeafThreads = 256, kLeafBatch = 4;
+template <bool SPEC>
+__global__ __launch_bounds__(kLeafThreads) void k_leaf_moments(
+    const double4 *__restrict__ xq, int64_t n, const int8_t *__restrict__ Lv,
+    const int8_t *__restrict__ Lf, const int32_t *__restrict__ lend,
+    const int32_t *__restrict__ noff, const double4 *__restrict__ ngeo, int4 *ninfo,
+    double *mom64, float4 *nrec, int32_t *leafof, double *spec, const int32_t *flags)
+{
+    __shared__ int4 slot[kLeafThreads / kWave][kWave];   // (p, k, t, level) of each start, by rank
+    if (*flags) return;   // no other kernel runs meanwhile: the whole block reads the same word
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    const int64_t p = blockIdx.x * (int64_t)kLeafThreads + threadIdx.x;
+    int Lp = 0, lf = 0, no = 0, le = 0;
+    if (p < n) {
+        Lp = Lv[p];
+        lf = Lf[p];
+        no = noff[p];
+        le = lend[p];
+    }
+    const bool start = p < n && lf > Lp;
+    const unsigned long long sm = __ballot(start);
+    if (start) {
+        int64_t t = le;
+        if (t < 0) {
+            t = p + 1;
+            while ((int)Lv[t] >= lf) ++t;   // Lv[n] = -1 ends the scan
+        }
+        slot[wv][__popcll(sm & ((1ull << lane) - 1ull))] =
+            make_int4((int)p, no + (lf - Lp - 1), (int)t, lf);
+    }
+    __syncthreads();
+    const int ns = __popcll(sm);
+    for (int b0 = 0; b0 < ns; b0 += kWave / 4) {
+        const int gi = b0 + (lane >> 2), sub = lane & 3;
+        const bool on = gi < ns;
+        const int4 sl = on ? slot[wv][gi] : make_int4(0, 0, 0, 0);
+        const double4 g = on ? ngeo[sl.y] : make_double4(0.0, 0.0, 0.0, 0.0);
+        double m[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+        double sq[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int64_t q0 = (int64_t)sl.x + sub; on && q0 < sl.z; q0 += 4 * kLeafBatch) {
+            double4 a[kLeafBatch];
+#pragma unroll
+            for (int u = 0; u < kLeafBatch; ++u) {
+                const int64_t q = q0 + 4 * u;
+                a[u] = xq[q < sl.z ? q : sl.x];
+            }
+#pragma unroll
+            for (int u = 0; u < kLeafBatch; ++u) {
+                if (q0 + 4 * u >= sl.z) break;
+                leafof[q0 + 4 * u] = sl.y;
+                moment_terms(a[u], g, m, sq, SPEC);
+            }
+        }
+        // the group's four sums (every lane of the wave is active here)
+#pragma unroll
+        for (int i = 0; i < 10; ++i) {
+            m[i] += dpp_d<0xB1, 0xf>(m[i]);   // quad_perm [1, 0, 3, 2]
+            m[i] += dpp_d<0x4E, 0xf>(m[i]);   // quad_perm [2, 3, 0, 1]
+        }
+        if (SPEC) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                sq[i] += dpp_d<0xB1, 0xf>(sq[i]);
+                sq[i] += dpp_d<0x4E, 0xf>(sq[i]);
+            }
+        }
+        if (on && sub == 0) {
+            const int k = sl.y, cnt = sl.z - sl.x, skip = noff[sl.z], info = sl.w | 256;
+            if (SPEC) spec_store(spec, k, g, sq);
+            ninfo[k] = make_int4(sl.x, cnt, skip, info);
+            *(double4 *)(nrec + 8 * (int64_t)k) = g;
+            *(int4 *)(nrec + 8 * (int64_t)k + 2) = make_int4(skip, sl.x, cnt, info);
+            store_moments(mom64, nrec, k, g, m);
+        }
+    }
+}
+
+// High bit of each byte of x set where that byte (taken mod 128) is < v,
+// for 0 < v <= 127; the bias 0x80 per byte keeps borrows inside each byte.
+__device__ __forceinline__ uint32_t bytes_below(uint32_t x, uint32_t v)
+{
+    return ~((x & 0x7F7F7F7Fu) + 0x80808080u - v * 0x01010101u) & 0x80808080u;
+}
+// the four byte flags (bits 7, 15, 23, 31) gathered into bits 0..3
+__device__ __forceinline__ uint32_t gather4(uint32_t m)
+{
+    return ((m >> 7) & 1u) | ((m >> 14) & 2u) | ((m >> 21) & 4u) | ((m >> 28) & 8u);
+}
+
+// ---------------------------------------------------------------------------
+// 6b. internal nodes, each by one wave.  The node (p, l) holds the positions
+//     p .. t-1, t the first later position with L(t) < l (L is -1 at every
+//     cloud edge and at n).  Its children are the nodes of level l + 1 that
+//     start at p (node k + 1) and at each position s in (p, t) with L(s) = l
+//     (node noff[s], the first node there).  The wave reads the level bytes
+//     of the next 1024 positions, 16 per lane; for a node that runs past
+//     them, eight 8-ary searches over the sorted keys, eight lanes each, find
+//     its end (the first key whose level-l prefix exceeds the node's prefix
+//     P) and the start of each child octant o (the first key whose
+//     level-(l + 1) prefix is at least 8 P + o).  It writes the count, the
+//     skip link noff[t] (the node after the subtree in preorder), the walk
+//     record's header, the children in order (-1 after the last) and each
+//     child's parent.  A node of at most direct_max particles then sums its
+//     particles' moments about its centre, lane j taking particles p + j,
+//     p + j + 64, ..., and the lanes' sums are added in a fixed order; a
+//     larger node is listed for 6c.
+// ---------------------------------------------------------------------------
+constexpr int kNodeThreads = 256, kNodeSpan = 16, kRangeWin = 16 * kWave;
+// the largest node summed from its particles, for trees below and from
+// kUpperWide particles on (measured from 256 to 2048 on 524,288 and
+// 4,194,304 particles: 1024 and 2048 within a microsecond on the first,
+// 1024 the faster on the second)
+constexpr int kDirectMax = 1024, kDirectMaxWide = 1024;
+constexpr int kDirectFirst = 4;   // particles per lane read with the level window
 
 template <bool SPEC>
 __global__ __launch_bounds__(kNodeThreads) void k_node_moments(
@@ -1761,7 +1790,8 @@ void launch_build(Ctx *c, const double *x, const double *q, const int64_t *offse
     // 6. moments: every leaf, then the internal levels from the deepest up
     //    (and the per-species pseudo-particles when the walk uses them)
     double *spec = c->p.expansion == UCP_EXPANSION_SPECIES ? c->d_spec : nullptr;
-    hipLaunchKernelGGL(k_leaf_moments, grid_for(n, kLeafThreads), dim3(kLeafThreads), 0, s,
+    auto leaf_kernel = spec ? k_leaf_moments<true> : k_leaf_moments<false>;
+    hipLaunchKernelGGL(leaf_kernel, grid_for(n, kLeafThreads), dim3(kLeafThreads), 0, s,
                        (const double4 *)c->d_xq, n, (const int8_t *)c->d_L,
                        (const int8_t *)c->d_leaf, (const int32_t *)c->d_lend,
                        (const int32_t *)c->d_noff, (const double4 *)c->d_ngeo, c->d_ninfo,
