@@ -1025,6 +1025,18 @@ __device__ __forceinline__ double dpp_d(double v)
 // and 8 (every lane then holds its row's sum), then row 0 into row 1 and
 // row 2 into row 3 (lane 15 and 47 broadcast), then rows 0-1 into rows 2-3
 // (lane 31 broadcast).  All lanes must be active.
+// the sum of v over each row of 16 lanes, in every lane of the row, added
+// in a fixed order (swaps of lane pairs and quads, rotations by 4 and 8).
+// All lanes must be active.
+__device__ __forceinline__ double row_dsum(double v)
+{
+    v += dpp_d<0xB1, 0xf>(v);    // quad_perm [1, 0, 3, 2]
+    v += dpp_d<0x4E, 0xf>(v);    // quad_perm [2, 3, 0, 1]
+    v += dpp_d<0x124, 0xf>(v);   // row_ror 4
+    v += dpp_d<0x128, 0xf>(v);   // row_ror 8
+    return v;
+}
+
 __device__ __forceinline__ double wave_dsum(double v)
 {
     v += dpp_d<0xB1, 0xf>(v);    // quad_perm [1, 0, 3, 2]
@@ -1214,7 +1226,115 @@ __global__ __launch_bounds__(kNodeThreads) void k_node_moments(
         const int4 infl = ninfo[kr];
         const double4 gl = ngeo[kr];
         const bool inner = kl < nn && !(lv & kLeafBit);
-        unsigned long long im = __ballot(inner);
+        // Small nodes first, four at a time: row r (16 lanes) takes the r-th
+        // of the next four internal nodes, reads the levels of the 256
+        // positions after it, and when the node ends there it writes its
+        // records and parents and sums its particles (lane j: p + j, p + j +
+        // 16, ...), the row's sums added by DPP in a fixed order.  A node that
+        // runs past those positions is left to the whole wave below.
+        unsigned long long todo = __ballot(inner), big = 0ull;
+        const int row = lane >> 4, rl = lane & 15;
+        while (todo != 0ull) {
+            unsigned long long mm = todo;
+            for (int r = 0; r < row; ++r) mm &= mm - 1ull;
+            const int src = mm != 0ull ? __builtin_ctzll(mm) : -1;
+            for (int r = 0; r < 4; ++r) todo &= todo - 1ull;
+            const int srcc = src >= 0 ? src : 0;
+            const int k = (int)(s0 + srcc);
+            const int64_t p = __shfl(infl.x, srcc);
+            const int iw = __shfl(infl.w, srcc);
+            const int l = iw & 255;
+            const double4 g = make_double4(__shfl(gl.x, srcc), __shfl(gl.y, srcc),
+                                           __shfl(gl.z, srcc), __shfl(gl.w, srcc));
+            bool mine = src >= 0;
+            if (mine && (p < 0 || p >= n || (iw & 256) || l >= b || k + 1 >= nn)) {
+                if (rl == 0) atomicOr(flags, UCP_FLAG_INTERNAL);
+                mine = false;
+            }
+            const int64_t pp = mine ? p : 0;
+            // the row's particles, read with its level window
+            double4 xa[kDirectFirst];
+#pragma unroll
+            for (int u = 0; u < kDirectFirst; ++u) {
+                const int64_t q = pp + rl + 16 * u;
+                xa[u] = xq[q < n ? q : pp];
+            }
+            const int64_t base = (pp + 1) & ~(int64_t)15;
+            const int64_t q0 = base + 16 * rl;
+            uint32_t endm = 0, eqm = 0;
+            if (mine && q0 <= n) {
+                const uint4 v = *(const uint4 *)(Lv + q0);
+                const uint32_t d[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int w = 0; w < 4; ++w) {
+                    const uint32_t lt = bytes_below(d[w], (uint32_t)l) | (d[w] & 0x80808080u);
+                    const uint32_t eq = bytes_below(d[w], (uint32_t)l + 1) & ~lt;
+                    endm |= gather4(lt) << (4 * w);
+                    eqm |= gather4(eq) << (4 * w);
+                }
+                const int lo = (int)max<int64_t>(0, pp + 1 - q0);
+                const int hi = (int)min<int64_t>(16, n + 1 - q0);
+                const uint32_t valid = ((1u << hi) - 1u) & ~((1u << lo) - 1u);
+                endm &= valid;
+                eqm &= valid;
+            }
+            const unsigned long long he = __ballot(endm != 0);
+            const uint32_t rowend = (uint32_t)(he >> (16 * row)) & 0xFFFFu;
+            const int f = rowend != 0u ? __builtin_ctz(rowend) : 0;
+            const uint32_t ef = (uint32_t)__shfl((int)endm, 16 * row + f);
+            const int64_t t = base + 16 * f + (ef != 0u ? __builtin_ctz(ef) : 0);
+            const bool ok = mine && rowend != 0u;
+            {
+                // the nodes that run past their row's window, by span slot
+                const unsigned long long bb = __ballot(mine && rowend == 0u && rl == 0);
+                for (int r = 0; r < 4; ++r)
+                    if ((bb >> (16 * r)) & 1ull) big |= 1ull << __shfl(srcc, 16 * r);
+            }
+            double m[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+            double sq[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            if (ok) {
+                // parents of the children after the first (L == l before t)
+                uint32_t cm = eqm;
+                const int64_t lim = t - q0;
+                if (lim <= 0) cm = 0;
+                else if (lim < 16) cm &= (1u << lim) - 1u;
+                while (cm != 0u) {
+                    npar[noff[q0 + __builtin_ctz(cm)]] = k;
+                    cm &= cm - 1u;
+                }
+#pragma unroll
+                for (int u = 0; u < kDirectFirst; ++u)
+                    if (pp + rl + 16 * u < t) moment_terms(xa[u], g, m, sq, with_spec);
+                for (int64_t q = pp + rl + 16 * kDirectFirst; q < t; q += 16 * kDirectFirst) {
+#pragma unroll
+                    for (int u = 0; u < kDirectFirst; ++u) {
+                        const int64_t qq = q + 16 * u;
+                        xa[u] = xq[qq < t ? qq : pp];
+                    }
+#pragma unroll
+                    for (int u = 0; u < kDirectFirst; ++u)
+                        if (q + 16 * u < t) moment_terms(xa[u], g, m, sq, with_spec);
+                }
+            }
+            // the row's sums (every lane of the wave is active here)
+#pragma unroll
+            for (int i = 0; i < 10; ++i) m[i] = row_dsum(m[i]);
+            if (with_spec) {
+#pragma unroll
+                for (int i = 0; i < 8; ++i) sq[i] = row_dsum(sq[i]);
+            }
+            if (ok && rl == 0) {
+                const int cntp = (int)(t - pp), skip = noff[t];
+                npar[k + 1] = k;
+                if (t < pp + 2) atomicOr(flags, UCP_FLAG_INTERNAL);
+                ninfo[k] = make_int4((int)pp, cntp, skip, iw);
+                *(double4 *)(nrec + 8 * (int64_t)k) = g;
+                *(int4 *)(nrec + 8 * (int64_t)k + 2) = make_int4(skip, (int)pp, cntp, iw);
+                if (with_spec) spec_store(spec, k, g, sq);
+                store_moments(mom64, nrec, k, g, m);
+            }
+        }
+        unsigned long long im = big;
         while (im != 0ull) {
             const int src = __builtin_ctzll(im);
             im &= im - 1ull;
