@@ -133,7 +133,7 @@ void free_all(Ctx *c)
 {
     void *ptrs[] = {c->d_off,  c->d_mm,     c->d_cube,  c->d_key[0], c->d_key[1], c->d_key[2],
                     c->d_val[0], c->d_val[1], c->d_val[2], c->d_hist, c->d_histscan, c->d_xin, c->d_xq, c->d_L,
-                    c->d_leaf, c->d_cnt,    c->d_lend, c->d_lvlmax, c->d_noff,  c->d_goff,   c->d_gnode,  c->d_gcl, c->d_scanblk,
+                    c->d_leaf, c->d_cnt,    c->d_lend, c->d_lvlmax, c->d_offstat, c->d_noff,  c->d_goff,   c->d_gnode,  c->d_gcl, c->d_scanblk,
                     c->d_ngeo, c->d_ninfo,  c->d_npar,  c->d_mom64,  c->d_nrec,
                     c->d_groups, c->d_gstat, c->d_acc,  c->d_ctr,    c->d_flags,  c->d_epart,
                     c->d_leafof, c->d_w,    c->d_xsrc,  c->d_cbar,  c->d_lobar, c->d_lomin, c->d_wq,
@@ -312,6 +312,7 @@ ucp_status ucp_create(ucp_ctx **out, int64_t n_max, int32_t clouds_max, const uc
     ALLOC(c->d_cnt, N + 1);
     ALLOC(c->d_lend, N + 1);
     ALLOC(c->d_lvlmax, N / 256 + 2);
+    ALLOC(c->d_offstat, N / 4096 + 2);
     ALLOC(c->d_noff, N + 1);
     ALLOC(c->d_goff, N + 1);
     ALLOC(c->d_gnode, N + 1);

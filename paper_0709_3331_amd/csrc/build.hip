@@ -61,8 +61,8 @@ __device__ __forceinline__ int block_excl_scan(int v, int *total);
 __device__ __forceinline__ bool grid_barrier(unsigned long long *bar, unsigned long long target);
 
 // per-build state: cloud extents, counters (the walk's included), the walk's
-// queue heads, the sort's tickets, digit counts and the first pass's
-// look-back status words (every block); then block 0
+// queue heads, the sort's tickets, digit counts and the look-back words of
+// the sort's first pass and of the node offsets (every block); then block 0
 // moves the last build's flags that ucp_get_stats has not yet reported
 // (flags[2] holds the reported ones) into the sticky word (flags[1], cleared
 // only by ucp_get_stats) and clears the flag word, sets the cloud offsets ({0, n} for one cloud, or a
@@ -70,7 +70,8 @@ __device__ __forceinline__ bool grid_barrier(unsigned long long *bar, unsigned l
 // chunk group of each cloud and their total
 __global__ __launch_bounds__(kScanBlock) void k_build_reset(
     unsigned long long *mm, int clouds, unsigned long long *ctr, uint32_t *sortctl,
-    uint32_t *ghist, uint32_t *status0, int64_t nstatus, const int64_t *__restrict__ src_off,
+    uint32_t *ghist, uint32_t *status0, int64_t nstatus, unsigned long long *offstat,
+    int64_t noffstat, const int64_t *__restrict__ src_off,
     int64_t n, int G, int64_t *off, int32_t *gcl, int32_t *goff_n, unsigned long long *wq,
     int32_t *flags)
 {
@@ -82,6 +83,7 @@ __global__ __launch_bounds__(kScanBlock) void k_build_reset(
     if (t0 < kSortTickets) sortctl[t0] = 0;
     if (t0 < kSortPassesMax * 256) ghist[t0] = 0;
     for (int64_t t = t0; t < nstatus; t += (int64_t)gridDim.x * blockDim.x) status0[t] = 0;
+    for (int64_t t = t0; t < noffstat; t += (int64_t)gridDim.x * blockDim.x) offstat[t] = 0;
     if (blockIdx.x != 0) return;
     if (threadIdx.x == 0) {
         flags[1] |= flags[0] & ~flags[2];
@@ -891,58 +893,155 @@ __global__ __launch_bounds__(kLvlTile) void k_levels(const uint64_t *__restrict_
 // ---------------------------------------------------------------------------
 // 5. node records: the nodes starting at position p are the boxes of levels
 //    L(p)+1 .. leaf(p) holding p, numbered noff[p] + (l - L(p) - 1) in
-//    preorder.  This kernel writes what follows from p and l alone (box
-//    centre, side^2, first particle, level and leaf flag); the box's integer
-//    coordinates are those of particle p, quantised again exactly as the keys
-//    were, so no key is decoded and either curve works.  The particle count,
-//    the skip link and the parent of an internal node are found by the
-//    moments pass below.
+//    preorder.  One kernel finds noff (below) and writes what follows from p
+//    and l alone (box centre, side^2, first particle, level and leaf flag);
+//    the box's integer coordinates are those of particle p, quantised again
+//    exactly as the keys were, so no key is decoded and either curve works.
+//    The particle count, the skip link and the parent of an internal node
+//    are found by the moments pass below.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_nodes(
+// The node offsets noff (the exclusive prefix of the per-position node
+// counts) and the deepest leaf level come from one pass over tiles of
+// kOffTile positions: a tile sums its counts and takes the maximum of its
+// level blocks' deepest leaves, publishes both at once (kOffAgg), combines
+// the earlier tiles' words, 64 at a time, back to the nearest one that holds
+// the inclusive totals (kOffIncl) and publishes its own.  Tiles are taken in
+// the order blocks start (a ticket), so every wait ends; a bounded spin
+// turns a lost tile into an internal-error flag.  Word: flag (bits 62-63) |
+// deepest level (bits 32-39) | count (bits 0-31).  The tile then writes the
+// records of the nodes starting at its positions.
+constexpr int kOffThreads = kScanBlock, kOffItems = 4, kOffTile = kOffThreads * kOffItems;
+constexpr unsigned long long kOffAgg = 1ull << 62, kOffIncl = 2ull << 62;
+static_assert(kOffTile % kLvlTile == 0, "a tile holds whole level blocks");
+
+__global__ __launch_bounds__(kOffThreads) void k_offsets_nodes(
+    const int32_t *__restrict__ cnt, const int32_t *__restrict__ blkmax, int nlvlblk,
     const double4 *__restrict__ xq, int64_t n, const int64_t *__restrict__ off, int clouds,
     const double4 *__restrict__ cube, int b, const int8_t *__restrict__ Lv,
-    const int8_t *__restrict__ Lf, const int32_t *__restrict__ noff, int64_t node_cap,
-    double4 *ngeo, int4 *ninfo, int32_t *npar, uint8_t *nlev, const int32_t *__restrict__ blkmax,
-    int nlvlblk, unsigned long long *ctr, int32_t *flags)
+    const int8_t *__restrict__ Lf, int64_t node_cap, int32_t *noff, double4 *ngeo, int4 *ninfo,
+    int32_t *npar, uint8_t *nlev, unsigned long long *stat, unsigned long long *ctr,
+    int32_t *flags)
 {
+    __shared__ int tile_s, tot_s, lmax_s;
+    __shared__ unsigned long long excl_s;
+    if (threadIdx.x == 0) tile_s = (int)atomicAdd(&ctr[CTR_OFFTICKET], 1ull);
+    __syncthreads();
+    const int tile = tile_s;
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    const int64_t p0 = (int64_t)tile * kOffTile + kOffItems * threadIdx.x;
+    int c[kOffItems];
+    int mine = 0;
+#pragma unroll
+    for (int u = 0; u < kOffItems; ++u) {
+        c[u] = p0 + u <= n ? cnt[p0 + u] : 0;
+        mine += c[u];
+    }
+    // deepest leaf of the tile's level blocks
+    int lm = 0;
+    {
+        const int64_t lb = (int64_t)tile * (kOffTile / kLvlTile) + threadIdx.x;
+        if (threadIdx.x < kOffTile / kLvlTile && lb < nlvlblk) lm = blkmax[lb];
+        for (int o = kWave / 2; o > 0; o >>= 1) lm = max(lm, __shfl_xor(lm, o));
+    }
+    int tot;
+    const int ex = block_excl_scan(mine, &tot_s);   // barriers inside
+    tot = tot_s;
+    if (threadIdx.x == 0) {
+        lmax_s = lm;   // wave 0 holds the level blocks
+        __hip_atomic_store(stat + tile,
+                           (tile == 0 ? kOffIncl : kOffAgg) | ((unsigned long long)(lm & 255) << 32) |
+                               (uint32_t)tot,
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    // wave 0: the totals of the earlier tiles
+    if (wv == 0) {
+        unsigned long long cs = 0;
+        int ms = 0;
+        bool bad = false;
+        for (int64_t j = (int64_t)tile - 1; j >= 0 && !bad; j -= kWave) {
+            const int64_t jj = j - lane;
+            unsigned long long w = jj >= 0 ? __hip_atomic_load(stat + jj, __ATOMIC_RELAXED,
+                                                               __HIP_MEMORY_SCOPE_AGENT)
+                                          : kOffIncl;
+            int spins = 0;
+            while (__ballot((w >> 62) == 0ull) != 0ull) {
+                if (++spins > kLookbackSpin) {
+                    bad = true;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+                if ((w >> 62) == 0ull)
+                    w = __hip_atomic_load(stat + jj, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            if (bad) break;
+            // the words up to the nearest inclusive one (going back)
+            const unsigned long long inc = __ballot((w >> 62) == 2ull);
+            const int first = inc != 0ull ? __builtin_ctzll(inc) : kWave - 1;
+            unsigned long long cc = lane <= first ? (w & 0xffffffffull) : 0ull;
+            int mm = lane <= first ? (int)((w >> 32) & 255ull) : 0;
+            for (int o = kWave / 2; o > 0; o >>= 1) {
+                cc += __shfl_xor(cc, o);
+                mm = max(mm, __shfl_xor(mm, o));
+            }
+            cs += cc;
+            ms = max(ms, mm);
+            if (inc != 0ull) break;
+        }
+        if (lane == 0) {
+            if (bad) atomicOr(flags, UCP_FLAG_INTERNAL);
+            excl_s = cs;
+            const unsigned long long cin = cs + (unsigned long long)tot;
+            const int min_ = max(ms, lmax_s);
+            if (tile > 0)
+                __hip_atomic_store(stat + tile,
+                                   kOffIncl | ((unsigned long long)(min_ & 255) << 32) |
+                                       (uint32_t)cin,
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            // the tile holding position n has the totals
+            const int64_t tb = (int64_t)tile * kOffTile;
+            if (tb <= n && n < tb + kOffTile) {
+                ctr[CTR_MAXLEVEL] = (unsigned long long)min_;
+                if (cin > (unsigned long long)node_cap) atomicOr(flags, UCP_FLAG_NODE_OVERFLOW);
+            }
+        }
+    }
+    __syncthreads();
+    const int64_t k0t = (int64_t)excl_s + ex;
+    int64_t kk = k0t;
+#pragma unroll
+    for (int u = 0; u < kOffItems; ++u) {
+        if (p0 + u <= n) noff[p0 + u] = (int32_t)kk;
+        kk += c[u];
+    }
+    // the records of the nodes starting at this thread's positions
     if (*flags) return;
-    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if ((int64_t)noff[n] > node_cap) {
-        if (p == 0) atomicOr(flags, UCP_FLAG_NODE_OVERFLOW);
-        return;
-    }
-    const int Lp = p < n ? (int)Lv[p] : 0, lf = p < n ? (int)Lf[p] : 0;
-    // deepest leaf level: the maximum of the level pass's block maxima
-    if (blockIdx.x == 0) {
-        __shared__ int wmax[4];
-        int lmax = 0;
-        for (int i = threadIdx.x; i < nlvlblk; i += blockDim.x) lmax = max(lmax, blkmax[i]);
-        for (int o = 32; o > 0; o >>= 1) lmax = max(lmax, __shfl_xor(lmax, o));
-        if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = lmax;
-        __syncthreads();
-        if (threadIdx.x == 0)
-            ctr[CTR_MAXLEVEL] = (unsigned long long)max(max(wmax[0], wmax[1]), max(wmax[2], wmax[3]));
-    }
-    if (p >= n || lf <= Lp) return;
-    const int c = cloud_of(off, clouds, p);
-    const double4 xp = xq[p];
-    const double4 c0 = cube[2 * c], c1 = cube[2 * c + 1];
-    const int e = (int)c1.y;
-    const uint64_t top = (1ull << b) - 1;
-    const uint64_t X = quantise(xp.x, c0.x, c1.x, top), Y = quantise(xp.y, c0.y, c1.x, top),
-                   Z = quantise(xp.z, c0.z, c1.x, top);
-    const int k0 = noff[p];
-    for (int l = Lp + 1; l <= lf; ++l) {
-        const int k = k0 + (l - Lp - 1);
-        // box centre c_d = lo_d + (2 k_d + 1) 2^(e - l - 1); the product is exact
-        const double h = ldexp(1.0, e - l - 1);
-        const double cx = c0.x + (double)(2 * (X >> (b - l)) + 1) * h;
-        const double cy = c0.y + (double)(2 * (Y >> (b - l)) + 1) * h;
-        const double cz = c0.z + (double)(2 * (Z >> (b - l)) + 1) * h;
-        ngeo[k] = make_double4(cx, cy, cz, ldexp(1.0, 2 * (e - l)));
-        ninfo[k] = make_int4((int)p, 0, 0, l | (l == lf ? 256 : 0));
-        nlev[k] = (uint8_t)(l | (l == lf ? kLeafBit : 0));
-        if (l == 0) npar[k] = -1;   // other parents are set by the moments pass
+    kk = k0t;
+    for (int u = 0; u < kOffItems; ++u) {
+        const int64_t p = p0 + u;
+        const int k0 = (int)kk;
+        kk += c[u];
+        if (p >= n || c[u] == 0) continue;
+        if (kk > node_cap) return;   // flagged by the tile holding position n
+        const int Lp = Lv[p], lf = Lf[p];
+        const int cl = cloud_of(off, clouds, p);
+        const double4 xp = xq[p];
+        const double4 c0 = cube[2 * cl], c1 = cube[2 * cl + 1];
+        const int e = (int)c1.y;
+        const uint64_t top = (1ull << b) - 1;
+        const uint64_t X = quantise(xp.x, c0.x, c1.x, top), Y = quantise(xp.y, c0.y, c1.x, top),
+                       Z = quantise(xp.z, c0.z, c1.x, top);
+        for (int l = Lp + 1; l <= lf; ++l) {
+            const int k = k0 + (l - Lp - 1);
+            // box centre c_d = lo_d + (2 k_d + 1) 2^(e - l - 1); the product is exact
+            const double h = ldexp(1.0, e - l - 1);
+            const double cx = c0.x + (double)(2 * (X >> (b - l)) + 1) * h;
+            const double cy = c0.y + (double)(2 * (Y >> (b - l)) + 1) * h;
+            const double cz = c0.z + (double)(2 * (Z >> (b - l)) + 1) * h;
+            ngeo[k] = make_double4(cx, cy, cz, ldexp(1.0, 2 * (e - l)));
+            ninfo[k] = make_int4((int)p, 0, 0, l | (l == lf ? 256 : 0));
+            nlev[k] = (uint8_t)(l | (l == lf ? kLeafBit : 0));
+            if (l == 0) npar[k] = -1;   // other parents are set by the moments pass
+        }
     }
 }
 
@@ -1803,7 +1902,8 @@ void launch_build(Ctx *c, const double *x, const double *q, const int64_t *offse
                                                    (int64_t)kSortPassesMax * 256, 1}),
                                 kScanBlock),
                        dim3(kScanBlock), 0, s, c->d_mm, clouds, c->d_ctr, c->d_sortctl,
-                       c->d_ghist, c->d_hist, nstatus, offsets_in, n, chunk ? G : 0, c->d_off,
+                       c->d_ghist, c->d_hist, nstatus, c->d_offstat,
+                       (n + kOffTile) / kOffTile, offsets_in, n, chunk ? G : 0, c->d_off,
                        c->d_gcl, c->d_goff + n, c->d_wq, c->d_flags);
     c->walk_armed = true;
 
@@ -1899,14 +1999,14 @@ void launch_build(Ctx *c, const double *x, const double *q, const int64_t *offse
                        (const uint64_t *)c->d_skey, n, (const int64_t *)c->d_off, clouds, b, cap,
                        c->d_L, c->d_leaf, c->d_cnt, c->d_lend, c->d_lvlmax,
                        (const int32_t *)c->d_flags);
-    scan_excl((const int32_t *)c->d_cnt, c->d_noff, n + 1, c->d_scanblk, s);
-    // 5. nodes
-    hipLaunchKernelGGL(k_nodes, grid_for(n, 256), dim3(256), 0, s, (const double4 *)c->d_xq, n,
+    // 5. node offsets, the deepest leaf level and the node records
+    hipLaunchKernelGGL(k_offsets_nodes, grid_for(n + 1, kOffTile), dim3(kOffThreads), 0, s,
+                       (const int32_t *)c->d_cnt, (const int32_t *)c->d_lvlmax,
+                       (int)((n + 1 + kLvlTile - 1) / kLvlTile), (const double4 *)c->d_xq, n,
                        (const int64_t *)c->d_off, clouds, (const double4 *)c->d_cube, b,
-                       (const int8_t *)c->d_L, (const int8_t *)c->d_leaf,
-                       (const int32_t *)c->d_noff, c->node_cap, c->d_ngeo, c->d_ninfo, c->d_npar,
-                       c->d_nlev, (const int32_t *)c->d_lvlmax,
-                       (int)((n + 1 + kLvlTile - 1) / kLvlTile), c->d_ctr, c->d_flags);
+                       (const int8_t *)c->d_L, (const int8_t *)c->d_leaf, c->node_cap, c->d_noff,
+                       c->d_ngeo, c->d_ninfo, c->d_npar, c->d_nlev, c->d_offstat, c->d_ctr,
+                       c->d_flags);
     // 6. moments: every leaf, then the internal levels from the deepest up
     //    (and the per-species pseudo-particles when the walk uses them)
     double *spec = c->p.expansion == UCP_EXPANSION_SPECIES ? c->d_spec : nullptr;

@@ -31,7 +31,7 @@ constexpr int kSpecVals = 12;                   // doubles per node of the speci
 
 // device counter slots (unsigned long long)
 enum { CTR_P2P = 0, CTR_M2P = 1, CTR_MAXLEVEL = 2, CTR_BARRIER = 3, CTR_VJPMAX = 4,
-       CTR_UPCOUNT = 5, CTR_SORTFULL = 6, CTR_SORTBAR = 7, CTR_NCTR = 8 };
+       CTR_UPCOUNT = 5, CTR_SORTFULL = 6, CTR_SORTBAR = 7, CTR_OFFTICKET = 8, CTR_NCTR = 9 };
 // walk work queues: one per XCD, each on its own 128-byte line
 constexpr int kWalkQueues = 8, kQStride = 16;
 
@@ -117,6 +117,7 @@ struct Ctx {
     int32_t *d_cnt = nullptr;               // [n_max + 1] per-position counts to scan
     int32_t *d_lend = nullptr;              // [n_max + 1] end of the leaf starting there (-1: scan)
     int32_t *d_lvlmax = nullptr;            // [n_max / 256 + 2] deepest leaf level per level-pass block
+    unsigned long long *d_offstat = nullptr; // [n_max / 4096 + 2] look-back words of the node offsets
     int32_t *d_noff = nullptr;              // [n_max + 1] first node starting at the position
     int32_t *d_goff = nullptr;              // [n_max + 1] first group starting at the position
     int32_t *d_gnode = nullptr;             // [n_max]
