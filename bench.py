@@ -173,17 +173,29 @@ def wave_balance(ts):
     the waves that start with the launch take the groups and the rest start
     as those end, find the queues empty and stop.  Reported: the span of the
     walk, how many waves started with the launch, the spread of their end
-    times, and the share of their wave-time spent idle after their own end
-    (the tail of the walk)."""
+    times, the share of their wave-time spent idle after their own end
+    (the tail of the walk), and each compute unit's busy time (its first
+    wave's start to its last wave's end) as min, mean, max and max / mean
+    over the units."""
     import numpy as np
-    t = ts.wave_clock()
+    t, unit = ts.wave_clock(units=True)
     span = float(t[:, 1].max())
     first = t[:, 0] <= 0.02 * span
     ends = t[first, 1]
+    # per compute unit: busy from its first wave's start to its last wave's end
+    cus, inv = np.unique(unit, return_inverse=True)
+    busy = np.full(cus.shape[0], -np.inf)
+    np.maximum.at(busy, inv, t[:, 1])
+    start = np.full(cus.shape[0], np.inf)
+    np.minimum.at(start, inv, t[:, 0])
+    busy -= start
     return {"waves": int(t.shape[0]), "waves_at_launch": int(first.sum()), "span_us": span,
             "launch_wave_end_us": {"min": float(ends.min()), "p10": float(np.quantile(ends, 0.1)),
                                    "median": float(np.median(ends)), "max": float(ends.max())},
-            "launch_wave_idle_share": float(np.mean(span - ends) / span)}
+            "launch_wave_idle_share": float(np.mean(span - ends) / span),
+            "per_cu_busy_us": {"cus": int(cus.shape[0]), "min": float(busy.min()),
+                               "mean": float(busy.mean()), "max": float(busy.max()),
+                               "max_over_mean": float(busy.max() / busy.mean())}}
 
 
 def per_particle_rel(f, ref):

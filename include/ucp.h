@@ -288,9 +288,11 @@ ucp_status ucp_get_stats(ucp_ctx *c, ucp_stats *out, void *stream);
  *         6 per-group interaction counts of the last force call
  *         (int32[groups][2]: accepted boxes, P2P source particles)
  *         7 per-cloud cube (double[clouds][4]: lo xyz, e)
- *         8 the start and end of every wave of the last force walk launched
- *         with ucp_set_timing on (uint64[waves][2], ticks of the GPU's
- *         100 MHz real-time counter; waves = 4 * ceil(CUs * W / 4), W the
+ *         8 the start, end and compute unit of every wave of the last force
+ *         walk launched with ucp_set_timing on (uint64[waves][3]: start and
+ *         end in ticks of the GPU's 100 MHz real-time counter, then
+ *         XCC_ID << 32 | HW_ID as the hardware reports them, whose bits 8-15
+ *         with the XCC_ID name the CU; waves = 4 * ceil(CUs * W / 4), W the
  *         walk_waves parameter or 32 when it is 0): the balance of the
  *         persistent walk
  * Errors: UCP_EINVAL (unknown `which`, buffer too small).                  */

@@ -283,7 +283,10 @@ ucp_status ucp_create(ucp_ctx **out, int64_t n_max, int32_t clouds_max, const uc
     c->clouds_max = clouds_max;
     c->node_cap = 4 * n_max + 64 * (int64_t)clouds_max + 1024;
     if (c->node_cap > 0x7fffffffLL) c->node_cap = 0x7fffffffLL;
-    const int64_t ntiles = (n_max + ucp::kSortTile - 1) / ucp::kSortTile;
+    // status words of the sort: 256 per tile of kSortTile elements, and one
+    // tile more, which a pass over the wide tiles clears when n is an odd
+    // number of small tiles
+    const int64_t ntiles = (n_max + ucp::kSortTile - 1) / ucp::kSortTile + 1;
     c->hist_cap = 256 * ntiles;
     const int64_t scan_items = (int64_t)ucp::kScanBlock * ucp::kScanItems;
     const int64_t nblk = ((n_max + 1 > c->hist_cap ? n_max + 1 : c->hist_cap) + scan_items - 1) / scan_items + 2;
@@ -334,7 +337,7 @@ ucp_status ucp_create(ucp_ctx **out, int64_t n_max, int32_t clouds_max, const uc
     ALLOC(c->d_wq, ucp::kWalkQueues * ucp::kQStride);
     ALLOC(c->d_flags, 4);
     ALLOC(c->d_epart, 4 * 256);
-    ALLOC(c->d_wclock, 2 * ((size_t)std::max(c->num_cu, 1) * 64 + 4));
+    ALLOC(c->d_wclock, 3 * ((size_t)std::max(c->num_cu, 1) * 64 + 4));
 #undef ALLOC
     // set-up of this device's static adjoint scratch (ucp_force_vjp_noalloc)
     void *scratch_dev = nullptr;
@@ -629,7 +632,7 @@ ucp_status ucp_debug_copy(ucp_ctx *c, int32_t which, void *dst, int64_t bytes, v
     case 5: src = c->d_groups; need = 16 * (int64_t)groups; break;
     case 6: src = c->d_gstat; need = 8 * (int64_t)groups; break;
     case 7: src = c->d_cube; need = 32 * (int64_t)c->clouds; break;
-    case 8: src = c->d_wclock; need = 16 * c->wclock_waves; break;
+    case 8: src = c->d_wclock; need = 24 * c->wclock_waves; break;
     default: return fail(c, UCP_EINVAL, "ucp_debug_copy: unknown array");
     }
     if (bytes < need) return fail(c, UCP_EINVAL, "ucp_debug_copy: buffer too small, need " + std::to_string(need));

@@ -451,7 +451,7 @@ static void scan_excl(const int32_t *in, int32_t *out, int64_t n, int32_t *blk, 
 //    once.
 //    The digit counts of every pass are found first, in one kernel (they do
 //    not depend on the order).  Each pass is one kernel: a tile of kSortTile
-//    elements is ranked (inside a round of kSortThreads each wave ranks equal
+//    elements (twice that above kSortWideN particles) is ranked (inside a round of kSortThreads each wave ranks equal
 //    digits with ballots, and the waves and rounds are ordered through LDS),
 //    its digit counts are published, its digit prefixes over the earlier
 //    tiles are found by a decoupled look-back, and the tile is scattered.
@@ -505,33 +505,44 @@ constexpr int kLookbackSpin = 1 << 18;
 constexpr int kLbSeg = 4;
 static_assert(kSortThreads == 4 * 256, "the look-back takes four lanes per digit");
 
-// LDS of one tile of a pass
-struct SortLds {
-    uint32_t wh[kSortItems][kSortThreads / 64][256];   // per-(round, wave) digit counts, then offsets
+// LDS of one tile of a pass, ITEMS rounds of kSortThreads elements
+template <int ITEMS>
+struct SortLdsT {
+    uint32_t wh[ITEMS][kSortThreads / 64][256];   // per-(round, wave) digit counts, then offsets
     uint32_t boff[256], rsh[256], bsh[256];
     int btot, tile_sh;
 };
+using SortLds = SortLdsT<kSortItems>;
+// The passes over the top digits of a cloud above kSortWideN particles take
+// tiles of kSortWideItems rounds: half as many tiles, so the look-backs are
+// half as long, while there are still more tiles than CUs (N = 4,194,304:
+// 1024 tiles of 4096 keys).  Below it the tiles of kSortItems rounds keep
+// every CU busy.  Status words stay laid out per tile of kSortTile elements
+// (that is what the gated full sort uses), so a pass over wide tiles clears
+// the next pass's words of every small tile it covers.
+constexpr int kSortWideItems = 2 * kSortItems;
+constexpr int64_t kSortWideN = int64_t(1) << 20;
 
 // One tile of a pass: ranked, its counts published, its prefixes found by the
 // look-back, scattered.  `below` is, on thread tid < 256, the exclusive prefix
 // of digit tid over the pass's digit totals; L.wh is zero on entry.
-template <bool CLOUD>
+template <bool CLOUD, int ITEMS>
 __device__ __forceinline__ void radix_tile(
-    SortLds &L, int tile, int below, const uint64_t *__restrict__ kin,
+    SortLdsT<ITEMS> &L, int tile, int below, const uint64_t *__restrict__ kin,
     const uint32_t *__restrict__ vin, uint64_t *kout, uint32_t *vout, int64_t n, int shift,
     const int64_t *__restrict__ off, int clouds, uint32_t *status, uint32_t *status_next,
     const double4 *__restrict__ xin, double4 *xq, int32_t *flags)
 {
     constexpr int NW = kSortThreads / 64;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int64_t base = (int64_t)tile * kSortTile;
+    const int64_t base = (int64_t)tile * (kSortThreads * ITEMS);
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    uint64_t k[kSortItems];
-    uint32_t v[kSortItems], d[kSortItems], lrank[kSortItems];
-    bool valid[kSortItems];
-    double4 g[kSortItems];
+    uint64_t k[ITEMS];
+    uint32_t v[ITEMS], d[ITEMS], lrank[ITEMS];
+    bool valid[ITEMS];
+    double4 g[ITEMS];
 #pragma unroll
-    for (int it = 0; it < kSortItems; ++it) {
+    for (int it = 0; it < ITEMS; ++it) {
         const int64_t e = base + it * kSortThreads + tid;
         valid[it] = e < n;
         k[it] = valid[it] ? kin[e] : 0ull;
@@ -543,7 +554,7 @@ __device__ __forceinline__ void radix_tile(
     // and the look-back
     if (xq) {
 #pragma unroll
-        for (int it = 0; it < kSortItems; ++it) {
+        for (int it = 0; it < ITEMS; ++it) {
             const int64_t i = v[it];
             const bool in = valid[it] && i < n;   // always, unless the records are inconsistent
             if (valid[it] && !in) atomicOr(flags, UCP_FLAG_INTERNAL);
@@ -552,7 +563,7 @@ __device__ __forceinline__ void radix_tile(
     }
     // rank equal digits inside each wave and round
 #pragma unroll
-    for (int it = 0; it < kSortItems; ++it) {
+    for (int it = 0; it < ITEMS; ++it) {
         uint64_t peers = __ballot(valid[it]);
         for (int bit = 0; bit < 8; ++bit) {
             const uint64_t bb = __ballot((d[it] >> bit) & 1u);
@@ -565,7 +576,7 @@ __device__ __forceinline__ void radix_tile(
     if (tid < 256) {
         // the tile's count of digit tid, and each (round, wave)'s offset inside it
         uint32_t r = 0;
-        for (int it = 0; it < kSortItems; ++it)
+        for (int it = 0; it < ITEMS; ++it)
             for (int ww = 0; ww < NW; ++ww) {
                 const uint32_t c = L.wh[it][ww][tid];
                 L.wh[it][ww][tid] = r;
@@ -576,7 +587,11 @@ __device__ __forceinline__ void radix_tile(
                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         L.rsh[tid] = r;
         L.bsh[tid] = (uint32_t)below;
-        status_next[(int64_t)tile * 256 + tid] = 0u;   // the next pass's status
+        // the next pass's status words, for every tile of kSortTile elements
+        // that this tile covers
+#pragma unroll
+        for (int r = 0; r < ITEMS / kSortItems; ++r)
+            status_next[((int64_t)tile * (ITEMS / kSortItems) + r) * 256 + tid] = 0u;
     }
     __syncthreads();
     // look-back over the earlier tiles' published words, four lanes per digit
@@ -636,7 +651,7 @@ __device__ __forceinline__ void radix_tile(
     }
     __syncthreads();
 #pragma unroll
-    for (int it = 0; it < kSortItems; ++it)
+    for (int it = 0; it < ITEMS; ++it)
         if (valid[it]) {
             const uint32_t dst = L.boff[d[it]] + L.wh[it][w][d[it]] + lrank[it];
             if ((int64_t)dst >= n) {   // only inconsistent prefixes lead here
@@ -649,24 +664,24 @@ __device__ __forceinline__ void radix_tile(
         }
 }
 
-// one pass, one tile per block
-template <bool CLOUD>
+// one pass, one tile of ITEMS rounds per block
+template <bool CLOUD, int ITEMS>
 __global__ __launch_bounds__(kSortThreads) void k_radix_pass(
     const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint64_t *kout,
     uint32_t *vout, int64_t n, int shift, const int64_t *__restrict__ off, int clouds,
     const uint32_t *__restrict__ ghist, uint32_t *status, uint32_t *status_next,
     uint32_t *ticket, const double4 *__restrict__ xin, double4 *xq, int32_t *flags)
 {
-    __shared__ SortLds L;
+    __shared__ SortLdsT<ITEMS> L;
     if (*flags) return;
     const int tid = threadIdx.x;
     if (tid == 0) L.tile_sh = (int)atomicAdd(ticket, 1u);
-    for (int j = tid; j < kSortItems * (kSortThreads / 64) * 256; j += kSortThreads)
+    for (int j = tid; j < ITEMS * (kSortThreads / 64) * 256; j += kSortThreads)
         (&L.wh[0][0][0])[j] = 0;
     // digit totals of this pass and their exclusive prefix over the digits
     const uint32_t tot = tid < 256 ? ghist[tid] : 0u;
     const int below = block_excl_scan((int)tot, &L.btot);   // synchronises the block
-    radix_tile<CLOUD>(L, L.tile_sh, below, kin, vin, kout, vout, n, shift, off, clouds, status,
+    radix_tile<CLOUD, ITEMS>(L, L.tile_sh, below, kin, vin, kout, vout, n, shift, off, clouds, status,
                       status_next, xin, xq, flags);
 }
 
@@ -716,10 +731,10 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_full(
             const int tile = L.tile_sh;
             if (tile >= ntiles) break;   // the same on every thread of the block
             if (P.cloud)
-                radix_tile<true>(L, tile, below, P.kin, P.vin, P.kout, P.vout, n, P.shift, off,
+                radix_tile<true, kSortItems>(L, tile, below, P.kin, P.vin, P.kout, P.vout, n, P.shift, off,
                                  clouds, P.status, P.status_next, xin, P.xq, flags);
             else
-                radix_tile<false>(L, tile, below, P.kin, P.vin, P.kout, P.vout, n, P.shift, off,
+                radix_tile<false, kSortItems>(L, tile, below, P.kin, P.vin, P.kout, P.vout, n, P.shift, off,
                                   clouds, P.status, P.status_next, xin, P.xq, flags);
             __syncthreads();
         }
@@ -1919,7 +1934,7 @@ void launch_build(Ctx *c, const double *x, const double *q, const int64_t *offse
     const int key_passes = (3 * b + 7) / 8;
     // three top digits (boxes of level 7-8) leave runs of a few particles up
     // to about 2^20 particles; above that a fourth keeps ranking cheap
-    const int top_passes = std::min(n > (int64_t(1) << 20) ? 4 : 3, key_passes);
+    const int top_passes = std::min(n > kSortWideN ? 4 : 3, key_passes);
     int cloud_passes = 0;
     if (clouds > 1) {
         int cbits = 0;
@@ -1956,20 +1971,18 @@ void launch_build(Ctx *c, const double *x, const double *q, const int64_t *offse
     for (int d = key_passes - top_passes; d < key_passes; ++d) digits.push_back(d);
     for (int d = 0; d < cloud_passes; ++d) digits.push_back(key_passes + d);
     int cur = 0;
+    const bool wide = n > kSortWideN;
+    const int ptiles = wide ? (int)((n + kSortThreads * kSortWideItems - 1) / (kSortThreads * kSortWideItems))
+                            : ntiles;
     for (size_t i = 0; i < digits.size(); ++i) {
         // the first pass goes to the buffer that makes the last one land in 1
         const int to = i == 0 ? ((digits.size() - 1) % 2 == 0 ? 1 : 2) : (cur == 1 ? 2 : 1);
         const SortPassArgs a = pass_args(cur, to, digits[i], nullptr);
-        if (a.cloud)
-            hipLaunchKernelGGL(k_radix_pass<true>, dim3(ntiles), dim3(kSortThreads), 0, s, a.kin,
-                               a.vin, a.kout, a.vout, n, a.shift, (const int64_t *)c->d_off,
-                               clouds, a.ghist, a.status, a.status_next, a.ticket,
-                               (const double4 *)c->d_xin, a.xq, c->d_flags);
-        else
-            hipLaunchKernelGGL(k_radix_pass<false>, dim3(ntiles), dim3(kSortThreads), 0, s, a.kin,
-                               a.vin, a.kout, a.vout, n, a.shift, (const int64_t *)c->d_off,
-                               clouds, a.ghist, a.status, a.status_next, a.ticket,
-                               (const double4 *)c->d_xin, a.xq, c->d_flags);
+        auto kern = a.cloud ? (wide ? k_radix_pass<true, kSortWideItems> : k_radix_pass<true, kSortItems>)
+                            : (wide ? k_radix_pass<false, kSortWideItems> : k_radix_pass<false, kSortItems>);
+        hipLaunchKernelGGL(kern, dim3(ptiles), dim3(kSortThreads), 0, s, a.kin, a.vin, a.kout,
+                           a.vout, n, a.shift, (const int64_t *)c->d_off, clouds, a.ghist, a.status,
+                           a.status_next, a.ticket, (const double4 *)c->d_xin, a.xq, c->d_flags);
         cur = to;
     }
     // each run of equal top digits ordered by ranking, into buffer 2

@@ -168,8 +168,8 @@ struct Ctx {
     int timing = 0;
     std::vector<hipEvent_t> ev;             // pairs
     int64_t ev_used = 0;
-    unsigned long long *d_wclock = nullptr; // [2 * num_cu * 64] start and end of every wave of
-                                            // the last walk launched with timing on
+    unsigned long long *d_wclock = nullptr; // [3 * num_cu * 64] start, end and unit of every
+                                            // wave of the last walk launched with timing on
     int64_t wclock_waves = 0;               // waves of that walk
 
     std::string err;

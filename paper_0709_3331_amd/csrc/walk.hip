@@ -77,7 +77,7 @@ struct WalkArgs {
     const double *spec;     // per-species pseudo-particles (UCP_EXPANSION_SPECIES)
     double theta;
     int L;
-    unsigned long long *wclock;   // or null: each wave's start and end (real-time counter)
+    unsigned long long *wclock;   // or null: each wave's start, end (real-time counter) and unit
 };
 
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -1017,13 +1017,22 @@ __device__ __forceinline__ void walk_body(const WalkArgs &a)
     }
 }
 
-// each wave's own busy span (start, end), for the balance of the persistent
-// waves, when the launch asks for it
+// each wave's own busy span (start, end) and the compute unit it ran on, for
+// the balance of the persistent waves, when the launch asks for it.  The unit
+// is read at the start from the hardware registers HW_ID (CU, shader array and
+// shader engine in bits 8-15) and XCC_ID (the XCD), kept as XCC_ID << 32 |
+// HW_ID.
 __device__ __forceinline__ void wave_stamp(unsigned long long *wclock, int end)
 {
-    if (wclock && (threadIdx.x & 63) == 0)
-        wclock[2 * (4 * (int64_t)blockIdx.x + (threadIdx.x >> 6)) + end] =
-            __builtin_amdgcn_s_memrealtime();
+    if (wclock && (threadIdx.x & 63) == 0) {
+        unsigned long long *w = wclock + 3 * (4 * (int64_t)blockIdx.x + (threadIdx.x >> 6));
+        w[end] = __builtin_amdgcn_s_memrealtime();
+        if (!end) {
+            const unsigned hw = __builtin_amdgcn_s_getreg((31 << 11) | 4);    // HW_ID, 32 bits
+            const unsigned xcc = __builtin_amdgcn_s_getreg((31 << 11) | 20);  // XCC_ID, 32 bits
+            w[2] = (unsigned long long)xcc << 32 | hw;
+        }
+    }
 }
 
 template <int PREC, int MODE, bool KELBG, bool SPEC>

@@ -110,16 +110,25 @@ class TreeSolver:
     def timing_read(self):
         return L.ucp_timing_read(self.h)
 
-    def wave_clock(self):
+    def wave_clock(self, units=False):
         """Start and end (microseconds, from the first start) of every wave of
-        the last force walk launched with timing on: array [waves, 2]."""
+        the last force walk launched with timing on: array [waves, 2].  With
+        units=True also the compute unit each wave ran on, as one integer per
+        wave (XCD * 256 + bits 8-15 of the wave's HW_ID: CU, shader array and
+        shader engine)."""
         cu = torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count
         w = self.params.walk_waves if self.params.walk_waves > 0 else 32
         waves = 4 * ((cu * w + 3) // 4)
-        out = np.zeros((waves, 2), dtype=np.uint64)
+        out = np.zeros((waves, 3), dtype=np.uint64)
         L.ucp_debug_copy(self.h, 8, out.ctypes.data_as(C.c_void_p), out.nbytes, _stream())
-        t = out.astype(np.float64) / 100.0   # 100 MHz real-time counter
-        return t - t[:, 0].min()
+        t = out[:, :2].astype(np.float64) / 100.0   # 100 MHz real-time counter
+        t = t - t[:, 0].min()
+        if not units:
+            return t
+        ids = out[:, 2]
+        unit = ((ids >> np.uint64(32)) & np.uint64(0xF)) * np.uint64(256) + \
+            ((ids >> np.uint64(8)) & np.uint64(0xFF))
+        return t, unit.astype(np.int64)
 
     # -- introspection (host numpy arrays)
     def debug(self, which):

@@ -217,6 +217,30 @@ def test_sort_falls_back_to_the_full_sort_for_long_runs(batched):
         ts.close()
 
 
+def test_sort_with_wide_tiles_above_2_20_particles():
+    # Above 2^20 particles the radix passes take tiles of 4096 keys over the
+    # top four digits.  An odd number of 2048-key tiles makes the last wide
+    # tile clear the status words of one small tile past the end; the
+    # clustered case then runs the gated full sort, whose 2048-key tiles read
+    # status words that the wide passes cleared.
+    n = 2 ** 20 + 2048 * 2 + 100
+    assert (n + 2047) // 2048 % 2 == 1
+    xg = inputs.gaussian_cloud(n, 1.0, 1e-3, 1e-5, 510)
+    xc, qc = _clustered(3000, n - 3000, 83)
+    assert _top_run(xc, bits=31) > 2048
+    ts = TreeSolver(n, theta=0.5, eps=0.005)
+    for name, x, q in (("gaussian", xg.x, xg.q), ("clustered", xc, qc)):
+        say(f"[sort] wide tiles, {name}, n={n}")
+        ts.build(torch.from_numpy(x).cuda(), torch.from_numpy(q).cuda())
+        st = ts.stats()
+        keys, perm = ts.debug("keys"), ts.debug("perm").astype(np.int64)
+        t = oracle.Tree(x, q, 0.5, 0.005)
+        np.testing.assert_array_equal(keys, t.sorted_keys())
+        np.testing.assert_array_equal(perm, t.perm())
+        assert st["nodes"] == t.nnodes
+    ts.close()
+
+
 def test_full_sort_with_several_tiles_per_block():
     # 295 tiles of 2048 keys: more than the full sort's resident blocks, so
     # each block takes several tiles per pass

@@ -425,11 +425,24 @@ def test_wave_clocks_of_a_timed_walk():
     ts.timing(True)
     ts.forces(cl.n)
     ms, launches = ts.timing_read()
-    t = ts.wave_clock()
+    t, unit = ts.wave_clock(units=True)
     ts.timing(False)
     ts.stats()
     ts.close()
-    say(f"[clock] waves={t.shape[0]} span {t[:, 1].max():.1f} us, event {1e3 * ms:.1f} us")
+    ncu = torch.cuda.get_device_properties(0).multi_processor_count
+    cus, counts = np.unique(unit, return_counts=True)
+    say(f"[clock] waves={t.shape[0]} span {t[:, 1].max():.1f} us, event {1e3 * ms:.1f} us; "
+        f"{cus.shape[0]} units of {ncu} CUs, waves per unit {counts.min()}-{counts.max()}")
     assert launches == 1
     assert t.shape[0] % 4 == 0 and np.all(t[:, 1] >= t[:, 0]) and t[:, 0].min() == 0.0
     assert t[:, 1].max() <= 1e3 * ms + 20.0
+    # the units name the CUs: every CU runs waves of the launch (8 blocks of
+    # 4 waves per CU), and no unit ever holds more waves at once than a CU can
+    # (4 per SIMD under the walk's LDS)
+    assert cus.shape[0] == ncu
+    for u in cus:
+        iv = t[unit == u]
+        ev = np.concatenate([np.stack([iv[:, 0], np.ones(len(iv))], 1),
+                             np.stack([iv[:, 1], -np.ones(len(iv))], 1)])
+        ev = ev[np.lexsort((ev[:, 1], ev[:, 0]))]   # at equal times, ends first
+        assert np.cumsum(ev[:, 1]).max() <= 16, f"unit {u} holds more than 16 waves at once"
