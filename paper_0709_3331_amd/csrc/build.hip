@@ -451,8 +451,9 @@ static void scan_excl(const int32_t *in, int32_t *out, int64_t n, int32_t *blk, 
 //    once.
 //    The digit counts of every pass are found first, in one kernel (they do
 //    not depend on the order).  Each pass is one kernel: a tile of kSortTile
-//    elements (twice that above kSortWideN particles) is ranked (inside a round of kSortThreads each wave ranks equal
-//    digits with ballots, and the waves and rounds are ordered through LDS),
+//    elements (twice that above kSortWideN particles) is ranked (inside a
+//    round of kSortThreads each wave ranks equal digits with ballots, and the
+//    waves and rounds are ordered through LDS),
 //    its digit counts are published, its digit prefixes over the earlier
 //    tiles are found by a decoupled look-back, and the tile is scattered.
 // ---------------------------------------------------------------------------
@@ -513,8 +514,8 @@ struct SortLdsT {
     int btot, tile_sh;
 };
 using SortLds = SortLdsT<kSortItems>;
-// The passes over the top digits of a cloud above kSortWideN particles take
-// tiles of kSortWideItems rounds: half as many tiles, so the look-backs are
+// The passes of a build of more than kSortWideN particles take tiles of
+// kSortWideItems rounds: half as many tiles, so the look-backs are
 // half as long, while there are still more tiles than CUs (N = 4,194,304:
 // 1024 tiles of 4096 keys).  Below it the tiles of kSortItems rounds keep
 // every CU busy.  Status words stay laid out per tile of kSortTile elements
@@ -590,8 +591,8 @@ __device__ __forceinline__ void radix_tile(
         // the next pass's status words, for every tile of kSortTile elements
         // that this tile covers
 #pragma unroll
-        for (int r = 0; r < ITEMS / kSortItems; ++r)
-            status_next[((int64_t)tile * (ITEMS / kSortItems) + r) * 256 + tid] = 0u;
+        for (int h = 0; h < ITEMS / kSortItems; ++h)
+            status_next[((int64_t)tile * (ITEMS / kSortItems) + h) * 256 + tid] = 0u;
     }
     __syncthreads();
     // look-back over the earlier tiles' published words, four lanes per digit
@@ -681,8 +682,8 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_pass(
     // digit totals of this pass and their exclusive prefix over the digits
     const uint32_t tot = tid < 256 ? ghist[tid] : 0u;
     const int below = block_excl_scan((int)tot, &L.btot);   // synchronises the block
-    radix_tile<CLOUD, ITEMS>(L, L.tile_sh, below, kin, vin, kout, vout, n, shift, off, clouds, status,
-                      status_next, xin, xq, flags);
+    radix_tile<CLOUD, ITEMS>(L, L.tile_sh, below, kin, vin, kout, vout, n, shift, off, clouds,
+                             status, status_next, xin, xq, flags);
 }
 
 // The passes of the full sort behind the finish, in one launch whose blocks
@@ -731,11 +732,13 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_full(
             const int tile = L.tile_sh;
             if (tile >= ntiles) break;   // the same on every thread of the block
             if (P.cloud)
-                radix_tile<true, kSortItems>(L, tile, below, P.kin, P.vin, P.kout, P.vout, n, P.shift, off,
-                                 clouds, P.status, P.status_next, xin, P.xq, flags);
+                radix_tile<true, kSortItems>(L, tile, below, P.kin, P.vin, P.kout, P.vout, n,
+                                             P.shift, off, clouds, P.status, P.status_next, xin,
+                                             P.xq, flags);
             else
-                radix_tile<false, kSortItems>(L, tile, below, P.kin, P.vin, P.kout, P.vout, n, P.shift, off,
-                                  clouds, P.status, P.status_next, xin, P.xq, flags);
+                radix_tile<false, kSortItems>(L, tile, below, P.kin, P.vin, P.kout, P.vout, n,
+                                              P.shift, off, clouds, P.status, P.status_next, xin,
+                                              P.xq, flags);
             __syncthreads();
         }
         // every block passes every barrier, so that the count of arrivals
@@ -1972,14 +1975,16 @@ void launch_build(Ctx *c, const double *x, const double *q, const int64_t *offse
     for (int d = 0; d < cloud_passes; ++d) digits.push_back(key_passes + d);
     int cur = 0;
     const bool wide = n > kSortWideN;
-    const int ptiles = wide ? (int)((n + kSortThreads * kSortWideItems - 1) / (kSortThreads * kSortWideItems))
-                            : ntiles;
+    constexpr int kWideTile = kSortThreads * kSortWideItems;
+    const int ptiles = wide ? (int)((n + kWideTile - 1) / kWideTile) : ntiles;
     for (size_t i = 0; i < digits.size(); ++i) {
         // the first pass goes to the buffer that makes the last one land in 1
         const int to = i == 0 ? ((digits.size() - 1) % 2 == 0 ? 1 : 2) : (cur == 1 ? 2 : 1);
         const SortPassArgs a = pass_args(cur, to, digits[i], nullptr);
-        auto kern = a.cloud ? (wide ? k_radix_pass<true, kSortWideItems> : k_radix_pass<true, kSortItems>)
-                            : (wide ? k_radix_pass<false, kSortWideItems> : k_radix_pass<false, kSortItems>);
+        auto kern = a.cloud ? (wide ? k_radix_pass<true, kSortWideItems>
+                                    : k_radix_pass<true, kSortItems>)
+                            : (wide ? k_radix_pass<false, kSortWideItems>
+                                    : k_radix_pass<false, kSortItems>);
         hipLaunchKernelGGL(kern, dim3(ptiles), dim3(kSortThreads), 0, s, a.kin, a.vin, a.kout,
                            a.vout, n, a.shift, (const int64_t *)c->d_off, clouds, a.ghist, a.status,
                            a.status_next, a.ticket, (const double4 *)c->d_xin, a.xq, c->d_flags);
