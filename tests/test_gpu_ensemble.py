@@ -43,8 +43,14 @@ def test_full_ensemble_sampled_clouds_match_oracle():
         f = ts.tree_forces(x, q, offs).cpu().numpy()
         st = ts.stats()
         assert st["clouds"] == clouds
+        # above 2^20 particles the sort's passes (cloud digits included) take
+        # 4096-key tiles: each sampled cloud's keys and order bit-exact
+        keys, perm = ts.debug("keys"), ts.debug("perm").astype(np.int64)
         for c in pick:
             a, b = off[c], off[c + 1]
+            t = oracle.Tree(ens.x[a:b], ens.q[a:b], prm["theta"], prm["eps"])
+            np.testing.assert_array_equal(keys[a:b], t.sorted_keys())
+            np.testing.assert_array_equal(perm[a:b] - a, t.perm())
             ref = oracle.tree_forces(ens.x[a:b], ens.q[a:b], prm["theta"], prm["eps"], G=64)
             e = relrms(f[a:b], ref["f"])
             say(f"[ensemble]   prec={prec} cloud {c} (N={b - a}) rel RMS {e:.3e}")
