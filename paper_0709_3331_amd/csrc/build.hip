@@ -1780,9 +1780,24 @@ __global__ __launch_bounds__(kUpperThreads) void k_moments_upper(
     held.k = -1;
     held.l = -1;
     if (t0 < cnt) held = node_at(t0);
+    // the deepest level of a listed node: the levels below it hold none.
+    // Every block reads the whole list, so all agree on the number of levels
+    // (and of grid barriers).
+    __shared__ int lbig_s;
+    if (threadIdx.x == 0) lbig_s = -1;
+    __syncthreads();
+    int lb = -1;
+    for (int i = threadIdx.x; i < cnt; i += kUpperThreads) {
+        const int k = uplist[i];
+        if (k >= 0 && k < nn) lb = max(lb, (int)nlev[k]);
+    }
+    for (int o = 32; o > 0; o >>= 1) lb = max(lb, __shfl_xor(lb, o));
+    if ((threadIdx.x & 63) == 0) atomicMax(&lbig_s, lb);
+    __syncthreads();
+    const int ltop = min(lbig_s, maxl - 1);
     unsigned long long target = 0;
     bool wait = true;
-    for (int l = maxl - 1; l >= 0; --l) {
+    for (int l = ltop; l >= 0; --l) {
         // one reading of the flags for the whole block, so that its threads
         // agree on every loop bound below
         if (threadIdx.x == 0)
