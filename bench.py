@@ -421,6 +421,59 @@ def bench_large(args, prec, dev):
             "sampled_groups": int(len(range(0, t.ngroups, 997))), "sampled_targets": 1024}
 
 
+def vjp_timing(args, dev):
+    """The force VJP beside the forward walk on the N = 65,536 cloud of the
+    differentiable rollout (theta = 0.5, eps = 0.01), same tree: --warmup
+    untimed pairs, then --steps forward walks (HIP events around each walk
+    launch) and --steps VJPs (torch events on the stream the library launches
+    on, around the whole call: the adjoint walk with its preparation and the
+    push down to the particles).  The cotangent u is standard normal."""
+    import numpy as np
+    import torch
+
+    from paper_0709_3331_amd import _lib as L
+    from paper_0709_3331_amd import inputs
+    from paper_0709_3331_amd.tree import TreeSolver
+
+    cl, prm = inputs.adjoint(0)
+    n = cl.n
+    prec = L.UCP_SPLIT if args.precision == "split" else L.UCP_FP64
+    x, q = (torch.from_numpy(a).to(dev) for a in (cl.x, cl.q))
+    gm = L.UCP_GROUP_CHUNK if args.group_mode == "chunk" else L.UCP_GROUP_NODE
+    ts = TreeSolver(n, curve=CURVE, theta=prm["theta"], eps=prm["eps"], precision=prec,
+                    group_size=args.group_size, list_len=args.list_len, group_mode=gm,
+                    leaf_cap=args.leaf_cap, walk_waves=args.walk_waves)
+    ts.tree_forces(x, q)
+    st = ts.stats()
+    u = torch.from_numpy(np.random.default_rng(1).standard_normal((n, 3))).to(dev)
+    for _ in range(args.warmup):
+        ts.forces(n)
+        ts.vjp(u)
+    torch.cuda.synchronize()
+    ts.timing(True)
+    for _ in range(args.steps):
+        ts.forces(n)
+    torch.cuda.synchronize()
+    fwd_tot, launches = ts.timing_read()
+    fwd_ms = fwd_tot / max(launches, 1)
+    ts.timing(False)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        ts.vjp(u)
+    e1.record()
+    torch.cuda.synchronize()
+    vjp_ms = e0.elapsed_time(e1) / args.steps
+    ts.check()
+    ts.close()
+    return {"workload": f"N={n} Gaussian cloud (sigma=1), theta={prm['theta']}, eps={prm['eps']}, "
+                        f"G={args.group_size} ({args.group_mode} groups), leaf_cap={args.leaf_cap}",
+            "n": n, "precision": args.precision, "steps": args.steps, "warmup": args.warmup,
+            "forward_walk_ms": fwd_ms, "forward_walk_launches": launches, "vjp_ms": vjp_ms,
+            "vjp_over_forward_walk": vjp_ms / fwd_ms, "m2p": st["m2p"], "p2p": st["p2p"],
+            "interactions_per_particle": (st["m2p"] + st["p2p"]) / n}
+
+
 def bench_adjoint(prec, dev):
     """Differentiable rollout of the N = 65,536 cloud (eps = 0.01, checkpoint
     every 20 steps); loss = final ion kinetic energy; gradient with respect to
@@ -754,10 +807,12 @@ def main():
     ap.add_argument("--study", choices=["opening", "relaxation"],
                     help="run a study instead of the benchmark and print its JSON line")
     ap.add_argument("--study-dt", type=float, default=1e-6, help="time step of the study")
-    ap.add_argument("--workload", choices=["metric", "large"], default="metric",
+    ap.add_argument("--workload", choices=["metric", "large", "adjoint"], default="metric",
                     help="metric: the N=524,288 cloud (the benchmark); large: the N=4,194,304 "
                          "cloud (eps=0.002, 10%% hot electrons) under the same step protocol, "
-                         "for profiling its build")
+                         "for profiling its build; adjoint: the N=65,536 cloud of the "
+                         "differentiable rollout, --steps forward walks and force VJPs timed "
+                         "(prints that JSON line instead of the benchmark's)")
     args = ap.parse_args()
     global CURVE
     CURVE = 1 if args.curve == "hilbert" else 0
@@ -781,6 +836,9 @@ def main():
         return
     if args.study == "relaxation":
         print(json.dumps({"command": command, **relaxation_study(dev)}), flush=True)
+        return
+    if args.workload == "adjoint":
+        print(json.dumps({"command": command, **vjp_timing(args, dev)}), flush=True)
         return
     cl, prm = inputs.metric(0) if args.workload == "metric" else inputs.large(0)
     n = cl.n
