@@ -44,6 +44,8 @@ namespace ucp {
 
 // what a walk launch computes
 enum { kWalkForce = 0, kWalkForcePhi = 1, kWalkVjp = 2 };
+// at most this many waves share an adjoint group's evaluation
+constexpr int kMaxParts = 4;
 
 struct WalkArgs {
     const double4 *xq;
@@ -78,6 +80,7 @@ struct WalkArgs {
     double theta;
     int L;
     unsigned long long *wclock;   // or null: each wave's start, end (real-time counter) and unit
+    int parts;              // adjoint: waves that share a group's evaluation (1 otherwise)
 };
 
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -474,6 +477,7 @@ struct Target {
     int i;                       // sorted index of the lane's target
     double E0, E1, E2, PH;       // field and potential, or the target-side adjoint
     double C0, C1, C2;           // adjoint: the lane's share of the cube-origin cotangent
+    int part, ck;                // adjoint: this wave's share of the group, chunks seen
 };
 
 // Evaluate the M2P and P2P index lists of a group.  Entries are staged into
@@ -494,7 +498,15 @@ __device__ __forceinline__ void flush_lists(const WalkArgs &a, const int4 *ml, i
     const T inv_lam = PREC == UCP_SPLIT ? (T)a.inv_lambdaf : (T)a.inv_lambda;
     const T tx = tg.tx, ty = tg.ty, tz = tg.tz;
     wave_sync();   // the lists were written by other lanes
+    // adjoint with the group shared by a.parts waves: every wave builds the
+    // same lists, and each staged chunk of boxes or source particles is
+    // evaluated by one of them, in turn
+    auto mine = [&]() {
+        if constexpr (ADJ) return a.parts == 1 || tg.ck++ % a.parts == tg.part;
+        else return true;
+    };
     for (int base = 0; base < nm; base += 64) {
+        if (!mine()) continue;
         const int cnt = min(64, nm - base);
         const int4 ent = ml[base + (lane < cnt ? lane : cnt - 1)];
         const int k = ent.x;
@@ -617,6 +629,7 @@ __device__ __forceinline__ void flush_lists(const WalkArgs &a, const int4 *ml, i
         lfirst[lane] = lf.x - (incl - cl);   // particle j = lfirst[l] + (global offset)
         wave_sync();
         for (int pb = 0; pb < total; pb += 64) {
+            if (!mine()) continue;
             const int ncur = min(64, total - pb);
             const int P = pb + (lane < ncur ? lane : ncur - 1);
             // leaf holding concatenated particle P: first l with pfx[l] > P
@@ -745,6 +758,9 @@ __device__ __forceinline__ void walk_body(const WalkArgs &a)
     // every loop below is bounded by these totals, whatever the records hold
     const int ng = min(*a.ngroups, (int)a.n);
     const int nn = *a.nnodes;
+    // the queues hand out units: group g, share `part` of its evaluation
+    const int parts = MODE == kWalkVjp ? max(1, min(a.parts, kMaxParts)) : 1;
+    const int nu = ng * parts;
     // Groups are split into kWalkQueues contiguous ranges, one per XCD (work
     // groups are dispatched to the XCDs in turn, so block b runs on XCD
     // b mod 8): neighbouring groups share most of their lists, and keeping
@@ -758,14 +774,15 @@ __device__ __forceinline__ void walk_body(const WalkArgs &a)
     for (;;) {
         const unsigned long long old =
             atomicAdd(&a.wq[kQStride * qx], lane == 0 ? 1ull : 0ull);
-        const int g0 = (int)(((int64_t)ng * qx) / kWalkQueues);
-        const int g1 = (int)(((int64_t)ng * (qx + 1)) / kWalkQueues);
-        const int g = g0 + uni((int)min(old, (unsigned long long)ng));
-        if (g >= g1) {
+        const int g0 = (int)(((int64_t)nu * qx) / kWalkQueues);
+        const int g1 = (int)(((int64_t)nu * (qx + 1)) / kWalkQueues);
+        const int un = g0 + uni((int)min(old, (unsigned long long)nu));
+        if (un >= g1) {
             if (++exhausted == kWalkQueues) break;
             qx = qx + 1 == kWalkQueues ? 0 : qx + 1;
             continue;
         }
+        const int g = parts == 1 ? un : un / parts, part = un - g * parts;
         const int4 gr = a.groups[g];
         const int gfirst = uni(gr.x), c = uni(gr.y), gnode = uni(gr.z), root = uni(gr.w);
         if (gfirst < 0 || c < 1 || c > kMaxGroup || (int64_t)gfirst + c > a.n || gnode < 0 ||
@@ -809,6 +826,8 @@ __device__ __forceinline__ void walk_body(const WalkArgs &a)
         tg.i = i;
         tg.E0 = tg.E1 = tg.E2 = tg.PH = 0.0;
         tg.C0 = tg.C1 = tg.C2 = 0.0;
+        tg.part = part;
+        tg.ck = 0;
         stk[0] = make_int2(root, min(((const int *)(a.nrec + 8 * (int64_t)root + 2))[0], nn));
         int sp = 1;
         wave_sync();
@@ -990,6 +1009,15 @@ __device__ __forceinline__ void walk_body(const WalkArgs &a)
                 }
                 if (a.phiout) a.phiout[ci] = s3;
             }
+        } else if (parts > 1) {
+            // a shared group's waves add their shares (acc cleared beforehand)
+            if (act && sub == 0) {
+                double *ac = (double *)(a.acc + i);
+                atomicAdd(ac + 0, s0);
+                atomicAdd(ac + 1, s1);
+                atomicAdd(ac + 2, s2);
+                atomicAdd(ac + 3, s3);
+            }
         } else {
             a.acc[(act && sub == 0) ? (int64_t)i : a.n_spare + lane] =
                 make_double4(s0, s1, s2, s3);
@@ -1007,13 +1035,15 @@ __device__ __forceinline__ void walk_body(const WalkArgs &a)
             const double v = lane == 0 ? c0 : lane == 1 ? c1 : c2;
             if (lane < 3) atomicAdd(a.lobar + 4 * (int64_t)cl + lane, v);
         }
+        // counts once per group (every wave of a shared group has the same)
         const int tot_m = wave_isum(my_m), tot_src = wave_isum(my_src);
-        a.gstat[g] = make_int2(tot_m, tot_src);   // same value from every lane
+        if (part == 0) a.gstat[g] = make_int2(tot_m, tot_src);   // same value from every lane
         const unsigned long long zero = 0ull;
+        const bool count = lane == 0 && part == 0;
         atomicAdd(&a.ctr[CTR_P2P],
-                  lane == 0 ? (unsigned long long)c * (unsigned long long)tot_src : zero);
+                  count ? (unsigned long long)c * (unsigned long long)tot_src : zero);
         atomicAdd(&a.ctr[CTR_M2P],
-                  lane == 0 ? (unsigned long long)c * (unsigned long long)tot_m : zero);
+                  count ? (unsigned long long)c * (unsigned long long)tot_m : zero);
     }
 }
 
@@ -1126,7 +1156,8 @@ __global__ __launch_bounds__(256) void k_vjp_prep(const double *__restrict__ u,
                                                  const int64_t *__restrict__ off, int clouds,
                                                  const double4 *__restrict__ cube,
                                                  double4 *w, double *xsrc, double *cbar,
-                                                 uint32_t *lomin, const int32_t *flags)
+                                                 uint32_t *lomin, double4 *acc,
+                                                 const int32_t *flags)
 {
     if (*flags) return;
     const double inv = 1.0 / vjp_scale(ctr);
@@ -1138,6 +1169,7 @@ __global__ __launch_bounds__(256) void k_vjp_prep(const double *__restrict__ u,
         const double qq = x.w * inv;
         w[p] = make_double4(qq * u[3 * i], qq * u[3 * i + 1], qq * u[3 * i + 2], 0.0);
         *(double4 *)(xsrc + 4 * p) = make_double4(0.0, 0.0, 0.0, 0.0);
+        acc[p] = make_double4(0.0, 0.0, 0.0, 0.0);   // shared groups add their shares
         const int cl = cloud_of(off, clouds, p);
         const double4 lo = cube[2 * cl];
         if (x.x == lo.x) atomicMin(lomin + 3 * cl + 0, (uint32_t)i);
@@ -1271,6 +1303,7 @@ static WalkArgs walk_args(Ctx *c)
     wa.theta = c->p_built.theta;
     wa.L = c->p_built.list_len;
     wa.wclock = nullptr;
+    wa.parts = 1;
     return wa;
 }
 
@@ -1312,10 +1345,31 @@ void launch_forces(Ctx *c, double *f, double *phi, hipStream_t s)
     if (c->timing) (void)hipEventRecord(e1, s);
 }
 
+// Waves that share one group of the adjoint walk.  The adjoint's evaluation
+// is four times the forward walk's, and a wave alone on its SIMD issues at
+// about 0.4 of what several waves do together; so when the groups are fewer
+// than the waves the device holds at once, each group's staged chunks are
+// split between up to kMaxParts waves (each builds the same lists).  The
+// group count is estimated as n / G; it only sets the split.
+template <int PREC>
+static int vjp_parts(const Ctx *c)
+{
+    int blocks = 0;
+    const size_t lds = (size_t)4 * walk_wave_bytes<PREC>(c->p_built.list_len);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &blocks, k_walk<PREC, kWalkVjp, false, false>, 256, lds) != hipSuccess ||
+        blocks < 1)
+        blocks = 1;
+    const int64_t resident = (int64_t)4 * blocks * std::max(c->num_cu, 1);
+    const int64_t groups = std::max<int64_t>(1, c->n / std::max(c->p_built.group_size, 1));
+    return (int)std::max<int64_t>(1, std::min<int64_t>(kMaxParts, resident / groups));
+}
+
 void launch_vjp(Ctx *c, const VjpScratch &sc, const double *u, double *xbar, hipStream_t s)
 {
     const int64_t n = c->n;
     WalkArgs wa = walk_args(c);
+    wa.parts = c->p_built.precision == UCP_SPLIT ? vjp_parts<UCP_SPLIT>(c) : vjp_parts<UCP_FP64>(c);
     wa.w = sc.w;
     wa.cbar = sc.cbar;
     wa.xsrc = sc.xsrc;
@@ -1327,7 +1381,7 @@ void launch_vjp(Ctx *c, const VjpScratch &sc, const double *u, double *xbar, hip
     hipLaunchKernelGGL(k_vjp_prep, dim3(1024), dim3(256), 0, s, u, (const double4 *)c->d_xq,
                        (const uint32_t *)c->d_perm, n, (const int32_t *)(c->d_noff + n),
                        (const unsigned long long *)c->d_ctr, (const int64_t *)c->d_off, c->clouds,
-                       (const double4 *)c->d_cube, sc.w, sc.xsrc, sc.cbar, sc.lomin,
+                       (const double4 *)c->d_cube, sc.w, sc.xsrc, sc.cbar, sc.lomin, c->d_acc,
                        (const int32_t *)c->d_flags);
     hipLaunchKernelGGL(k_walk_reset, dim3(1), dim3(64), 0, s, c->d_ctr, c->d_wq);
     c->walk_armed = false;
