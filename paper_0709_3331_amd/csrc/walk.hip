@@ -1349,8 +1349,13 @@ void launch_forces(Ctx *c, double *f, double *phi, hipStream_t s)
 // is four times the forward walk's, and a wave alone on its SIMD issues at
 // about 0.4 of what several waves do together; so when the groups are fewer
 // than the waves the device holds at once, each group's staged chunks are
-// split between up to kMaxParts waves (each builds the same lists).  The
-// group count is estimated as n / G; it only sets the split.
+// split between up to kMaxParts waves (each builds the same lists): with at
+// least two resident waves per group, one more than that, so that units are
+// left for the waves that finish first (N = 65,536, 1024 groups: 4 shares of a group with 3072
+// resident SPLIT waves measured 1.14 ms per VJP against 1.22 ms for 3 and
+// 1.42 ms for 2; in FP64, 2048 resident waves, 3 shares 1.66 ms against 1.71
+// ms for 2 and 1.76 ms for 4).  The group count is estimated as n / G; it
+// only sets the split.
 template <int PREC>
 static int vjp_parts(const Ctx *c)
 {
@@ -1362,7 +1367,8 @@ static int vjp_parts(const Ctx *c)
         blocks = 1;
     const int64_t resident = (int64_t)4 * blocks * std::max(c->num_cu, 1);
     const int64_t groups = std::max<int64_t>(1, c->n / std::max(c->p_built.group_size, 1));
-    return (int)std::max<int64_t>(1, std::min<int64_t>(kMaxParts, resident / groups));
+    const int64_t per = resident / groups;   // resident waves per group
+    return per < 2 ? 1 : (int)std::min<int64_t>(kMaxParts, per + 1);
 }
 
 void launch_vjp(Ctx *c, const VjpScratch &sc, const double *u, double *xbar, hipStream_t s)
