@@ -67,6 +67,10 @@ CASES = [
     ("chunk", 3000, 21, 0.5, 0.01, 8, 64, L.UCP_GROUP_CHUNK),
     ("node-ragged", 2002, 22, 0.6, 0.01, 4, 32, L.UCP_GROUP_NODE),
     ("per-particle", 700, 23, 0.7, 0.02, 1, 1, L.UCP_GROUP_CHUNK),
+    # 2000 groups: fewer than two resident adjoint waves per group on the
+    # device's 256 CUs, so each group is one wave's alone (the smaller cases
+    # share every group between several waves)
+    ("per-particle-unshared", 2000, 28, 0.5, 0.01, 1, 1, L.UCP_GROUP_CHUNK),
 ]
 
 
