@@ -421,6 +421,52 @@ def bench_large(args, prec, dev):
             "sampled_groups": int(len(range(0, t.ngroups, 997))), "sampled_targets": 1024}
 
 
+def ensemble_steps(args, dev):
+    """The 64-cloud ensemble's batched Verlet steps at the setting the
+    autotuner picks for it (G = 64 chunk groups, L = 128, leaf capacity 24,
+    the figures of the benchmark's ensemble section), enqueued directly with
+    HIP events around every walk, for a kernel trace: --warmup untimed steps,
+    then --steps timed ones."""
+    import torch
+
+    from paper_0709_3331_amd import _lib as L
+    from paper_0709_3331_amd import inputs
+    from paper_0709_3331_amd.tree import TreeSolver
+
+    ens, off, eprm = inputs.ensemble()
+    clouds = len(off) - 1
+    n = int(off[-1])
+    x, v, q, m = (torch.from_numpy(a).to(dev) for a in (ens.x, ens.v, ens.q, ens.m))
+    offs = torch.from_numpy(off).to(dev)
+    prec = L.UCP_SPLIT if args.precision == "split" else L.UCP_FP64
+    gm = L.UCP_GROUP_CHUNK if args.group_mode == "chunk" else L.UCP_GROUP_NODE
+    ts = TreeSolver(n, clouds, curve=CURVE, theta=eprm["theta"], eps=eprm["eps"], precision=prec,
+                    group_size=args.group_size, list_len=args.list_len, group_mode=gm,
+                    leaf_cap=args.leaf_cap, walk_waves=args.walk_waves)
+    f = ts.tree_forces(x, q, offs)
+    ts.timing(True)
+    for _ in range(args.warmup):
+        ts.step(x, v, f, q, m, eprm["dt"], 1, offsets=offs)
+    torch.cuda.synchronize()
+    ts.timing_read()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ts.step(x, v, f, q, m, eprm["dt"], 1, offsets=offs)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wms, wc = ts.timing_read()
+    ts.timing(False)
+    st = ts.stats()
+    ts.close()
+    return {"workload": f"64-cloud ensemble, N={n} in all, eps={eprm['eps']}, theta={eprm['theta']}, "
+                        f"G={args.group_size} ({args.group_mode} groups), L={args.list_len}, "
+                        f"leaf_cap={args.leaf_cap}, one KDK Verlet step dt={eprm['dt']}",
+            "n": n, "clouds": clouds, "precision": args.precision, "steps": args.steps,
+            "warmup": args.warmup, "path": "directly enqueued steps",
+            "ms_per_step": 1e3 * (t1 - t0) / args.steps, "walk_ms": wms / max(wc, 1),
+            "interactions_per_particle": (st["m2p"] + st["p2p"]) / n}
+
+
 def vjp_timing(args, dev):
     """The force VJP beside the forward walk on the N = 65,536 cloud of the
     differentiable rollout (theta = 0.5, eps = 0.01), same tree: --warmup
@@ -807,12 +853,15 @@ def main():
     ap.add_argument("--study", choices=["opening", "relaxation"],
                     help="run a study instead of the benchmark and print its JSON line")
     ap.add_argument("--study-dt", type=float, default=1e-6, help="time step of the study")
-    ap.add_argument("--workload", choices=["metric", "large", "adjoint"], default="metric",
+    ap.add_argument("--workload", choices=["metric", "large", "adjoint", "ensemble"],
+                    default="metric",
                     help="metric: the N=524,288 cloud (the benchmark); large: the N=4,194,304 "
                          "cloud (eps=0.002, 10%% hot electrons) under the same step protocol, "
                          "for profiling its build; adjoint: the N=65,536 cloud of the "
-                         "differentiable rollout, --steps forward walks and force VJPs timed "
-                         "(prints that JSON line instead of the benchmark's)")
+                         "differentiable rollout, --steps forward walks and force VJPs timed; "
+                         "ensemble: the 64-cloud ensemble, --steps batched steps enqueued "
+                         "directly at the autotuner's setting (these two print their own JSON "
+                         "line instead of the benchmark's)")
     args = ap.parse_args()
     global CURVE
     CURVE = 1 if args.curve == "hilbert" else 0
@@ -839,6 +888,9 @@ def main():
         return
     if args.workload == "adjoint":
         print(json.dumps({"command": command, **vjp_timing(args, dev)}), flush=True)
+        return
+    if args.workload == "ensemble":
+        print(json.dumps({"command": command, **ensemble_steps(args, dev)}), flush=True)
         return
     cl, prm = inputs.metric(0) if args.workload == "metric" else inputs.large(0)
     n = cl.n
