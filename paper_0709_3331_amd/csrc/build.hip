@@ -140,7 +140,7 @@ __device__ __forceinline__ double wave_max(double v)
 }
 
 // per block: min/max of its chunk, reduced through LDS, one atomic per
-// component; a chunk that straddles clouds falls back to per-particle atomics
+// component and cloud (a chunk that straddles clouds is reduced cloud by cloud)
 __global__ __launch_bounds__(256) void k_cube_reduce(const double *__restrict__ x, int64_t n,
                                                     const int64_t *__restrict__ off, int clouds,
                                                     unsigned long long *mm, int32_t *flags)
@@ -152,11 +152,15 @@ __global__ __launch_bounds__(256) void k_cube_reduce(const double *__restrict__ 
     const int64_t last = min(base + (int64_t)256 * kCubeItems, n) - 1;
     const int c0 = cloud_of(off, clouds, base), c1 = cloud_of(off, clouds, last);
     bool bad = false;
-    if (c0 == c1) {
+    // the chunk's particles cloud by cloud (a chunk may straddle clouds): per
+    // cloud one block reduction and one atomic per component
+    for (int c = c0; c <= c1; ++c) {
+        const int64_t lo = max(base, off[c]), hi = min(last + 1, off[c + 1]);
+        if (lo >= hi) continue;   // the same on every thread of the block
         double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
         for (int it = 0; it < kCubeItems; ++it) {
             const int64_t i = base + it * 256 + threadIdx.x;
-            if (i < n) {
+            if (i >= lo && i < hi) {
                 for (int d = 0; d < 3; ++d) {
                     const double v = x[3 * i + d];
                     bad |= !isfinite(v);
@@ -179,22 +183,10 @@ __global__ __launch_bounds__(256) void k_cube_reduce(const double *__restrict__ 
             const int d = threadIdx.x;
             double v = red[d][0];
             for (int j = 1; j < 4; ++j) v = d < 3 ? fmin(v, red[d][j]) : fmax(v, red[d][j]);
-            if (d < 3) atomicMin(&mm[6 * c0 + d], f64_ordered(v));
-            else atomicMax(&mm[6 * c0 + d], f64_ordered(v));
+            if (d < 3) atomicMin(&mm[6 * c + d], f64_ordered(v));
+            else atomicMax(&mm[6 * c + d], f64_ordered(v));
         }
-    } else {
-        for (int it = 0; it < kCubeItems; ++it) {
-            const int64_t i = base + it * 256 + threadIdx.x;
-            if (i < n) {
-                const int c = cloud_of(off, clouds, i);
-                for (int d = 0; d < 3; ++d) {
-                    const double v = x[3 * i + d];
-                    bad |= !isfinite(v);
-                    atomicMin(&mm[6 * c + d], f64_ordered(v));
-                    atomicMax(&mm[6 * c + 3 + d], f64_ordered(v));
-                }
-            }
-        }
+        __syncthreads();   // red is reused by the next cloud
     }
     if (bad) atomicOr(flags, UCP_FLAG_NONFINITE);
 }
