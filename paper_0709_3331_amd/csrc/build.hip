@@ -751,8 +751,13 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_full(
 // scanned outwards from the element, four keys per round of loads, counting
 // as it goes; a run longer than kFinishMax is not ranked but raises `full`,
 // the word that gates the full sort.  The kernel writes the sorted keys and
-// indices and gathers x and q.
-constexpr int kFinishMax = 2048;
+// indices and gathers x and q.  Ranking costs each element the length of its
+// run, so the limit is kept low: the longest runs of the initial clouds here
+// hold 3-27 particles, while a cloud whose cube has grown (electrons thrown
+// out by unresolved encounters) has many runs of hundreds to thousands, for
+// which one full sort is cheaper (N = 4,194,304 after 50 steps: the finish
+// took 2.4 ms with a limit of 2048, 0.16 ms with 256, the full sort 1.1 ms).
+constexpr int kFinishMax = 256;
 constexpr int kFinishThreads = 256, kFinishHalo = 64;   // keys staged in LDS on either side
 __global__ __launch_bounds__(kFinishThreads) void k_sort_finish(
     const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint64_t *kout,

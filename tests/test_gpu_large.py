@@ -181,11 +181,15 @@ def _top_run(x, bits=23):
     return int(cnt.max())
 
 
-@pytest.mark.parametrize("batched", [False, True], ids=["one-cloud", "batched"])
-def test_sort_falls_back_to_the_full_sort_for_long_runs(batched):
-    x1, q1 = _clustered(3000, 5000, 80)
+FINISH_MAX = 256   # longest run of equal top digits that the finish ranks
+
+
+@pytest.mark.parametrize("batched,tight", [(False, 3000), (True, 3000), (False, 1000)],
+                         ids=["one-cloud", "batched", "one-cloud-run-1000"])
+def test_sort_falls_back_to_the_full_sort_for_long_runs(batched, tight):
+    x1, q1 = _clustered(tight, 5000, 80)
     x2, q2 = _clustered(10, 2500, 81)
-    assert _top_run(x1) > 2048 and _top_run(x2) <= 2048
+    assert _top_run(x1) > FINISH_MAX and _top_run(x2) <= FINISH_MAX
     say(f"[sort] long run of {_top_run(x1)} equal top digits, batched={batched}")
     parts = [(x1, q1), (x2, q2)] if batched else [(x1, q1)]
     x = np.concatenate([p[0] for p in parts]); q = np.concatenate([p[1] for p in parts])
